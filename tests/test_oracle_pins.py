@@ -1,0 +1,529 @@
+"""Pins of the CPU oracle against facts fixed outside it: values and maps
+printed in the paper, closed forms, exact rational arithmetic, brute force
+and textbook algorithms.  CPU only."""
+import heapq
+import itertools
+import math
+import os
+import struct
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2312_05492_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def setup_module(module):
+    O.build(force=False)
+
+
+# ------------------------------------------------------------------ Eq. 1
+def test_alpha_knots_printed_in_eq1():
+    # Eq. 1 (Sec. V-C.2): 2 above 1e-1, knots 1.75/1.5/1.25 at 1e-2/1e-3/1e-4,
+    # 1 at and below 1e-5
+    for eps, want in [(1e-1, 2.0), (0.5, 2.0), (10.0, 2.0), (1e-2, 1.75), (1e-3, 1.5),
+                      (1e-4, 1.25), (1e-5, 1.0), (1e-7, 1.0), (0.0, 1.0)]:
+        assert O.alpha(eps) == pytest.approx(want, abs=1e-15), eps
+
+
+def test_alpha_piecewise_linear_and_continuous():
+    knots = [1e-5, 1e-4, 1e-3, 1e-2, 1e-1]
+    vals = [1.0, 1.25, 1.5, 1.75, 2.0]
+    for (e0, v0), (e1, v1) in zip(zip(knots, vals), zip(knots[1:], vals[1:])):
+        mid = 0.5 * (e0 + e1)
+        assert O.alpha(mid) == pytest.approx(0.5 * (v0 + v1), abs=1e-12)
+        # left limit at the upper knot equals the knot value (continuity)
+        assert O.alpha(e1 * (1 - 1e-12)) == pytest.approx(v1, abs=1e-9)
+    grid = np.logspace(-7, 0, 400)
+    a = [O.alpha(e) for e in grid]
+    assert all(x <= y for x, y in zip(a, a[1:]))
+
+
+# -------------------------------------------------------- rounding of bounds
+def test_round_down_is_largest_float_below():
+    rng = np.random.default_rng(7)
+    for v in list(rng.uniform(1e-12, 1e3, 200)) + [1.0, 0.1, 1e-3, 3.0e38]:
+        f = O.round_down(float(v))
+        assert Fraction(float(f)) <= Fraction(float(v))
+        up = np.nextafter(f, np.float32(np.inf))
+        assert Fraction(float(up)) > Fraction(float(v))
+    assert O.round_down(0.0) == 0.0
+    assert O.round_down(1e300) == np.finfo(np.float32).max
+
+
+def test_level_bounds_exact_rational():
+    # Sec. V-B.2: e_l = e / alpha^(l-1), l = 1 at stride 1; checked exactly
+    x = synth.spectral_field((24, 20, 40), seed=11)
+    for eb in (1e-2, 1e-3, 1e-4, 3e-3):
+        cfg = O.plan(x, O.Params(shape=x.shape, eb=eb))
+        e_abs = Fraction(eb) * (Fraction(float(cfg.vmax)) - Fraction(float(cfg.vmin)))
+        a = Fraction(cfg.alpha)
+        assert cfg.levels == 3
+        for l in range(1, 4):
+            exact = e_abs / a ** (l - 1)
+            f = cfg.el[l - 1]
+            assert Fraction(float(f)) <= exact
+            assert Fraction(float(np.nextafter(f, np.float32(np.inf)))) > exact
+        assert cfg.el[0] >= cfg.el[1] >= cfg.el[2]
+        assert cfg.ebx2[0] == np.float32(2) * cfg.el[0]
+
+
+def test_level_bounds_at_1e3_ratio():
+    # at eps = 1e-3, alpha = 1.5: e_2/e_1 ~ 2/3 and e_3/e_1 ~ 4/9
+    x = synth.spectral_field((24, 20, 40), seed=12)
+    cfg = O.plan(x, O.Params(shape=x.shape, eb=1e-3))
+    assert cfg.alpha == pytest.approx(1.5, abs=1e-15)
+    assert cfg.el[1] / cfg.el[0] == pytest.approx(2 / 3, rel=1e-6)
+    assert cfg.el[2] / cfg.el[0] == pytest.approx(4 / 9, rel=1e-6)
+
+
+# ------------------------------------------------------ spline formulas
+def _poly(coef, t):
+    return sum(c * t ** k for k, c in enumerate(coef))
+
+
+def test_spline_exactness_on_polynomials():
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        c = [int(v) for v in rng.integers(-20, 21, size=4)]
+        lin1 = c[:2]
+        quad = c[:3]
+        cub = c
+        f = lambda cf, t: np.float32(_poly(cf, t))
+        # linear: nodes -1, 1
+        assert O.stencil(O.ST_LINEAR, 0, f(lin1, -1), f(lin1, 1), 0) == f(lin1, 0)
+        # quadratic: nodes -3,-1,1 (left) and -1,1,3 (right)
+        assert O.stencil(O.ST_QUAD_LEFT, f(quad, -3), f(quad, -1), f(quad, 1), 0) == f(quad, 0)
+        assert O.stencil(O.ST_QUAD_RIGHT, 0, f(quad, -1), f(quad, 1), f(quad, 3)) == f(quad, 0)
+        # cubic not-a-knot: the Lagrange cubic on -3,-1,1,3
+        args = [f(cub, t) for t in (-3, -1, 1, 3)]
+        assert O.stencil(O.ST_NAK, *args) == f(cub, 0)
+        # natural cubic reproduces linears exactly
+        args = [f(lin1, t) for t in (-3, -1, 1, 3)]
+        assert O.stencil(O.ST_NAT, *args) == f(lin1, 0)
+
+
+def test_spline_weights_match_lagrange_and_paper():
+    # NAK and the quadratics are the Lagrange weights at 0 (Sec. V-B.1)
+    def lagrange(nodes):
+        w = []
+        for i, ti in enumerate(nodes):
+            num = Fraction(1)
+            for j, tj in enumerate(nodes):
+                if j != i:
+                    num *= Fraction(0 - tj, ti - tj)
+            w.append(num)
+        return w
+    assert lagrange([-3, -1, 1, 3]) == [Fraction(-1, 16), Fraction(9, 16), Fraction(9, 16),
+                                        Fraction(-1, 16)]
+    assert lagrange([-3, -1, 1]) == [Fraction(-1, 8), Fraction(6, 8), Fraction(3, 8)]
+    unit = np.eye(4, dtype=np.float32)
+    got_nak = [O.stencil(O.ST_NAK, *u) for u in unit]
+    assert [Fraction(float(g)) for g in got_nak] == lagrange([-3, -1, 1, 3])
+    got_ql = [O.stencil(O.ST_QUAD_LEFT, *u) for u in unit[:3]]
+    assert [Fraction(float(g)) for g in got_ql] == lagrange([-3, -1, 1])
+    got_qr = [O.stencil(O.ST_QUAD_RIGHT, *u) for u in unit[1:]]
+    assert [Fraction(float(g)) for g in got_qr] == lagrange([-1, 1, 3])
+    # natural cubic: -3/40, 23/40, 23/40, -3/40 each within half an ulp
+    for u, wt in zip(unit, [Fraction(-3, 40), Fraction(23, 40), Fraction(23, 40), Fraction(-3, 40)]):
+        g = O.stencil(O.ST_NAT, *u)
+        ulp = Fraction(float(np.spacing(np.float32(abs(float(wt))))))
+        assert abs(Fraction(float(g)) - wt) <= ulp / 2
+
+
+def test_natural_cubic_not_exact_on_quadratics_and_nak_not_on_quartics():
+    # x^2 at nodes -3,-1,1,3: natural gives -1/5 (true 0); NAK gives 0
+    a, b, c, d = (np.float32(v) for v in (9, 1, 1, 9))
+    assert O.stencil(O.ST_NAT, a, b, c, d) == np.float32(-0.2)
+    assert O.stencil(O.ST_NAK, a, b, c, d) == 0.0
+    a, b, c, d = (np.float32(v) for v in (81, 1, 1, 81))
+    assert O.stencil(O.ST_NAK, a, b, c, d) == np.float32(-9.0)
+
+
+# ---------------------------------------------- Fig. spline-on-2D-slice
+def _golden_map():
+    rows = []
+    with open(os.path.join(GOLDEN, "spline_map_9x9.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            rows.append(line.split())
+    return np.array(rows)
+
+
+def _class_letters(cls):
+    m = {O.CLS_ANCHOR: "A", O.CLS_LINEAR: "L", O.CLS_QUAD: "Q", O.CLS_CUBIC: "C", O.CLS_ONE: "1",
+         O.CLS_NONE: "."}
+    return np.vectorize(m.get)(cls)
+
+
+def _map_for_order(order):
+    x = synth.spectral_field((9, 9), seed=5)
+    p = O.Params(shape=(9, 9), eb=1e-3, S=8, window=(8, 8), order=order, interp=(O.NAK, O.NAK))
+    c = O.compress(x, p, want_cls=True)
+    # array axis 0 is the figure's dim0 (its columns), axis 1 its dim1 (rows)
+    return _class_letters(c.cls).T
+
+
+def test_spline_map_matches_paper_figure():
+    fig = _golden_map()
+    assert fig.shape == (9, 9)
+    got = _map_for_order((0, 1))          # dim0 first, as the figure
+    assert (got == fig).all(), "\n%s" % got
+
+
+def test_spline_map_reverse_order_differs():
+    fig = _golden_map()
+    got = _map_for_order((1, 0))
+    assert (got != fig).sum() == 8
+
+
+def test_spline_map_3d_slice():
+    # a z = 0 slice of the 3D scheme with z processed first is the 2D figure
+    x = synth.spectral_field((9, 9, 9), seed=6)
+    p = O.Params(shape=(9, 9, 9), eb=1e-3, S=8, window=(8, 8, 8), order=(0, 1, 2),
+                 interp=(O.NAK,) * 3)
+    c = O.compress(x, p, want_cls=True)
+    assert (_class_letters(c.cls[0]).T == _golden_map()).all()
+
+
+# ------------------------------------------------ whole-predictor pins
+def _ramp(shape, coef=(3, -2, 5), off=7):
+    g = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+    return (off + sum(c * a for c, a in zip(coef, g))).astype(np.float32)
+
+
+@pytest.mark.parametrize("interp", [O.LIN, O.NAK, O.NAT, O.AUTO])
+def test_integer_ramp_all_codes_centre(interp):
+    # every n_d = 1 (mod S): no one-neighbour case; all splines exact on linears
+    x = _ramp((17, 17, 33))
+    p = O.Params(shape=x.shape, eb=1e-3, interp=(interp,) * 3)
+    c = O.compress(x, p)
+    assert (c.codes == p.R).all()
+    assert np.array_equal(c.recon.view(np.uint32), x.view(np.uint32))
+    assert c.outlier_idx.size == 0
+
+
+def test_integer_cubic_exact_at_four_point_stencils():
+    # P(x) integer cubic (values < 2^24), constant in y and z; NAK chosen.
+    # n_x = 65 = 1 (mod 32) so that every window has its far anchor plane
+    xs = np.arange(65)
+    P = xs ** 3 - 30 * xs ** 2 + 7 * xs + 5
+    x = np.broadcast_to(P.astype(np.float32), (17, 17, 65)).copy()
+    p = O.Params(shape=x.shape, eb=1e-4)
+    c = O.compress(x, p)
+    assert c.config.spline[0] == O.NAK
+    cz, cy, cx = np.meshgrid(np.arange(17), np.arange(17), np.arange(65), indexing="ij")
+    sel = (cz % 4 == 0) & (cy % 4 == 0) & np.isin(cx % 32, [12, 20])
+    assert sel.sum() > 0
+    assert (c.codes[sel] == p.R).all()
+
+
+def test_tiny_bound_every_prediction_is_outlier():
+    x = synth.spectral_field((20, 18, 40), seed=8)
+    p = O.Params(shape=x.shape, eb=1e-30, eb_mode=O.EB_ABS)
+    c = O.compress(x, p)
+    is_anchor = np.zeros(x.shape, bool)
+    is_anchor[::8, ::8, ::8] = True
+    assert (c.codes[is_anchor] == p.R).all()
+    assert (c.codes[~is_anchor] == 0).all()
+    assert np.array_equal(c.recon.view(np.uint32), x.view(np.uint32))
+    assert c.outlier_idx.size == x.size - is_anchor.sum()
+    assert np.array_equal(c.outlier_idx, np.flatnonzero(~is_anchor.ravel()))
+    assert np.array_equal(c.outlier_val, x.ravel()[~is_anchor.ravel()])
+
+
+def test_anchors_are_the_lattice_points():
+    x = synth.spectral_field((21, 30, 45), seed=9)
+    c = O.compress(x, O.Params(shape=x.shape, eb=1e-3))
+    assert np.array_equal(c.anchors, x[::8, ::8, ::8].ravel())
+    assert c.anchors.size == math.ceil(21 / 8) * math.ceil(30 / 8) * math.ceil(45 / 8)
+    x2 = synth.spectral_field((50, 70), seed=9)
+    c2 = O.compress(x2, O.Params(shape=x2.shape, eb=1e-3))
+    assert np.array_equal(c2.anchors, x2[::16, ::16].ravel())
+
+
+CASES = [
+    ("bumps64", lambda: synth.bumps_field((64, 64, 64), seed=1), dict(eb=1e-3)),
+    ("spec3d", lambda: synth.spectral_field((33, 41, 70), seed=2, mean=10), dict(eb=1e-4)),
+    ("spec3d_lin", lambda: synth.spectral_field((20, 24, 50), seed=3),
+     dict(eb=1e-3, interp=(O.LIN, O.AUTO, O.AUTO))),
+    ("abs", lambda: synth.spectral_field((19, 27, 36), seed=4), dict(eb=0.01, eb_mode=O.EB_ABS)),
+    ("alpha1", lambda: synth.spectral_field((19, 27, 36), seed=4), dict(eb=1e-2, alpha=1.0)),
+    ("clim2d", lambda: synth.climate_field(301, shape=(90, 180)), dict(eb=1e-3)),
+    ("spec2d", lambda: synth.spectral_field((77, 131), beta=3.0, seed=5), dict(eb=1e-4)),
+    ("front", lambda: synth.front_field((30, 40, 50), seed=6), dict(eb=1e-2)),
+]
+
+
+@pytest.mark.parametrize("name,gen,kw", CASES, ids=[c[0] for c in CASES])
+def test_error_bound_roundtrip_and_windows(name, gen, kw):
+    x = gen()
+    p = O.Params(shape=x.shape, **kw)
+    c = O.compress(x, p)
+    cfg = c.config
+    err = np.abs(c.recon.astype(np.float64) - x.astype(np.float64))
+    # |x - x'| <= e_l <= e <= eb * range, at every point (FP64)
+    assert err.max() <= float(cfg.el[0])
+    bound_abs = kw["eb"] * (float(x.max()) - float(x.min())) if p.eb_mode == O.EB_REL else kw["eb"]
+    assert float(cfg.el[0]) <= bound_abs
+    # decompression replays the compressor's reconstruction bit for bit
+    d = O.decompress_parts(p, cfg, c.anchors, c.codes, c.outlier_idx, c.outlier_val)
+    assert np.array_equal(d.view(np.uint32), c.recon.view(np.uint32))
+    # the window-by-window formulation gives the same codes and values
+    wc, wr = O.compress_windowed(x, p, cfg)
+    assert np.array_equal(wc, c.codes)
+    assert np.array_equal(wr.view(np.uint32), c.recon.view(np.uint32))
+    # outliers: ascending, code 0, original values
+    assert np.all(np.diff(c.outlier_idx.astype(np.int64)) > 0)
+    assert np.array_equal(np.flatnonzero(c.codes.ravel() == 0), c.outlier_idx)
+    assert np.array_equal(x.ravel()[c.outlier_idx], c.outlier_val)
+    # the blob decodes, through the oracle's own parser, to the same values
+    y = O.decompress_blob(c.blob())
+    assert np.array_equal(y.view(np.uint32), c.recon.view(np.uint32))
+
+
+def test_level_bound_holds_per_level():
+    x = synth.spectral_field((33, 33, 65), seed=21)
+    p = O.Params(shape=x.shape, eb=1e-3)
+    c = O.compress(x, p)
+    err = np.abs(c.recon.astype(np.float64) - x.astype(np.float64))
+    cz, cy, cx = np.meshgrid(*[np.arange(s) for s in x.shape], indexing="ij")
+    for l, s in [(3, 4), (2, 2)]:
+        # points of level l: all coordinates multiples of s, not all of 2s
+        on = (cz % s == 0) & (cy % s == 0) & (cx % s == 0) & ~(
+            (cz % (2 * s) == 0) & (cy % (2 * s) == 0) & (cx % (2 * s) == 0))
+        assert err[on].max() <= float(c.config.el[l - 1])
+
+
+# --------------------------------------------------- quantiser edges
+def _edge_field(v):
+    x = np.zeros((17, 17), dtype=np.float32)
+    x[8, 0] = v          # first point of the first pass: predicted as 0
+    return x
+
+
+@pytest.mark.parametrize("v,code", [(2.5, 512 + 2), (3.5, 512 + 4), (-2.5, 512 - 2),
+                                    (0.5, 512), (1.5, 514), (510.5, 1022), (511.0, 1023),
+                                    (-511.0, 1), (511.5, 0), (-511.5, 0), (512.0, 0),
+                                    (1e6, 0)])
+def test_quantiser_round_half_even_and_radius(v, code):
+    # e = 0.5 exactly, alpha = 1: bin width 1, q = round-half-even(residual),
+    # |q| >= R = 512 is an outlier (Sec. III-A)
+    p = O.Params(shape=(17, 17), eb=0.5, eb_mode=O.EB_ABS, alpha=1.0, S=16, window=(16, 16),
+                 order=(0, 1), interp=(O.LIN, O.LIN))
+    c = O.compress(_edge_field(v), p)
+    assert c.codes[8, 0] == code
+    if code == 0:
+        assert c.recon[8, 0] == np.float32(v)
+    else:
+        assert c.recon[8, 0] == np.float32(code - 512)
+
+
+def test_zero_bound_keeps_only_exact_predictions():
+    x = np.full((20, 30, 40), 3.0, dtype=np.float32)
+    x[5, 7, 9] = 4.0
+    p = O.Params(shape=x.shape, eb=0.0, eb_mode=O.EB_ABS)
+    c = O.compress(x, p)
+    assert c.config.e == 0.0
+    assert np.array_equal(c.recon, x)
+    assert c.codes[5, 7, 9] == 0
+    # constant with exact products: every prediction exact except near the spike
+    assert (c.codes == 512).mean() > 0.95
+
+
+def test_nonfinite_rejected():
+    x = np.zeros((16, 16, 16), dtype=np.float32)
+    x[3, 4, 5] = np.nan
+    with pytest.raises(O.OracleError) as e:
+        O.plan(x, O.Params(shape=x.shape))
+    assert e.value.code == -2
+
+
+# --------------------------------------------------------- profiling
+def test_profile_cubic_along_x_picks_nak():
+    xs = np.arange(40)
+    P = (xs ** 3 - 20 * xs ** 2 + 3).astype(np.float32)
+    x = np.broadcast_to(P, (16, 16, 40)).copy()
+    cfg = O.plan(x, O.Params(shape=x.shape))
+    assert cfg.prof[0][1] == 0.0 and cfg.prof[0][2] > 0.0
+    assert cfg.spline[0] == O.NAK
+
+
+def test_profile_cosine_picks_natural():
+    # cos(pi x / 3): per-sample NAK error 5/16|cos|, natural 11/40|cos|
+    xs = np.arange(48, dtype=np.float64)
+    P = np.cos(np.pi * xs / 3).astype(np.float32)
+    x = np.broadcast_to(P, (16, 16, 48)).copy()
+    cfg = O.plan(x, O.Params(shape=x.shape))
+    assert cfg.spline[0] == O.NAT
+    pos = [min(max((2 * t + 1) * 48 // 8, 3), 44) for t in range(4)]
+    s = 16 * sum(abs(math.cos(math.pi * c / 3)) for c in pos)
+    assert cfg.prof[0][1] == pytest.approx(5 / 16 * s, rel=1e-5)
+    assert cfg.prof[0][2] == pytest.approx(11 / 40 * s, rel=1e-5)
+
+
+def test_profile_order_least_smooth_first():
+    rng = np.random.default_rng(4)
+    smooth = synth.spectral_field((24, 24), beta=3.0, seed=3)
+    rough_z = rng.standard_normal(24).astype(np.float32)
+    x = (smooth[None, :, :] + 5 * rough_z[:, None, None]).astype(np.float32)
+    cfg = O.plan(x, O.Params(shape=x.shape))
+    assert cfg.order[0] == 2          # z (slowest) first
+    x2 = np.ascontiguousarray(np.transpose(x, (1, 2, 0)))   # rough along x now
+    cfg2 = O.plan(x2, O.Params(shape=x2.shape))
+    assert cfg2.order[0] == 0
+    # no profile needed when everything is given
+    cfg3 = O.plan(x, O.Params(shape=x.shape, interp=(O.NAK,) * 3, order=(0, 1, 2)))
+    assert not cfg3.profiled and cfg3.order == (2, 1, 0)
+
+
+# ------------------------------------------------------ histogram
+def test_histogram_is_bincount():
+    rng = np.random.default_rng(1)
+    codes = rng.integers(0, 1024, size=100000).astype(np.uint16)
+    assert np.array_equal(O.histogram(codes, 1024), np.bincount(codes, minlength=1024))
+
+
+# ------------------------------------------------------ Huffman
+def _cost(h, ln):
+    return int(np.sum(h.astype(np.int64) * ln.astype(np.int64)))
+
+
+def _kraft(ln):
+    return sum(Fraction(1, 2 ** int(l)) for l in ln if l)
+
+
+def _brute_optimal(h, lmax):
+    m = len(h)
+    best = None
+    for ln in itertools.product(range(1, min(m, lmax + 1)), repeat=m):
+        if sum(Fraction(1, 2 ** l) for l in ln) <= 1:
+            c = sum(a * b for a, b in zip(h, ln))
+            best = c if best is None else min(best, c)
+    return best
+
+
+def test_huffman_optimal_vs_brute_force():
+    rng = np.random.default_rng(2)
+    for trial in range(40):
+        m = int(rng.integers(2, 7))
+        h = rng.integers(1, 50, size=m).astype(np.uint32)
+        for lmax in (24, 3):
+            if 2 ** lmax < m:
+                continue
+            ln = O.huffman_lengths(h, lmax)
+            assert ln.max() <= lmax
+            assert _kraft(ln) == 1
+            assert _cost(h, ln) == _brute_optimal(list(map(int, h)), lmax)
+
+
+def _heap_huffman_cost(h):
+    hp = [int(v) for v in h if v]
+    heapq.heapify(hp)
+    cost = 0
+    while len(hp) > 1:
+        a = heapq.heappop(hp)
+        b = heapq.heappop(hp)
+        cost += a + b
+        heapq.heappush(hp, a + b)
+    return cost
+
+
+def test_huffman_matches_textbook_when_limit_not_binding():
+    rng = np.random.default_rng(3)
+    for trial in range(10):
+        h = np.zeros(1024, dtype=np.uint32)
+        g = np.clip(rng.geometric(0.3, size=200000) * rng.choice([-1, 1], size=200000) + 512, 0, 1023)
+        np.add.at(h, g, 1)
+        ln = O.huffman_lengths(h)
+        assert _cost(h, ln) == _heap_huffman_cost(h)
+        assert _kraft(ln) == 1
+        assert all((ln[s] > 0) == (h[s] > 0) for s in range(1024))
+
+
+def test_huffman_length_limit_binds():
+    fib = [1, 1]
+    while len(fib) < 32:
+        fib.append(fib[-1] + fib[-2])
+    h = np.array(fib, dtype=np.uint32)
+    ln = O.huffman_lengths(h, 24)
+    assert ln.max() == 24
+    assert _kraft(ln) == 1
+    assert _cost(h, ln) >= _heap_huffman_cost(h)
+    # a small limit on a small alphabet is optimal among limited codes
+    h2 = np.array([1, 1, 2, 3, 5, 8], dtype=np.uint32)
+    ln2 = O.huffman_lengths(h2, 3)
+    assert ln2.max() <= 3 and _cost(h2, ln2) == _brute_optimal(list(map(int, h2)), 3)
+
+
+def test_huffman_single_symbol():
+    h = np.zeros(1024, dtype=np.uint32)
+    h[512] = 77
+    ln = O.huffman_lengths(h)
+    assert ln[512] == 1 and ln.sum() == 1
+
+
+def test_canonical_codes_rfc1951_example():
+    # RFC 1951 Sec. 3.2.2: lengths (3,3,3,3,3,2,4,4) for A..H give
+    # A 010, B 011, C 100, D 101, E 110, F 00, G 1110, H 1111
+    ln = np.array([3, 3, 3, 3, 3, 2, 4, 4], dtype=np.uint8)
+    code = O.canonical_codes(ln)
+    assert list(code) == [0b010, 0b011, 0b100, 0b101, 0b110, 0b00, 0b1110, 0b1111]
+
+
+def test_bitstream_hand_example():
+    # lengths (1,2,2) -> codes 0, 10, 11; chunk C = 4
+    ln = np.array([1, 2, 2], dtype=np.uint8)
+    cw = O.canonical_codes(ln)
+    assert list(cw) == [0b0, 0b10, 0b11]
+    cb, words = O.encode(np.array([0, 1, 2, 0, 2, 2, 1], dtype=np.uint16), ln, cw, 4)
+    assert list(cb) == [6, 6]
+    assert list(words) == [0b010110 << 26, 0b111110 << 26]
+    assert list(O.decode(words, cb, 7, 4, ln)) == [0, 1, 2, 0, 2, 2, 1]
+
+
+def test_encode_decode_identity_random():
+    rng = np.random.default_rng(9)
+    for chunk in (256, 1024, 2048):
+        sym = np.clip(np.round(rng.normal(512, 3, size=50001)), 0, 1023).astype(np.uint16)
+        h = O.histogram(sym, 1024)
+        ln = O.huffman_lengths(h)
+        cw = O.canonical_codes(ln)
+        cb, words = O.encode(sym, ln, cw, chunk)
+        assert int(cb.astype(np.int64).sum()) == _cost(h, ln)
+        assert words.size == sum((int(b) + 31) // 32 for b in cb)
+        assert np.array_equal(O.decode(words, cb, sym.size, chunk, ln), sym)
+
+
+# ------------------------------------------------------ blob and metrics
+def test_blob_crc_detects_corruption_and_truncation():
+    x = synth.bumps_field((24, 24, 40), seed=3)
+    c = O.compress(x, O.Params(shape=x.shape, eb=1e-3))
+    b = bytearray(c.blob())
+    O.parse(bytes(b))
+    for pos in (10, 300, len(b) - 5):
+        bad = bytearray(b)
+        bad[pos] ^= 0x10
+        with pytest.raises(O.OracleError):
+            O.parse(bytes(bad))
+    with pytest.raises(O.OracleError):
+        O.parse(bytes(b[:-8]))
+
+
+def test_compression_ratio_below_one_bit_ceiling():
+    # >= 1 bit per symbol plus 32 bits per anchor: CR <= 32 / (1 + 32/S^D)
+    x = synth.bumps_field((64, 64, 64), seed=1)
+    c = O.compress(x, O.Params(shape=x.shape, eb=1e-2))
+    cr = x.nbytes / len(c.blob())
+    assert 20 < cr < 32 / (1 + 32 / 512)
+
+
+def test_psnr_closed_form():
+    x = np.linspace(0, 10, 1000).astype(np.float32)
+    y = x + np.float32(0.01)
+    assert O.psnr(x, y) == pytest.approx(20 * math.log10(10 / 0.01), abs=1e-3)
