@@ -1,0 +1,245 @@
+/*
+ * szi.h -- C ABI of libszi, an MI355X (gfx950) implementation of the G-Interp
+ * error-bounded lossy compressor of cuSZ-i (arXiv 2312.05492).
+ *
+ * The compression pipeline is the one of Fig. overview (Sec. IV):
+ *   prediction-quantisation by multi-level spline interpolation with
+ *   anchor points (Sec. V-A, V-B), auto-tuned by data profiling
+ *   (Sec. V-C), then a quant-code histogram and coarse-grained Huffman
+ *   encoding with outliers gathered by stream compaction (Sec. VI-A).
+ * Decompression decodes the quant-codes and replays the same predictions
+ * (Sec. V-B.1).  The closed de-redundancy pass of Sec. VI-B is not part of
+ * this library.
+ *
+ * Conventions
+ *  - Every call returns sz_status: 0 on success, a negative code on error.
+ *    On error outputs are left untouched and sz_last_error(ctx) returns a
+ *    message.  Nothing aborts the process.
+ *  - Fields are FP32, C-order.  sz_dims.n[0] is the FASTEST dimension (x);
+ *    n[ndim-1] the slowest.  A numpy array of shape (nz, ny, nx) has
+ *    n = {nx, ny, nz}.
+ *  - "stream" arguments are hipStream_t values passed as void* (NULL = the
+ *    default stream).  Work is enqueued on that stream.
+ *  - Device pointers must belong to the context's device.  The caller owns
+ *    every input and output buffer it passes; the library never writes to an
+ *    input.  Buffers inside sz_result belong to the context until
+ *    sz_result_free.
+ *  - A context may be used by one host thread at a time.  Independent
+ *    contexts on the same device may run concurrently on different streams.
+ *  - Limits: ndim in {2, 3}; 1 <= total points < 2^32; radius R in
+ *    [2, 1024]; Huffman chunk in {256, 512, 1024, 2048}; anchor stride and
+ *    window fixed to the defaults below.
+ */
+#ifndef SZI_H
+#define SZI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SZ_OK = 0,
+    SZ_ERR_INVALID_ARG = -1,  /* bad pointer, size, shape or parameter */
+    SZ_ERR_NONFINITE = -2,    /* the input field holds NaN or Inf */
+    SZ_ERR_OOM = -3,          /* device allocation failed or budget exceeded */
+    SZ_ERR_DEVICE = -4,       /* a HIP runtime call failed */
+    SZ_ERR_CORRUPT = -5,      /* a blob failed its size or CRC-32 checks */
+    SZ_ERR_UNSUPPORTED = -6,  /* a valid option this build does not implement */
+    SZ_ERR_CAPACITY = -7      /* a caller buffer is too small */
+} sz_status;
+
+/* Error-bound mode (Sec. V-C.1): an absolute bound, or one relative to the
+ * value range (the relative bound times the range is the absolute one). */
+typedef enum { SZ_EB_ABS = 0, SZ_EB_REL = 1 } sz_eb_mode;
+
+/* Spline per dimension (Sec. V-B.1).  LINEAR uses the linear spline even
+ * where four neighbours exist; the cubic modes use the quadratic splines
+ * where only three exist.  AUTO picks the cubic with the lower profiled
+ * error (Sec. V-C.2). */
+typedef enum {
+    SZ_INTERP_LINEAR = 0,
+    SZ_INTERP_CUBIC_NAK = 1,      /* not-a-knot: (-1, 9, 9, -1)/16 */
+    SZ_INTERP_CUBIC_NATURAL = 2,  /* natural: (-3, 23, 23, -3)/40 */
+    SZ_INTERP_CUBIC_AUTO = 3
+} sz_interp;
+
+typedef struct {
+    uint32_t ndim;      /* 2 or 3 */
+    uint32_t reserved;  /* 0 */
+    uint64_t n[3];      /* n[0] fastest; entries >= ndim ignored */
+} sz_dims;
+
+typedef struct {
+    int32_t eb_mode;        /* sz_eb_mode */
+    int32_t reserved0;      /* 0 */
+    double eb;              /* >= 0, finite */
+    int32_t interp[3];      /* sz_interp per dimension index (0 = fastest) */
+    int32_t order[3];       /* order[k] = dimension index of the k-th pass at
+                               every level; order[0] < 0 = auto (least smooth
+                               first, Sec. V-C.2) */
+    double alpha;           /* level-bound reduction factor (Sec. V-B.2);
+                               <= 0 = Eq. 1; 1 = the same bound everywhere */
+    uint32_t radius;        /* R: codes q+R in 1..2R-1, 0 = outlier; 0 = 512 */
+    uint32_t huff_chunk;    /* symbols per Huffman chunk; 0 = 1024 */
+    uint32_t anchor_stride; /* 0 = default: 8 in 3D, 16 in 2D (Sec. V-A) */
+    uint32_t window[3];     /* 0 = default: (32, 8, 8) in 3D, (64, 16) in 2D,
+                               i.e. four basic blocks along x (Sec. V-D) */
+} sz_params;
+
+/* A compressed field.  Device pointers are owned by the context until
+ * sz_result_free.  codes and hist are kept for inspection; they are not
+ * part of the serialized blob. */
+typedef struct {
+    float* anchors;          /* lattice points, C-order, lossless */
+    uint64_t n_anchors;
+    uint16_t* codes;         /* n quant-codes: q+R; 0 = outlier; R at anchors */
+    uint64_t n;
+    uint32_t* outlier_idx;   /* ascending linear indices */
+    float* outlier_val;      /* original values at those indices */
+    uint64_t n_outliers;
+    uint32_t* words;         /* Huffman bitstream */
+    uint64_t n_words;
+    uint16_t* chunk_bits;    /* bit count of every chunk */
+    uint64_t n_chunks;
+    uint32_t* hist;          /* 2R symbol counts */
+    uint8_t* code_len;       /* 2R canonical code lengths (device) */
+    uint64_t compressed_bytes;  /* size of the serialized blob */
+    uint8_t header[256];     /* blob header (host copy), layout below */
+    void* internal;          /* library bookkeeping; do not touch */
+} sz_result;
+
+typedef struct sz_ctx sz_ctx;
+
+/* Fill p with the defaults: REL 1e-3, AUTO splines and order, Eq. 1 alpha,
+ * R = 512, chunk 1024, default stride and window. */
+void sz_params_default(sz_params* p);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the
+ * device memory the context may hold (0 = no cap). */
+sz_status sz_ctx_create(sz_ctx** out, int device, uint64_t hbm_budget_bytes);
+sz_status sz_ctx_destroy(sz_ctx* ctx);
+const char* sz_last_error(const sz_ctx* ctx);
+/* Device bytes held by the context now (pools included). */
+uint64_t sz_ctx_bytes_in_use(const sz_ctx* ctx);
+
+/* Launch shape of the persistent interpolation kernels: workgroups per
+ * compute unit (1..64; default 8).  Arithmetic-neutral: every setting gives
+ * byte-identical results; it only trades occupancy against tail effects. */
+sz_status sz_ctx_set_grid(sz_ctx* ctx, int workgroups_per_cu);
+
+/* Per-stage device timing.  When enabled, the context records a HIP event
+ * pair around every kernel launch (on the stream the kernel runs on) and
+ * accumulates the elapsed times once the call has synchronized.  Stages: */
+typedef enum {
+    SZ_STAGE_RANGE = 0,     /* value range, Sec. V-C.1 */
+    SZ_STAGE_PROFILE = 1,   /* sampled spline errors, Sec. V-C.1 */
+    SZ_STAGE_PLAN = 2,      /* alpha, level bounds, splines, order */
+    SZ_STAGE_INTERP = 3,    /* interpolation predictor-quantiser + histogram */
+    SZ_STAGE_CODEBOOK = 4,  /* histogram read-back, host codebook, upload */
+    SZ_STAGE_HUFF_STATS = 5,
+    SZ_STAGE_SCAN = 6,
+    SZ_STAGE_ENCODE = 7,    /* Huffman packing + outlier compaction */
+    SZ_STAGE_DECODE = 8,    /* Huffman decode */
+    SZ_STAGE_SCATTER = 9,   /* outliers into the output */
+    SZ_STAGE_REPLAY = 10,   /* interpolation replay (decompression) */
+    SZ_STAGE_COUNT = 11
+} sz_stage;
+/* enable != 0 turns timing on (and clears the totals). */
+sz_status sz_ctx_set_timing(sz_ctx* ctx, int enable);
+/* ms[SZ_STAGE_COUNT] receive accumulated milliseconds, launches[] the
+ * number of timed intervals per stage (either may be NULL); reset != 0
+ * clears the totals afterwards. */
+sz_status sz_ctx_read_timing(sz_ctx* ctx, double* ms, uint64_t* launches, int reset);
+
+/* Compress the device field d_in (n[0]*n[1]*n[2] floats).  Runs the whole
+ * pipeline on `stream`: range and profiling (Sec. V-C.1), auto-tuning
+ * (Sec. V-C.2, Eq. 1), level bounds (Sec. V-B.2), the interpolation
+ * predictor-quantiser with a fused histogram (Sec. V-A/B/D, VI-A), the host
+ * codebook (Sec. VI-A), Huffman encoding and outlier compaction.  Returns
+ * when *out is complete (the call synchronizes the stream).
+ * Errors: INVALID_ARG, NONFINITE, OOM, DEVICE, UNSUPPORTED. */
+sz_status sz_compress(sz_ctx* ctx, const float* d_in, const sz_dims* dims,
+                      const sz_params* params, void* stream, sz_result* out);
+
+/* Compress nfields fields in one pass of batched launches: one persistent
+ * interpolation launch over every window of every field, one batched
+ * encode.  d_in[i], dims[i], params[i] describe field i; outs[i] receives
+ * its result, byte-identical to what sz_compress returns for it alone. */
+sz_status sz_compress_batch(sz_ctx* ctx, uint32_t nfields, const float* const* d_in,
+                            const sz_dims* dims, const sz_params* params, void* stream,
+                            sz_result* outs);
+
+/* Decompress a device-resident result into d_out (n floats), replaying the
+ * predictions (Sec. V-B.1).  Returns after the stream has completed.
+ * Errors: INVALID_ARG, OOM, DEVICE, CORRUPT. */
+sz_status sz_decompress(sz_ctx* ctx, const sz_result* res, float* d_out, void* stream);
+
+/* Decompress several results in batched launches (one decode launch, one
+ * replay launch over all windows of all fields). */
+sz_status sz_decompress_batch(sz_ctx* ctx, uint32_t nfields, const sz_result* res,
+                              float* const* d_out, void* stream);
+
+/* Write the blob of res to host memory host_dst (capacity cap bytes).
+ * *written receives res->compressed_bytes.  CAPACITY if cap is too small. */
+sz_status sz_serialize(sz_ctx* ctx, const sz_result* res, void* host_dst, uint64_t cap,
+                       uint64_t* written);
+
+/* Parse a host blob (checking sizes and every CRC-32), copy it to the
+ * device and fill *out so that sz_decompress can run on it.
+ * Errors: CORRUPT, UNSUPPORTED (other version), OOM, DEVICE. */
+sz_status sz_upload(sz_ctx* ctx, const void* host_blob, uint64_t bytes, void* stream,
+                    sz_result* out);
+
+/* Release the device buffers of a result (safe on a zeroed result). */
+sz_status sz_result_free(sz_ctx* ctx, sz_result* res);
+
+/* Copy one section of a result to host memory (for inspection and tests).
+ * *written receives the section size in bytes. */
+typedef enum {
+    SZ_SEC_ANCHORS = 0, SZ_SEC_CODES = 1, SZ_SEC_OUTLIER_IDX = 2, SZ_SEC_OUTLIER_VAL = 3,
+    SZ_SEC_WORDS = 4, SZ_SEC_CHUNK_BITS = 5, SZ_SEC_HIST = 6, SZ_SEC_CODE_LEN = 7
+} sz_section;
+sz_status sz_result_read(sz_ctx* ctx, const sz_result* res, int32_t section, void* host_dst,
+                         uint64_t cap, uint64_t* written);
+
+/*
+ * Blob layout, little-endian; each section zero-padded to 8 bytes.
+ *   off  size  field
+ *     0     4  magic "SZI1"
+ *     4     4  u32 version = 1
+ *     8     4  u32 ndim
+ *    12     4  u32 anchor stride S
+ *    16    24  u64 n[3]           (unused dimensions 0)
+ *    40    12  u32 window[3]      (unused dimensions 0)
+ *    52     4  u32 radius R
+ *    56     4  u32 Huffman length limit (24)
+ *    60     4  u32 Huffman chunk C
+ *    64     4  u32 eb_mode
+ *    68     4  u32 levels L = log2 S
+ *    72     8  f64 eb as given
+ *    80     8  f64 alpha used
+ *    88    12  f32 vmin, vmax, e (absolute bound, rounded down to FP32)
+ *   100    12  i32 spline per dimension (0 linear, 1 NAK, 2 natural)
+ *   112    12  i32 order (unused -1)
+ *   124     4  reserved 0
+ *   128    64  f32 e_l for l = 1..16 (l = 1 is stride 1; unused 0)
+ *   192    32  u64 n_anchors, n_chunks, n_words, n_outliers
+ *   224    24  u32 CRC-32 of each section (unpadded)
+ *   248     4  reserved 0
+ *   252     4  u32 CRC-32 of bytes 0..251
+ *   256        anchors f32[n_anchors], code_len u8[2R], chunk_bits u16[n_chunks],
+ *              words u32[n_words], outlier_idx u32[n_outliers],
+ *              outlier_val f32[n_outliers]
+ * Huffman: canonical codes from the lengths; chunk j covers symbols
+ * [jC, min((j+1)C, n)), its codewords packed most-significant bit first
+ * from bit 31 of its first word, zero-padded to a word; chunks follow each
+ * other word-aligned.
+ */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SZI_H */

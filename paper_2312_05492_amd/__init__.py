@@ -1,1 +1,303 @@
-"""MI355X-native G-Interp error-bounded compressor (cuSZ-i, arXiv 2312.05492)."""
+"""MI355X-native G-Interp error-bounded compressor (cuSZ-i, arXiv 2312.05492).
+
+A thin ctypes binding of ``libszi.so`` (the C ABI in ``include/szi.h``):
+argument marshalling only.  Every step of compression and decompression runs
+in the library's HIP kernels (and, for the Huffman codebook, in its native
+host code, as the paper builds the codebook on the CPU).  PyTorch supplies
+device memory and the current stream.
+
+    import torch, paper_2312_05492_amd as szi
+    ctx = szi.Context()
+    res = ctx.compress(x_cuda_f32, eb=1e-3)          # relative bound
+    y = ctx.decompress(res)                           # torch tensor on the GPU
+    blob = res.blob()                                 # bytes
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libszi.so")
+
+STAGES = ["range", "profile", "plan", "interp", "codebook", "huff_stats", "scan", "encode",
+          "decode", "scatter", "replay"]
+SZ_OK = 0
+ERRORS = {-1: "INVALID_ARG", -2: "NONFINITE", -3: "OOM", -4: "DEVICE", -5: "CORRUPT",
+          -6: "UNSUPPORTED", -7: "CAPACITY"}
+EB_ABS, EB_REL = 0, 1
+LINEAR, CUBIC_NAK, CUBIC_NATURAL, CUBIC_AUTO = 0, 1, 2, 3
+SEC_ANCHORS, SEC_CODES, SEC_OUTLIER_IDX, SEC_OUTLIER_VAL, SEC_WORDS, SEC_CHUNK_BITS, \
+    SEC_HIST, SEC_CODE_LEN = range(8)
+_SEC_DTYPE = {SEC_ANCHORS: np.float32, SEC_CODES: np.uint16, SEC_OUTLIER_IDX: np.uint32,
+              SEC_OUTLIER_VAL: np.float32, SEC_WORDS: np.uint32, SEC_CHUNK_BITS: np.uint16,
+              SEC_HIST: np.uint32, SEC_CODE_LEN: np.uint8}
+
+
+class SzDims(C.Structure):
+    _fields_ = [("ndim", C.c_uint32), ("reserved", C.c_uint32), ("n", C.c_uint64 * 3)]
+
+
+class SzParams(C.Structure):
+    _fields_ = [("eb_mode", C.c_int32), ("reserved0", C.c_int32), ("eb", C.c_double),
+                ("interp", C.c_int32 * 3), ("order", C.c_int32 * 3), ("alpha", C.c_double),
+                ("radius", C.c_uint32), ("huff_chunk", C.c_uint32),
+                ("anchor_stride", C.c_uint32), ("window", C.c_uint32 * 3)]
+
+
+class SzResult(C.Structure):
+    _fields_ = [("anchors", C.c_void_p), ("n_anchors", C.c_uint64),
+                ("codes", C.c_void_p), ("n", C.c_uint64),
+                ("outlier_idx", C.c_void_p), ("outlier_val", C.c_void_p),
+                ("n_outliers", C.c_uint64),
+                ("words", C.c_void_p), ("n_words", C.c_uint64),
+                ("chunk_bits", C.c_void_p), ("n_chunks", C.c_uint64),
+                ("hist", C.c_void_p), ("code_len", C.c_void_p),
+                ("compressed_bytes", C.c_uint64), ("header", C.c_uint8 * 256),
+                ("internal", C.c_void_p)]
+
+
+class SzError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libszi.so; raises when it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libszi.so is not built: run `python -m paper_2312_05492_amd.build`"
+                               " (or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        vp = C.c_void_p
+        L.sz_params_default.restype = None
+        L.sz_params_default.argtypes = [P(SzParams)]
+        L.sz_ctx_create.restype = C.c_int
+        L.sz_ctx_create.argtypes = [P(vp), C.c_int, C.c_uint64]
+        L.sz_ctx_destroy.restype = C.c_int
+        L.sz_ctx_destroy.argtypes = [vp]
+        L.sz_last_error.restype = C.c_char_p
+        L.sz_last_error.argtypes = [vp]
+        L.sz_ctx_bytes_in_use.restype = C.c_uint64
+        L.sz_ctx_bytes_in_use.argtypes = [vp]
+        L.sz_ctx_set_grid.restype = C.c_int
+        L.sz_ctx_set_grid.argtypes = [vp, C.c_int]
+        L.sz_ctx_set_timing.restype = C.c_int
+        L.sz_ctx_set_timing.argtypes = [vp, C.c_int]
+        L.sz_ctx_read_timing.restype = C.c_int
+        L.sz_ctx_read_timing.argtypes = [vp, P(C.c_double), P(C.c_uint64), C.c_int]
+        L.sz_compress.restype = C.c_int
+        L.sz_compress.argtypes = [vp, vp, P(SzDims), P(SzParams), vp, P(SzResult)]
+        L.sz_compress_batch.restype = C.c_int
+        L.sz_compress_batch.argtypes = [vp, C.c_uint32, P(vp), P(SzDims), P(SzParams), vp,
+                                        P(SzResult)]
+        L.sz_decompress.restype = C.c_int
+        L.sz_decompress.argtypes = [vp, P(SzResult), vp, vp]
+        L.sz_decompress_batch.restype = C.c_int
+        L.sz_decompress_batch.argtypes = [vp, C.c_uint32, P(SzResult), P(vp), vp]
+        L.sz_serialize.restype = C.c_int
+        L.sz_serialize.argtypes = [vp, P(SzResult), vp, C.c_uint64, P(C.c_uint64)]
+        L.sz_upload.restype = C.c_int
+        L.sz_upload.argtypes = [vp, vp, C.c_uint64, vp, P(SzResult)]
+        L.sz_result_free.restype = C.c_int
+        L.sz_result_free.argtypes = [vp, P(SzResult)]
+        L.sz_result_read.restype = C.c_int
+        L.sz_result_read.argtypes = [vp, P(SzResult), C.c_int32, vp, C.c_uint64,
+                                     P(C.c_uint64)]
+        _lib = L
+    return _lib
+
+
+def make_dims(shape) -> SzDims:
+    d = SzDims()
+    d.ndim = len(shape)
+    for ax, s in enumerate(shape):
+        d.n[len(shape) - 1 - ax] = int(s)
+    return d
+
+
+def make_params(ndim, eb=1e-3, eb_mode=EB_REL, interp=None, order=None, alpha=0.0, radius=512,
+                chunk=1024) -> SzParams:
+    """interp and order are given per numpy axis (slowest first), as in the
+    oracle's Params; they are stored per dimension index (0 = fastest)."""
+    p = SzParams()
+    lib().sz_params_default(C.byref(p))
+    p.eb_mode = eb_mode
+    p.eb = float(eb)
+    if interp is not None:
+        for ax, v in enumerate(interp):
+            p.interp[ndim - 1 - ax] = int(v)
+    if order is not None:
+        for k, ax in enumerate(order):
+            p.order[k] = ndim - 1 - int(ax)
+    p.alpha = float(alpha)
+    p.radius = int(radius)
+    p.huff_chunk = int(chunk)
+    return p
+
+
+def _stream(torch, device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Result:
+    """A compressed field held in device memory by its context."""
+
+    def __init__(self, ctx: "Context", raw: SzResult, shape):
+        self.ctx = ctx
+        self.raw = raw
+        self.shape = tuple(shape)
+
+    @property
+    def compressed_bytes(self):
+        return self.raw.compressed_bytes
+
+    @property
+    def n_outliers(self):
+        return self.raw.n_outliers
+
+    def ratio(self):
+        return 4.0 * self.raw.n / self.raw.compressed_bytes
+
+    def read(self, section) -> np.ndarray:
+        L = lib()
+        need = C.c_uint64(0)
+        L.sz_result_read(self.ctx.h, C.byref(self.raw), section, None, 0, C.byref(need))
+        out = np.zeros(max(need.value, 1), dtype=np.uint8)
+        self.ctx._check(L.sz_result_read(self.ctx.h, C.byref(self.raw), section,
+                                         out.ctypes.data_as(C.c_void_p), out.size,
+                                         C.byref(need)))
+        return out[:need.value].view(_SEC_DTYPE[section]).copy()
+
+    def blob(self) -> bytes:
+        buf = (C.c_uint8 * self.raw.compressed_bytes)()
+        w = C.c_uint64(0)
+        self.ctx._check(lib().sz_serialize(self.ctx.h, C.byref(self.raw), buf,
+                                           self.raw.compressed_bytes, C.byref(w)))
+        return bytes(buf)
+
+    def header(self) -> bytes:
+        return bytes(self.raw.header)
+
+    def free(self):
+        if self.raw.internal:
+            lib().sz_result_free(self.ctx.h, C.byref(self.raw))
+
+    def __del__(self):
+        try:
+            if self.ctx.h and self.raw.internal:
+                self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """A libszi context on one GPU (device memory pool, staging buffers)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        import torch
+        self.torch = torch
+        self.device = device
+        h = C.c_void_p()
+        rc = lib().sz_ctx_create(C.byref(h), device, hbm_budget)
+        if rc != SZ_OK:
+            raise SzError(rc, "sz_ctx_create failed")
+        self.h = h
+
+    def _check(self, rc):
+        if rc != SZ_OK:
+            raise SzError(rc, lib().sz_last_error(self.h).decode())
+
+    def close(self):
+        if self.h:
+            lib().sz_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bytes_in_use(self):
+        return lib().sz_ctx_bytes_in_use(self.h)
+
+    def set_grid(self, per_cu: int):
+        self._check(lib().sz_ctx_set_grid(self.h, per_cu))
+
+    def set_timing(self, on: bool):
+        self._check(lib().sz_ctx_set_timing(self.h, 1 if on else 0))
+
+    def read_timing(self, reset: bool = False) -> dict:
+        ms = (C.c_double * len(STAGES))()
+        n = (C.c_uint64 * len(STAGES))()
+        self._check(lib().sz_ctx_read_timing(self.h, ms, n, 1 if reset else 0))
+        return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}
+
+    def _field(self, x):
+        t = self.torch
+        if not (isinstance(x, t.Tensor) and x.is_cuda and x.dtype == t.float32):
+            raise TypeError("expected a float32 CUDA tensor")
+        if not x.is_contiguous():
+            raise ValueError("field must be contiguous")
+        return x
+
+    def compress(self, x, **kw) -> Result:
+        x = self._field(x)
+        d = make_dims(x.shape)
+        p = make_params(x.dim(), **kw)
+        r = SzResult()
+        self._check(lib().sz_compress(self.h, C.c_void_p(x.data_ptr()), C.byref(d), C.byref(p),
+                                      _stream(self.torch, x.device), C.byref(r)))
+        return Result(self, r, x.shape)
+
+    def compress_batch(self, xs, params=None) -> list:
+        xs = [self._field(x) for x in xs]
+        n = len(xs)
+        params = params or [{}] * n
+        ins = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+        dims = (SzDims * n)(*[make_dims(x.shape) for x in xs])
+        ps = (SzParams * n)(*[make_params(x.dim(), **kw) for x, kw in zip(xs, params)])
+        outs = (SzResult * n)()
+        self._check(lib().sz_compress_batch(self.h, n, ins, dims, ps,
+                                            _stream(self.torch, xs[0].device), outs))
+        return [Result(self, outs[i], xs[i].shape) for i in range(n)]
+
+    def decompress(self, res: Result, out=None):
+        t = self.torch
+        if out is None:
+            out = t.empty(res.shape, dtype=t.float32, device="cuda:%d" % self.device)
+        self._check(lib().sz_decompress(self.h, C.byref(res.raw), C.c_void_p(out.data_ptr()),
+                                        _stream(t, out.device)))
+        return out
+
+    def decompress_batch(self, results, outs=None):
+        t = self.torch
+        n = len(results)
+        if outs is None:
+            outs = [t.empty(r.shape, dtype=t.float32, device="cuda:%d" % self.device)
+                    for r in results]
+        raw = (SzResult * n)(*[r.raw for r in results])
+        ptrs = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+        self._check(lib().sz_decompress_batch(self.h, n, raw, ptrs, _stream(t, outs[0].device)))
+        return outs
+
+    def upload(self, blob: bytes, shape=None) -> Result:
+        buf = (C.c_uint8 * len(blob)).from_buffer_copy(blob)
+        r = SzResult()
+        self._check(lib().sz_upload(self.h, buf, len(blob), _stream(self.torch, self.device),
+                                    C.byref(r)))
+        if shape is None:
+            import struct
+            ndim = struct.unpack_from("<I", blob, 8)[0]
+            n = struct.unpack_from("<3Q", blob, 16)
+            shape = tuple(reversed(n[:ndim]))
+        return Result(self, r, shape)

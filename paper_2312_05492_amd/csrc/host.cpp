@@ -1,0 +1,1164 @@
+// host.cpp -- the C ABI of libszi (include/szi.h): contexts, device memory
+// pools, parameter checks, orchestration of the gfx950 kernels, the host
+// Huffman codebook (Sec. VI-A builds it on the CPU), blob serialization.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "szi.h"
+#include "szi_internal.h"
+
+using namespace szi;
+
+// ------------------------------------------------------------ context
+struct sz_ctx {
+    int device = 0;
+    int num_cus = 256;
+    uint64_t budget = 0;       // 0 = unlimited
+    uint64_t held = 0;         // bytes obtained from hipMalloc and not freed
+    std::multimap<size_t, void*> free_blocks;
+    std::unordered_map<void*, size_t> block_size;
+    std::string err;
+    void* pinned = nullptr;    // host staging buffer
+    size_t pinned_bytes = 0;
+    int grid_per_cu = 8;       // persistent workgroups per CU (tunable)
+    // stage timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_free;
+    struct Mark {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+    double stage_ms[SZ_STAGE_COUNT] = {0};
+    uint64_t stage_n[SZ_STAGE_COUNT] = {0};
+};
+
+namespace {
+
+sz_status fail(sz_ctx* c, sz_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(ctx, SZ_ERR_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                 \
+    } while (0)
+
+size_t round_block(size_t b) { return (b + 511) & ~(size_t)511; }
+
+// Caching allocator: freed blocks are kept for reuse (every API call
+// synchronizes its stream before returning, so a freed block is idle).
+sz_status pool_alloc(sz_ctx* c, size_t bytes, void** out) {
+    if (bytes == 0) bytes = 1;
+    bytes = round_block(bytes);
+    auto it = c->free_blocks.lower_bound(bytes);
+    if (it != c->free_blocks.end() && it->first <= 2 * bytes + 65536) {
+        *out = it->second;
+        c->free_blocks.erase(it);
+        return SZ_OK;
+    }
+    if (c->budget && c->held + bytes > c->budget) {
+        // release cached blocks before giving up
+        for (auto& kv : c->free_blocks) {
+            (void)hipFree(kv.second);
+            c->held -= c->block_size[kv.second];
+            c->block_size.erase(kv.second);
+        }
+        c->free_blocks.clear();
+        if (c->held + bytes > c->budget)
+            return fail(c, SZ_ERR_OOM, "device budget of %llu bytes exceeded (%llu held, %llu asked)",
+                        (unsigned long long)c->budget, (unsigned long long)c->held,
+                        (unsigned long long)bytes);
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        for (auto& kv : c->free_blocks) {
+            (void)hipFree(kv.second);
+            c->held -= c->block_size[kv.second];
+            c->block_size.erase(kv.second);
+        }
+        c->free_blocks.clear();
+        e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, SZ_ERR_OOM, "hipMalloc(%zu) failed", bytes);
+        }
+    }
+    c->held += bytes;
+    c->block_size[p] = bytes;
+    *out = p;
+    return SZ_OK;
+}
+
+void pool_free(sz_ctx* c, void* p) {
+    if (!p) return;
+    auto it = c->block_size.find(p);
+    if (it == c->block_size.end()) return;
+    c->free_blocks.emplace(it->second, p);
+}
+
+sz_status pinned_reserve(sz_ctx* c, size_t bytes) {
+    if (c->pinned_bytes >= bytes) return SZ_OK;
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    c->pinned = nullptr;
+    c->pinned_bytes = 0;
+    size_t nb = std::max(bytes, (size_t)1 << 20);
+    HIP_TRY(c, hipHostMalloc(&c->pinned, nb, hipHostMallocDefault));
+    c->pinned_bytes = nb;
+    return SZ_OK;
+}
+
+// ---- stage timing: event pairs recorded around launches, resolved after
+// the call's final synchronization
+hipEvent_t ev_get(sz_ctx* c) {
+    if (!c->ev_free.empty()) {
+        hipEvent_t e = c->ev_free.back();
+        c->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+struct StageMark {
+    sz_ctx* c;
+    int stage;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    StageMark(sz_ctx* cc, int s, hipStream_t stream) : c(cc), stage(s), st(stream) {
+        if (c->timing && (a = ev_get(c))) (void)hipEventRecord(a, st);
+    }
+    ~StageMark() {
+        if (!a) return;
+        hipEvent_t b = ev_get(c);
+        if (!b) {
+            c->ev_free.push_back(a);
+            return;
+        }
+        (void)hipEventRecord(b, st);
+        c->marks.push_back({stage, a, b});
+    }
+};
+
+// after the stream has synchronized
+void resolve_marks(sz_ctx* c) {
+    for (auto& m : c->marks) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
+            c->stage_ms[m.stage] += ms;
+            c->stage_n[m.stage] += 1;
+        } else {
+            (void)hipGetLastError();
+        }
+        c->ev_free.push_back(m.a);
+        c->ev_free.push_back(m.b);
+    }
+    c->marks.clear();
+}
+
+#define STAGE(c, s, st) StageMark stage_mark_##s(c, s, st)
+
+// discards the marks of a call that ended early (declared first in a call,
+// so it runs after every StageMark of that call)
+struct MarkGuard {
+    sz_ctx* c;
+    ~MarkGuard() {
+        for (auto& m : c->marks) {
+            c->ev_free.push_back(m.a);
+            c->ev_free.push_back(m.b);
+        }
+        c->marks.clear();
+    }
+};
+
+// scratch allocations released together at the end of a call
+struct Scratch {
+    sz_ctx* c;
+    std::vector<void*> blocks;
+    explicit Scratch(sz_ctx* cc) : c(cc) {}
+    ~Scratch() {
+        for (void* p : blocks) pool_free(c, p);
+    }
+    template <class T>
+    sz_status get(size_t count, T** out) {
+        void* p;
+        sz_status s = pool_alloc(c, count * sizeof(T), &p);
+        if (s) return s;
+        blocks.push_back(p);
+        *out = static_cast<T*>(p);
+        return SZ_OK;
+    }
+};
+
+// ------------------------------------------------------------ CRC-32 (IEEE)
+uint32_t crc32_update(uint32_t crc, const uint8_t* p, size_t n) {
+    static uint32_t table[256];
+    static std::once_flag once;
+    std::call_once(once, [] {
+        for (uint32_t i = 0; i < 256; ++i) {
+            uint32_t c = i;
+            for (int k = 0; k < 8; ++k) c = (c & 1) ? 0xEDB88320u ^ (c >> 1) : c >> 1;
+            table[i] = c;
+        }
+    });
+    crc = ~crc;
+    for (size_t i = 0; i < n; ++i) crc = table[(crc ^ p[i]) & 0xFF] ^ (crc >> 8);
+    return ~crc;
+}
+
+// ------------------------------------------------------------ codebook
+// Length-limited Huffman lengths by package-merge, with the tie-breaking
+// fixed so that the lengths are unique: leaves ordered by (count, symbol);
+// each round pairs consecutive items of the previous round's list and
+// merges the pairs into the leaves, a leaf first on equal weight; the first
+// 2m-2 items of the last round decide the lengths.
+void huffman_lengths(const uint32_t* h, int nsym, int lmax, uint8_t* len) {
+    std::memset(len, 0, nsym);
+    std::vector<std::pair<uint64_t, int>> leaf;
+    for (int s = 0; s < nsym; ++s)
+        if (h[s]) leaf.emplace_back(h[s], s);
+    const size_t m = leaf.size();
+    if (m == 0) return;
+    if (m == 1) {
+        len[leaf[0].second] = 1;
+        return;
+    }
+    std::sort(leaf.begin(), leaf.end());
+    std::vector<std::vector<uint64_t>> wt(lmax);
+    std::vector<std::vector<int>> sym(lmax);   // -1 marks a package
+    for (auto& l : leaf) {
+        wt[0].push_back(l.first);
+        sym[0].push_back(l.second);
+    }
+    for (int lv = 1; lv < lmax; ++lv) {
+        const std::vector<uint64_t>& pw = wt[lv - 1];
+        const size_t npk = pw.size() / 2;
+        size_t i = 0, j = 0;
+        while (i < m || j < npk) {
+            const bool take_leaf =
+                j >= npk || (i < m && leaf[i].first <= pw[2 * j] + pw[2 * j + 1]);
+            if (take_leaf) {
+                wt[lv].push_back(leaf[i].first);
+                sym[lv].push_back(leaf[i].second);
+                ++i;
+            } else {
+                wt[lv].push_back(pw[2 * j] + pw[2 * j + 1]);
+                sym[lv].push_back(-1);
+                ++j;
+            }
+        }
+    }
+    size_t take = 2 * m - 2;
+    for (int lv = lmax - 1; lv >= 0; --lv) {
+        size_t pk = 0;
+        const size_t lim = std::min(take, sym[lv].size());
+        for (size_t k = 0; k < lim; ++k) {
+            if (sym[lv][k] >= 0)
+                len[sym[lv][k]]++;
+            else
+                ++pk;
+        }
+        take = 2 * pk;
+    }
+}
+
+// canonical codewords: by length, then symbol, consecutive values
+void canonical(const uint8_t* len, int nsym, uint32_t* code, uint32_t* first, uint32_t* count) {
+    uint32_t nlen[kLmax + 2] = {0};
+    for (int s = 0; s < nsym; ++s)
+        if (len[s]) nlen[len[s]]++;
+    uint32_t next[kLmax + 2] = {0};
+    uint32_t c = 0;
+    for (int l = 1; l <= kLmax; ++l) {
+        c = (c + nlen[l - 1]) << 1;
+        next[l] = c;
+        if (first) first[l] = c;
+        if (count) count[l] = nlen[l];
+    }
+    for (int s = 0; s < nsym; ++s) code[s] = len[s] ? next[len[s]]++ : 0;
+}
+
+// cbook entries (len << 24 | codeword) and the decode tables
+void build_tables(const uint8_t* len, int nsym, uint32_t* cbook, uint32_t* dtab) {
+    std::vector<uint32_t> code(nsym);
+    uint32_t first[kLmax + 2] = {0}, count[kLmax + 2] = {0};
+    canonical(len, nsym, code.data(), first, count);
+    for (int s = 0; s < nsym; ++s) cbook[s] = ((uint32_t)len[s] << 24) | code[s];
+    std::memset(dtab, 0, sizeof(uint32_t) * dtab_words(nsym));
+    for (int s = 0; s < nsym; ++s) {
+        const int l = len[s];
+        if (l == 0 || l > kLutBits) continue;
+        const uint32_t lo = code[s] << (kLutBits - l), hi = (code[s] + 1) << (kLutBits - l);
+        for (uint32_t e = lo; e < hi; ++e) dtab[e] = ((uint32_t)l << 16) | (uint32_t)s;
+    }
+    uint32_t off = 0;
+    for (int l = 0; l <= kLmax; ++l) {
+        dtab[kDtFirst + l] = first[l];
+        dtab[kDtCount + l] = l == 0 ? 0 : count[l];
+        dtab[kDtOffset + l] = off;
+        if (l > 0)
+            for (int s = 0; s < nsym; ++s)
+                if (len[s] == l) dtab[kDtSorted + off++] = (uint32_t)s;
+    }
+}
+
+bool kraft_ok(const uint8_t* len, int nsym) {
+    // sum 2^-len <= 1 with at least one code; all lengths <= kLmax
+    uint64_t sum = 0;
+    int present = 0;
+    for (int s = 0; s < nsym; ++s) {
+        if (!len[s]) continue;
+        if (len[s] > kLmax) return false;
+        sum += (uint64_t)1 << (kLmax - len[s]);
+        ++present;
+    }
+    return present > 0 && sum <= ((uint64_t)1 << kLmax);
+}
+
+// ------------------------------------------------------------ bookkeeping
+struct ResultInternal {
+    std::vector<void*> blocks;     // device blocks owned by the result
+    FieldPlan plan;                // host copy
+    sz_dims dims;
+    int S, w[3], R, chunk, eb_mode;
+    double eb;
+    std::vector<uint8_t> code_len; // host copy
+    uint32_t* d_cbook = nullptr;
+    uint32_t* d_dtab = nullptr;
+};
+
+ResultInternal* ri(const sz_result* r) { return static_cast<ResultInternal*>(r->internal); }
+
+template <class T>
+sz_status res_alloc(sz_ctx* c, ResultInternal* R, size_t count, T** out) {
+    void* p;
+    sz_status s = pool_alloc(c, count * sizeof(T), &p);
+    if (s) return s;
+    R->blocks.push_back(p);
+    *out = static_cast<T*>(p);
+    return SZ_OK;
+}
+
+void release_result(sz_ctx* c, sz_result* r) {
+    ResultInternal* R = ri(r);
+    if (R) {
+        for (void* p : R->blocks) pool_free(c, p);
+        delete R;
+    }
+    std::memset(r, 0, sizeof(*r));
+}
+
+struct Geometry {
+    int ndim, n[3], S, L, w[3], nwin[3], na[3], R, chunk;
+    uint64_t npts, nanch, nwin_total, nchunks;
+};
+
+sz_status check_field(sz_ctx* c, const sz_dims* d, const sz_params* p, Geometry& g) {
+    if (!d || !p) return fail(c, SZ_ERR_INVALID_ARG, "null dims or params");
+    if (d->ndim != 2 && d->ndim != 3)
+        return fail(c, SZ_ERR_UNSUPPORTED, "ndim %u (2 and 3 are supported)", d->ndim);
+    g.ndim = (int)d->ndim;
+    uint64_t npts = 1;
+    for (int k = 0; k < 3; ++k) {
+        if (k < g.ndim) {
+            if (d->n[k] == 0 || d->n[k] >= (1ull << 31))
+                return fail(c, SZ_ERR_INVALID_ARG, "n[%d] = %llu", k, (unsigned long long)d->n[k]);
+            g.n[k] = (int)d->n[k];
+            npts *= d->n[k];
+        } else {
+            g.n[k] = 1;
+        }
+    }
+    if (npts >= 0xFFFFFFFFull)
+        return fail(c, SZ_ERR_INVALID_ARG, "field of %llu points (limit 2^32 - 1)",
+                    (unsigned long long)npts);
+    g.npts = npts;
+    if (p->eb_mode != SZ_EB_ABS && p->eb_mode != SZ_EB_REL)
+        return fail(c, SZ_ERR_INVALID_ARG, "eb_mode %d", p->eb_mode);
+    if (!(p->eb >= 0.0) || p->eb > 1e300)
+        return fail(c, SZ_ERR_INVALID_ARG, "error bound %g", p->eb);
+    if (!(p->alpha <= 1e300)) return fail(c, SZ_ERR_INVALID_ARG, "alpha %g", p->alpha);
+    if (p->alpha > 0.0 && p->alpha < 1.0)
+        return fail(c, SZ_ERR_INVALID_ARG, "alpha %g < 1", p->alpha);
+    for (int k = 0; k < g.ndim; ++k)
+        if (p->interp[k] < 0 || p->interp[k] > 3)
+            return fail(c, SZ_ERR_INVALID_ARG, "interp[%d] = %d", k, p->interp[k]);
+    if (p->order[0] >= 0) {
+        int seen = 0;
+        for (int k = 0; k < g.ndim; ++k) {
+            if (p->order[k] < 0 || p->order[k] >= g.ndim || (seen >> p->order[k]) & 1)
+                return fail(c, SZ_ERR_INVALID_ARG, "order is not a permutation");
+            seen |= 1 << p->order[k];
+        }
+    }
+    g.R = p->radius ? (int)p->radius : 512;
+    if (g.R < 2 || g.R > kMaxRadius)
+        return fail(c, SZ_ERR_UNSUPPORTED, "radius %d (2..%d supported)", g.R, kMaxRadius);
+    g.chunk = p->huff_chunk ? (int)p->huff_chunk : 1024;
+    if (g.chunk != 256 && g.chunk != 512 && g.chunk != 1024 && g.chunk != 2048)
+        return fail(c, SZ_ERR_UNSUPPORTED, "Huffman chunk %d", g.chunk);
+    const int S = g.ndim == 3 ? 8 : 16;
+    if (p->anchor_stride && (int)p->anchor_stride != S)
+        return fail(c, SZ_ERR_UNSUPPORTED, "anchor stride %u (this build: %d)", p->anchor_stride, S);
+    const int wdef[3] = {g.ndim == 3 ? 32 : 64, g.ndim == 3 ? 8 : 16, g.ndim == 3 ? 8 : 1};
+    for (int k = 0; k < g.ndim; ++k)
+        if (p->window[k] && (int)p->window[k] != wdef[k])
+            return fail(c, SZ_ERR_UNSUPPORTED, "window[%d] = %u (this build: %d)", k,
+                        p->window[k], wdef[k]);
+    g.S = S;
+    g.L = g.ndim == 3 ? 3 : 4;
+    g.nwin_total = 1;
+    g.nanch = 1;
+    for (int k = 0; k < 3; ++k) {
+        g.w[k] = wdef[k];
+        g.nwin[k] = (g.n[k] + g.w[k] - 1) / g.w[k];
+        g.na[k] = k < g.ndim ? (g.n[k] + S - 1) / S : 1;
+        g.nwin_total *= g.nwin[k];
+        g.nanch *= g.na[k];
+    }
+    g.nchunks = (npts + g.chunk - 1) / g.chunk;
+    return SZ_OK;
+}
+
+void fill_desc(const Geometry& g, const sz_params* p, FieldDesc& f) {
+    std::memset(&f, 0, sizeof f);
+    f.ndim = g.ndim;
+    for (int k = 0; k < 3; ++k) {
+        f.n[k] = g.n[k];
+        f.w[k] = g.w[k];
+        f.nwin[k] = g.nwin[k];
+        f.na[k] = g.na[k];
+        f.interp[k] = k < g.ndim ? p->interp[k] : 0;
+        f.order_req[k] = (p->order[0] >= 0 && k < g.ndim) ? p->order[k] : -1;
+    }
+    f.S = g.S;
+    f.L = g.L;
+    f.R = g.R;
+    f.chunk = g.chunk;
+    f.eb_mode = p->eb_mode;
+    f.eb = p->eb;
+    f.alpha_req = p->alpha;
+    f.npts = g.npts;
+    f.nchunks = g.nchunks;
+    f.need_prof = p->order[0] < 0;
+    for (int k = 0; k < g.ndim; ++k)
+        if (p->interp[k] == SZ_INTERP_CUBIC_AUTO) f.need_prof = 1;
+}
+
+void put32(uint8_t* h, int off, uint32_t v) { std::memcpy(h + off, &v, 4); }
+void put64(uint8_t* h, int off, uint64_t v) { std::memcpy(h + off, &v, 8); }
+void putf(uint8_t* h, int off, float v) { std::memcpy(h + off, &v, 4); }
+void putd(uint8_t* h, int off, double v) { std::memcpy(h + off, &v, 8); }
+uint32_t get32(const uint8_t* h, int off) { uint32_t v; std::memcpy(&v, h + off, 4); return v; }
+uint64_t get64(const uint8_t* h, int off) { uint64_t v; std::memcpy(&v, h + off, 8); return v; }
+float getf(const uint8_t* h, int off) { float v; std::memcpy(&v, h + off, 4); return v; }
+double getd(const uint8_t* h, int off) { double v; std::memcpy(&v, h + off, 8); return v; }
+
+uint64_t pad8(uint64_t b) { return (b + 7) & ~(uint64_t)7; }
+
+uint64_t blob_bytes(const sz_result* r, int R) {
+    return 256 + pad8(r->n_anchors * 4) + pad8((uint64_t)2 * R) + pad8(r->n_chunks * 2) +
+           pad8(r->n_words * 4) + pad8(r->n_outliers * 4) + pad8(r->n_outliers * 4);
+}
+
+// header without CRCs (they are filled by sz_serialize)
+void make_header(const sz_result* r, const ResultInternal* R, uint8_t* h) {
+    std::memset(h, 0, 256);
+    std::memcpy(h, "SZI1", 4);
+    put32(h, 4, 1);
+    put32(h, 8, R->dims.ndim);
+    put32(h, 12, (uint32_t)R->S);
+    for (int k = 0; k < 3; ++k) {
+        put64(h, 16 + 8 * k, k < (int)R->dims.ndim ? R->dims.n[k] : 0);
+        put32(h, 40 + 4 * k, k < (int)R->dims.ndim ? (uint32_t)R->w[k] : 0);
+    }
+    put32(h, 52, (uint32_t)R->R);
+    put32(h, 56, kLmax);
+    put32(h, 60, (uint32_t)R->chunk);
+    put32(h, 64, (uint32_t)R->eb_mode);
+    put32(h, 68, (uint32_t)R->plan.levels);
+    putd(h, 72, R->eb);
+    putd(h, 80, R->plan.alpha);
+    putf(h, 88, R->plan.vmin);
+    putf(h, 92, R->plan.vmax);
+    putf(h, 96, R->plan.e);
+    for (int k = 0; k < 3; ++k) {
+        const bool used = k < (int)R->dims.ndim;
+        put32(h, 100 + 4 * k, used ? (uint32_t)R->plan.spline[k] : 0u);
+        put32(h, 112 + 4 * k, used ? (uint32_t)R->plan.order[k] : 0xFFFFFFFFu);
+    }
+    for (int l = 0; l < 16; ++l) putf(h, 128 + 4 * l, l < R->plan.levels ? R->plan.el[l] : 0.0f);
+    put64(h, 192, r->n_anchors);
+    put64(h, 200, r->n_chunks);
+    put64(h, 208, r->n_words);
+    put64(h, 216, r->n_outliers);
+}
+
+}  // namespace
+
+// ======================================================================
+extern "C" {
+
+void sz_params_default(sz_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->eb_mode = SZ_EB_REL;
+    p->eb = 1e-3;
+    for (int k = 0; k < 3; ++k) {
+        p->interp[k] = SZ_INTERP_CUBIC_AUTO;
+        p->order[k] = -1;
+    }
+    p->alpha = 0.0;
+    p->radius = 512;
+    p->huff_chunk = 1024;
+}
+
+sz_status sz_ctx_create(sz_ctx** out, int device, uint64_t hbm_budget_bytes) {
+    if (!out) return SZ_ERR_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return SZ_ERR_DEVICE;
+    }
+    if (device < 0 || device >= ndev) return SZ_ERR_INVALID_ARG;
+    sz_ctx* c = new sz_ctx();
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return SZ_ERR_DEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->num_cus = prop.multiProcessorCount;
+    *out = c;
+    return SZ_OK;
+}
+
+sz_status sz_ctx_destroy(sz_ctx* c) {
+    if (!c) return SZ_OK;
+    (void)hipSetDevice(c->device);
+    for (auto& kv : c->block_size) (void)hipFree(kv.first);
+    for (auto& m : c->marks) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete c;
+    return SZ_OK;
+}
+
+const char* sz_last_error(const sz_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+uint64_t sz_ctx_bytes_in_use(const sz_ctx* c) { return c ? c->held : 0; }
+
+sz_status sz_ctx_set_timing(sz_ctx* c, int enable) {
+    if (!c) return SZ_ERR_INVALID_ARG;
+    c->timing = enable != 0;
+    for (int k = 0; k < SZ_STAGE_COUNT; ++k) {
+        c->stage_ms[k] = 0.0;
+        c->stage_n[k] = 0;
+    }
+    return SZ_OK;
+}
+
+sz_status sz_ctx_read_timing(sz_ctx* c, double* ms, uint64_t* launches, int reset) {
+    if (!c) return SZ_ERR_INVALID_ARG;
+    for (int k = 0; k < SZ_STAGE_COUNT; ++k) {
+        if (ms) ms[k] = c->stage_ms[k];
+        if (launches) launches[k] = c->stage_n[k];
+        if (reset) {
+            c->stage_ms[k] = 0.0;
+            c->stage_n[k] = 0;
+        }
+    }
+    return SZ_OK;
+}
+
+// tuning hook: persistent workgroups per CU for the interpolation launches
+sz_status sz_ctx_set_grid(sz_ctx* c, int workgroups_per_cu) {
+    if (!c || workgroups_per_cu < 1 || workgroups_per_cu > 64) return SZ_ERR_INVALID_ARG;
+    c->grid_per_cu = workgroups_per_cu;
+    return SZ_OK;
+}
+
+sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, const sz_dims* dims,
+                            const sz_params* params, void* stream, sz_result* outs) {
+    if (!c) return SZ_ERR_INVALID_ARG;
+    if (nf == 0 || !d_in || !dims || !params || !outs)
+        return fail(c, SZ_ERR_INVALID_ARG, "empty batch or null argument");
+    HIP_TRY(c, hipSetDevice(c->device));
+    MarkGuard mark_guard{c};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<Geometry> geo(nf);
+    std::vector<FieldDesc> fd(nf);
+    for (uint32_t i = 0; i < nf; ++i) {
+        if (!d_in[i]) return fail(c, SZ_ERR_INVALID_ARG, "field %u: null input", i);
+        sz_status s = check_field(c, &dims[i], &params[i], geo[i]);
+        if (s) return s;
+        fill_desc(geo[i], &params[i], fd[i]);
+        fd[i].in = d_in[i];
+    }
+    // results (released on any error below)
+    std::vector<sz_result> res(nf);
+    std::memset(res.data(), 0, sizeof(sz_result) * nf);
+    struct Guard {
+        sz_ctx* c;
+        std::vector<sz_result>* r;
+        bool keep = false;
+        ~Guard() {
+            if (!keep)
+                for (auto& x : *r) release_result(c, &x);
+        }
+    } guard{c, &res};
+    uint64_t chunk_base = 0;
+    int max_R = 0, max_chunk = 0;
+    for (uint32_t i = 0; i < nf; ++i) {
+        ResultInternal* R = new ResultInternal();
+        res[i].internal = R;
+        R->dims = dims[i];
+        R->S = geo[i].S;
+        for (int k = 0; k < 3; ++k) R->w[k] = geo[i].w[k];
+        R->R = geo[i].R;
+        R->chunk = geo[i].chunk;
+        R->eb_mode = params[i].eb_mode;
+        R->eb = params[i].eb;
+        const int nsym = 2 * geo[i].R;
+        sz_status s;
+        if ((s = res_alloc(c, R, geo[i].nanch, &res[i].anchors))) return s;
+        if ((s = res_alloc(c, R, geo[i].npts, &res[i].codes))) return s;
+        if ((s = res_alloc(c, R, nsym, &res[i].hist))) return s;
+        if ((s = res_alloc(c, R, nsym, &res[i].code_len))) return s;
+        if ((s = res_alloc(c, R, nsym, &R->d_cbook))) return s;
+        if ((s = res_alloc(c, R, dtab_words(nsym), &R->d_dtab))) return s;
+        if ((s = res_alloc(c, R, geo[i].nchunks, &res[i].chunk_bits))) return s;
+        res[i].n = geo[i].npts;
+        res[i].n_anchors = geo[i].nanch;
+        res[i].n_chunks = geo[i].nchunks;
+        fd[i].codes = res[i].codes;
+        fd[i].anchors = res[i].anchors;
+        fd[i].hist = res[i].hist;
+        fd[i].chunk_bits = res[i].chunk_bits;
+        fd[i].cbook = R->d_cbook;
+        fd[i].chunk_base = chunk_base;
+        chunk_base += geo[i].nchunks;
+        max_R = std::max(max_R, geo[i].R);
+        max_chunk = std::max(max_chunk, geo[i].chunk);
+    }
+    const uint64_t total_chunks = chunk_base;
+
+    Scratch sc(c);
+    FieldDesc* d_fd;
+    FieldPlan* d_plan;
+    float *d_pmin, *d_pmax;
+    uint32_t* d_pbad;
+    uint64_t* d_items;
+    sz_status s;
+    if ((s = sc.get(nf, &d_fd)) || (s = sc.get(nf, &d_plan)) ||
+        (s = sc.get((size_t)nf * kRangeBlocks, &d_pmin)) ||
+        (s = sc.get((size_t)nf * kRangeBlocks, &d_pmax)) ||
+        (s = sc.get((size_t)nf * kRangeBlocks, &d_pbad)) || (s = sc.get(2 * (nf + 1), &d_items)))
+        return s;
+    // work lists: one per dimensionality, fields in input order
+    std::vector<uint32_t> grp[2];
+    for (uint32_t i = 0; i < nf; ++i) grp[geo[i].ndim == 3 ? 0 : 1].push_back(i);
+    // stage descriptors grouped: 3D fields first, then 2D, so that each
+    // group's item offsets index a contiguous slice of the descriptor array
+    std::vector<uint32_t> perm;
+    for (int gi = 0; gi < 2; ++gi) perm.insert(perm.end(), grp[gi].begin(), grp[gi].end());
+    std::vector<FieldDesc> fds(nf);
+    for (uint32_t k = 0; k < nf; ++k) fds[k] = fd[perm[k]];
+    std::vector<uint64_t> items(2 * (nf + 1), 0);
+    uint64_t nitems[2] = {0, 0};
+    {
+        uint32_t k = 0;
+        for (int gi = 0; gi < 2; ++gi) {
+            uint64_t* io = items.data() + gi * (nf + 1);
+            io[0] = 0;
+            for (size_t j = 0; j < grp[gi].size(); ++j, ++k)
+                io[j + 1] = io[j] + geo[grp[gi][j]].nwin_total;
+            nitems[gi] = grp[gi].empty() ? 0 : io[grp[gi].size()];
+        }
+    }
+    const size_t stage1 = sizeof(FieldDesc) * nf + sizeof(uint64_t) * items.size();
+    if ((s = pinned_reserve(c, std::max<size_t>(stage1, sizeof(FieldPlan) * nf +
+                                                           sizeof(uint32_t) * 2 * max_R * nf))))
+        return s;
+    HIP_TRY(c, hipMemcpyAsync(d_fd, fds.data(), sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipMemcpyAsync(d_items, items.data(), sizeof(uint64_t) * items.size(),
+                              hipMemcpyHostToDevice, st));
+    for (uint32_t k = 0; k < nf; ++k)
+        HIP_TRY(c, launch_fill_u32(fds[k].hist, 2 * (uint64_t)fds[k].R, 0, st));
+    {
+        STAGE(c, SZ_STAGE_RANGE, st);
+        HIP_TRY(c, launch_range(d_fd, (int)nf, d_pmin, d_pmax, d_pbad, st));
+    }
+    {
+        STAGE(c, SZ_STAGE_PROFILE, st);
+        HIP_TRY(c, launch_profile(d_fd, d_plan, (int)nf, st));
+    }
+    {
+        STAGE(c, SZ_STAGE_PLAN, st);
+        HIP_TRY(c, launch_plan(d_fd, d_plan, (int)nf, d_pmin, d_pmax, d_pbad, st));
+    }
+    const int grid = c->num_cus * c->grid_per_cu;
+    {
+        uint32_t base = 0;
+        for (int gi = 0; gi < 2; ++gi) {
+            if (!grp[gi].empty()) {
+                STAGE(c, SZ_STAGE_INTERP, st);
+                HIP_TRY(c, launch_compress(gi == 0 ? 3 : 2, d_fd + base, d_plan + base,
+                                           (int)grp[gi].size(), d_items + gi * (nf + 1),
+                                           nitems[gi], grid, max_R, st));
+            }
+            base += (uint32_t)grp[gi].size();
+        }
+    }
+    // sync 1: plans and histograms to the host
+    std::unique_ptr<StageMark> cb_mark(new StageMark(c, SZ_STAGE_CODEBOOK, st));
+    std::vector<FieldPlan> plans(nf);
+    std::vector<std::vector<uint32_t>> hist(nf);
+    HIP_TRY(c, hipMemcpyAsync(plans.data(), d_plan, sizeof(FieldPlan) * nf, hipMemcpyDeviceToHost, st));
+    for (uint32_t k = 0; k < nf; ++k) {
+        hist[k].resize(2 * fds[k].R);
+        HIP_TRY(c, hipMemcpyAsync(hist[k].data(), fds[k].hist, sizeof(uint32_t) * hist[k].size(),
+                                  hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(c, hipStreamSynchronize(st));
+    for (uint32_t k = 0; k < nf; ++k)
+        if (plans[k].status == -2)
+            return fail(c, SZ_ERR_NONFINITE, "field %u holds %u non-finite values", perm[k],
+                        plans[k].nonfinite);
+
+    // host codebooks (Sec. VI-A), exact buffer sizes from the histogram
+    std::vector<std::vector<uint32_t>> cbook(nf), dtab(nf);
+    for (uint32_t k = 0; k < nf; ++k) {
+        const uint32_t i = perm[k];
+        ResultInternal* R = ri(&res[i]);
+        R->plan = plans[k];
+        const int nsym = 2 * fds[k].R;
+        R->code_len.assign(nsym, 0);
+        huffman_lengths(hist[k].data(), nsym, kLmax, R->code_len.data());
+        cbook[k].resize(nsym);
+        dtab[k].resize(dtab_words(nsym));
+        build_tables(R->code_len.data(), nsym, cbook[k].data(), dtab[k].data());
+        uint64_t bits = 0;
+        for (int sy = 0; sy < nsym; ++sy) bits += (uint64_t)hist[k][sy] * R->code_len[sy];
+        const uint64_t nout = hist[k][0];
+        const uint64_t wcap = bits / 32 + geo[i].nchunks + 1;
+        if ((s = res_alloc(c, R, wcap, &res[i].words))) return s;
+        if ((s = res_alloc(c, R, std::max<uint64_t>(nout, 1), &res[i].outlier_idx))) return s;
+        if ((s = res_alloc(c, R, std::max<uint64_t>(nout, 1), &res[i].outlier_val))) return s;
+        res[i].n_outliers = nout;
+        fds[k].words = res[i].words;
+        fds[k].outlier_idx = res[i].outlier_idx;
+        fds[k].outlier_val = res[i].outlier_val;
+        fds[k].n_outliers = nout;
+        fds[k].words_cap = wcap;
+        fds[k].dtab = R->d_dtab;
+        HIP_TRY(c, hipMemcpyAsync(res[i].code_len, R->code_len.data(), nsym, hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(R->d_cbook, cbook[k].data(), sizeof(uint32_t) * nsym,
+                                  hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(R->d_dtab, dtab[k].data(), sizeof(uint32_t) * dtab[k].size(),
+                                  hipMemcpyHostToDevice, st));
+    }
+    // Huffman encode: per-field block ranges of 16 chunks
+    std::vector<uint64_t> boff(nf + 1, 0);
+    for (uint32_t k = 0; k < nf; ++k) boff[k + 1] = boff[k] + (fds[k].nchunks + 15) / 16;
+    // chunk_base must follow the descriptor order
+    {
+        uint64_t cb = 0;
+        for (uint32_t k = 0; k < nf; ++k) {
+            fds[k].chunk_base = cb;
+            cb += fds[k].nchunks;
+        }
+    }
+    uint64_t* d_boff;
+    uint32_t *d_cwords, *d_couts;
+    uint64_t *d_woff, *d_ooff, *d_tot;
+    if ((s = sc.get(nf + 1, &d_boff)) || (s = sc.get(total_chunks, &d_cwords)) ||
+        (s = sc.get(total_chunks, &d_couts)) || (s = sc.get(total_chunks + 1, &d_woff)) ||
+        (s = sc.get(total_chunks + 1, &d_ooff)) || (s = sc.get(2, &d_tot)))
+        return s;
+    HIP_TRY(c, hipMemcpyAsync(d_fd, fds.data(), sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipMemcpyAsync(d_boff, boff.data(), sizeof(uint64_t) * (nf + 1), hipMemcpyHostToDevice, st));
+    cb_mark.reset();
+    {
+        STAGE(c, SZ_STAGE_HUFF_STATS, st);
+        HIP_TRY(c, launch_huff_stats(d_fd, (int)nf, d_boff, boff[nf], d_cwords, d_couts, 2 * max_R, st));
+    }
+    {
+        STAGE(c, SZ_STAGE_SCAN, st);
+        HIP_TRY(c, launch_scan_pairs(d_cwords, d_couts, total_chunks, nullptr, 0, d_woff, d_ooff, d_tot, st));
+        // the scan writes exclusive offsets for [0, n); the totals close them
+        HIP_TRY(c, hipMemcpyAsync(d_woff + total_chunks, d_tot, sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(d_ooff + total_chunks, d_tot + 1, sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    }
+    {
+        STAGE(c, SZ_STAGE_ENCODE, st);
+        HIP_TRY(c, launch_huff_encode(d_fd, (int)nf, d_boff, boff[nf], d_woff, d_ooff, 2 * max_R,
+                                      max_chunk, st));
+    }
+    // sync 2: word offsets at the field boundaries
+    std::vector<uint64_t> wb(nf + 1);
+    for (uint32_t k = 0; k <= nf; ++k) {
+        const uint64_t at = k < nf ? fds[k].chunk_base : total_chunks;
+        HIP_TRY(c, hipMemcpyAsync(&wb[k], d_woff + at, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(c, hipStreamSynchronize(st));
+    resolve_marks(c);
+    for (uint32_t k = 0; k < nf; ++k) {
+        const uint32_t i = perm[k];
+        res[i].n_words = wb[k + 1] - wb[k];
+        res[i].compressed_bytes = blob_bytes(&res[i], fds[k].R);
+        make_header(&res[i], ri(&res[i]), res[i].header);
+    }
+    guard.keep = true;
+    for (uint32_t i = 0; i < nf; ++i) outs[i] = res[i];
+    return SZ_OK;
+}
+
+sz_status sz_compress(sz_ctx* c, const float* d_in, const sz_dims* dims, const sz_params* params,
+                      void* stream, sz_result* out) {
+    if (!c) return SZ_ERR_INVALID_ARG;
+    if (!out) return fail(c, SZ_ERR_INVALID_ARG, "null result");
+    const float* ins[1] = {d_in};
+    return sz_compress_batch(c, 1, ins, dims, params, stream, out);
+}
+
+sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, float* const* d_out,
+                              void* stream) {
+    if (!c) return SZ_ERR_INVALID_ARG;
+    if (nf == 0 || !res || !d_out) return fail(c, SZ_ERR_INVALID_ARG, "empty batch or null argument");
+    HIP_TRY(c, hipSetDevice(c->device));
+    MarkGuard mark_guard{c};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Scratch sc(c);
+    std::vector<FieldDesc> fds(nf);
+    std::vector<FieldPlan> plans(nf);
+    std::vector<uint32_t> grp[2];
+    std::vector<Geometry> geo(nf);
+    int max_R = 0;
+    for (uint32_t i = 0; i < nf; ++i) {
+        const ResultInternal* R = ri(&res[i]);
+        if (!R || !d_out[i] || !res[i].words || !res[i].chunk_bits || !res[i].anchors)
+            return fail(c, SZ_ERR_INVALID_ARG, "result %u is empty or output is null", i);
+        sz_params p;
+        sz_params_default(&p);
+        p.radius = (uint32_t)R->R;
+        p.huff_chunk = (uint32_t)R->chunk;
+        p.eb_mode = R->eb_mode;
+        p.eb = R->eb >= 0 ? R->eb : 0;
+        sz_status s = check_field(c, &R->dims, &p, geo[i]);
+        if (s) return s;
+        if (res[i].n != geo[i].npts || res[i].n_chunks != geo[i].nchunks ||
+            res[i].n_anchors != geo[i].nanch)
+            return fail(c, SZ_ERR_CORRUPT, "result %u: sizes do not match its dimensions", i);
+        grp[geo[i].ndim == 3 ? 0 : 1].push_back(i);
+        max_R = std::max(max_R, geo[i].R);
+    }
+    std::vector<uint32_t> perm;
+    for (int gi = 0; gi < 2; ++gi) perm.insert(perm.end(), grp[gi].begin(), grp[gi].end());
+    uint64_t cb = 0;
+    std::vector<uint64_t> dboff(nf + 1, 0), coff(nf + 1, 0);
+    for (uint32_t k = 0; k < nf; ++k) {
+        const uint32_t i = perm[k];
+        const ResultInternal* R = ri(&res[i]);
+        FieldDesc& f = fds[k];
+        sz_params p;
+        sz_params_default(&p);
+        fill_desc(geo[i], &p, f);
+        f.out = d_out[i];
+        f.anchors = res[i].anchors;
+        f.words = res[i].words;
+        f.chunk_bits = res[i].chunk_bits;
+        f.outlier_idx = res[i].outlier_idx;
+        f.outlier_val = res[i].outlier_val;
+        f.n_outliers = res[i].n_outliers;
+        f.dtab = R->d_dtab;
+        f.chunk_base = cb;
+        uint16_t* codes;
+        sz_status s = sc.get(geo[i].npts, &codes);
+        if (s) return s;
+        f.codes = codes;
+        cb += geo[i].nchunks;
+        coff[k + 1] = cb;
+        dboff[k + 1] = dboff[k] + (geo[i].nchunks + 255) / 256;
+        plans[k] = R->plan;
+    }
+    const uint64_t total_chunks = cb;
+    std::vector<uint64_t> items(2 * (nf + 1), 0);
+    uint64_t nitems[2] = {0, 0};
+    for (int gi = 0; gi < 2; ++gi) {
+        uint64_t* io = items.data() + gi * (nf + 1);
+        for (size_t j = 0; j < grp[gi].size(); ++j) io[j + 1] = io[j] + geo[grp[gi][j]].nwin_total;
+        nitems[gi] = grp[gi].empty() ? 0 : io[grp[gi].size()];
+    }
+    FieldDesc* d_fd;
+    FieldPlan* d_plan;
+    uint64_t *d_items, *d_dboff, *d_coff, *d_woff;
+    uint32_t* d_tmp;
+    sz_status s;
+    if ((s = sc.get(nf, &d_fd)) || (s = sc.get(nf, &d_plan)) || (s = sc.get(items.size(), &d_items)) ||
+        (s = sc.get(nf + 1, &d_dboff)) || (s = sc.get(nf + 1, &d_coff)) ||
+        (s = sc.get(total_chunks + 2, &d_woff)) || (s = sc.get(std::max<uint64_t>(total_chunks, 1), &d_tmp)))
+        return s;
+    HIP_TRY(c, hipMemcpyAsync(d_fd, fds.data(), sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipMemcpyAsync(d_plan, plans.data(), sizeof(FieldPlan) * nf, hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipMemcpyAsync(d_items, items.data(), sizeof(uint64_t) * items.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipMemcpyAsync(d_dboff, dboff.data(), sizeof(uint64_t) * (nf + 1), hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipMemcpyAsync(d_coff, coff.data(), sizeof(uint64_t) * (nf + 1), hipMemcpyHostToDevice, st));
+    {
+        STAGE(c, SZ_STAGE_SCAN, st);
+        HIP_TRY(c, launch_scan_words(d_fd, (int)nf, d_coff, total_chunks, d_tmp, d_woff, st));
+    }
+    {
+        STAGE(c, SZ_STAGE_DECODE, st);
+        HIP_TRY(c, launch_huff_decode(d_fd, (int)nf, d_dboff, dboff[nf], d_woff, 2 * max_R, st));
+    }
+    {
+        STAGE(c, SZ_STAGE_SCATTER, st);
+        HIP_TRY(c, launch_scatter_outliers(d_fd, (int)nf, st));
+    }
+    const int grid = c->num_cus * c->grid_per_cu;
+    uint32_t base = 0;
+    for (int gi = 0; gi < 2; ++gi) {
+        if (!grp[gi].empty()) {
+            STAGE(c, SZ_STAGE_REPLAY, st);
+            HIP_TRY(c, launch_decompress(gi == 0 ? 3 : 2, d_fd + base, d_plan + base,
+                                         (int)grp[gi].size(), d_items + gi * (nf + 1), nitems[gi],
+                                         grid, st));
+        }
+        base += (uint32_t)grp[gi].size();
+    }
+    HIP_TRY(c, hipStreamSynchronize(st));
+    resolve_marks(c);
+    return SZ_OK;
+}
+
+sz_status sz_decompress(sz_ctx* c, const sz_result* res, float* d_out, void* stream) {
+    if (!c) return SZ_ERR_INVALID_ARG;
+    float* outs[1] = {d_out};
+    return sz_decompress_batch(c, 1, res, outs, stream);
+}
+
+sz_status sz_result_free(sz_ctx* c, sz_result* r) {
+    if (!c || !r) return SZ_ERR_INVALID_ARG;
+    release_result(c, r);
+    return SZ_OK;
+}
+
+sz_status sz_result_read(sz_ctx* c, const sz_result* r, int32_t section, void* dst, uint64_t cap,
+                         uint64_t* written) {
+    if (!c || !r || !r->internal) return fail(c, SZ_ERR_INVALID_ARG, "empty result");
+    const ResultInternal* R = ri(r);
+    const void* src = nullptr;
+    uint64_t bytes = 0;
+    switch (section) {
+    case SZ_SEC_ANCHORS: src = r->anchors; bytes = r->n_anchors * 4; break;
+    case SZ_SEC_CODES: src = r->codes; bytes = r->codes ? r->n * 2 : 0; break;
+    case SZ_SEC_OUTLIER_IDX: src = r->outlier_idx; bytes = r->n_outliers * 4; break;
+    case SZ_SEC_OUTLIER_VAL: src = r->outlier_val; bytes = r->n_outliers * 4; break;
+    case SZ_SEC_WORDS: src = r->words; bytes = r->n_words * 4; break;
+    case SZ_SEC_CHUNK_BITS: src = r->chunk_bits; bytes = r->n_chunks * 2; break;
+    case SZ_SEC_HIST: src = r->hist; bytes = r->hist ? (uint64_t)2 * R->R * 4 : 0; break;
+    case SZ_SEC_CODE_LEN: src = r->code_len; bytes = (uint64_t)2 * R->R; break;
+    default: return fail(c, SZ_ERR_INVALID_ARG, "section %d", section);
+    }
+    if (written) *written = bytes;
+    if (bytes > cap) return fail(c, SZ_ERR_CAPACITY, "section needs %llu bytes", (unsigned long long)bytes);
+    if (bytes == 0) return SZ_OK;
+    if (!dst) return fail(c, SZ_ERR_INVALID_ARG, "null destination");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+    return SZ_OK;
+}
+
+sz_status sz_serialize(sz_ctx* c, const sz_result* r, void* dst, uint64_t cap, uint64_t* written) {
+    if (!c || !r || !r->internal) return fail(c, SZ_ERR_INVALID_ARG, "empty result");
+    const ResultInternal* R = ri(r);
+    const uint64_t total = blob_bytes(r, R->R);
+    if (written) *written = total;
+    if (cap < total) return fail(c, SZ_ERR_CAPACITY, "blob needs %llu bytes", (unsigned long long)total);
+    if (!dst) return fail(c, SZ_ERR_INVALID_ARG, "null destination");
+    HIP_TRY(c, hipSetDevice(c->device));
+    uint8_t* out = static_cast<uint8_t*>(dst);
+    std::memset(out, 0, total);
+    uint8_t* h = out;
+    make_header(r, R, h);
+    struct Sec {
+        const void* src;
+        uint64_t bytes;
+    } secs[6] = {{r->anchors, r->n_anchors * 4},   {r->code_len, (uint64_t)2 * R->R},
+                 {r->chunk_bits, r->n_chunks * 2}, {r->words, r->n_words * 4},
+                 {r->outlier_idx, r->n_outliers * 4}, {r->outlier_val, r->n_outliers * 4}};
+    uint64_t pos = 256;
+    for (int k = 0; k < 6; ++k) {
+        if (secs[k].bytes) HIP_TRY(c, hipMemcpy(out + pos, secs[k].src, secs[k].bytes, hipMemcpyDeviceToHost));
+        put32(h, 224 + 4 * k, crc32_update(0, out + pos, secs[k].bytes));
+        pos += pad8(secs[k].bytes);
+    }
+    put32(h, 252, crc32_update(0, h, 252));
+    return SZ_OK;
+}
+
+sz_status sz_upload(sz_ctx* c, const void* blob, uint64_t bytes, void* stream, sz_result* out) {
+    if (!c) return SZ_ERR_INVALID_ARG;
+    if (!blob || !out) return fail(c, SZ_ERR_INVALID_ARG, "null argument");
+    const uint8_t* b = static_cast<const uint8_t*>(blob);
+    if (bytes < 256) return fail(c, SZ_ERR_CORRUPT, "blob shorter than its header");
+    if (std::memcmp(b, "SZI1", 4)) return fail(c, SZ_ERR_CORRUPT, "bad magic");
+    if (crc32_update(0, b, 252) != get32(b, 252)) return fail(c, SZ_ERR_CORRUPT, "header CRC mismatch");
+    if (get32(b, 4) != 1) return fail(c, SZ_ERR_UNSUPPORTED, "blob version %u", get32(b, 4));
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    sz_dims d;
+    std::memset(&d, 0, sizeof d);
+    d.ndim = get32(b, 8);
+    for (int k = 0; k < 3; ++k) d.n[k] = get64(b, 16 + 8 * k);
+    sz_params p;
+    sz_params_default(&p);
+    p.radius = get32(b, 52);
+    p.huff_chunk = get32(b, 60);
+    p.eb_mode = (int32_t)get32(b, 64);
+    p.eb = getd(b, 72);
+    p.anchor_stride = get32(b, 12);
+    for (int k = 0; k < 3 && k < (int)d.ndim; ++k) p.window[k] = get32(b, 40 + 4 * k);
+    Geometry g;
+    sz_status s = check_field(c, &d, &p, g);
+    if (s) return s == SZ_ERR_INVALID_ARG ? fail(c, SZ_ERR_CORRUPT, "header: %s", c->err.c_str()) : s;
+    if (get32(b, 56) != (uint32_t)kLmax || (int)get32(b, 68) != g.L)
+        return fail(c, SZ_ERR_CORRUPT, "header: length limit or level count");
+    sz_result r;
+    std::memset(&r, 0, sizeof r);
+    r.n = g.npts;
+    r.n_anchors = get64(b, 192);
+    r.n_chunks = get64(b, 200);
+    r.n_words = get64(b, 208);
+    r.n_outliers = get64(b, 216);
+    if (r.n_anchors != g.nanch || r.n_chunks != g.nchunks || r.n_outliers > g.npts ||
+        r.n_words > (g.npts * kLmax) / 32 + g.nchunks + 1)
+        return fail(c, SZ_ERR_CORRUPT, "header: section sizes");
+    const int nsym = 2 * g.R;
+    if (blob_bytes(&r, g.R) != bytes) return fail(c, SZ_ERR_CORRUPT, "blob length %llu", (unsigned long long)bytes);
+    const uint64_t secb[6] = {r.n_anchors * 4, (uint64_t)nsym, r.n_chunks * 2,
+                              r.n_words * 4, r.n_outliers * 4, r.n_outliers * 4};
+    uint64_t off[6], pos = 256;
+    for (int k = 0; k < 6; ++k) {
+        off[k] = pos;
+        if (crc32_update(0, b + pos, secb[k]) != get32(b, 224 + 4 * k))
+            return fail(c, SZ_ERR_CORRUPT, "section %d CRC mismatch", k);
+        pos += pad8(secb[k]);
+    }
+    {
+        // the chunk bit counts must account for exactly the stored words, and
+        // outlier indices must lie inside the field
+        uint64_t words = 0;
+        for (uint64_t j = 0; j < r.n_chunks; ++j) {
+            uint16_t cbits;
+            std::memcpy(&cbits, b + off[2] + 2 * j, 2);
+            words += (cbits + 31u) / 32u;
+        }
+        if (words != r.n_words) return fail(c, SZ_ERR_CORRUPT, "chunk sizes do not match the words");
+        for (uint64_t j = 0; j < r.n_outliers; ++j)
+            if (get32(b + off[4] + 4 * j, 0) >= g.npts)
+                return fail(c, SZ_ERR_CORRUPT, "outlier index outside the field");
+    }
+    ResultInternal* R = new ResultInternal();
+    r.internal = R;
+    R->dims = d;
+    R->S = g.S;
+    for (int k = 0; k < 3; ++k) R->w[k] = g.w[k];
+    R->R = g.R;
+    R->chunk = g.chunk;
+    R->eb_mode = p.eb_mode;
+    R->eb = p.eb;
+    R->code_len.assign(b + off[1], b + off[1] + nsym);
+    if (!kraft_ok(R->code_len.data(), nsym) && r.n > 0) {
+        release_result(c, &r);
+        return fail(c, SZ_ERR_CORRUPT, "code lengths do not form a prefix code");
+    }
+    std::memset(&R->plan, 0, sizeof R->plan);
+    R->plan.alpha = getd(b, 80);
+    R->plan.vmin = getf(b, 88);
+    R->plan.vmax = getf(b, 92);
+    R->plan.e = getf(b, 96);
+    R->plan.levels = g.L;
+    for (int l = 0; l < g.L; ++l) {
+        R->plan.el[l] = getf(b, 128 + 4 * l);
+        R->plan.ebx2[l] = 2.0f * R->plan.el[l];
+    }
+    int seen = 0;
+    for (int k = 0; k < 3; ++k) {
+        R->plan.spline[k] = (int32_t)get32(b, 100 + 4 * k);
+        R->plan.order[k] = (int32_t)get32(b, 112 + 4 * k);
+        if (k < g.ndim) {
+            if (R->plan.spline[k] < 0 || R->plan.spline[k] > 2 || R->plan.order[k] < 0 ||
+                R->plan.order[k] >= g.ndim || ((seen >> R->plan.order[k]) & 1)) {
+                release_result(c, &r);
+                return fail(c, SZ_ERR_CORRUPT, "header: spline or order");
+            }
+            seen |= 1 << R->plan.order[k];
+        }
+    }
+    std::vector<uint32_t> cbook(nsym), dtab(dtab_words(nsym));
+    build_tables(R->code_len.data(), nsym, cbook.data(), dtab.data());
+    if ((s = res_alloc(c, R, r.n_anchors, &r.anchors)) || (s = res_alloc(c, R, nsym, &r.code_len)) ||
+        (s = res_alloc(c, R, std::max<uint64_t>(r.n_chunks, 1), &r.chunk_bits)) ||
+        (s = res_alloc(c, R, std::max<uint64_t>(r.n_words, 1), &r.words)) ||
+        (s = res_alloc(c, R, std::max<uint64_t>(r.n_outliers, 1), &r.outlier_idx)) ||
+        (s = res_alloc(c, R, std::max<uint64_t>(r.n_outliers, 1), &r.outlier_val)) ||
+        (s = res_alloc(c, R, nsym, &R->d_cbook)) || (s = res_alloc(c, R, dtab.size(), &R->d_dtab))) {
+        release_result(c, &r);
+        return s;
+    }
+    void* dsts[6] = {r.anchors, r.code_len, r.chunk_bits, r.words, r.outlier_idx, r.outlier_val};
+    for (int k = 0; k < 6; ++k)
+        if (secb[k]) {
+            hipError_t e = hipMemcpyAsync(dsts[k], b + off[k], secb[k], hipMemcpyHostToDevice, st);
+            if (e != hipSuccess) {
+                release_result(c, &r);
+                return fail(c, SZ_ERR_DEVICE, "upload copy: %s", hipGetErrorString(e));
+            }
+        }
+    hipError_t e1 = hipMemcpyAsync(R->d_cbook, cbook.data(), 4 * nsym, hipMemcpyHostToDevice, st);
+    hipError_t e2 = hipMemcpyAsync(R->d_dtab, dtab.data(), 4 * dtab.size(), hipMemcpyHostToDevice, st);
+    hipError_t e3 = hipStreamSynchronize(st);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        release_result(c, &r);
+        return fail(c, SZ_ERR_DEVICE, "upload copy failed");
+    }
+    std::memcpy(r.header, b, 256);
+    r.compressed_bytes = bytes;
+    *out = r;
+    return SZ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// szi_internal.h -- structures shared by libszi's host code and its gfx950
+// kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace szi {
+
+constexpr int kMaxLevels = 8;
+constexpr int kLmax = 24;          // Huffman length limit
+constexpr int kLutBits = 10;       // decode look-up table width
+constexpr int kMaxRadius = 1024;   // LDS histogram holds 2R <= 2048 bins
+constexpr int kRangeBlocks = 1024; // partial min/max blocks per field
+constexpr int kThreads = 256;      // threads per interpolation workgroup
+
+// Static description of one field, written by the host before launch.
+struct FieldDesc {
+    int32_t ndim;
+    int32_t n[3];          // n[0] fastest; unused dims 1
+    int32_t w[3];          // window; unused dims 1
+    int32_t nwin[3];       // windows per dimension
+    int32_t na[3];         // anchors per dimension
+    int32_t S, L, R;
+    int32_t eb_mode;
+    int32_t need_prof;
+    int32_t interp[3];     // requested splines (AUTO allowed)
+    int32_t order_req[3];  // requested order; order_req[0] < 0 = auto
+    int32_t chunk;         // Huffman chunk
+    double eb;
+    double alpha_req;
+    uint64_t npts;
+    uint64_t chunk_base;   // first chunk of this field in a batch
+    uint64_t nchunks;
+    uint64_t n_outliers;
+    uint64_t words_cap;    // capacity of words (encode)
+    const float* in;       // compress input
+    float* out;            // decompress output
+    uint16_t* codes;
+    float* anchors;
+    uint32_t* hist;        // 2R bins
+    // Huffman encode/decode
+    const uint32_t* cbook; // per symbol: len << 24 | codeword
+    uint32_t* words;
+    uint16_t* chunk_bits;
+    uint32_t* outlier_idx;
+    float* outlier_val;
+    const uint32_t* dtab;  // decode tables (see DecodeTables layout)
+};
+
+// Per-field plan computed on the device from the range and the profile.
+struct FieldPlan {
+    float vmin, vmax;
+    uint32_t nonfinite;
+    int32_t status;        // 0 ok, -2 non-finite input
+    double range, eps, e_abs;
+    float e;
+    int32_t levels;
+    double alpha;
+    float el[kMaxLevels];
+    float ebx2[kMaxLevels];
+    float inv[kMaxLevels];
+    int32_t spline[3];
+    int32_t order[3];
+    double prof[3][3];     // [dim][linear, NAK, natural] L1 errors
+};
+
+// Decode tables, one u32 array per field:
+//   [0, 1<<kLutBits)           LUT: len << 16 | symbol (len 0 = longer code)
+//   first[kLmax+1], count[kLmax+1], offset[kLmax+1]
+//   sorted symbols (nsym entries, by (length, symbol))
+constexpr int kDtFirst = 1 << kLutBits;
+constexpr int kDtCount = kDtFirst + kLmax + 1;
+constexpr int kDtOffset = kDtCount + kLmax + 1;
+constexpr int kDtSorted = kDtOffset + kLmax + 1;
+__host__ __device__ inline int dtab_words(int nsym) { return kDtSorted + nsym; }
+
+// ---- launchers (kernels.hip) ----
+hipError_t launch_range(const FieldDesc* d_fields, int nfields, float* d_part_min,
+                        float* d_part_max, uint32_t* d_part_bad, hipStream_t st);
+hipError_t launch_profile(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
+                          hipStream_t st);
+hipError_t launch_plan(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
+                       const float* d_part_min, const float* d_part_max,
+                       const uint32_t* d_part_bad, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_compress(int ndim, const FieldDesc* d_fields, const FieldPlan* d_plans,
+                           int nfields, const uint64_t* d_item_off, uint64_t nitems,
+                           int grid, int max_R, hipStream_t st);
+hipError_t launch_decompress(int ndim, const FieldDesc* d_fields, const FieldPlan* d_plans,
+                             int nfields, const uint64_t* d_item_off, uint64_t nitems,
+                             int grid, hipStream_t st);
+hipError_t launch_huff_stats(const FieldDesc* d_fields, int nfields,
+                             const uint64_t* d_chunk_off, uint64_t nchunks_total,
+                             uint32_t* d_cwords, uint32_t* d_couts, int max_nsym,
+                             hipStream_t st);
+hipError_t launch_scan_pairs(const uint32_t* d_a, const uint32_t* d_b, uint64_t n,
+                             const uint64_t* d_seg_start, int nseg, uint64_t* d_aoff,
+                             uint64_t* d_boff, uint64_t* d_totals, hipStream_t st);
+hipError_t launch_huff_encode(const FieldDesc* d_fields, int nfields,
+                              const uint64_t* d_chunk_off, uint64_t nchunks_total,
+                              const uint64_t* d_word_off, const uint64_t* d_out_off,
+                              int max_nsym, int max_chunk, hipStream_t st);
+hipError_t launch_scan_words(const FieldDesc* d_fields, int nfields,
+                             const uint64_t* d_chunk_off, uint64_t nchunks_total,
+                             uint32_t* d_tmp, uint64_t* d_word_off, hipStream_t st);
+hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields,
+                              const uint64_t* d_chunk_off, uint64_t nchunks_total,
+                              const uint64_t* d_word_off, int max_nsym, hipStream_t st);
+hipError_t launch_scatter_outliers(const FieldDesc* d_fields, int nfields, hipStream_t st);
+
+}  // namespace szi

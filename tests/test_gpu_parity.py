@@ -1,0 +1,227 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bit-exact for everything: anchors, quant-codes, outlier lists, histogram,
+code lengths, chunk bit counts, Huffman words, the serialized blob, and the
+decompressed field.  Runs on an MI355X only (marker ``gpu``)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2312_05492_amd as szi
+from paper_2312_05492_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    O.build(force=False)
+    c = szi.Context(0)
+    yield c
+    c.close()
+
+
+def _to_gpu(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _oracle_params(shape, kw):
+    m = dict(kw)
+    if "radius" in m:
+        m["R"] = m.pop("radius")
+    return O.Params(shape=shape, **m)
+
+
+def _bits(a):
+    return np.ascontiguousarray(a).view(np.uint32)
+
+
+def check_case(ctx, name, x, kw):
+    print("\n[parity] %s shape=%s params=%s" % (name, x.shape, kw), flush=True)
+    ref = O.compress(x, _oracle_params(x.shape, kw))
+    res = ctx.compress(_to_gpu(x), **kw)
+    try:
+        # section by section first, for a readable failure
+        assert np.array_equal(res.read(szi.SEC_ANCHORS), ref.anchors), "anchors"
+        codes = res.read(szi.SEC_CODES)
+        want = ref.codes.ravel()
+        if not np.array_equal(codes, want):
+            bad = np.flatnonzero(codes != want)
+            raise AssertionError("codes differ at %d points, first %s: gpu %s oracle %s" % (
+                bad.size, np.unravel_index(bad[:5], x.shape), codes[bad[:5]], want[bad[:5]]))
+        assert np.array_equal(res.read(szi.SEC_HIST), ref.hist), "histogram"
+        assert np.array_equal(res.read(szi.SEC_CODE_LEN), ref.code_len), "code lengths"
+        assert np.array_equal(res.read(szi.SEC_OUTLIER_IDX), ref.outlier_idx), "outlier idx"
+        assert np.array_equal(_bits(res.read(szi.SEC_OUTLIER_VAL)), _bits(ref.outlier_val)), \
+            "outlier values"
+        assert np.array_equal(res.read(szi.SEC_CHUNK_BITS), ref.chunk_bits), "chunk bits"
+        assert np.array_equal(res.read(szi.SEC_WORDS), ref.words), "huffman words"
+        blob = res.blob()
+        oblob = ref.blob()
+        if blob != oblob:
+            diff = [i for i in range(min(len(blob), len(oblob))) if blob[i] != oblob[i]][:8]
+            raise AssertionError("blobs differ (len %d vs %d) at bytes %s" % (
+                len(blob), len(oblob), diff))
+        # decompression replays the oracle's reconstruction bit for bit
+        y = ctx.decompress(res).cpu().numpy()
+        assert np.array_equal(_bits(y), _bits(ref.recon)), "decompressed field"
+        err = np.abs(y.astype(np.float64) - x.astype(np.float64)).max() if x.size else 0.0
+        assert err <= float(ref.config.el[0])
+        # the oracle's blob decompresses on the GPU; the GPU blob in the oracle
+        up = ctx.upload(oblob)
+        y2 = ctx.decompress(up).cpu().numpy()
+        up.free()
+        assert np.array_equal(_bits(y2), _bits(ref.recon)), "decompress of the oracle blob"
+        y3 = O.decompress_blob(blob)
+        assert np.array_equal(_bits(y3), _bits(ref.recon)), "oracle decode of the gpu blob"
+    finally:
+        res.free()
+    return ref
+
+
+def _spec(shape, seed, beta=5.0 / 3.0, mean=0.0):
+    return lambda: synth.spectral_field(shape, beta=beta, seed=seed, mean=mean)
+
+
+def _const(shape, v):
+    return lambda: np.full(shape, v, dtype=np.float32)
+
+
+CASES = [
+    ("small64_bumps", synth.workload_small, {}),
+    ("odd_17_33_65", _spec((17, 33, 65), 3), {}),
+    ("ragged_100_37_53_e4", _spec((100, 37, 53), 4, mean=10.0), dict(eb=1e-4)),
+    ("linear_all", _spec((40, 48, 70), 5), dict(interp=(0, 0, 0))),
+    ("mixed_zlin", _spec((40, 48, 70), 5), dict(interp=(0, 3, 3))),
+    ("nak_order_xyz", _spec((24, 40, 66), 6), dict(interp=(1, 1, 1), order=(2, 1, 0))),
+    ("natural", _spec((24, 40, 66), 6, beta=3.0), dict(interp=(2, 2, 2))),
+    ("abs_bound", _spec((31, 29, 47), 7), dict(eb=0.01, eb_mode=0)),
+    ("alpha_one", _spec((31, 29, 47), 7), dict(eb=1e-2, alpha=1.0)),
+    ("eb_1e2", _spec((31, 29, 47), 8, beta=3.0), dict(eb=1e-2)),
+    ("tiny_bound_all_outliers", _spec((19, 21, 37), 9), dict(eb=1e-30, eb_mode=0)),
+    ("zero_bound", _spec((19, 21, 37), 9), dict(eb=0.0, eb_mode=0)),
+    ("constant_zero_range", _const((20, 30, 40), 2.5), {}),
+    ("constant_abs0", _const((20, 30, 40), 3.0), dict(eb=0.0, eb_mode=0)),
+    ("denormal_values", lambda: (synth.spectral_field((18, 20, 40), seed=10) * np.float32(1e-40)),
+     dict(eb=1e-44, eb_mode=0)),
+    ("radius_64", _spec((30, 30, 60), 11, beta=1.0), dict(eb=1e-4, radius=64)),
+    ("chunk_256", _spec((30, 30, 60), 12), dict(chunk=256)),
+    ("chunk_2048", _spec((30, 30, 60), 12), dict(chunk=2048)),
+    ("thin_1x9x100", _spec((1, 9, 100), 13), {}),
+    ("line_1x1x3000", _spec((1, 1, 3000), 14), {}),
+    ("column_70x1x1", _spec((70, 1, 1), 15), {}),
+    ("single_point_3d", _const((1, 1, 1), 1.5), {}),
+    ("multi_window_33_17_129", _spec((33, 17, 129), 16), {}),
+    ("front_3d", lambda: synth.front_field((30, 40, 50), seed=17), dict(eb=1e-2)),
+    ("climate_2d", lambda: synth.climate_field(301, shape=(90, 180)), {}),
+    ("spectral_2d_e4", _spec((77, 131), 18, beta=3.0), dict(eb=1e-4)),
+    ("line_2d_1x5000", _spec((1, 5000), 19), {}),
+    ("column_2d_300x1", _spec((300, 1), 20), {}),
+    ("single_point_2d", _const((1, 1), -4.0), {}),
+    ("linear_2d", _spec((65, 129), 21), dict(interp=(0, 0))),
+]
+
+
+@pytest.mark.parametrize("name,gen,kw", CASES, ids=[c[0] for c in CASES])
+def test_parity(ctx, name, gen, kw):
+    check_case(ctx, name, gen(), kw)
+
+
+def test_batch_equals_single_calls(ctx):
+    fields = [synth.spectral_field((20, 30, 70), seed=31), synth.climate_field(302, shape=(60, 130)),
+              synth.spectral_field((9, 17, 33), seed=32, beta=3.0),
+              synth.spectral_field((50, 70), seed=33)]
+    params = [dict(eb=1e-3), dict(eb=1e-4), dict(eb=1e-2, interp=(0, 3, 3)), dict(eb=0.05, eb_mode=0)]
+    print("\n[parity] batch of %d fields" % len(fields), flush=True)
+    outs = ctx.compress_batch([_to_gpu(f) for f in fields], params)
+    for f, kw, r in zip(fields, params, outs):
+        ref = O.compress(f, _oracle_params(f.shape, kw))
+        assert r.blob() == ref.blob()
+    ys = ctx.decompress_batch(outs)
+    for f, kw, y in zip(fields, params, ys):
+        ref = O.compress(f, _oracle_params(f.shape, kw))
+        assert np.array_equal(_bits(y.cpu().numpy()), _bits(ref.recon))
+    for r in outs:
+        r.free()
+
+
+def test_launch_shape_is_arithmetic_neutral(ctx):
+    x = synth.spectral_field((40, 50, 90), seed=41)
+    print("\n[parity] grid sweep", flush=True)
+    blobs = []
+    for per_cu in (1, 2, 8, 16):
+        ctx.set_grid(per_cu)
+        r = ctx.compress(_to_gpu(x))
+        blobs.append(r.blob())
+        r.free()
+    ctx.set_grid(8)
+    assert all(b == blobs[0] for b in blobs)
+
+
+def test_repeat_is_deterministic(ctx):
+    x = synth.bumps_field((64, 64, 64), seed=3)
+    print("\n[parity] repeat", flush=True)
+    g = _to_gpu(x)
+    r1 = ctx.compress(g)
+    r2 = ctx.compress(g)
+    assert r1.blob() == r2.blob()
+    r1.free()
+    r2.free()
+
+
+def test_nonfinite_input_rejected(ctx):
+    x = synth.spectral_field((16, 16, 40), seed=5)
+    x[3, 4, 5] = np.inf
+    print("\n[errors] non-finite", flush=True)
+    with pytest.raises(szi.SzError) as e:
+        ctx.compress(_to_gpu(x))
+    assert e.value.code == -2
+
+
+def test_corrupt_blob_rejected(ctx):
+    x = synth.spectral_field((16, 16, 40), seed=6)
+    r = ctx.compress(_to_gpu(x))
+    blob = bytearray(r.blob())
+    r.free()
+    print("\n[errors] corrupt blob", flush=True)
+    for pos in (20, 300, len(blob) - 3):
+        bad = bytearray(blob)
+        bad[pos] ^= 0x04
+        with pytest.raises(szi.SzError) as e:
+            ctx.upload(bytes(bad))
+        assert e.value.code == -5
+    with pytest.raises(szi.SzError) as e:
+        ctx.upload(bytes(blob[:-8]))
+    assert e.value.code == -5
+
+
+def test_budget_exceeded_is_oom():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = szi.Context(0, hbm_budget=1 << 20)
+    x = synth.spectral_field((64, 64, 64), seed=7)
+    print("\n[errors] budget", flush=True)
+    with pytest.raises(szi.SzError) as e:
+        c.compress(_to_gpu(x))
+    assert e.value.code == -3
+    c.close()
+
+
+def test_full_size_512_cube(ctx):
+    # the benchmark's workload at its full size: 512^3, rel 1e-3, AUTO
+    print("\n[parity] 512^3 full size", flush=True)
+    x = synth.workload_large()
+    ref = O.compress(x, O.Params(shape=x.shape, eb=1e-3))
+    res = ctx.compress(_to_gpu(x), eb=1e-3)
+    assert res.blob() == ref.blob()
+    y = ctx.decompress(res).cpu().numpy()
+    assert np.array_equal(_bits(y), _bits(ref.recon))
+    res.free()
