@@ -398,6 +398,8 @@ def parse(blob: bytes) -> dict:
     f = _HEADER.unpack(head)
     if f[0] != MAGIC or f[1] != VERSION:
         raise OracleError(-5, "parse (magic)")
+    if struct.unpack_from("<I", head, 124)[0] or struct.unpack_from("<I", head, 248)[0]:
+        raise OracleError(-5, "parse (reserved words)")
     i = 0
     out = {}
     names = ["magic", "version", "ndim", "S", "n0", "n1", "n2", "w0", "w1", "w2", "R", "lmax",
@@ -416,6 +418,8 @@ def parse(blob: bytes) -> dict:
         raw = blob[pos:pos + nb]
         if len(raw) != nb or zlib.crc32(raw) & 0xFFFFFFFF != out["crc%d" % k]:
             raise OracleError(-5, "parse (section %d crc)" % k)
+        if any(blob[pos + nb:pos + nb + ((-nb) % 8)]):
+            raise OracleError(-5, "parse (section %d padding)" % k)
         secs.append(np.frombuffer(raw, dtype=dt).copy())
         pos += nb + ((-nb) % 8)
     if pos != len(blob):

@@ -1075,8 +1075,12 @@ sz_status sz_upload(sz_ctx* c, const void* blob, uint64_t bytes, void* stream, s
         off[k] = pos;
         if (crc32_update(0, b + pos, secb[k]) != get32(b, 224 + 4 * k))
             return fail(c, SZ_ERR_CORRUPT, "section %d CRC mismatch", k);
+        for (uint64_t q = pos + secb[k]; q < pos + pad8(secb[k]); ++q)
+            if (b[q]) return fail(c, SZ_ERR_CORRUPT, "section %d padding is not zero", k);
         pos += pad8(secb[k]);
     }
+    if (get32(b, 124) || get32(b, 248))
+        return fail(c, SZ_ERR_CORRUPT, "reserved header words are not zero");
     {
         // the chunk bit counts must account for exactly the stored words, and
         // outlier indices must lie inside the field

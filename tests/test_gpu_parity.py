@@ -206,7 +206,7 @@ def test_budget_exceeded_is_oom():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    c = szi.Context(0, hbm_budget=1 << 20)
+    c = szi.Context(0, hbm_budget=64 << 10)   # below the 512 KiB code array
     x = synth.spectral_field((64, 64, 64), seed=7)
     print("\n[errors] budget", flush=True)
     with pytest.raises(szi.SzError) as e:

@@ -506,7 +506,7 @@ def test_blob_crc_detects_corruption_and_truncation():
     c = O.compress(x, O.Params(shape=x.shape, eb=1e-3))
     b = bytearray(c.blob())
     O.parse(bytes(b))
-    for pos in (10, 300, len(b) - 5):
+    for pos in (10, 300, len(b) - 5, len(b) - 1):
         bad = bytearray(b)
         bad[pos] ^= 0x10
         with pytest.raises(O.OracleError):
