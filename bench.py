@@ -57,6 +57,9 @@ def main():
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--eb", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain device copy of the input (4n bytes read, 4n written) "
+                         "before the steps, to scale HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; the compressor's path is single-GPU "
@@ -79,6 +82,9 @@ def main():
     ctx = szi.Context(0)
     kw = dict(eb=args.eb)
 
+    if args.calibrate_copy:
+        out.copy_(d_x)
+        torch.cuda.synchronize()
     for _ in range(args.warmup):
         r = ctx.compress(d_x, **kw)
         ctx.decompress(r, out)

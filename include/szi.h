@@ -125,8 +125,9 @@ const char* sz_last_error(const sz_ctx* ctx);
 uint64_t sz_ctx_bytes_in_use(const sz_ctx* ctx);
 
 /* Launch shape of the persistent interpolation kernels: workgroups per
- * compute unit (1..64; default 8).  Arithmetic-neutral: every setting gives
- * byte-identical results; it only trades occupancy against tail effects. */
+ * compute unit (1..64), or 0 (the default) for as many as are resident at
+ * once.  Arithmetic-neutral: every setting gives byte-identical results; it
+ * only trades occupancy against tail effects. */
 sz_status sz_ctx_set_grid(sz_ctx* ctx, int workgroups_per_cu);
 
 /* Per-stage device timing.  When enabled, the context records a HIP event

@@ -1,0 +1,98 @@
+// dev_common.h -- device helpers shared by libszi's gfx950 kernels.
+#pragma once
+
+#include <float.h>
+#include <math.h>
+
+#include "szi_internal.h"
+
+namespace szi {
+
+// Pointers read from a descriptor are generic to the compiler, which then
+// emits flat memory instructions: 64-bit VGPR addresses, and each access
+// also counts against the LDS wait counter.  Casting them to the global
+// address space gives global_* instructions with a scalar base.
+#define SZI_G __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ SZI_G T* gp(T* p) {
+    return (SZI_G T*)p;
+}
+template <class T>
+__device__ __forceinline__ const SZI_G T* gp(const T* p) {
+    return (const SZI_G T*)p;
+}
+// builtin vectors for wide global loads (no constructors, so they load
+// through address-space-qualified pointers)
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef uint32_t vu4 __attribute__((ext_vector_type(4)));
+typedef uint32_t vu2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void gatomic_add(SZI_G uint32_t* p, uint32_t v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------- helpers
+__device__ __forceinline__ float wave_min(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+// exclusive prefix sum across the 64 lanes of a wave
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total) {
+    const int lane = threadIdx.x & 63;
+    uint32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    *total = __shfl(x, 63);
+    return x - v;
+}
+
+// Division by a small divisor m (< kMagicN) of dividends t < 2^16 through a
+// multiply-high by ceil(2^32 / m); exact because t * m < 2^32.  The
+// multipliers come from a constant table, so no divide runs on the GPU.
+constexpr int kMagicN = 2048;
+struct MagicTable {
+    uint32_t v[kMagicN];
+    constexpr MagicTable() : v() {
+        for (int m = 0; m < kMagicN; ++m) v[m] = m > 1 ? 0xFFFFFFFFu / (uint32_t)m + 1u : 0u;
+    }
+};
+static __constant__ MagicTable kMagic = MagicTable();
+
+struct FastDiv {
+    uint32_t m, mg;
+    __device__ __forceinline__ void set(uint32_t mm) {
+        m = mm;
+        mg = kMagic.v[mm];
+    }
+    __device__ __forceinline__ uint32_t div(uint32_t t) const { return m > 1 ? __umulhi(t, mg) : t; }
+};
+
+__device__ __forceinline__ bool finite_bits(float v) {
+    return (__float_as_uint(v) & 0x7f800000u) != 0x7f800000u;
+}
+
+// spline kinds per dimension (include/szi.h sz_interp)
+enum { SPL_LIN = 0, SPL_NAK = 1, SPL_NAT = 2, SPL_AUTO = 3 };
+
+// field of a block index given prefix offsets boff[0..nfields]
+__device__ __forceinline__ int block_field(const uint64_t* __restrict__ boff, int nfields,
+                                           uint64_t b) {
+    int lo = 0, hi = nfields - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (boff[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+}  // namespace szi

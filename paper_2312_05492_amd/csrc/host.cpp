@@ -30,7 +30,9 @@ struct sz_ctx {
     std::string err;
     void* pinned = nullptr;    // host staging buffer
     size_t pinned_bytes = 0;
-    int grid_per_cu = 8;       // persistent workgroups per CU (tunable)
+    int grid_per_cu = 0;       // persistent workgroups per CU; 0 = resident capacity
+    uint16_t* d_ptab[2] = {nullptr, nullptr};     // pass tables, 3D and 2D
+    PassMeta* d_pmeta[2] = {nullptr, nullptr};
     // stage timing
     bool timing = false;
     std::vector<hipEvent_t> ev_free;
@@ -214,6 +216,80 @@ struct Scratch {
         return SZ_OK;
     }
 };
+
+// ------------------------------------------------------------ pass tables
+// For every processing order of a full window, the block points of each pass
+// (Sec. V-A: levels from stride S/2 to 1, one pass per dimension in order).
+void build_pass_table(int nd, std::vector<uint16_t>& ent, std::vector<PassMeta>& meta) {
+    const int W[3] = {nd == 3 ? 32 : 64, nd == 3 ? 8 : 16, nd == 3 ? 8 : 0};
+    const int B[3] = {W[0] + 1, W[1] + 1, nd == 3 ? W[2] + 1 : 1};
+    const int L = nd == 3 ? 3 : 4;
+    const int nperm = nd == 3 ? kPerm3 : kPerm2;
+    for (int id = 0; id < nperm; ++id) {
+        int order[3];
+        if (nd == 3) {
+            order[0] = id / 2;
+            const int r0 = order[0] == 0 ? 1 : 0, r1 = order[0] == 2 ? 1 : 2;   // the others, ascending
+            order[1] = (id & 1) ? r1 : r0;
+            order[2] = (id & 1) ? r0 : r1;
+        } else {
+            order[0] = id;
+            order[1] = 1 - id;
+            order[2] = -1;
+        }
+        PassMeta m;
+        std::memset(&m, 0, sizeof m);
+        int pass = 0;
+        for (int lvl = L; lvl >= 1; --lvl) {
+            const int sp = 1 << (lvl - 1);
+            for (int k = 0; k < nd; ++k, ++pass) {
+                const int d = order[k];
+                m.off[pass] = (uint32_t)ent.size();
+                std::vector<uint16_t> edge;   // points without a full cubic stencil
+                for (int c2 = 0; c2 < B[2]; ++c2)
+                    for (int c1 = 0; c1 < B[1]; ++c1)
+                        for (int c0 = 0; c0 < B[0]; ++c0) {
+                            const int c[3] = {c0, c1, c2};
+                            bool in = true;
+                            for (int kk = 0; kk < nd; ++kk) {
+                                const int j = order[kk];
+                                if (kk == k) in = in && c[j] % (2 * sp) == sp;
+                                else if (kk < k) in = in && c[j] % sp == 0;
+                                else in = in && c[j] % (2 * sp) == 0;
+                            }
+                            if (!in) continue;
+                            const int li = c0 + B[0] * (c1 + B[1] * c2);
+                            const int cd = c[d];
+                            const int m3 = cd >= 3 * sp, p3 = cd + 3 * sp <= W[d];
+                            const uint16_t e = (uint16_t)(li | (m3 << 12) | (p3 << 13));
+                            if (m3 && p3) ent.push_back(e);
+                            else edge.push_back(e);
+                        }
+                m.ncub[pass] = (uint32_t)ent.size() - m.off[pass];
+                ent.insert(ent.end(), edge.begin(), edge.end());
+                m.cnt[pass] = (uint32_t)ent.size() - m.off[pass];
+            }
+        }
+        meta.push_back(m);
+    }
+}
+
+sz_status ensure_tables(sz_ctx* c) {
+    for (int t = 0; t < 2; ++t) {
+        if (c->d_ptab[t]) continue;
+        std::vector<uint16_t> ent;
+        std::vector<PassMeta> meta;
+        build_pass_table(t == 0 ? 3 : 2, ent, meta);
+        void *pe = nullptr, *pm = nullptr;
+        HIP_TRY(c, hipMalloc(&pe, ent.size() * sizeof(uint16_t)));
+        HIP_TRY(c, hipMalloc(&pm, meta.size() * sizeof(PassMeta)));
+        HIP_TRY(c, hipMemcpy(pe, ent.data(), ent.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(pm, meta.data(), meta.size() * sizeof(PassMeta), hipMemcpyHostToDevice));
+        c->d_ptab[t] = static_cast<uint16_t*>(pe);
+        c->d_pmeta[t] = static_cast<PassMeta*>(pm);
+    }
+    return SZ_OK;
+}
 
 // ------------------------------------------------------------ CRC-32 (IEEE)
 uint32_t crc32_update(uint32_t crc, const uint8_t* p, size_t n) {
@@ -565,6 +641,10 @@ sz_status sz_ctx_destroy(sz_ctx* c) {
     if (!c) return SZ_OK;
     (void)hipSetDevice(c->device);
     for (auto& kv : c->block_size) (void)hipFree(kv.first);
+    for (int t = 0; t < 2; ++t) {
+        if (c->d_ptab[t]) (void)hipFree(c->d_ptab[t]);
+        if (c->d_pmeta[t]) (void)hipFree(c->d_pmeta[t]);
+    }
     for (auto& m : c->marks) {
         (void)hipEventDestroy(m.a);
         (void)hipEventDestroy(m.b);
@@ -604,7 +684,7 @@ sz_status sz_ctx_read_timing(sz_ctx* c, double* ms, uint64_t* launches, int rese
 
 // tuning hook: persistent workgroups per CU for the interpolation launches
 sz_status sz_ctx_set_grid(sz_ctx* c, int workgroups_per_cu) {
-    if (!c || workgroups_per_cu < 1 || workgroups_per_cu > 64) return SZ_ERR_INVALID_ARG;
+    if (!c || workgroups_per_cu < 0 || workgroups_per_cu > 64) return SZ_ERR_INVALID_ARG;
     c->grid_per_cu = workgroups_per_cu;
     return SZ_OK;
 }
@@ -617,6 +697,10 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
     HIP_TRY(c, hipSetDevice(c->device));
     MarkGuard mark_guard{c};
     hipStream_t st = static_cast<hipStream_t>(stream);
+    {
+        sz_status ts = ensure_tables(c);
+        if (ts) return ts;
+    }
     std::vector<Geometry> geo(nf);
     std::vector<FieldDesc> fd(nf);
     for (uint32_t i = 0; i < nf; ++i) {
@@ -728,7 +812,6 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
         STAGE(c, SZ_STAGE_PLAN, st);
         HIP_TRY(c, launch_plan(d_fd, d_plan, (int)nf, d_pmin, d_pmax, d_pbad, st));
     }
-    const int grid = c->num_cus * c->grid_per_cu;
     {
         uint32_t base = 0;
         for (int gi = 0; gi < 2; ++gi) {
@@ -736,7 +819,8 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
                 STAGE(c, SZ_STAGE_INTERP, st);
                 HIP_TRY(c, launch_compress(gi == 0 ? 3 : 2, d_fd + base, d_plan + base,
                                            (int)grp[gi].size(), d_items + gi * (nf + 1),
-                                           nitems[gi], grid, max_R, st));
+                                           nitems[gi], c->d_ptab[gi], c->d_pmeta[gi], c->num_cus,
+                                           c->grid_per_cu, max_R, st));
             }
             base += (uint32_t)grp[gi].size();
         }
@@ -789,56 +873,98 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
         HIP_TRY(c, hipMemcpyAsync(R->d_dtab, dtab[k].data(), sizeof(uint32_t) * dtab[k].size(),
                                   hipMemcpyHostToDevice, st));
     }
-    // Huffman encode: per-field block ranges of 16 chunks
-    std::vector<uint64_t> boff(nf + 1, 0);
-    for (uint32_t k = 0; k < nf; ++k) boff[k + 1] = boff[k] + (fds[k].nchunks + 15) / 16;
-    // chunk_base must follow the descriptor order
+    // Huffman encode.  The encode kernels are specialised on the chunk size,
+    // so the fields are ordered by chunk size into contiguous groups; each
+    // group runs stats -> block scan -> encode over blocks of
+    // kEncBlockChunks chunks (blocks never straddle fields).
+    std::vector<uint32_t> hord(nf);
+    for (uint32_t k = 0; k < nf; ++k) hord[k] = k;
+    std::stable_sort(hord.begin(), hord.end(),
+                     [&](uint32_t x, uint32_t y) { return fds[x].chunk < fds[y].chunk; });
+    std::vector<FieldDesc> hfd(nf);
+    std::vector<uint64_t> hboff(nf + 1, 0);   // global block prefix in hfd order
     {
         uint64_t cb = 0;
-        for (uint32_t k = 0; k < nf; ++k) {
-            fds[k].chunk_base = cb;
-            cb += fds[k].nchunks;
+        for (uint32_t j = 0; j < nf; ++j) {
+            hfd[j] = fds[hord[j]];
+            hfd[j].chunk_base = cb;
+            cb += hfd[j].nchunks;
+            hboff[j + 1] = hboff[j] + (hfd[j].nchunks + kEncBlockChunks - 1) / kEncBlockChunks;
         }
     }
-    uint64_t* d_boff;
-    uint32_t *d_cwords, *d_couts;
-    uint64_t *d_woff, *d_ooff, *d_tot;
-    if ((s = sc.get(nf + 1, &d_boff)) || (s = sc.get(total_chunks, &d_cwords)) ||
-        (s = sc.get(total_chunks, &d_couts)) || (s = sc.get(total_chunks + 1, &d_woff)) ||
-        (s = sc.get(total_chunks + 1, &d_ooff)) || (s = sc.get(2, &d_tot)))
+    struct Group {
+        uint32_t fs, fe;   // field slice in hfd
+    };
+    std::vector<Group> groups;
+    for (uint32_t j = 0; j < nf; ++j)
+        if (groups.empty() || hfd[groups.back().fs].chunk != hfd[j].chunk) groups.push_back({j, j + 1});
+        else groups.back().fe = j + 1;
+    const uint64_t total_blocks = hboff[nf];
+    // per group: block prefix (group-local) and offsets with one closing slot
+    std::vector<uint64_t> gboff;            // concatenated group-local prefixes
+    std::vector<uint64_t> gboff_at(groups.size()), goff_at(groups.size());
+    for (size_t g = 0; g < groups.size(); ++g) {
+        gboff_at[g] = gboff.size();
+        goff_at[g] = hboff[groups[g].fs] + g;
+        for (uint32_t j = groups[g].fs; j <= groups[g].fe; ++j)
+            gboff.push_back(hboff[j] - hboff[groups[g].fs]);
+    }
+    FieldDesc* d_hfd;
+    uint64_t *d_gboff, *d_bwoff, *d_booff;
+    uint32_t *d_cwords, *d_couts, *d_bw, *d_bo;
+    if ((s = sc.get(nf, &d_hfd)) || (s = sc.get(gboff.size(), &d_gboff)) ||
+        (s = sc.get(std::max<uint64_t>(total_chunks, 1), &d_cwords)) ||
+        (s = sc.get(std::max<uint64_t>(total_chunks, 1), &d_couts)) ||
+        (s = sc.get(std::max<uint64_t>(total_blocks, 1), &d_bw)) ||
+        (s = sc.get(std::max<uint64_t>(total_blocks, 1), &d_bo)) ||
+        (s = sc.get(total_blocks + groups.size(), &d_bwoff)) ||
+        (s = sc.get(total_blocks + groups.size(), &d_booff)))
         return s;
-    HIP_TRY(c, hipMemcpyAsync(d_fd, fds.data(), sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
-    HIP_TRY(c, hipMemcpyAsync(d_boff, boff.data(), sizeof(uint64_t) * (nf + 1), hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipMemcpyAsync(d_hfd, hfd.data(), sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipMemcpyAsync(d_gboff, gboff.data(), sizeof(uint64_t) * gboff.size(),
+                              hipMemcpyHostToDevice, st));
     cb_mark.reset();
-    {
-        STAGE(c, SZ_STAGE_HUFF_STATS, st);
-        HIP_TRY(c, launch_huff_stats(d_fd, (int)nf, d_boff, boff[nf], d_cwords, d_couts, 2 * max_R, st));
+    for (size_t g = 0; g < groups.size(); ++g) {
+        const uint32_t fs = groups[g].fs, nfg = groups[g].fe - groups[g].fs;
+        const uint64_t b0 = hboff[fs], nb = hboff[groups[g].fe] - b0;
+        const int chunk = hfd[fs].chunk;
+        {
+            STAGE(c, SZ_STAGE_HUFF_STATS, st);
+            HIP_TRY(c, launch_huff_stats(d_hfd + fs, (int)nfg, d_gboff + gboff_at[g], nb, chunk,
+                                         d_cwords, d_couts, d_bw + b0, d_bo + b0, 2 * max_R, st));
+        }
+        {
+            STAGE(c, SZ_STAGE_SCAN, st);
+            HIP_TRY(c, launch_scan_blocks(d_bw + b0, d_bo + b0, nb, d_bwoff + goff_at[g],
+                                          d_booff + goff_at[g], st));
+        }
+        {
+            STAGE(c, SZ_STAGE_ENCODE, st);
+            HIP_TRY(c, launch_huff_encode(d_hfd + fs, (int)nfg, d_gboff + gboff_at[g], nb, chunk,
+                                          d_cwords, d_couts, d_bwoff + goff_at[g],
+                                          d_booff + goff_at[g], 2 * max_R, st));
+        }
     }
-    {
-        STAGE(c, SZ_STAGE_SCAN, st);
-        HIP_TRY(c, launch_scan_pairs(d_cwords, d_couts, total_chunks, nullptr, 0, d_woff, d_ooff, d_tot, st));
-        // the scan writes exclusive offsets for [0, n); the totals close them
-        HIP_TRY(c, hipMemcpyAsync(d_woff + total_chunks, d_tot, sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(d_ooff + total_chunks, d_tot + 1, sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
-    }
-    {
-        STAGE(c, SZ_STAGE_ENCODE, st);
-        HIP_TRY(c, launch_huff_encode(d_fd, (int)nf, d_boff, boff[nf], d_woff, d_ooff, 2 * max_R,
-                                      max_chunk, st));
-    }
-    // sync 2: word offsets at the field boundaries
-    std::vector<uint64_t> wb(nf + 1);
-    for (uint32_t k = 0; k <= nf; ++k) {
-        const uint64_t at = k < nf ? fds[k].chunk_base : total_chunks;
-        HIP_TRY(c, hipMemcpyAsync(&wb[k], d_woff + at, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    }
+    // sync 2: block word offsets (small) to the host
+    std::vector<uint64_t> bwoff(total_blocks + groups.size());
+    HIP_TRY(c, hipMemcpyAsync(bwoff.data(), d_bwoff, sizeof(uint64_t) * bwoff.size(),
+                              hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
     resolve_marks(c);
-    for (uint32_t k = 0; k < nf; ++k) {
-        const uint32_t i = perm[k];
-        res[i].n_words = wb[k + 1] - wb[k];
-        res[i].compressed_bytes = blob_bytes(&res[i], fds[k].R);
-        make_header(&res[i], ri(&res[i]), res[i].header);
+    for (size_t g = 0; g < groups.size(); ++g) {
+        for (uint32_t j = groups[g].fs; j < groups[g].fe; ++j) {
+            const uint64_t lo = gboff[gboff_at[g] + (j - groups[g].fs)];
+            const uint64_t hi = gboff[gboff_at[g] + (j - groups[g].fs) + 1];
+            const uint32_t k = hord[j];
+            const uint32_t i = perm[k];
+            res[i].n_words = bwoff[goff_at[g] + hi] - bwoff[goff_at[g] + lo];
+            if (res[i].n_words > fds[k].words_cap)   // the histogram sized the stream
+                return fail(c, SZ_ERR_DEVICE, "field %u: %llu Huffman words exceed the %llu sized "
+                            "from the histogram", i, (unsigned long long)res[i].n_words,
+                            (unsigned long long)fds[k].words_cap);
+            res[i].compressed_bytes = blob_bytes(&res[i], fds[k].R);
+            make_header(&res[i], ri(&res[i]), res[i].header);
+        }
     }
     guard.keep = true;
     for (uint32_t i = 0; i < nf; ++i) outs[i] = res[i];
@@ -860,6 +986,10 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
     HIP_TRY(c, hipSetDevice(c->device));
     MarkGuard mark_guard{c};
     hipStream_t st = static_cast<hipStream_t>(stream);
+    {
+        sz_status ts = ensure_tables(c);
+        if (ts) return ts;
+    }
     Scratch sc(c);
     std::vector<FieldDesc> fds(nf);
     std::vector<FieldPlan> plans(nf);
@@ -887,7 +1017,7 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
     std::vector<uint32_t> perm;
     for (int gi = 0; gi < 2; ++gi) perm.insert(perm.end(), grp[gi].begin(), grp[gi].end());
     uint64_t cb = 0;
-    std::vector<uint64_t> dboff(nf + 1, 0), coff(nf + 1, 0);
+    std::vector<uint64_t> dboff(nf + 1, 0);
     for (uint32_t k = 0; k < nf; ++k) {
         const uint32_t i = perm[k];
         const ResultInternal* R = ri(&res[i]);
@@ -902,6 +1032,7 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         f.outlier_idx = res[i].outlier_idx;
         f.outlier_val = res[i].outlier_val;
         f.n_outliers = res[i].n_outliers;
+        f.words_cap = res[i].n_words;
         f.dtab = R->d_dtab;
         f.chunk_base = cb;
         uint16_t* codes;
@@ -909,11 +1040,9 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         if (s) return s;
         f.codes = codes;
         cb += geo[i].nchunks;
-        coff[k + 1] = cb;
-        dboff[k + 1] = dboff[k] + (geo[i].nchunks + 255) / 256;
+        dboff[k + 1] = dboff[k] + (geo[i].nchunks + kDecBlockChunks - 1) / kDecBlockChunks;
         plans[k] = R->plan;
     }
-    const uint64_t total_chunks = cb;
     std::vector<uint64_t> items(2 * (nf + 1), 0);
     uint64_t nitems[2] = {0, 0};
     for (int gi = 0; gi < 2; ++gi) {
@@ -921,40 +1050,41 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         for (size_t j = 0; j < grp[gi].size(); ++j) io[j + 1] = io[j] + geo[grp[gi][j]].nwin_total;
         nitems[gi] = grp[gi].empty() ? 0 : io[grp[gi].size()];
     }
+    const uint64_t nblocks = dboff[nf];
     FieldDesc* d_fd;
     FieldPlan* d_plan;
-    uint64_t *d_items, *d_dboff, *d_coff, *d_woff;
-    uint32_t* d_tmp;
+    uint64_t *d_items, *d_dboff, *d_bwoff;
+    uint32_t* d_bsum;
     sz_status s;
     if ((s = sc.get(nf, &d_fd)) || (s = sc.get(nf, &d_plan)) || (s = sc.get(items.size(), &d_items)) ||
-        (s = sc.get(nf + 1, &d_dboff)) || (s = sc.get(nf + 1, &d_coff)) ||
-        (s = sc.get(total_chunks + 2, &d_woff)) || (s = sc.get(std::max<uint64_t>(total_chunks, 1), &d_tmp)))
+        (s = sc.get(nf + 1, &d_dboff)) || (s = sc.get(nblocks + 1, &d_bwoff)) ||
+        (s = sc.get(std::max<uint64_t>(nblocks, 1), &d_bsum)))
         return s;
     HIP_TRY(c, hipMemcpyAsync(d_fd, fds.data(), sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
     HIP_TRY(c, hipMemcpyAsync(d_plan, plans.data(), sizeof(FieldPlan) * nf, hipMemcpyHostToDevice, st));
     HIP_TRY(c, hipMemcpyAsync(d_items, items.data(), sizeof(uint64_t) * items.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(c, hipMemcpyAsync(d_dboff, dboff.data(), sizeof(uint64_t) * (nf + 1), hipMemcpyHostToDevice, st));
-    HIP_TRY(c, hipMemcpyAsync(d_coff, coff.data(), sizeof(uint64_t) * (nf + 1), hipMemcpyHostToDevice, st));
     {
         STAGE(c, SZ_STAGE_SCAN, st);
-        HIP_TRY(c, launch_scan_words(d_fd, (int)nf, d_coff, total_chunks, d_tmp, d_woff, st));
+        HIP_TRY(c, launch_chunk_words(d_fd, (int)nf, d_dboff, nblocks, d_bsum, st));
+        HIP_TRY(c, launch_scan_blocks(d_bsum, nullptr, nblocks, d_bwoff, nullptr, st));
     }
     {
         STAGE(c, SZ_STAGE_DECODE, st);
-        HIP_TRY(c, launch_huff_decode(d_fd, (int)nf, d_dboff, dboff[nf], d_woff, 2 * max_R, st));
+        HIP_TRY(c, launch_huff_decode(d_fd, (int)nf, d_dboff, nblocks, d_bwoff, 2 * max_R, st));
     }
     {
         STAGE(c, SZ_STAGE_SCATTER, st);
         HIP_TRY(c, launch_scatter_outliers(d_fd, (int)nf, st));
     }
-    const int grid = c->num_cus * c->grid_per_cu;
     uint32_t base = 0;
     for (int gi = 0; gi < 2; ++gi) {
         if (!grp[gi].empty()) {
             STAGE(c, SZ_STAGE_REPLAY, st);
             HIP_TRY(c, launch_decompress(gi == 0 ? 3 : 2, d_fd + base, d_plan + base,
                                          (int)grp[gi].size(), d_items + gi * (nf + 1), nitems[gi],
-                                         grid, st));
+                                         c->d_ptab[gi], c->d_pmeta[gi], c->num_cus,
+                                         c->grid_per_cu, st));
         }
         base += (uint32_t)grp[gi].size();
     }

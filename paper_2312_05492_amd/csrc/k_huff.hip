@@ -1,0 +1,449 @@
+// k_huff.hip -- chunked Huffman encode/decode with fused outlier compaction
+// (Sec. VI-A) on gfx950.
+//
+// Encode: kEncChunks consecutive chunks of one field per workgroup (4 wave64,
+// one chunk per wave at a time, C/64 consecutive symbols per lane).
+//   k_huff_stats   bit count and outlier count of every chunk; sums per
+//                  workgroup block
+//   k_scan_blocks  exclusive scan of the block sums (one workgroup)
+//   k_huff_encode  chunk offsets = block offset + in-block prefix; packs the
+//                  codewords MSB-first through LDS and writes the outliers
+//                  (index, original value) in ascending index order
+// Decode: one lane per chunk, kDecChunks chunks per workgroup.
+//   k_chunk_words  word count of every chunk, sums per block
+//   k_scan_blocks  exclusive scan of the block sums
+//   k_huff_decode  in-block scan, then a table-driven canonical decode with
+//                  a prefetched word queue; symbols are staged in LDS and
+//                  written to global memory in coalesced rows
+#include "dev_common.h"
+
+namespace szi {
+
+constexpr int kEncChunks = 16;
+constexpr int kDecChunks = 256;
+constexpr int kStage = 32;   // decoded symbols per lane staged in LDS
+constexpr int kStageRow = kStage + 2;   // u16 per staged row: 17 words, so rows spread over banks
+
+// symbols [s0, s0 + per) of the code array (all inside the field)
+template <int PER>
+__device__ __forceinline__ void load_syms(const SZI_G uint16_t* __restrict__ codes, uint64_t s0,
+                                          uint32_t* sym) {
+    if (PER >= 8) {
+        const SZI_G vu4* p = reinterpret_cast<const SZI_G vu4*>(codes + s0);
+#pragma unroll
+        for (int k = 0; k < PER / 8; ++k) {
+            const vu4 w = p[k];
+            const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                sym[8 * k + 2 * j] = ww[j] & 0xFFFFu;
+                sym[8 * k + 2 * j + 1] = ww[j] >> 16;
+            }
+        }
+    } else {
+        const vu2 w = *reinterpret_cast<const SZI_G vu2*>(codes + s0);
+        sym[0] = w.x & 0xFFFFu;
+        sym[1] = w.x >> 16;
+        sym[2] = w.y & 0xFFFFu;
+        sym[3] = w.y >> 16;
+    }
+}
+
+template <int PER>
+__device__ __forceinline__ void lane_syms(const FieldDesc& fd, uint64_t ch, int lane,
+                                          uint32_t* sym, int& nsym_lane) {
+    const uint64_t s0 = ch * (uint64_t)(PER * 64) + (uint64_t)lane * PER;
+    if (s0 + PER <= fd.npts) {
+        load_syms<PER>(gp(fd.codes), s0, sym);
+        nsym_lane = PER;
+    } else {
+        nsym_lane = s0 < fd.npts ? (int)(fd.npts - s0) : 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) sym[k] = k < nsym_lane ? gp(fd.codes)[s0 + k] : 0u;
+    }
+}
+
+template <int PER>
+__global__ __launch_bounds__(256) void k_huff_stats(const FieldDesc* __restrict__ F, int nfields,
+                                                    const uint64_t* __restrict__ boff,
+                                                    uint32_t* cwords, uint32_t* couts,
+                                                    uint32_t* bw, uint32_t* bo) {
+    extern __shared__ uint32_t cb[];
+    __shared__ uint32_t sw[kEncChunks], so[kEncChunks];
+    const int f = block_field(boff, nfields, blockIdx.x);
+    const FieldDesc& fd = F[f];
+    const int nsym = 2 * fd.R;
+    for (int s = threadIdx.x; s < nsym; s += blockDim.x) cb[s] = gp(fd.cbook)[s];
+    __syncthreads();
+    const uint64_t first = (blockIdx.x - boff[f]) * kEncChunks;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int j = wave; j < kEncChunks; j += 4) {
+        const uint64_t ch = first + j;
+        uint32_t words = 0, zeros = 0;
+        if (ch < fd.nchunks) {   // uniform across the wave
+            uint32_t sym[PER];
+            int ns;
+            lane_syms<PER>(fd, ch, lane, sym, ns);
+            uint32_t bits = 0;
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const bool live = k < ns;
+                bits += live ? cb[sym[k]] >> 24 : 0u;
+                zeros += (live && sym[k] == 0) ? 1u : 0u;
+            }
+            bits = wave_sum(bits);
+            zeros = wave_sum(zeros);
+            words = (bits + 31) >> 5;
+            if (lane == 0) {
+                gp(fd.chunk_bits)[ch] = (uint16_t)bits;
+                cwords[fd.chunk_base + ch] = words;
+                couts[fd.chunk_base + ch] = zeros;
+            }
+        }
+        if (lane == 0) {
+            sw[j] = words;
+            so[j] = zeros;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t a = 0, b = 0;
+        for (int j = 0; j < kEncChunks; ++j) {
+            a += sw[j];
+            b += so[j];
+        }
+        bw[blockIdx.x] = a;
+        bo[blockIdx.x] = b;
+    }
+}
+
+// Exclusive scan of up to two u32 arrays of length n into u64 offsets; one
+// workgroup of 1024 threads, contiguous runs per thread.  off[n] receives
+// the total.
+__global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t* __restrict__ a,
+                                                      const uint32_t* __restrict__ b, uint64_t n,
+                                                      uint64_t* aoff, uint64_t* boff) {
+    const int t = threadIdx.x;
+    const uint64_t per = (n + 1023) / 1024;
+    const uint64_t beg = t * per, end = beg + per < n ? beg + per : n;
+    uint64_t sa = 0, sb = 0;
+    for (uint64_t i = beg; i < end; ++i) {
+        sa += a[i];
+        if (b) sb += b[i];
+    }
+    __shared__ uint64_t xa[1024], xb[1024];
+    xa[t] = sa;
+    xb[t] = sb;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const uint64_t ya = t >= o ? xa[t - o] : 0, yb = t >= o ? xb[t - o] : 0;
+        __syncthreads();
+        xa[t] += ya;
+        xb[t] += yb;
+        __syncthreads();
+    }
+    uint64_t ra = xa[t] - sa, rb = xb[t] - sb;
+    for (uint64_t i = beg; i < end; ++i) {
+        aoff[i] = ra;
+        ra += a[i];
+        if (b) {
+            boff[i] = rb;
+            rb += b[i];
+        }
+    }
+    if (t == 1023) {
+        aoff[n] = xa[1023];
+        if (b) boff[n] = xb[1023];
+    }
+}
+
+template <int PER>
+__global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict__ F, int nfields,
+                                                     const uint64_t* __restrict__ boff,
+                                                     const uint32_t* __restrict__ cwords,
+                                                     const uint32_t* __restrict__ couts,
+                                                     const uint64_t* __restrict__ bwoff,
+                                                     const uint64_t* __restrict__ booff) {
+    extern __shared__ uint32_t smem[];
+    constexpr int C = PER * 64;
+    constexpr int MCW = (C * kLmax + 31) / 32 + 1;   // words of the longest chunk
+    const int f = block_field(boff, nfields, blockIdx.x);
+    const FieldDesc& fd = F[f];
+    const int nsym = 2 * fd.R;
+    uint32_t* cb = smem;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t* wbuf = smem + nsym + wave * MCW;
+    for (int s = threadIdx.x; s < nsym; s += blockDim.x) cb[s] = gp(fd.cbook)[s];
+    __syncthreads();
+    const uint64_t blk_local = blockIdx.x - boff[f];
+    const uint64_t first = blk_local * kEncChunks;
+    // this field's sections start at 0: subtract the offsets of its first block
+    const uint64_t wbase = bwoff[boff[f]], obase = booff[boff[f]];
+    const uint64_t bw0 = bwoff[blockIdx.x] - wbase, bo0 = booff[blockIdx.x] - obase;
+    // in-block exclusive prefix of the chunk word and outlier counts
+    uint32_t cw = 0, co = 0;
+    if (lane < kEncChunks && first + lane < fd.nchunks) {
+        cw = cwords[fd.chunk_base + first + lane];
+        co = couts[fd.chunk_base + first + lane];
+    }
+    uint32_t tw, to;
+    const uint32_t pw = wave_excl_scan(cw, &tw);
+    const uint32_t po = wave_excl_scan(co, &to);
+    for (int j0 = 0; j0 < kEncChunks; j0 += 4) {
+        const int j = j0 + wave;
+        const uint64_t ch = first + j;
+        const bool live = ch < fd.nchunks;   // uniform across the wave
+        uint32_t sym[PER];
+        int ns = 0;
+        if (live) lane_syms<PER>(fd, ch, lane, sym, ns);
+        uint32_t bits = 0, zeros = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const bool on = k < ns;
+            bits += on ? cb[sym[k]] >> 24 : 0u;
+            zeros += (on && sym[k] == 0) ? 1u : 0u;
+        }
+        uint32_t tb, tz;
+        const uint32_t boffl = wave_excl_scan(bits, &tb);
+        const uint32_t zoffl = wave_excl_scan(zeros, &tz);
+        const int nw = live ? (int)((tb + 31) >> 5) : 0;
+        for (int k = lane; k < nw; k += 64) wbuf[k] = 0;
+        __syncthreads();
+        const uint64_t ow = bw0 + __shfl(pw, j);
+        const uint64_t oo = bo0 + __shfl(po, j);
+        uint32_t pos = boffl;
+        uint32_t zo = zoffl;
+        const uint64_t s0 = ch * (uint64_t)C + (uint64_t)lane * PER;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            if (k < ns) {
+                const uint32_t e = cb[sym[k]];
+                const uint32_t len = e >> 24, code = e & 0xFFFFFFu;
+                const uint32_t wi = pos >> 5, bo = pos & 31;
+                const uint64_t sh = (uint64_t)code << (64 - len - bo);   // MSB first
+                atomicOr(&wbuf[wi], (uint32_t)(sh >> 32));
+                if (bo + len > 32) atomicOr(&wbuf[wi + 1], (uint32_t)sh);
+                pos += len;
+                if (sym[k] == 0) {
+                    if (oo + zo < fd.n_outliers) {   // the histogram sized the list
+                        gp(fd.outlier_idx)[oo + zo] = (uint32_t)(s0 + k);
+                        gp(fd.outlier_val)[oo + zo] = gp(fd.in)[s0 + k];
+                    }
+                    ++zo;
+                }
+            }
+        }
+        __syncthreads();
+        for (int k = lane; k < nw; k += 64)
+            if (ow + k < fd.words_cap) gp(fd.words)[ow + k] = wbuf[k];
+        __syncthreads();
+    }
+}
+
+// word count of every chunk and their sums per decode block
+__global__ __launch_bounds__(kDecChunks) void k_chunk_words(const FieldDesc* __restrict__ F,
+                                                            int nfields,
+                                                            const uint64_t* __restrict__ boff,
+                                                            uint32_t* bsum) {
+    const int f = block_field(boff, nfields, blockIdx.x);
+    const FieldDesc& fd = F[f];
+    const uint64_t ch = (blockIdx.x - boff[f]) * kDecChunks + threadIdx.x;
+    uint32_t w = ch < fd.nchunks ? ((uint32_t)gp(fd.chunk_bits)[ch] + 31u) >> 5 : 0u;
+    w = wave_sum(w);
+    __shared__ uint32_t s[kDecChunks / 64];
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t a = 0;
+        for (int k = 0; k < kDecChunks / 64; ++k) a += s[k];
+        bsum[blockIdx.x] = a;
+    }
+}
+
+// one lane decodes one chunk: canonical decode with a 2^kLutBits table for
+// short codes and a first-code search for longer ones
+__global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __restrict__ F,
+                                                            int nfields,
+                                                            const uint64_t* __restrict__ boff,
+                                                            const uint64_t* __restrict__ bwoff) {
+    extern __shared__ uint32_t smem[];
+    const int f = block_field(boff, nfields, blockIdx.x);
+    const FieldDesc& fd = F[f];
+    const int nsym = 2 * fd.R;
+    const int ntab = dtab_words(nsym);
+    uint32_t* tab = smem;
+    uint32_t* scan = smem + ntab;                                     // kDecChunks
+    uint16_t* stage = reinterpret_cast<uint16_t*>(scan + kDecChunks);  // kDecChunks x kStageRow
+    for (int k = threadIdx.x; k < ntab; k += blockDim.x) tab[k] = gp(fd.dtab)[k];
+    const int tid = threadIdx.x;
+    const uint64_t first = (blockIdx.x - boff[f]) * kDecChunks;
+    const uint64_t ch = first + tid;
+    const bool live = ch < fd.nchunks;
+    const uint32_t cbits = live ? (uint32_t)gp(fd.chunk_bits)[ch] : 0u;
+    const uint32_t nw = (cbits + 31) >> 5;
+    // in-block exclusive scan of the word counts
+    uint32_t tot;
+    const uint32_t wx = wave_excl_scan(nw, &tot);
+    if ((tid & 63) == 0) scan[tid >> 6] = tot;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < (tid >> 6); ++k) before += scan[k];
+    __syncthreads();
+    const uint64_t w0 = bwoff[blockIdx.x] - bwoff[boff[f]] + before + wx;
+    // never read past the field's word array, whatever the chunk sizes say
+    const uint64_t wend = w0 + nw < fd.words_cap ? w0 + nw : fd.words_cap;
+    const SZI_G uint32_t* words = gp(fd.words);
+    const int C = fd.chunk;
+    const uint64_t s0 = ch * (uint64_t)C;
+    const int cnt = !live ? 0 : (s0 + C <= fd.npts ? C : (int)(fd.npts - s0));
+    // Words enter the 64-bit bit buffer from an 8-word queue.  The queue is
+    // reloaded at the start of every stage of kStage symbols with all eight
+    // loads in flight at once, so the decode loop itself never waits on
+    // memory unless a stage needs more than 8 words (long codes).
+    uint64_t wp = w0;          // next word not yet shifted into the bit buffer
+    uint64_t buf = 0;          // next bits, most significant first
+    int nb = 0;
+    const int rows_per_pass = kDecChunks * kStage;
+    for (int k0 = 0; k0 < C; k0 += kStage) {
+        uint32_t q0, q1, q2, q3, q4, q5, q6, q7;
+        q0 = wp + 0 < wend ? words[wp + 0] : 0u;
+        q1 = wp + 1 < wend ? words[wp + 1] : 0u;
+        q2 = wp + 2 < wend ? words[wp + 2] : 0u;
+        q3 = wp + 3 < wend ? words[wp + 3] : 0u;
+        q4 = wp + 4 < wend ? words[wp + 4] : 0u;
+        q5 = wp + 5 < wend ? words[wp + 5] : 0u;
+        q6 = wp + 6 < wend ? words[wp + 6] : 0u;
+        q7 = wp + 7 < wend ? words[wp + 7] : 0u;
+        int qn = 8;
+        for (int k = 0; k < kStage; ++k) {
+            if (k0 + k >= cnt) break;
+            if (nb <= 32) {
+                uint32_t nxt;
+                if (qn > 0) {
+                    nxt = q0;
+                    q0 = q1; q1 = q2; q2 = q3; q3 = q4; q4 = q5; q5 = q6; q6 = q7;
+                    --qn;
+                } else {
+                    nxt = wp < wend ? words[wp] : 0u;   // more than 8 words in one stage
+                }
+                ++wp;
+                buf |= (uint64_t)nxt << (32 - nb);
+                nb += 32;
+            }
+            const uint32_t e = tab[buf >> (64 - kLutBits)];
+            uint32_t len = e >> 16, sym = e & 0xFFFFu;
+            if (len == 0) {
+                for (int l = kLutBits + 1; l <= kLmax; ++l) {
+                    const uint32_t code = (uint32_t)(buf >> (64 - l));
+                    const uint32_t rel = code - tab[kDtFirst + l];
+                    if (rel < tab[kDtCount + l]) {
+                        sym = tab[kDtSorted + tab[kDtOffset + l] + rel];
+                        len = l;
+                        break;
+                    }
+                }
+                if (len == 0) len = 1;   // corrupt stream: consume a bit and go on
+            }
+            stage[tid * kStageRow + k] = (uint16_t)sym;
+            buf <<= len;
+            nb -= (int)len;
+        }
+        // wp counts the words shifted into the bit buffer: the words left in
+        // the queue are reloaded by the next stage
+        __syncthreads();
+        // write the staged rows: row r holds kStage symbols of chunk first + r
+        const uint32_t* st32 = reinterpret_cast<const uint32_t*>(stage);
+        for (int e = tid; e < rows_per_pass / 2; e += kDecChunks) {
+            const int r = e / (kStage / 2), c2 = e % (kStage / 2);
+            const uint64_t chr = first + r;
+            if (chr >= fd.nchunks) continue;
+            const uint64_t sb = chr * (uint64_t)C + k0 + 2 * c2;
+            const int se = r * kStageRow + 2 * c2;   // staged symbol index
+            if (sb + 1 < fd.npts && ((sb & 1) == 0)) {
+                *reinterpret_cast<SZI_G uint32_t*>(gp(fd.codes) + sb) = st32[se / 2];
+            } else {
+                if (sb < fd.npts) gp(fd.codes)[sb] = stage[se];
+                if (sb + 1 < fd.npts) gp(fd.codes)[sb + 1] = stage[se + 1];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scatter_outliers(const FieldDesc* __restrict__ F) {
+    const FieldDesc& fd = F[blockIdx.y];
+    const uint64_t n = fd.npts;
+    const uint64_t no = fd.n_outliers;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < no;
+         k += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t idx = gp(fd.outlier_idx)[k];
+        if (idx < n) gp(fd.out)[idx] = gp(fd.outlier_val)[k];
+    }
+}
+
+// ------------------------------------------------------- launchers
+hipError_t launch_huff_stats(const FieldDesc* d_fields, int nfields, const uint64_t* d_boff,
+                             uint64_t nblocks, int chunk, uint32_t* d_cwords, uint32_t* d_couts,
+                             uint32_t* d_bw, uint32_t* d_bo, int max_nsym, hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    const size_t lds = (size_t)max_nsym * sizeof(uint32_t);
+    const dim3 g((unsigned)nblocks), b(256);
+    switch (chunk) {
+    case 256: hipLaunchKernelGGL(k_huff_stats<4>, g, b, lds, st, d_fields, nfields, d_boff, d_cwords, d_couts, d_bw, d_bo); break;
+    case 512: hipLaunchKernelGGL(k_huff_stats<8>, g, b, lds, st, d_fields, nfields, d_boff, d_cwords, d_couts, d_bw, d_bo); break;
+    case 1024: hipLaunchKernelGGL(k_huff_stats<16>, g, b, lds, st, d_fields, nfields, d_boff, d_cwords, d_couts, d_bw, d_bo); break;
+    case 2048: hipLaunchKernelGGL(k_huff_stats<32>, g, b, lds, st, d_fields, nfields, d_boff, d_cwords, d_couts, d_bw, d_bo); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_blocks(const uint32_t* d_a, const uint32_t* d_b, uint64_t n,
+                              uint64_t* d_aoff, uint64_t* d_boff, hipStream_t st) {
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, d_a, d_b, n, d_aoff, d_boff);
+    return hipGetLastError();
+}
+
+hipError_t launch_huff_encode(const FieldDesc* d_fields, int nfields, const uint64_t* d_boff,
+                              uint64_t nblocks, int chunk, const uint32_t* d_cwords,
+                              const uint32_t* d_couts, const uint64_t* d_bwoff,
+                              const uint64_t* d_booff, int max_nsym, hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    const int mcw = (chunk * kLmax + 31) / 32 + 1;
+    const size_t lds = ((size_t)max_nsym + 4 * (size_t)mcw) * sizeof(uint32_t);
+    const dim3 g((unsigned)nblocks), b(256);
+    switch (chunk) {
+    case 256: hipLaunchKernelGGL(k_huff_encode<4>, g, b, lds, st, d_fields, nfields, d_boff, d_cwords, d_couts, d_bwoff, d_booff); break;
+    case 512: hipLaunchKernelGGL(k_huff_encode<8>, g, b, lds, st, d_fields, nfields, d_boff, d_cwords, d_couts, d_bwoff, d_booff); break;
+    case 1024: hipLaunchKernelGGL(k_huff_encode<16>, g, b, lds, st, d_fields, nfields, d_boff, d_cwords, d_couts, d_bwoff, d_booff); break;
+    case 2048: hipLaunchKernelGGL(k_huff_encode<32>, g, b, lds, st, d_fields, nfields, d_boff, d_cwords, d_couts, d_bwoff, d_booff); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_words(const FieldDesc* d_fields, int nfields, const uint64_t* d_dboff,
+                              uint64_t nblocks, uint32_t* d_bsum, hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chunk_words, dim3((unsigned)nblocks), dim3(kDecChunks), 0, st, d_fields,
+                       nfields, d_dboff, d_bsum);
+    return hipGetLastError();
+}
+
+hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields, const uint64_t* d_dboff,
+                              uint64_t nblocks, const uint64_t* d_bwoff, int max_nsym,
+                              hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    const size_t lds = (size_t)(dtab_words(max_nsym) + kDecChunks) * sizeof(uint32_t) +
+                       (size_t)kDecChunks * kStageRow * sizeof(uint16_t);
+    hipLaunchKernelGGL(k_huff_decode, dim3((unsigned)nblocks), dim3(kDecChunks), lds, st,
+                       d_fields, nfields, d_dboff, d_bwoff);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_outliers(const FieldDesc* d_fields, int nfields, hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter_outliers, dim3(256, nfields), dim3(256), 0, st, d_fields);
+    return hipGetLastError();
+}
+
+}  // namespace szi

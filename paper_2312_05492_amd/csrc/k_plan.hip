@@ -1,0 +1,276 @@
+// k_plan.hip -- value range, sampled spline profiling and the FP64 plan
+// (Sec. V-C.1, Eq. 1, Sec. V-B.2, Sec. V-C.2) on gfx950.
+#include "dev_common.h"
+
+namespace szi {
+
+// ------------------------------------------------------- value range
+// Partial min / max / non-finite counts: kRangeBlocks blocks per field.
+__global__ __launch_bounds__(256) void k_range(const FieldDesc* __restrict__ F, float* pmin,
+                                               float* pmax, uint32_t* pbad) {
+    const FieldDesc& f = F[blockIdx.y];
+    const SZI_G float* in = gp(f.in);
+    const uint64_t n = f.npts;
+    float mn = INFINITY, mx = -INFINITY;
+    uint32_t bad = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t head = 0;
+    if ((reinterpret_cast<uintptr_t>(in) & 15) == 0) {
+        const SZI_G vf4* in4 = reinterpret_cast<const SZI_G vf4*>(in);
+        const uint64_t n4 = n / 4;
+        uint64_t i = tid;
+        for (; i + 3 * stride < n4; i += 4 * stride) {
+            const vf4 a = in4[i], b = in4[i + stride], c = in4[i + 2 * stride], d = in4[i + 3 * stride];
+            float vv[16] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w,
+                            c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w};
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                mn = fminf(mn, vv[k]);
+                mx = fmaxf(mx, vv[k]);
+                bad += finite_bits(vv[k]) ? 0u : 1u;
+            }
+        }
+        for (; i < n4; i += stride) {
+            const vf4 a = in4[i];
+            float vv[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                mn = fminf(mn, vv[k]);
+                mx = fmaxf(mx, vv[k]);
+                bad += finite_bits(vv[k]) ? 0u : 1u;
+            }
+        }
+        head = n4 * 4;
+    }
+    for (uint64_t i = head + tid; i < n; i += stride) {
+        float v = in[i];
+        mn = fminf(mn, v);
+        mx = fmaxf(mx, v);
+        bad += finite_bits(v) ? 0u : 1u;
+    }
+    __shared__ float smn[4], smx[4];
+    __shared__ uint32_t sbad[4];
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    bad = wave_sum(bad);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        smn[w] = mn;
+        smx[w] = mx;
+        sbad[w] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 4; ++k) {
+            mn = fminf(mn, smn[k]);
+            mx = fmaxf(mx, smx[k]);
+            bad += sbad[k];
+        }
+        const uint64_t o = (uint64_t)blockIdx.y * gridDim.x + blockIdx.x;
+        pmin[o] = mn;
+        pmax[o] = mx;
+        pbad[o] = bad;
+    }
+}
+
+// ------------------------------------------------------- profiling
+// Sec. V-C.1: a uniform 4^D sub-grid of samples; at each, the linear and
+// both cubic splines along every dimension on original values (stride 1);
+// L1 errors accumulated in FP64 in ascending sample order.
+__device__ __forceinline__ int sample_pos(int nd, int t) {
+    int v = (int)(((int64_t)(2 * t + 1) * nd) / 8);
+    if (nd >= 7) {
+        v = v < 3 ? 3 : v;
+        v = v > nd - 4 ? nd - 4 : v;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(64) void k_profile(const FieldDesc* __restrict__ F, FieldPlan* P) {
+    const FieldDesc& f = F[blockIdx.x];
+    __shared__ double err[64][3][3];
+    const int t = threadIdx.x;
+    const int D = f.ndim;
+    const int ns = D == 3 ? 64 : 16;
+    for (int d = 0; d < 3; ++d)
+        for (int k = 0; k < 3; ++k) err[t][d][k] = 0.0;
+    if (f.need_prof && t < ns) {
+        int c[3];
+        c[0] = sample_pos(f.n[0], t & 3);
+        c[1] = sample_pos(f.n[1], (t >> 2) & 3);
+        c[2] = D == 3 ? sample_pos(f.n[2], t >> 4) : 0;
+        const int64_t st[3] = {1, f.n[0], (int64_t)f.n[0] * f.n[1]};
+        const int64_t gi = c[0] + st[1] * c[1] + st[2] * c[2];
+        const SZI_G float* in = gp(f.in);
+        const float x = in[gi];
+        for (int d = 0; d < D; ++d) {
+            if (f.n[d] < 7) continue;
+            const float a = in[gi - 3 * st[d]], b = in[gi - st[d]];
+            const float cc = in[gi + st[d]], dd = in[gi + 3 * st[d]];
+            const float pl = (b + cc) * 0.5f;
+            const float pk = (9.0f * (b + cc) - (a + dd)) * 0.0625f;
+            const float pn = (23.0f * (b + cc) - 3.0f * (a + dd)) / 40.0f;
+            err[t][d][0] = fabs((double)x - (double)pl);
+            err[t][d][1] = fabs((double)x - (double)pk);
+            err[t][d][2] = fabs((double)x - (double)pn);
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        double s[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        if (f.need_prof)
+            for (int k = 0; k < ns; ++k)
+                for (int d = 0; d < D; ++d)
+                    if (f.n[d] >= 7)
+                        for (int e = 0; e < 3; ++e) s[d][e] = s[d][e] + err[k][d][e];
+        for (int d = 0; d < 3; ++d)
+            for (int e = 0; e < 3; ++e) P[blockIdx.x].prof[d][e] = s[d][e];
+    }
+}
+
+// ------------------------------------------------------- plan
+// Sec. V-C.1 (absolute/relative bound from the range), Eq. 1 (alpha),
+// Sec. V-B.2 (level bounds), Sec. V-C.2 (spline per dimension, order).
+__device__ double eq1_alpha(double eps) {
+    if (eps >= 1e-1) return 2.0;
+    if (eps >= 1e-2) return 1.75 + 0.25 * (eps - 1e-2) / (1e-1 - 1e-2);
+    if (eps >= 1e-3) return 1.5 + 0.25 * (eps - 1e-3) / (1e-2 - 1e-3);
+    if (eps >= 1e-4) return 1.25 + 0.25 * (eps - 1e-4) / (1e-3 - 1e-4);
+    if (eps >= 1e-5) return 1.0 + 0.25 * (eps - 1e-5) / (1e-4 - 1e-5);
+    return 1.0;
+}
+
+// largest float not above v (v >= 0)
+__device__ float floor_to_f32(double v) {
+    if (!(v > 0.0)) return 0.0f;
+    if (v >= (double)FLT_MAX) return FLT_MAX;
+    float f = (float)v;
+    if ((double)f > v) f = __uint_as_float(__float_as_uint(f) - 1u);
+    return f;
+}
+
+__global__ __launch_bounds__(256) void k_plan(const FieldDesc* __restrict__ F, FieldPlan* P,
+                                              const float* pmin, const float* pmax,
+                                              const uint32_t* pbad) {
+    const FieldDesc& f = F[blockIdx.x];
+    FieldPlan& p = P[blockIdx.x];
+    float mn = INFINITY, mx = -INFINITY;
+    uint32_t bad = 0;
+    for (int i = threadIdx.x; i < kRangeBlocks; i += blockDim.x) {
+        const uint64_t o = (uint64_t)blockIdx.x * kRangeBlocks + i;
+        mn = fminf(mn, pmin[o]);
+        mx = fmaxf(mx, pmax[o]);
+        bad += pbad[o];
+    }
+    __shared__ float smn[4], smx[4];
+    __shared__ uint32_t sbad[4];
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    bad = wave_sum(bad);
+    if ((threadIdx.x & 63) == 0) {
+        smn[threadIdx.x >> 6] = mn;
+        smx[threadIdx.x >> 6] = mx;
+        sbad[threadIdx.x >> 6] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int k = 1; k < 4; ++k) {
+        mn = fminf(mn, smn[k]);
+        mx = fmaxf(mx, smx[k]);
+        bad += sbad[k];
+    }
+    p.vmin = mn + 0.0f;
+    p.vmax = mx + 0.0f;
+    p.nonfinite = bad;
+    p.status = bad ? -2 : 0;
+    p.range = (double)p.vmax - (double)p.vmin;
+    if (f.eb_mode == 1) {
+        p.eps = f.eb;
+        p.e_abs = f.eb * p.range;
+    } else {
+        p.e_abs = f.eb;
+        p.eps = p.range > 0.0 ? f.eb / p.range : (f.eb > 0.0 ? INFINITY : 0.0);
+    }
+    p.e = floor_to_f32(p.e_abs);
+    p.alpha = f.alpha_req > 0.0 ? f.alpha_req : eq1_alpha(p.eps);
+    p.levels = f.L;
+    double apow = 1.0;
+    for (int l = 0; l < kMaxLevels; ++l) {
+        if (l < f.L) {
+            p.el[l] = floor_to_f32(p.e_abs / apow);
+            p.ebx2[l] = 2.0f * p.el[l];
+            p.inv[l] = 1.0f / p.ebx2[l];
+            apow = apow * p.alpha;
+        } else {
+            p.el[l] = 0.0f;
+            p.ebx2[l] = 0.0f;
+            p.inv[l] = 0.0f;
+        }
+    }
+    const int D = f.ndim;
+    double score[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < 3; ++d) {
+        int s = d < D ? f.interp[d] : SPL_LIN;
+        if (s == SPL_AUTO) s = p.prof[d][2] < p.prof[d][1] ? SPL_NAT : SPL_NAK;
+        p.spline[d] = s;
+        score[d] = p.prof[d][s];
+    }
+    if (f.order_req[0] >= 0) {
+        for (int k = 0; k < 3; ++k) p.order[k] = k < D ? f.order_req[k] : -1;
+    } else {
+        // least smooth first; a strictly larger error wins, else the slower
+        bool used[3] = {false, false, false};
+        for (int k = 0; k < 3; ++k) {
+            if (k >= D) {
+                p.order[k] = -1;
+                continue;
+            }
+            int best = -1;
+            for (int d = D - 1; d >= 0; --d) {
+                if (used[d]) continue;
+                if (best < 0 || score[d] > score[best]) best = d;
+            }
+            used[best] = true;
+            p.order[k] = best;
+        }
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ------------------------------------------------------- launchers
+hipError_t launch_range(const FieldDesc* d_fields, int nfields, float* d_part_min,
+                        float* d_part_max, uint32_t* d_part_bad, hipStream_t st) {
+    hipLaunchKernelGGL(k_range, dim3(kRangeBlocks, nfields), dim3(256), 0, st, d_fields,
+                       d_part_min, d_part_max, d_part_bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_profile(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_profile, dim3(nfields), dim3(64), 0, st, d_fields, d_plans);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
+                       const float* d_part_min, const float* d_part_max,
+                       const uint32_t* d_part_bad, hipStream_t st) {
+    hipLaunchKernelGGL(k_plan, dim3(nfields), dim3(256), 0, st, d_fields, d_plans, d_part_min,
+                       d_part_max, d_part_bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace szi

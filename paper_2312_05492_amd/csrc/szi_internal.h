@@ -13,6 +13,8 @@ constexpr int kLutBits = 10;       // decode look-up table width
 constexpr int kMaxRadius = 1024;   // LDS histogram holds 2R <= 2048 bins
 constexpr int kRangeBlocks = 1024; // partial min/max blocks per field
 constexpr int kThreads = 256;      // threads per interpolation workgroup
+constexpr int kEncBlockChunks = 16;   // Huffman chunks per encode workgroup
+constexpr int kDecBlockChunks = 256;  // Huffman chunks per decode workgroup
 
 // Static description of one field, written by the host before launch.
 struct FieldDesc {
@@ -65,6 +67,22 @@ struct FieldPlan {
     double prof[3][3];     // [dim][linear, NAK, natural] L1 errors
 };
 
+// Pass tables of a full window (block extents W+1 in every dimension): for
+// every processing order, the block points of each pass, i0 fastest.
+// Entry: u16 = li | m3 << 12 | p3 << 13 (li the LDS index, m3/p3 whether the
+// neighbours at -3s/+3s along the pass dimension lie in the window; the one
+// at +s always does in a full window).  Meta per order: offset and count of
+// each pass, passes numbered (L - lvl) * ND + k.  Within a pass the points
+// with all four neighbours (a cubic stencil) come first.
+constexpr int kMaxPasses = 9;
+struct PassMeta {
+    uint32_t off[kMaxPasses];
+    uint32_t cnt[kMaxPasses];
+    uint32_t ncub[kMaxPasses];   // leading entries with all four neighbours
+};
+// order id: 3D 2*o0 + (o1 > o2), 2D o0
+constexpr int kPerm3 = 6, kPerm2 = 2;
+
 // Decode tables, one u32 array per field:
 //   [0, 1<<kLutBits)           LUT: len << 16 | symbol (len 0 = longer code)
 //   first[kLmax+1], count[kLmax+1], offset[kLmax+1]
@@ -86,27 +104,26 @@ hipError_t launch_plan(const FieldDesc* d_fields, FieldPlan* d_plans, int nfield
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_compress(int ndim, const FieldDesc* d_fields, const FieldPlan* d_plans,
                            int nfields, const uint64_t* d_item_off, uint64_t nitems,
-                           int grid, int max_R, hipStream_t st);
+                           const uint16_t* d_ptab, const PassMeta* d_pmeta, int num_cus,
+                           int per_cu, int max_R, hipStream_t st);
 hipError_t launch_decompress(int ndim, const FieldDesc* d_fields, const FieldPlan* d_plans,
                              int nfields, const uint64_t* d_item_off, uint64_t nitems,
-                             int grid, hipStream_t st);
-hipError_t launch_huff_stats(const FieldDesc* d_fields, int nfields,
-                             const uint64_t* d_chunk_off, uint64_t nchunks_total,
-                             uint32_t* d_cwords, uint32_t* d_couts, int max_nsym,
-                             hipStream_t st);
-hipError_t launch_scan_pairs(const uint32_t* d_a, const uint32_t* d_b, uint64_t n,
-                             const uint64_t* d_seg_start, int nseg, uint64_t* d_aoff,
-                             uint64_t* d_boff, uint64_t* d_totals, hipStream_t st);
-hipError_t launch_huff_encode(const FieldDesc* d_fields, int nfields,
-                              const uint64_t* d_chunk_off, uint64_t nchunks_total,
-                              const uint64_t* d_word_off, const uint64_t* d_out_off,
-                              int max_nsym, int max_chunk, hipStream_t st);
-hipError_t launch_scan_words(const FieldDesc* d_fields, int nfields,
-                             const uint64_t* d_chunk_off, uint64_t nchunks_total,
-                             uint32_t* d_tmp, uint64_t* d_word_off, hipStream_t st);
-hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields,
-                              const uint64_t* d_chunk_off, uint64_t nchunks_total,
-                              const uint64_t* d_word_off, int max_nsym, hipStream_t st);
+                             const uint16_t* d_ptab, const PassMeta* d_pmeta, int num_cus,
+                             int per_cu, hipStream_t st);
+hipError_t launch_huff_stats(const FieldDesc* d_fields, int nfields, const uint64_t* d_boff,
+                             uint64_t nblocks, int chunk, uint32_t* d_cwords, uint32_t* d_couts,
+                             uint32_t* d_bw, uint32_t* d_bo, int max_nsym, hipStream_t st);
+hipError_t launch_scan_blocks(const uint32_t* d_a, const uint32_t* d_b, uint64_t n,
+                              uint64_t* d_aoff, uint64_t* d_boff, hipStream_t st);
+hipError_t launch_huff_encode(const FieldDesc* d_fields, int nfields, const uint64_t* d_boff,
+                              uint64_t nblocks, int chunk, const uint32_t* d_cwords,
+                              const uint32_t* d_couts, const uint64_t* d_bwoff,
+                              const uint64_t* d_booff, int max_nsym, hipStream_t st);
+hipError_t launch_chunk_words(const FieldDesc* d_fields, int nfields, const uint64_t* d_dboff,
+                              uint64_t nblocks, uint32_t* d_bsum, hipStream_t st);
+hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields, const uint64_t* d_dboff,
+                              uint64_t nblocks, const uint64_t* d_bwoff, int max_nsym,
+                              hipStream_t st);
 hipError_t launch_scatter_outliers(const FieldDesc* d_fields, int nfields, hipStream_t st);
 
 }  // namespace szi
