@@ -31,8 +31,6 @@ struct sz_ctx {
     void* pinned = nullptr;    // host staging buffer
     size_t pinned_bytes = 0;
     int grid_per_cu = 0;       // persistent workgroups per CU; 0 = resident capacity
-    uint16_t* d_ptab[2] = {nullptr, nullptr};     // pass tables, 3D and 2D
-    PassMeta* d_pmeta[2] = {nullptr, nullptr};
     // stage timing
     bool timing = false;
     std::vector<hipEvent_t> ev_free;
@@ -216,80 +214,6 @@ struct Scratch {
         return SZ_OK;
     }
 };
-
-// ------------------------------------------------------------ pass tables
-// For every processing order of a full window, the block points of each pass
-// (Sec. V-A: levels from stride S/2 to 1, one pass per dimension in order).
-void build_pass_table(int nd, std::vector<uint16_t>& ent, std::vector<PassMeta>& meta) {
-    const int W[3] = {nd == 3 ? 32 : 64, nd == 3 ? 8 : 16, nd == 3 ? 8 : 0};
-    const int B[3] = {W[0] + 1, W[1] + 1, nd == 3 ? W[2] + 1 : 1};
-    const int L = nd == 3 ? 3 : 4;
-    const int nperm = nd == 3 ? kPerm3 : kPerm2;
-    for (int id = 0; id < nperm; ++id) {
-        int order[3];
-        if (nd == 3) {
-            order[0] = id / 2;
-            const int r0 = order[0] == 0 ? 1 : 0, r1 = order[0] == 2 ? 1 : 2;   // the others, ascending
-            order[1] = (id & 1) ? r1 : r0;
-            order[2] = (id & 1) ? r0 : r1;
-        } else {
-            order[0] = id;
-            order[1] = 1 - id;
-            order[2] = -1;
-        }
-        PassMeta m;
-        std::memset(&m, 0, sizeof m);
-        int pass = 0;
-        for (int lvl = L; lvl >= 1; --lvl) {
-            const int sp = 1 << (lvl - 1);
-            for (int k = 0; k < nd; ++k, ++pass) {
-                const int d = order[k];
-                m.off[pass] = (uint32_t)ent.size();
-                std::vector<uint16_t> edge;   // points without a full cubic stencil
-                for (int c2 = 0; c2 < B[2]; ++c2)
-                    for (int c1 = 0; c1 < B[1]; ++c1)
-                        for (int c0 = 0; c0 < B[0]; ++c0) {
-                            const int c[3] = {c0, c1, c2};
-                            bool in = true;
-                            for (int kk = 0; kk < nd; ++kk) {
-                                const int j = order[kk];
-                                if (kk == k) in = in && c[j] % (2 * sp) == sp;
-                                else if (kk < k) in = in && c[j] % sp == 0;
-                                else in = in && c[j] % (2 * sp) == 0;
-                            }
-                            if (!in) continue;
-                            const int li = c0 + B[0] * (c1 + B[1] * c2);
-                            const int cd = c[d];
-                            const int m3 = cd >= 3 * sp, p3 = cd + 3 * sp <= W[d];
-                            const uint16_t e = (uint16_t)(li | (m3 << 12) | (p3 << 13));
-                            if (m3 && p3) ent.push_back(e);
-                            else edge.push_back(e);
-                        }
-                m.ncub[pass] = (uint32_t)ent.size() - m.off[pass];
-                ent.insert(ent.end(), edge.begin(), edge.end());
-                m.cnt[pass] = (uint32_t)ent.size() - m.off[pass];
-            }
-        }
-        meta.push_back(m);
-    }
-}
-
-sz_status ensure_tables(sz_ctx* c) {
-    for (int t = 0; t < 2; ++t) {
-        if (c->d_ptab[t]) continue;
-        std::vector<uint16_t> ent;
-        std::vector<PassMeta> meta;
-        build_pass_table(t == 0 ? 3 : 2, ent, meta);
-        void *pe = nullptr, *pm = nullptr;
-        HIP_TRY(c, hipMalloc(&pe, ent.size() * sizeof(uint16_t)));
-        HIP_TRY(c, hipMalloc(&pm, meta.size() * sizeof(PassMeta)));
-        HIP_TRY(c, hipMemcpy(pe, ent.data(), ent.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
-        HIP_TRY(c, hipMemcpy(pm, meta.data(), meta.size() * sizeof(PassMeta), hipMemcpyHostToDevice));
-        c->d_ptab[t] = static_cast<uint16_t*>(pe);
-        c->d_pmeta[t] = static_cast<PassMeta*>(pm);
-    }
-    return SZ_OK;
-}
 
 // ------------------------------------------------------------ CRC-32 (IEEE)
 uint32_t crc32_update(uint32_t crc, const uint8_t* p, size_t n) {
@@ -517,6 +441,13 @@ sz_status check_field(sz_ctx* c, const sz_dims* d, const sz_params* p, Geometry&
         g.nwin_total *= g.nwin[k];
         g.nanch *= g.na[k];
     }
+    // the window kernels address a block by 32-bit byte offsets from its
+    // origin and number windows with 32-bit integers
+    const uint64_t span = (uint64_t)g.w[0] + (uint64_t)g.w[1] * (uint64_t)g.n[0] +
+                          (g.ndim == 3 ? (uint64_t)g.w[2] * (uint64_t)g.n[0] * (uint64_t)g.n[1] : 0);
+    if (span * sizeof(float) >= (1ull << 32) || g.nwin_total >= (1ull << 31))
+        return fail(c, SZ_ERR_UNSUPPORTED, "field planes too large (window span %llu points)",
+                    (unsigned long long)span);
     g.nchunks = (npts + g.chunk - 1) / g.chunk;
     return SZ_OK;
 }
@@ -641,10 +572,6 @@ sz_status sz_ctx_destroy(sz_ctx* c) {
     if (!c) return SZ_OK;
     (void)hipSetDevice(c->device);
     for (auto& kv : c->block_size) (void)hipFree(kv.first);
-    for (int t = 0; t < 2; ++t) {
-        if (c->d_ptab[t]) (void)hipFree(c->d_ptab[t]);
-        if (c->d_pmeta[t]) (void)hipFree(c->d_pmeta[t]);
-    }
     for (auto& m : c->marks) {
         (void)hipEventDestroy(m.a);
         (void)hipEventDestroy(m.b);
@@ -697,10 +624,6 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
     HIP_TRY(c, hipSetDevice(c->device));
     MarkGuard mark_guard{c};
     hipStream_t st = static_cast<hipStream_t>(stream);
-    {
-        sz_status ts = ensure_tables(c);
-        if (ts) return ts;
-    }
     std::vector<Geometry> geo(nf);
     std::vector<FieldDesc> fd(nf);
     for (uint32_t i = 0; i < nf; ++i) {
@@ -787,7 +710,7 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
             uint64_t* io = items.data() + gi * (nf + 1);
             io[0] = 0;
             for (size_t j = 0; j < grp[gi].size(); ++j, ++k)
-                io[j + 1] = io[j] + geo[grp[gi][j]].nwin_total;
+                io[j + 1] = io[j] + (geo[grp[gi][j]].nwin_total + kWinPerGroup - 1) / kWinPerGroup;
             nitems[gi] = grp[gi].empty() ? 0 : io[grp[gi].size()];
         }
     }
@@ -818,8 +741,7 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
             if (!grp[gi].empty()) {
                 STAGE(c, SZ_STAGE_INTERP, st);
                 HIP_TRY(c, launch_compress(gi == 0 ? 3 : 2, d_fd + base, d_plan + base,
-                                           (int)grp[gi].size(), d_items + gi * (nf + 1),
-                                           nitems[gi], c->d_ptab[gi], c->d_pmeta[gi], c->num_cus,
+                                           d_items + gi * (nf + 1), nitems[gi], c->num_cus,
                                            c->grid_per_cu, max_R, st));
             }
             base += (uint32_t)grp[gi].size();
@@ -986,10 +908,6 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
     HIP_TRY(c, hipSetDevice(c->device));
     MarkGuard mark_guard{c};
     hipStream_t st = static_cast<hipStream_t>(stream);
-    {
-        sz_status ts = ensure_tables(c);
-        if (ts) return ts;
-    }
     Scratch sc(c);
     std::vector<FieldDesc> fds(nf);
     std::vector<FieldPlan> plans(nf);
@@ -1047,7 +965,8 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
     uint64_t nitems[2] = {0, 0};
     for (int gi = 0; gi < 2; ++gi) {
         uint64_t* io = items.data() + gi * (nf + 1);
-        for (size_t j = 0; j < grp[gi].size(); ++j) io[j + 1] = io[j] + geo[grp[gi][j]].nwin_total;
+        for (size_t j = 0; j < grp[gi].size(); ++j)
+            io[j + 1] = io[j] + (geo[grp[gi][j]].nwin_total + kWinPerGroup - 1) / kWinPerGroup;
         nitems[gi] = grp[gi].empty() ? 0 : io[grp[gi].size()];
     }
     const uint64_t nblocks = dboff[nf];
@@ -1082,8 +1001,7 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         if (!grp[gi].empty()) {
             STAGE(c, SZ_STAGE_REPLAY, st);
             HIP_TRY(c, launch_decompress(gi == 0 ? 3 : 2, d_fd + base, d_plan + base,
-                                         (int)grp[gi].size(), d_items + gi * (nf + 1), nitems[gi],
-                                         c->d_ptab[gi], c->d_pmeta[gi], c->num_cus,
+                                         d_items + gi * (nf + 1), nitems[gi], c->num_cus,
                                          c->grid_per_cu, st));
         }
         base += (uint32_t)grp[gi].size();

@@ -1,15 +1,22 @@
 // k_interp.hip -- the G-Interp predictor-quantiser (compression) and its
 // replay (decompression) on gfx950 (Sec. V-A, V-B, V-D; Sec. III-A).
 //
-// One window per iteration of a persistent workgroup of 4 wave64.  A window
-// owns the points [lo, lo + W) of each dimension; its block adds the far
-// faces (lo + W).  Neighbours are searched inside the point's own window
-// interval along the pass dimension only, so the faces shared by two windows
-// are computed identically by both and windows are independent.  Levels run
-// from stride S/2 to 1; at each level one pass per dimension in the planned
-// order, separated by workgroup barriers.  The block lives in LDS; a pass
-// reads neighbours and replaces values in place (points of one pass never
-// neighbour each other along the pass dimension).
+// One wave64 per window, kWaves windows per workgroup.  A window owns the
+// points [lo, lo + W) of each dimension; its block adds the far faces
+// (lo + W), which the next window owns.  Neighbours are searched inside the
+// point's own window interval along the pass dimension only, so a face point
+// is computed identically by both windows that hold it and windows are
+// independent.  A wave stages its block in LDS, runs the passes (levels from
+// stride S/2 down to 1, one pass per dimension in the planned order) without
+// any workgroup barrier, and writes out the points it owns.  The block of
+// the wave's next window is loaded into registers while the current one is
+// processed.
+//
+// A pass along dimension d at stride s works on lines: block points that
+// share every coordinate but d.  The targets of a line are its odd multiples
+// of s, its knowns the even ones.  A lane takes K consecutive targets of one
+// line, reads the K + 3 knowns around them once, and predicts all K; every
+// LDS offset along the line is a compile-time constant.
 //
 // Arithmetic: every FP32 expression is evaluated in the order written, one
 // rounding per operation (the library is built with -ffp-contract=off).
@@ -17,388 +24,528 @@
 
 namespace szi {
 
-constexpr int kLoadBatch = 11;  // global loads in flight per thread while staging a block
-
-template <int ND, int W0, int W1, int W2>
-struct Geom {
-    static constexpr int B0 = W0 + 1;
-    static constexpr int B1 = W1 + 1;
-    static constexpr int B2 = ND == 3 ? W2 + 1 : 1;
-    static constexpr int BN = B0 * B1 * B2;
-    static constexpr int O2 = ND == 3 ? W2 : 1;
-    static constexpr int OWN = W0 * W1 * O2;
-    static constexpr int PER = (BN + kThreads - 1) / kThreads;   // block points per thread
-};
-
-struct WinInfo {
-    int lo0, lo1, lo2;
-    int e0, e1, e2;      // block extents (own points + far face where present)
-    int o0, o1, o2;      // owned extents
-    bool full;
-    uint32_t gbase;      // linear index of the window origin
-};
-
-template <int ND, int W0, int W1, int W2>
-__device__ __forceinline__ void window_info(const FieldDesc& f, uint64_t w, WinInfo& wi) {
-    const uint32_t nw0 = (uint32_t)f.nwin[0], nw1 = (uint32_t)f.nwin[1];
-    const uint32_t wz = (uint32_t)(w / ((uint64_t)nw0 * nw1));
-    const uint32_t r = (uint32_t)(w - (uint64_t)wz * nw0 * nw1);
-    const uint32_t wy = r / nw0;
-    const uint32_t wx = r - wy * nw0;
-    wi.lo0 = (int)wx * W0;
-    wi.lo1 = (int)wy * W1;
-    wi.lo2 = ND == 3 ? (int)wz * W2 : 0;
-    const int s0 = f.n[0] - 1 - wi.lo0, s1 = f.n[1] - 1 - wi.lo1;
-    const int s2 = ND == 3 ? f.n[2] - 1 - wi.lo2 : 0;
-    wi.e0 = (s0 < W0 ? s0 : W0) + 1;
-    wi.e1 = (s1 < W1 ? s1 : W1) + 1;
-    wi.e2 = ND == 3 ? (s2 < W2 ? s2 : W2) + 1 : 1;
-    wi.o0 = wi.e0 < W0 ? wi.e0 : W0;
-    wi.o1 = wi.e1 < W1 ? wi.e1 : W1;
-    wi.o2 = ND == 3 ? (wi.e2 < W2 ? wi.e2 : W2) : 1;
-    wi.full = wi.e0 == W0 + 1 && wi.e1 == W1 + 1 && (ND == 2 || wi.e2 == W2 + 1);
-    wi.gbase = (uint32_t)wi.lo0 + (uint32_t)wi.lo1 * (uint32_t)f.n[0] +
-               (uint32_t)wi.lo2 * (uint32_t)f.n[0] * (uint32_t)f.n[1];
-}
-
-// The thread index, made opaque to the optimiser: per-thread offsets that
-// only depend on it would otherwise be hoisted out of the window loop and
-// held in registers for the whole kernel.
-__device__ __forceinline__ int opaque_tid() {
-    int t = threadIdx.x;
-    asm volatile("" : "+v"(t));
-    return t;
-}
-
-// Points of pass (level lvl, k-th dimension of the order): along the pass
-// dimension the odd multiples of s, along dimensions already passed at this
-// level the multiples of s, along those still to come the multiples of 2s
-// (s = 2^(lvl-1)).
-struct PassGrid {
-    int st0, st1, st2;
-    int sh0, sh1, sh2;
-    int m0, m1, m2;
-    uint32_t total;
-    FastDiv d0, d01;
-};
-
-__device__ __forceinline__ int order_pos(int o0, int o1, int j) {
-    return o0 == j ? 0 : (o1 == j ? 1 : 2);
-}
-
-__device__ __forceinline__ void pass_axis(int kj, int k, int lvl, int ext, int& st, int& sh,
-                                          int& m) {
-    st = kj == k ? (1 << (lvl - 1)) : 0;
-    sh = kj < k ? lvl - 1 : lvl;
-    m = ext > st ? ((ext - 1 - st) >> sh) + 1 : 0;
-}
+constexpr int kWaves = kWinPerGroup;    // windows in flight per workgroup, one per wave
+static_assert(kWaves * 64 == kThreads, "one wave per window of a group");
+constexpr int kPad = 8;                 // guard floats on both sides of a block in LDS
+constexpr int kXcds = 8;                // L2 domains; workgroup i runs on domain i % kXcds
 
 template <int ND>
-__device__ __forceinline__ void pass_grid(PassGrid& g, int o0, int o1, int k, int lvl, int e0,
-                                          int e1, int e2) {
-    pass_axis(order_pos(o0, o1, 0), k, lvl, e0, g.st0, g.sh0, g.m0);
-    pass_axis(order_pos(o0, o1, 1), k, lvl, e1, g.st1, g.sh1, g.m1);
-    if (ND == 3) {
-        pass_axis(order_pos(o0, o1, 2), k, lvl, e2, g.st2, g.sh2, g.m2);
-    } else {
-        g.st2 = 0;
-        g.sh2 = 0;
-        g.m2 = 1;
-    }
-    g.total = (uint32_t)(g.m0 * g.m1 * g.m2);
-    g.d0.set((uint32_t)g.m0);
-    g.d01.set((uint32_t)(g.m0 * g.m1));
-}
+struct Geo;
+template <>
+struct Geo<3> {
+    static constexpr int W0 = 32, W1 = 8, W2 = 8;   // window
+    static constexpr int B0 = 33, B1 = 9, B2 = 9;   // block (window + far faces)
+    static constexpr int SY = 33, SZ = 297;         // LDS strides
+    static constexpr int BN = B0 * B1 * B2;
+    static constexpr int SHS = 3;                   // log2 of the anchor stride
+    static constexpr int NPRE = 43;                 // block values per lane
+    static constexpr int NANCH = 20;                // anchors in a block
+};
+template <>
+struct Geo<2> {
+    static constexpr int W0 = 64, W1 = 16, W2 = 1;
+    static constexpr int B0 = 65, B1 = 17, B2 = 1;
+    static constexpr int SY = 65, SZ = 0;
+    static constexpr int BN = B0 * B1;
+    static constexpr int SHS = 4;
+    static constexpr int NPRE = 18;
+    static constexpr int NANCH = 10;
+};
+template <int ND>
+constexpr int vlen() { return kPad + Geo<ND>::BN + kPad; }
+template <int ND>
+constexpr int qlen() { return (Geo<ND>::BN + 2) & ~1; }
 
-// Sec. V-B.1 splines by neighbour availability.  b is always present; a,
-// c, d are read from clamped addresses (their own point when absent) and
-// then ignored.  spl is uniform across the pass.
-__device__ __forceinline__ float predict(int spl, bool m3, bool p1, bool p3, float a, float b,
-                                         float c, float d) {
-    const float sbc = b + c;
-    float p = sbc * 0.5f;                          // linear
-    if (spl != SPL_LIN) {
-        // quadratic: (-1/8, 6/8, 3/8) on (a, b, c) or (3/8, 6/8, -1/8) on (b, c, d)
-        const float wb = m3 ? 6.0f : 3.0f, wc = m3 ? 3.0f : 6.0f;
-        const float e = m3 ? a : d;
-        const float pq = ((wb * b + wc * c) - e) * 0.125f;
-        const float sad = a + d;
-        float pc;
-        if (spl == SPL_NAT)
-            pc = (23.0f * sbc - 3.0f * sad) / 40.0f;   // natural cubic
-        else
-            pc = (9.0f * sbc - sad) * 0.0625f;         // not-a-knot cubic
-        p = (m3 && p3) ? pc : ((m3 || p3) ? pq : p);
-    }
-    return p1 ? p : b;                             // one neighbour: x[n-1]
-}
-
-// One point of a pass: the prediction along the pass dimension, then
-// either the closed-loop quantisation (compression) or the replay.
-template <bool COMP>
-__device__ __forceinline__ void point(float* v, uint16_t* q, int li, bool m3, bool p1, bool p3,
-                                      int s1, int s3, int spl, float el, float ebx2, float inv,
-                                      float Rf, double eld, int R) {
-    const float b = v[li - s1];
-    const float c = v[p1 ? li + s1 : li];
-    const float a = v[m3 ? li - s3 : li];
-    const float dd = v[p3 ? li + s3 : li];
-    const float p = predict(spl, m3, p1, p3, a, b, c, dd);
-    if (COMP) {
-        const float x = v[li];
-        const float diff = x - p;
-        bool outl;
-        float qr = 0.0f;
-        float xr = p;
-        if (el == 0.0f) {   // uniform: keep exact predictions only
-            outl = !(diff == 0.0f);
-        } else {
-            const float qf = diff * inv;
-            qr = rintf(qf);                            // round half to even
-            // |rint(qf)| < R is equivalent to |qf| < R and |q| < R (R is an
-            // integer); NaN and Inf fail it
-            outl = !(fabsf(qr) < Rf);
-            xr = p + qr * ebx2;                        // qr is an exact small integer
-            outl = outl || !(fabs((double)x - (double)xr) <= eld);
-        }
-        v[li] = outl ? x : xr;
-        q[li] = outl ? (uint16_t)0 : (uint16_t)((int)qr + R);
-    } else {
-        const int code = q[li];
-        if (code != 0) v[li] = p + (float)(code - R) * ebx2;
-    }
-}
-
-// pass over the points of one (level, dimension) of a partial window
-template <int ND, class G, bool COMP>
-__device__ __forceinline__ void run_pass(float* v, uint16_t* q, const PassGrid& g, int d, int s,
-                                         int ed, int spl, float el, float ebx2, float inv,
-                                         int R) {
-    const int sd = d == 0 ? 1 : (d == 1 ? G::B0 : G::B0 * G::B1);
-    const int s1 = s * sd, s3 = 3 * s * sd;
-    const float Rf = (float)R;
-    const double eld = (double)el;
-    for (uint32_t t = opaque_tid(); t < g.total; t += kThreads) {
-        const uint32_t i2 = g.d01.div(t);
-        const uint32_t r = t - i2 * g.d01.m;
-        const uint32_t i1 = g.d0.div(r);
-        const uint32_t i0 = r - i1 * g.d0.m;
-        const int c0 = g.st0 + ((int)i0 << g.sh0);
-        const int c1 = g.st1 + ((int)i1 << g.sh1);
-        const int c2 = g.st2 + ((int)i2 << g.sh2);
-        const int li = c0 + G::B0 * (c1 + G::B1 * c2);
-        const int cd = d == 0 ? c0 : (d == 1 ? c1 : c2);
-        point<COMP>(v, q, li, cd >= 3 * s, cd + s < ed, cd + 3 * s < ed, s1, s3, spl, el, ebx2,
-                    inv, Rf, eld, R);
-    }
-}
-
-// pass over the points of one (level, dimension) of a full window, listed
-// in the pass table (LDS)
-template <int ND, class G, bool COMP>
-__device__ __forceinline__ void run_pass_tab(float* v, uint16_t* q, const uint16_t* ptab,
-                                             uint32_t off, uint32_t cnt, uint32_t ncub, int d,
-                                             int s, int spl, float el, float ebx2, float inv,
-                                             int R) {
-    const int sd = d == 0 ? 1 : (d == 1 ? G::B0 : G::B0 * G::B1);
-    const int s1 = s * sd, s3 = 3 * s * sd;
-    const float Rf = (float)R;
-    const double eld = (double)el;
-    for (uint32_t t = opaque_tid(); t < cnt; t += kThreads) {
-        const uint32_t e = ptab[off + t];
-        if (t < ncub)   // all four neighbours: the cubic stencil, no selects
-            point<COMP>(v, q, (int)(e & 0xFFFu), true, true, true, s1, s3, spl, el, ebx2, inv, Rf,
-                        eld, R);
-        else
-            point<COMP>(v, q, (int)(e & 0xFFFu), (e >> 12) & 1u, true, (e >> 13) & 1u, s1, s3,
-                        spl, el, ebx2, inv, Rf, eld, R);
-    }
-}
-
-// extents are passed as separate scalars: selecting a struct member by a
-// runtime dimension index would make the compiler address it in memory
-// Per-pass parameters of a field, kept in LDS so that a pass reads them with
-// one LDS access instead of dependent global loads of the plan.
-struct PassParam {
-    int32_t d, s, spl, sd;     // pass dimension, stride, spline, LDS stride along d
-    float el, ebx2, inv;       // level bound, 2*e_l, 1/(2*e_l)
-    int32_t lvl;
+// The window a wave works on.  Every member is wave-uniform.
+struct Win {
+    uint64_t gbase;          // linear index of the window origin
+    uint32_t n0, n01;        // field strides
+    int lo0, lo1, lo2;       // origin
+    int e0, e1, e2;          // block extents (owned points + far face where present)
+    int o0, o1, o2;          // owned extents
+    bool full;
 };
 
-template <int ND, class G, bool COMP, bool FULL>
-__device__ __forceinline__ void run_levels(float* v, uint16_t* q, const uint16_t* ptab,
-                                           const uint32_t* pmeta, const PassParam* pp,
-                                           int o0, int o1, int L, int R, int e0, int e1, int e2) {
-    const int npass = ND * L;
-    for (int pass = 0; pass < npass; ++pass) {
-        const PassParam r = pp[pass];
-        if (FULL) {
-            run_pass_tab<ND, G, COMP>(v, q, ptab, pmeta[pass], pmeta[kMaxPasses + pass],
-                                      pmeta[2 * kMaxPasses + pass], r.d, r.s, r.spl, r.el, r.ebx2,
-                                      r.inv, R);
+template <int ND>
+__device__ __forceinline__ Win make_win(const FieldDesc& f, uint32_t w) {
+    using G = Geo<ND>;
+    Win wi;
+    const uint32_t nw0 = (uint32_t)f.nwin[0];
+    const uint32_t nw01 = nw0 * (uint32_t)f.nwin[1];
+    const uint32_t wz = w / nw01;
+    const uint32_t r = w - wz * nw01;
+    const uint32_t wy = r / nw0;
+    const uint32_t wx = r - wy * nw0;
+    wi.n0 = (uint32_t)f.n[0];
+    wi.n01 = wi.n0 * (uint32_t)f.n[1];
+    wi.lo0 = (int)wx * G::W0;
+    wi.lo1 = (int)wy * G::W1;
+    wi.lo2 = ND == 3 ? (int)wz * G::W2 : 0;
+    const int s0 = f.n[0] - 1 - wi.lo0, s1 = f.n[1] - 1 - wi.lo1;
+    const int s2 = ND == 3 ? f.n[2] - 1 - wi.lo2 : 0;
+    wi.e0 = (s0 < G::W0 ? s0 : G::W0) + 1;
+    wi.e1 = (s1 < G::W1 ? s1 : G::W1) + 1;
+    wi.e2 = ND == 3 ? (s2 < G::W2 ? s2 : G::W2) + 1 : 1;
+    wi.o0 = wi.e0 < G::W0 ? wi.e0 : G::W0;
+    wi.o1 = wi.e1 < G::W1 ? wi.e1 : G::W1;
+    wi.o2 = ND == 3 ? (wi.e2 < G::W2 ? wi.e2 : G::W2) : 1;
+    wi.full = wi.e0 == G::B0 && wi.e1 == G::B1 && (ND == 2 || wi.e2 == G::B2);
+    wi.gbase = (uint64_t)wi.lo0 + (uint64_t)wi.lo1 * wi.n0 + (uint64_t)wi.lo2 * wi.n01;
+    return wi;
+}
+
+// byte offset from a window origin: the 64-bit base stays in scalar
+// registers and the per-lane part is a 32-bit offset (the host bounds the
+// span of a window below 4 GiB)
+template <class T>
+__device__ __forceinline__ const SZI_G T* at(const SZI_G T* base, uint32_t off) {
+    return (const SZI_G T*)((const SZI_G char*)base + (off * (uint32_t)sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ SZI_G T* at(SZI_G T* base, uint32_t off) {
+    return (SZI_G T*)((SZI_G char*)base + (off * (uint32_t)sizeof(T)));
+}
+
+// ------------------------------------------------------------ block staging
+// Slots of the block load, NPRE per lane; slot k of a lane is a (global
+// offset from the window origin, LDS index) pair and whether the lane holds
+// a point of the block there (of its in-extent part, for partial windows).
+// 3D: slots 0-35 hold rows (y, z) and (y, z + 4) of planes 0-7 (lanes 0-31
+// and 32-63, x = lane % 32), slots 36-40 rows (y, 8) and (y + 5, 8), slots
+// 41-42 the x = 32 column (row = lane and lane + 64).  2D: slots 0-16 rows
+// y (x = lane), slot 17 the x = 64 column (row = lane).
+template <int ND>
+struct LaneMap;
+
+template <>
+struct LaneMap<3> {
+    uint32_t x, hi;
+    uint32_t gA, gB, gC0, gC1;   // per-lane global offsets
+    int yc0, zc0, yc1, zc1;      // column rows
+    __device__ __forceinline__ void init(uint32_t lane, uint32_t n0, uint32_t n01) {
+        x = lane & 31u;
+        hi = lane >> 5;
+        gA = x + hi * 4u * n01;
+        gB = x + hi * 5u * n0;
+        yc0 = (int)(lane % 9u);
+        zc0 = (int)(lane / 9u);
+        yc1 = (int)((lane + 64u) % 9u);
+        zc1 = (int)((lane + 64u) / 9u);
+        gC0 = 32u + (uint32_t)yc0 * n0 + (uint32_t)zc0 * n01;
+        gC1 = 32u + (uint32_t)yc1 * n0 + (uint32_t)zc1 * n01;
+    }
+    template <bool FULL>
+    __device__ __forceinline__ bool slot(int k, const Win& wi, uint32_t& g, int& l) const {
+        if (k < 36) {
+            const int zl = k / 9, y = k % 9;
+            g = (uint32_t)y * wi.n0 + (uint32_t)zl * wi.n01 + gA;
+            l = zl * 297 + y * 33 + (int)x + (int)hi * (4 * 297);
+            return FULL || ((int)x < wi.e0 && y < wi.e1 && zl + 4 * (int)hi < wi.e2);
+        } else if (k < 41) {
+            const int p = k - 36;
+            g = (uint32_t)p * wi.n0 + 8u * wi.n01 + gB;
+            l = 8 * 297 + p * 33 + (int)x + (int)hi * (5 * 33);
+            const bool exists = p + 5 * (int)hi <= 8;
+            return exists && (FULL || ((int)x < wi.e0 && p + 5 * (int)hi < wi.e1 && 8 < wi.e2));
         } else {
-            const int ed = r.d == 0 ? e0 : (r.d == 1 ? e1 : e2);
-            PassGrid g;
-            pass_grid<ND>(g, o0, o1, pass % ND, r.lvl, e0, e1, e2);
-            run_pass<ND, G, COMP>(v, q, g, r.d, r.s, ed, r.spl, r.el, r.ebx2, r.inv, R);
+            const bool c1 = k == 42;
+            const int r = (int)(x + 32u * hi) + (c1 ? 64 : 0);
+            g = c1 ? gC1 : gC0;
+            l = 32 + 33 * r;
+            const int y = c1 ? yc1 : yc0, z = c1 ? zc1 : zc0;
+            return r < 81 && (FULL || (32 < wi.e0 && y < wi.e1 && z < wi.e2));
         }
-        __syncthreads();
     }
-}
+};
 
-template <int ND, class G>
-__device__ __forceinline__ void load_pass_params(PassParam* pp, const FieldPlan& pl, int L) {
-    const int npass = ND * L;
-    const int p = threadIdx.x;
-    if (p < npass) {
-        const int lvl = L - p / ND, k = p % ND;
-        const int d = pl.order[k];
-        PassParam r;
-        r.d = d;
-        r.s = 1 << (lvl - 1);
-        r.spl = pl.spline[d];
-        r.sd = d == 0 ? 1 : (d == 1 ? G::B0 : G::B0 * G::B1);
-        r.el = pl.el[lvl - 1];
-        r.ebx2 = pl.ebx2[lvl - 1];
-        r.inv = pl.inv[lvl - 1];
-        r.lvl = lvl;
-        pp[p] = r;
+template <>
+struct LaneMap<2> {
+    uint32_t x;
+    uint32_t gC;
+    __device__ __forceinline__ void init(uint32_t lane, uint32_t n0, uint32_t) {
+        x = lane;
+        gC = 64u + lane * n0;
     }
-}
-
-// copy the pass table of the field's order into LDS (after a barrier)
-template <int ND, class G>
-__device__ __forceinline__ void load_pass_table(uint16_t* ptab, uint32_t* pmeta,
-                                                const uint16_t* __restrict__ gtab,
-                                                const PassMeta* __restrict__ gmeta,
-                                                const FieldPlan& pl) {
-    const int id = ND == 3 ? 2 * pl.order[0] + (pl.order[1] > pl.order[2] ? 1 : 0) : pl.order[0];
-    const PassMeta& m = gmeta[id];
-    if (threadIdx.x < kMaxPasses) {
-        pmeta[threadIdx.x] = m.off[threadIdx.x] - m.off[0];
-        pmeta[kMaxPasses + threadIdx.x] = m.cnt[threadIdx.x];
-        pmeta[2 * kMaxPasses + threadIdx.x] = m.ncub[threadIdx.x];
+    template <bool FULL>
+    __device__ __forceinline__ bool slot(int k, const Win& wi, uint32_t& g, int& l) const {
+        if (k < 17) {
+            g = (uint32_t)k * wi.n0 + x;
+            l = k * 65 + (int)x;
+            return FULL || ((int)x < wi.e0 && k < wi.e1);
+        }
+        g = gC;
+        l = 64 + 65 * (int)x;
+        return x < 17u && (FULL || (64 < wi.e0 && (int)x < wi.e1));
     }
-    uint32_t total = 0;
-    for (int p = 0; p < ND * (ND == 3 ? 3 : 4); ++p) total += m.cnt[p];
-    const SZI_G uint16_t* src = gp(gtab) + m.off[0];
-    // rare path (once per field): keep it from holding many registers
-#pragma unroll 1
-    for (uint32_t t = threadIdx.x; t < total; t += kThreads) ptab[t] = src[t];
-}
+};
 
-// block point t -> block coordinates, for a full window (constant extents)
-// or a partial one (runtime extents)
-template <class G, bool FULL>
-__device__ __forceinline__ void block_coord(uint32_t t, const FastDiv& e0, const FastDiv& e01,
-                                            uint32_t& c0, uint32_t& c1, uint32_t& c2) {
-    if (FULL) {
-        c2 = t / (G::B0 * G::B1);
-        const uint32_t r = t - c2 * (G::B0 * G::B1);
-        c1 = r / G::B0;
-        c0 = r - c1 * G::B0;
-    } else {
-        c2 = e01.div(t);
-        const uint32_t r = t - c2 * e01.m;
-        c1 = e0.div(r);
-        c0 = r - c1 * e0.m;
-    }
-}
-
-template <int ND, int W0, int W1, int W2, bool FULL>
-__device__ __forceinline__ void compress_window(float* v, uint16_t* q, uint32_t* hist,
-                                                uint32_t& cntR, const uint16_t* ptab,
-                                                const uint32_t* pmeta, const PassParam* pp,
-                                                const FieldDesc& fd,
-                                                const FieldPlan& pl, const WinInfo& wi) {
-    using G = Geom<ND, W0, W1, W2>;
-    const int tid = opaque_tid();
-    const uint32_t n0 = (uint32_t)fd.n[0];
-    const uint32_t n01 = n0 * (uint32_t)fd.n[1];
-    const SZI_G float* base = gp(fd.in) + wi.gbase;
-    // load: every load of the block in flight before the first LDS store
-    {
-        FastDiv e0, e01;
-        e0.set((uint32_t)wi.e0);
-        e01.set((uint32_t)(wi.e0 * wi.e1));
-        const uint32_t tot = FULL ? (uint32_t)G::BN : (uint32_t)(wi.e0 * wi.e1 * wi.e2);
-        // batches of kLoadBatch loads in flight per thread
-        for (int k0 = 0; k0 < G::PER; k0 += kLoadBatch) {
-            float val[kLoadBatch];
-            int li[kLoadBatch];
+// Slots a lane does not load keep the value fill.
+template <int ND, bool FULL, class T, class U>
+__device__ __forceinline__ void load_block(U (&pre)[Geo<ND>::NPRE], const SZI_G T* wb,
+                                           const LaneMap<ND>& lm, const Win& wi, U fill) {
 #pragma unroll
-            for (int k = 0; k < kLoadBatch; ++k) {
-                const uint32_t t = tid + (k0 + k) * kThreads;
-                li[k] = -1;
-                if (t < tot) {
-                    uint32_t c0, c1, c2;
-                    block_coord<G, FULL>(t, e0, e01, c0, c1, c2);
-                    li[k] = (int)(c0 + G::B0 * (c1 + G::B1 * c2));
-                    val[k] = base[c0 + c1 * n0 + c2 * n01];
+    for (int k = 0; k < Geo<ND>::NPRE; ++k) {
+        uint32_t g;
+        int l;
+        U t = fill;
+        if (lm.template slot<FULL>(k, wi, g, l)) t = (U)*at(wb, g);
+        pre[k] = t;
+    }
+}
+
+template <int ND, bool FULL, class T, class U>
+__device__ __forceinline__ void commit_block(T* dst, const U (&pre)[Geo<ND>::NPRE],
+                                             const LaneMap<ND>& lm, const Win& wi) {
+#pragma unroll
+    for (int k = 0; k < Geo<ND>::NPRE; ++k) {
+        uint32_t g;
+        int l;
+        if (lm.template slot<FULL>(k, wi, g, l)) dst[l] = (T)pre[k];
+    }
+}
+
+// anchors of the block (Sec. V-A: stored losslessly), one per lane
+template <int ND>
+__device__ __forceinline__ bool anchor_slot(uint32_t lane, const FieldDesc& f, const Win& wi,
+                                            uint32_t& gi, int& li) {
+    using G = Geo<ND>;
+    constexpr int S = 1 << G::SHS;
+    const int ax = (int)(lane % 5u);
+    const int ay = ND == 3 ? (int)((lane / 5u) & 1u) : (int)(lane / 5u);
+    const int az = ND == 3 ? (int)(lane / 10u) : 0;
+    li = ax * S + ay * S * G::SY + az * S * G::SZ;
+    gi = (uint32_t)((wi.lo0 >> G::SHS) + ax) +
+         (uint32_t)f.na[0] * ((uint32_t)((wi.lo1 >> G::SHS) + ay) +
+                              (uint32_t)f.na[1] * (uint32_t)((wi.lo2 >> G::SHS) + az));
+    return lane < (uint32_t)G::NANCH && ax * S < wi.e0 && ay * S < wi.e1 && az * S < wi.e2;
+}
+
+// ------------------------------------------------------------------ passes
+// Sec. V-B.1 splines by neighbour availability (a = x[-3s], b = x[-s],
+// c = x[+s], d = x[+3s]); with one neighbour the value of x[-s].
+template <int SPL>
+__device__ __forceinline__ float predict(bool m3, bool p1, bool p3, float a, float b, float c,
+                                         float d) {
+    const float sbc = b + c;
+    float p = sbc * 0.5f;
+    if (SPL != SPL_LIN) {
+        if (m3 && p3) {
+            if (SPL == SPL_NAT)
+                p = (23.0f * sbc - 3.0f * (a + d)) / 40.0f;   // natural cubic
+            else
+                p = (9.0f * sbc - (a + d)) * 0.0625f;         // not-a-knot cubic
+        } else if (m3) {
+            p = ((6.0f * b + 3.0f * c) - a) * 0.125f;         // quadratic on a, b, c
+        } else if (p3) {
+            p = ((3.0f * b + 6.0f * c) - d) * 0.125f;         // quadratic on b, c, d
+        }
+    }
+    return p1 ? p : b;
+}
+
+// Quantiser constants of one level (Sec. III-A, Eq. 1).
+struct LvlQ {
+    float ebx2, inv, Rf;
+    double eld;
+    int R;
+    bool zero;   // e_l == 0: only exact predictions are kept
+};
+
+// One pass: dimension D, stride 1 << SH, spline SPL, over ntask tasks of
+// K targets.  Line i0 + ne * i1 starts at LDS index i0 * le + i1 * lf.
+template <int ND, int D, int SH, int SPL, bool COMP, bool FULL>
+__device__ __forceinline__ void pass_lines(float* v, uint16_t* q, uint32_t lane, uint32_t ntask,
+                                           uint32_t ne, FastDiv dvn, int le, int lf, int ed,
+                                           const LvlQ& lq) {
+    using G = Geo<ND>;
+    constexpr int s = 1 << SH;
+    constexpr int W = D == 0 ? G::W0 : (D == 1 ? G::W1 : G::W2);
+    constexpr int SD = D == 0 ? 1 : (D == 1 ? G::SY : G::SZ);
+    constexpr int T = W / (2 * s);   // targets per line
+    constexpr int K = T > 8 ? 8 : T;
+    constexpr int NSEG = T / K;
+    static_assert(NSEG == 1 || D == 0, "lines split into segments run along x only");
+    static_assert(NSEG == 1 || 2 * s <= kPad, "guard band narrower than the stencil");
+#pragma unroll 1
+    for (uint32_t t = lane; t < ntask; t += 64) {
+        const uint32_t seg = NSEG > 1 ? (t & (uint32_t)(NSEG - 1)) : 0u;
+        const uint32_t ln = NSEG > 1 ? t / (uint32_t)NSEG : t;
+        const uint32_t i1 = dvn.div(ln);
+        const uint32_t i0 = ln - i1 * ne;
+        const int p0 = (int)seg * (2 * K * s);   // segment start along D
+        const int base = (int)i0 * le + (int)i1 * lf + p0 * SD;
+        // knowns at (2i - 2) s from the segment start; whole lines read only
+        // the ones inside the block, split lines all of them (the guard band
+        // and the neighbouring line absorb the ends; the flags drop them)
+        float kn[K + 3];
+#pragma unroll
+        for (int i = 0; i < K + 3; ++i) {
+            const int pos = (2 * i - 2) * s;
+            kn[i] = (NSEG > 1 || (pos >= 0 && pos <= W)) ? v[base + pos * SD] : 0.0f;
+        }
+        float xt[K];
+        uint32_t ct[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int li = base + (2 * j + 1) * s * SD;
+            if (COMP)
+                xt[j] = v[li];
+            else
+                ct[j] = q[li];
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int pos = (2 * j + 1) * s;   // target position in the segment
+            const bool m3 = NSEG > 1 ? (j >= 1 || seg > 0u) : (j >= 1);
+            bool p3 = NSEG > 1 ? (j <= K - 2 || seg < (uint32_t)(NSEG - 1))
+                               : ((2 * j + 4) * s <= W);
+            bool p1 = true;
+            if (!FULL) {   // the window interval ends at ed - 1
+                p1 = p0 + pos + s <= ed - 1;
+                p3 = p0 + pos + 3 * s <= ed - 1;
+            }
+            const float p = predict<SPL>(m3, p1, p3, kn[j], kn[j + 1], kn[j + 2], kn[j + 3]);
+            const int li = base + pos * SD;
+            if (COMP) {
+                // closed-loop quantisation against e_l, with the exact check
+                const float xv = xt[j];
+                const float diff = xv - p;
+                const float qr = rintf(diff * lq.inv);   // round half to even
+                const int qi = (int)qr;
+                const float xr = lq.zero ? p : p + (float)qi * lq.ebx2;
+                // |rint(qf)| < R holds iff |qf| < R and |q| < R; NaN fails it
+                const bool ok = fabsf(qr) < lq.Rf && fabs((double)xv - (double)xr) <= lq.eld;
+                v[li] = ok ? xr : xv;
+                q[li] = (uint16_t)(ok ? qi + lq.R : 0);
+            } else {
+                const uint32_t code = ct[j];
+                const float tq = (float)((int)code - lq.R) * lq.ebx2;
+                if (code != 0u) v[li] = p + tq;   // code 0: outlier, value already staged
+            }
+        }
+    }
+}
+
+template <int ND, int D, int SH, bool COMP, bool FULL>
+__device__ __forceinline__ void pass_spline(float* v, uint16_t* q, uint32_t lane, int spl,
+                                            uint32_t nlines, uint32_t ne, int le, int lf,
+                                            const Win& wi, const LvlQ& lq) {
+    using G = Geo<ND>;
+    constexpr int W = D == 0 ? G::W0 : (D == 1 ? G::W1 : G::W2);
+    constexpr int T = W / (2 << SH);
+    constexpr int NSEG = T > 8 ? T / 8 : 1;
+    const uint32_t ntask = nlines * (uint32_t)NSEG;
+    const int ed = D == 0 ? wi.e0 : (D == 1 ? wi.e1 : wi.e2);
+    FastDiv dvn;
+    dvn.set(ne);
+    if (spl == SPL_LIN)
+        pass_lines<ND, D, SH, SPL_LIN, COMP, FULL>(v, q, lane, ntask, ne, dvn, le, lf, ed, lq);
+    else if (spl == SPL_NAT)
+        pass_lines<ND, D, SH, SPL_NAT, COMP, FULL>(v, q, lane, ntask, ne, dvn, le, lf, ed, lq);
+    else
+        pass_lines<ND, D, SH, SPL_NAK, COMP, FULL>(v, q, lane, ntask, ne, dvn, le, lf, ed, lq);
+}
+
+// A wave's own LDS accesses execute in program order; this keeps the
+// compiler from moving them across a pass boundary.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The passes of one level (stride s = 1 << SH).  Along the pass dimension
+// the odd multiples of s; along dimensions already passed at this level the
+// multiples of s, along those still to come the multiples of 2s.
+template <int ND, int SH, bool COMP, bool FULL>
+__device__ __forceinline__ void run_level(float* v, uint16_t* q, uint32_t lane,
+                                          const FieldPlan& pl, int R, const Win& wi) {
+    using G = Geo<ND>;
+    constexpr int s = 1 << SH;
+    LvlQ lq;
+    const float el = pl.el[SH];
+    lq.zero = el == 0.0f;
+    lq.ebx2 = pl.ebx2[SH];
+    lq.inv = lq.zero ? 0.0f : pl.inv[SH];
+    lq.eld = (double)el;
+    lq.R = R;
+    lq.Rf = (float)R;
+    const int o0 = pl.order[0], o1 = pl.order[1];
+#pragma unroll 1
+    for (int k = 0; k < ND; ++k) {
+        const int d = k == 0 ? o0 : (k == 1 ? o1 : pl.order[2]);
+        auto step = [&](int j) {   // line spacing along dimension j
+            const int pj = o0 == j ? 0 : (o1 == j ? 1 : 2);
+            return pj < k ? s : 2 * s;
+        };
+        if constexpr (ND == 3) {
+            const int e = d == 0 ? 1 : 0, f = d == 2 ? 1 : 2;
+            const int se = step(e), sf = step(f);
+            const uint32_t ne = (uint32_t)((e == 0 ? G::W0 : G::W1) / se + 1);
+            const uint32_t nf = (uint32_t)((f == 1 ? G::W1 : G::W2) / sf + 1);
+            const int le = se * (e == 0 ? 1 : G::SY);
+            const int lf = sf * (f == 1 ? G::SY : G::SZ);
+            if (d == 0)
+                pass_spline<ND, 0, SH, COMP, FULL>(v, q, lane, pl.spline[0], ne * nf, ne, le, lf,
+                                                   wi, lq);
+            else if (d == 1)
+                pass_spline<ND, 1, SH, COMP, FULL>(v, q, lane, pl.spline[1], ne * nf, ne, le, lf,
+                                                   wi, lq);
+            else
+                pass_spline<ND, 2, SH, COMP, FULL>(v, q, lane, pl.spline[2], ne * nf, ne, le, lf,
+                                                   wi, lq);
+        } else {
+            const int e = 1 - d;
+            const int se = step(e);
+            const uint32_t ne = (uint32_t)((e == 0 ? G::W0 : G::W1) / se + 1);
+            const int le = se * (e == 0 ? 1 : G::SY);
+            if (d == 0)
+                pass_spline<ND, 0, SH, COMP, FULL>(v, q, lane, pl.spline[0], ne, ne, le, 0, wi,
+                                                   lq);
+            else
+                pass_spline<ND, 1, SH, COMP, FULL>(v, q, lane, pl.spline[1], ne, ne, le, 0, wi,
+                                                   lq);
+        }
+        wave_sync();
+    }
+}
+
+template <int ND, bool COMP, bool FULL>
+__device__ __forceinline__ void run_levels(float* v, uint16_t* q, uint32_t lane,
+                                           const FieldPlan& pl, int R, const Win& wi) {
+    if constexpr (ND == 2) run_level<ND, 3, COMP, FULL>(v, q, lane, pl, R, wi);
+    run_level<ND, 2, COMP, FULL>(v, q, lane, pl, R, wi);
+    run_level<ND, 1, COMP, FULL>(v, q, lane, pl, R, wi);
+    run_level<ND, 0, COMP, FULL>(v, q, lane, pl, R, wi);
+}
+
+// ---------------------------------------------------------------- write-out
+// Rows of the owned part are covered in slots of RPS rows; a slot's rows
+// lie in one plane.  Lane = (sub, x-group).
+template <int ND, int PER_ROW>
+struct OutMap {
+    using G = Geo<ND>;
+    static constexpr int RPS = 64 / PER_ROW;
+    static constexpr int NS = G::W1 * (ND == 3 ? G::W2 : 1) / RPS;
+    static constexpr int y0(int k) { return (k * RPS) % G::W1; }
+    static constexpr int z0(int k) { return (k * RPS) / G::W1; }
+};
+
+// Owned quant-codes (anchors carry R), owned anchors, and the histogram of
+// the owned codes (Sec. VI-A; the centre code R is counted in a register).
+template <int ND, bool FULL>
+__device__ __forceinline__ void write_codes(const uint16_t* q, const float* v, uint32_t lane,
+                                            const FieldDesc& f, const Win& wi, uint32_t* hist,
+                                            uint32_t& cntR) {
+    using G = Geo<ND>;
+    using M = OutMap<ND, G::W0 / 2>;    // x-pairs
+    const uint32_t R = (uint32_t)f.R;
+    SZI_G uint16_t* cb = gp(f.codes) + wi.gbase;
+    const uint32_t sub = lane / (uint32_t)(G::W0 / 2);
+    const int x = 2 * (int)(lane % (uint32_t)(G::W0 / 2));
+    const int lq = x + (int)sub * G::SY;
+    const uint32_t gq = (uint32_t)x + sub * wi.n0;
+    if (FULL && (wi.n0 & 1u) == 0u) {
+        // one 32-bit store per pair (window origins and rows are even)
+#pragma unroll
+        for (int k = 0; k < M::NS; ++k) {
+            const int l = lq + M::y0(k) * G::SY + M::z0(k) * G::SZ;
+            const uint32_t c0 = q[l], c1 = q[l + 1];
+            const uint32_t g = gq + (uint32_t)M::y0(k) * wi.n0 + (uint32_t)M::z0(k) * wi.n01;
+            *at((SZI_G uint32_t*)cb, g >> 1) = c0 | (c1 << 16);
+            if (c0 == R) ++cntR; else atomicAdd(&hist[c0], 1u);
+            if (c1 == R) ++cntR; else atomicAdd(&hist[c1], 1u);
+        }
+    } else {
+#pragma unroll 1
+        for (int k = 0; k < M::NS; ++k) {
+            const int y = M::y0(k) + (int)sub, z = M::z0(k);
+            if (y >= wi.o1 || z >= wi.o2) continue;
+            const int l = x + y * G::SY + z * G::SZ;
+            const uint32_t g = (uint32_t)x + (uint32_t)y * wi.n0 + (uint32_t)z * wi.n01;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                if (x + i < wi.o0) {
+                    const uint32_t c = q[l + i];
+                    *at(cb, g + (uint32_t)i) = (uint16_t)c;
+                    if (c == R) ++cntR; else atomicAdd(&hist[c], 1u);
                 }
             }
-#pragma unroll
-            for (int k = 0; k < kLoadBatch; ++k)
-                if (li[k] >= 0) v[li[k]] = val[k];
         }
     }
-    __syncthreads();
-    run_levels<ND, G, true, FULL>(v, q, ptab, pmeta, pp, pl.order[0], pl.order[1], fd.L, fd.R,
-                                  wi.e0, wi.e1, wi.e2);
-    // owned codes (anchors carry R), anchors, histogram
-    const int R = fd.R;
-    const int smask = fd.S - 1;
-    const int shS = __builtin_ctz((unsigned)fd.S);
-    if (FULL && (n0 & 1) == 0) {
-        // pairs of x-neighbours: one 32-bit store per two codes
-        constexpr int HX = W0 / 2;
-        constexpr int NP = HX * W1 * G::O2;
-        for (int t = tid; t < NP; t += kThreads) {
-            const int px = t % HX, row = t / HX;
-            const int c1 = row % W1, c2 = row / W1;
-            const int c0 = 2 * px;
-            const int li = c0 + G::B0 * (c1 + G::B1 * c2);
-            const bool arow = ((c1 | c2) & smask) == 0;
-            const bool a0 = arow && (c0 & smask) == 0;   // c0 + 1 is odd: never an anchor
-            const uint32_t qa = a0 ? (uint32_t)R : q[li];
-            const uint32_t qb = q[li + 1];
-            const uint32_t g = wi.gbase + c0 + c1 * n0 + c2 * n01;
-            *reinterpret_cast<SZI_G uint32_t*>(gp(fd.codes) + g) = qa | (qb << 16);
-            if (a0) {
-                const uint32_t ax = (uint32_t)(wi.lo0 + c0) >> shS;
-                const uint32_t ay = (uint32_t)(wi.lo1 + c1) >> shS;
-                const uint32_t az = (uint32_t)(wi.lo2 + c2) >> shS;
-                gp(fd.anchors)[ax + (uint32_t)fd.na[0] * (ay + (uint32_t)fd.na[1] * az)] = v[li];
-            }
-            if (qa == (uint32_t)R) ++cntR; else atomicAdd(&hist[qa], 1u);
-            if (qb == (uint32_t)R) ++cntR; else atomicAdd(&hist[qb], 1u);
-        }
-    } else {
-        FastDiv o0, o01;
-        o0.set((uint32_t)wi.o0);
-        o01.set((uint32_t)(wi.o0 * wi.o1));
-        const uint32_t tot = (uint32_t)(wi.o0 * wi.o1 * wi.o2);
-        for (uint32_t t = tid; t < tot; t += kThreads) {
-            const uint32_t c2 = o01.div(t);
-            const uint32_t r = t - c2 * o01.m;
-            const uint32_t c1 = o0.div(r);
-            const uint32_t c0 = r - c1 * o0.m;
-            const int li = c0 + G::B0 * (c1 + G::B1 * c2);
-            const bool anchor = ((c0 | c1 | c2) & smask) == 0;
-            const uint32_t code = anchor ? (uint32_t)R : q[li];
-            gp(fd.codes)[wi.gbase + c0 + c1 * n0 + c2 * n01] = (uint16_t)code;
-            if (anchor) {
-                const uint32_t ax = (uint32_t)(wi.lo0 + c0) >> shS;
-                const uint32_t ay = (uint32_t)(wi.lo1 + c1) >> shS;
-                const uint32_t az = (uint32_t)(wi.lo2 + c2) >> shS;
-                gp(fd.anchors)[ax + (uint32_t)fd.na[0] * (ay + (uint32_t)fd.na[1] * az)] = v[li];
-            }
-            if (code == (uint32_t)R) ++cntR; else atomicAdd(&hist[code], 1u);
-        }
+    // owned anchors: x = 0, S, 2S, 3S of row 0
+    constexpr int S = 1 << G::SHS;
+    if (lane < (uint32_t)(G::W0 / S) && (int)lane * S < wi.o0) {
+        const uint32_t ai = (uint32_t)(wi.lo0 >> G::SHS) + lane +
+                            (uint32_t)f.na[0] * ((uint32_t)(wi.lo1 >> G::SHS) +
+                                                 (uint32_t)f.na[1] * (uint32_t)(wi.lo2 >> G::SHS));
+        gp(f.anchors)[ai] = v[(int)lane * S];
     }
-    __syncthreads();
 }
 
+// Owned reconstructed values.
+template <int ND, bool FULL>
+__device__ __forceinline__ void write_values(const float* v, uint32_t lane, const FieldDesc& f,
+                                             const Win& wi) {
+    using G = Geo<ND>;
+    using M = OutMap<ND, G::W0 / 4>;    // x-quads
+    SZI_G float* ob = gp(f.out) + wi.gbase;
+    const uint32_t sub = lane / (uint32_t)(G::W0 / 4);
+    const int x = 4 * (int)(lane % (uint32_t)(G::W0 / 4));
+    const int lq = x + (int)sub * G::SY;
+    const uint32_t gq = (uint32_t)x + sub * wi.n0;
+    if (FULL && (wi.n0 & 3u) == 0u && ((uintptr_t)f.out & 15u) == 0u) {
+#pragma unroll
+        for (int k = 0; k < M::NS; ++k) {
+            const int l = lq + M::y0(k) * G::SY + M::z0(k) * G::SZ;
+            vf4 o;
+            o.x = v[l];
+            o.y = v[l + 1];
+            o.z = v[l + 2];
+            o.w = v[l + 3];
+            const uint32_t g = gq + (uint32_t)M::y0(k) * wi.n0 + (uint32_t)M::z0(k) * wi.n01;
+            *at((SZI_G vf4*)ob, g >> 2) = o;
+        }
+    } else {
+#pragma unroll 1
+        for (int k = 0; k < M::NS; ++k) {
+            const int y = M::y0(k) + (int)sub, z = M::z0(k);
+            if (y >= wi.o1 || z >= wi.o2) continue;
+            const int l = x + y * G::SY + z * G::SZ;
+            const uint32_t g = (uint32_t)x + (uint32_t)y * wi.n0 + (uint32_t)z * wi.n01;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (x + i < wi.o0) *at(ob, g + (uint32_t)i) = v[l + i];
+        }
+    }
+}
+
+// ------------------------------------------------------------ group order
+// Work is handed out in groups of kWaves windows of one field (the host
+// pads each field to whole groups).  Workgroups on one L2 domain take one
+// contiguous eighth of the groups, so that windows sharing faces are
+// processed close in time on the same L2.
+struct GroupSeq {
+    uint64_t cur, end, step;
+};
+__device__ __forceinline__ GroupSeq group_seq(uint64_t ngroups) {
+    const uint32_t G = gridDim.x, b = blockIdx.x;
+    GroupSeq s;
+    if (G >= (uint32_t)kXcds && G % (uint32_t)kXcds == 0u) {
+        const uint64_t chunk = (ngroups + kXcds - 1) / kXcds;
+        const uint64_t lo = (uint64_t)(b % (uint32_t)kXcds) * chunk;
+        s.cur = lo + b / (uint32_t)kXcds;
+        s.end = lo + chunk < ngroups ? lo + chunk : ngroups;
+        s.step = G / (uint32_t)kXcds;
+    } else {
+        s.cur = b;
+        s.end = ngroups;
+        s.step = G;
+    }
+    return s;
+}
+
+// --------------------------------------------------------------- kernels
 __device__ __forceinline__ void flush_hist(uint32_t* hist, uint32_t& cntR, const FieldDesc& fd) {
     const uint32_t s = wave_sum(cntR);
     cntR = 0;
@@ -410,214 +557,225 @@ __device__ __forceinline__ void flush_hist(uint32_t* hist, uint32_t& cntR, const
     __syncthreads();
 }
 
-template <int ND, int W0, int W1, int W2>
+template <int ND>
 __global__ __launch_bounds__(kThreads) void k_compress(const FieldDesc* __restrict__ F,
                                                        const FieldPlan* __restrict__ P,
-                                                       const uint64_t* __restrict__ item_off,
-                                                       int nfields, uint64_t nitems,
-                                                       const uint16_t* __restrict__ gtab,
-                                                       const PassMeta* __restrict__ gmeta) {
-    using G = Geom<ND, W0, W1, W2>;
-    __shared__ float v[G::BN];
-    __shared__ uint16_t q[G::BN + 1];
-    __shared__ uint16_t ptab[G::BN + 1];
-    __shared__ uint32_t pmeta[3 * kMaxPasses];
-    __shared__ PassParam pp[kMaxPasses];
+                                                       const uint64_t* __restrict__ goff,
+                                                       uint64_t ngroups) {
+    using G = Geo<ND>;
+    __shared__ float vbuf[kWaves][vlen<ND>()];
+    __shared__ uint16_t qbuf[kWaves][qlen<ND>()];
     extern __shared__ uint32_t hist[];
-    int f = 0, cur = -1;
-    uint32_t cntR = 0;   // thread-private count of the centre code (Sec. VI-A, top-1 cache)
-    for (uint64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        while (it >= item_off[f + 1]) ++f;
-        if (f != cur) {
-            if (cur >= 0) flush_hist(hist, cntR, F[cur]);
-            cur = f;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t lane = threadIdx.x & 63u;
+    float* v = vbuf[wave] + kPad;
+    uint16_t* q = qbuf[wave];
+    const GroupSeq gs = group_seq(ngroups);
+    uint64_t g = gs.cur;
+    if (g >= gs.end) return;
+    int f = 0;
+    float pre[G::NPRE];   // block of the next window
+    LaneMap<ND> lm;
+    Win wn;
+    bool valid;
+    // window of group g for this wave, and the start of its block load
+    auto fetch = [&]() {
+        while (g >= goff[f + 1]) ++f;
+        const uint32_t w = (uint32_t)(g - goff[f]) * kWaves + (uint32_t)wave;
+        valid = w < (uint32_t)(F[f].nwin[0] * F[f].nwin[1] * F[f].nwin[2]);
+        if (valid) {
+            wn = make_win<ND>(F[f], w);
+            lm.init(lane, wn.n0, wn.n01);
+            const SZI_G float* wb = gp(F[f].in) + wn.gbase;
+            if (wn.full) load_block<ND, true>(pre, wb, lm, wn, 0.0f);
+            else load_block<ND, false>(pre, wb, lm, wn, 0.0f);
+        }
+    };
+    fetch();
+    int hf = -1;         // field whose histogram the workgroup accumulates
+    uint32_t cntR = 0;   // lane-private count of the centre code (top-1 cache)
+    while (true) {
+        const int fc = f;
+        const Win wc = wn;
+        const bool vc = valid;
+        if (fc != hf) {   // uniform over the workgroup: groups never span fields
+            if (hf >= 0) flush_hist(hist, cntR, F[hf]);
 #pragma unroll 1
-            for (int b = threadIdx.x; b < 2 * F[cur].R; b += kThreads) hist[b] = 0;
-            load_pass_table<ND, G>(ptab, pmeta, gtab, gmeta, P[f]);
-            load_pass_params<ND, G>(pp, P[f], F[f].L);
+            for (int b = threadIdx.x; b < 2 * F[fc].R; b += kThreads) hist[b] = 0;
+            // anchors never become targets: their codes stay R
+            uint32_t ga;
+            int la;
+            (void)anchor_slot<ND>(lane, F[fc], wc, ga, la);
+            if (lane < (uint32_t)G::NANCH) q[la] = (uint16_t)F[fc].R;
             __syncthreads();
+            hf = fc;
         }
-        const FieldDesc& fd = F[f];
-        const FieldPlan& pl = P[f];
-        WinInfo wi;
-        window_info<ND, W0, W1, W2>(fd, it - item_off[f], wi);
-        if (wi.full)
-            compress_window<ND, W0, W1, W2, true>(v, q, hist, cntR, ptab, pmeta, pp, fd, pl, wi);
-        else
-            compress_window<ND, W0, W1, W2, false>(v, q, hist, cntR, ptab, pmeta, pp, fd, pl, wi);
+        if (vc) {
+            if (wc.full) commit_block<ND, true>(v, pre, lm, wc);
+            else commit_block<ND, false>(v, pre, lm, wc);
+        }
+        g += gs.step;
+        const bool more = g < gs.end;
+        if (more) fetch();   // in flight during the passes below
+        if (vc) {
+            wave_sync();
+            const FieldDesc& fd = F[fc];
+            const FieldPlan& pl = P[fc];
+            if (wc.full) {
+                run_levels<ND, true, true>(v, q, lane, pl, fd.R, wc);
+                write_codes<ND, true>(q, v, lane, fd, wc, hist, cntR);
+            } else {
+                run_levels<ND, true, false>(v, q, lane, pl, fd.R, wc);
+                write_codes<ND, false>(q, v, lane, fd, wc, hist, cntR);
+            }
+            wave_sync();
+        }
+        if (!more) break;
     }
-    if (cur >= 0) flush_hist(hist, cntR, F[cur]);
+    flush_hist(hist, cntR, F[hf]);
 }
 
-template <int ND, int W0, int W1, int W2, bool FULL>
-__device__ __forceinline__ void decompress_window(float* v, uint16_t* q, const uint16_t* ptab,
-                                                  const uint32_t* pmeta, const PassParam* pp,
-                                                  const FieldDesc& fd,
-                                                  const FieldPlan& pl, const WinInfo& wi) {
-    using G = Geom<ND, W0, W1, W2>;
-    const int tid = opaque_tid();
-    const uint32_t n0 = (uint32_t)fd.n[0];
-    const uint32_t n01 = n0 * (uint32_t)fd.n[1];
-    const int smask = fd.S - 1;
-    const int shS = __builtin_ctz((unsigned)fd.S);
-    {
-        FastDiv e0, e01;
-        e0.set((uint32_t)wi.e0);
-        e01.set((uint32_t)(wi.e0 * wi.e1));
-        const uint32_t tot = FULL ? (uint32_t)G::BN : (uint32_t)(wi.e0 * wi.e1 * wi.e2);
-        for (int k0 = 0; k0 < G::PER; k0 += kLoadBatch) {
-            uint32_t code[kLoadBatch], gi[kLoadBatch];
-            int li[kLoadBatch];
-            uint32_t ai[kLoadBatch];   // anchor index + 1, or 0
-#pragma unroll
-            for (int k = 0; k < kLoadBatch; ++k) {
-                const uint32_t t = tid + (k0 + k) * kThreads;
-                li[k] = -1;
-                if (t < tot) {
-                    uint32_t c0, c1, c2;
-                    block_coord<G, FULL>(t, e0, e01, c0, c1, c2);
-                    li[k] = (int)(c0 + G::B0 * (c1 + G::B1 * c2));
-                    gi[k] = wi.gbase + c0 + c1 * n0 + c2 * n01;
-                    code[k] = gp(fd.codes)[gi[k]];
-                    ai[k] = 0;
-                    if (((c0 | c1 | c2) & smask) == 0) {
-                        const uint32_t ax = (uint32_t)(wi.lo0 + c0) >> shS;
-                        const uint32_t ay = (uint32_t)(wi.lo1 + c1) >> shS;
-                        const uint32_t az = (uint32_t)(wi.lo2 + c2) >> shS;
-                        ai[k] = 1 + ax + (uint32_t)fd.na[0] * (ay + (uint32_t)fd.na[1] * az);
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < kLoadBatch; ++k) {
-                if (li[k] < 0) continue;
-                q[li[k]] = (uint16_t)code[k];
-                if (ai[k])
-                    v[li[k]] = gp(fd.anchors)[ai[k] - 1];
-                else if (code[k] == 0)
-                    v[li[k]] = gp(fd.out)[gi[k]];   // outlier, scattered before the replay
-            }
-        }
-    }
-    __syncthreads();
-    run_levels<ND, G, false, FULL>(v, q, ptab, pmeta, pp, pl.order[0], pl.order[1], fd.L, fd.R,
-                                   wi.e0, wi.e1, wi.e2);
-    if (FULL && (n0 & 1) == 0) {
-        constexpr int HX = W0 / 2;
-        constexpr int NP = HX * W1 * G::O2;
-        for (int t = tid; t < NP; t += kThreads) {
-            const int px = t % HX, row = t / HX;
-            const int c1 = row % W1, c2 = row / W1;
-            const int c0 = 2 * px;
-            const int li = c0 + G::B0 * (c1 + G::B1 * c2);
-            typedef float vf2 __attribute__((ext_vector_type(2)));
-            vf2 o;
-            o.x = v[li];
-            o.y = v[li + 1];
-            *reinterpret_cast<SZI_G vf2*>(gp(fd.out) + wi.gbase + c0 + c1 * n0 + c2 * n01) = o;
-        }
-    } else {
-        FastDiv o0, o01;
-        o0.set((uint32_t)wi.o0);
-        o01.set((uint32_t)(wi.o0 * wi.o1));
-        const uint32_t tot = (uint32_t)(wi.o0 * wi.o1 * wi.o2);
-        for (uint32_t t = tid; t < tot; t += kThreads) {
-            const uint32_t c2 = o01.div(t);
-            const uint32_t r = t - c2 * o01.m;
-            const uint32_t c1 = o0.div(r);
-            const uint32_t c0 = r - c1 * o0.m;
-            gp(fd.out)[wi.gbase + c0 + c1 * n0 + c2 * n01] = v[c0 + G::B0 * (c1 + G::B1 * c2)];
-        }
-    }
-    __syncthreads();
-}
-
-template <int ND, int W0, int W1, int W2>
+template <int ND>
 __global__ __launch_bounds__(kThreads) void k_decompress(const FieldDesc* __restrict__ F,
                                                          const FieldPlan* __restrict__ P,
-                                                         const uint64_t* __restrict__ item_off,
-                                                         int nfields, uint64_t nitems,
-                                                         const uint16_t* __restrict__ gtab,
-                                                         const PassMeta* __restrict__ gmeta) {
-    using G = Geom<ND, W0, W1, W2>;
-    __shared__ float v[G::BN];
-    __shared__ uint16_t q[G::BN + 1];
-    __shared__ uint16_t ptab[G::BN + 1];
-    __shared__ uint32_t pmeta[3 * kMaxPasses];
-    __shared__ PassParam pp[kMaxPasses];
-    int f = 0, cur = -1;
-    for (uint64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        while (it >= item_off[f + 1]) ++f;
-        if (f != cur) {
-            cur = f;
-            load_pass_table<ND, G>(ptab, pmeta, gtab, gmeta, P[f]);
-            load_pass_params<ND, G>(pp, P[f], F[f].L);
-            __syncthreads();
+                                                         const uint64_t* __restrict__ goff,
+                                                         uint64_t ngroups) {
+    using G = Geo<ND>;
+    __shared__ float vbuf[kWaves][vlen<ND>()];
+    __shared__ uint16_t qbuf[kWaves][qlen<ND>()];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t lane = threadIdx.x & 63u;
+    float* v = vbuf[wave] + kPad;
+    uint16_t* q = qbuf[wave];
+    const GroupSeq gs = group_seq(ngroups);
+    uint64_t g = gs.cur;
+    if (g >= gs.end) return;
+    int f = 0;
+    // codes of the next window's block; slots outside it hold a value no
+    // code takes
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    uint32_t pre[G::NPRE];
+    float apre = 0.0f;   // one anchor per lane
+    LaneMap<ND> lm;
+    Win wn;
+    bool valid;
+    auto fetch = [&]() {
+        while (g >= goff[f + 1]) ++f;
+        const uint32_t w = (uint32_t)(g - goff[f]) * kWaves + (uint32_t)wave;
+        valid = w < (uint32_t)(F[f].nwin[0] * F[f].nwin[1] * F[f].nwin[2]);
+        if (valid) {
+            wn = make_win<ND>(F[f], w);
+            lm.init(lane, wn.n0, wn.n01);
+            const SZI_G uint16_t* cb = gp(F[f].codes) + wn.gbase;
+            if (wn.full) load_block<ND, true>(pre, cb, lm, wn, kNone);
+            else load_block<ND, false>(pre, cb, lm, wn, kNone);
+            uint32_t ga;
+            int la;
+            if (anchor_slot<ND>(lane, F[f], wn, ga, la)) apre = gp(F[f].anchors)[ga];
         }
-        const FieldDesc& fd = F[f];
-        WinInfo wi;
-        window_info<ND, W0, W1, W2>(fd, it - item_off[f], wi);
-        if (wi.full)
-            decompress_window<ND, W0, W1, W2, true>(v, q, ptab, pmeta, pp, fd, P[f], wi);
-        else
-            decompress_window<ND, W0, W1, W2, false>(v, q, ptab, pmeta, pp, fd, P[f], wi);
+    };
+    fetch();
+    while (true) {
+        const int fc = f;
+        const Win wc = wn;
+        const bool vc = valid;
+        if (vc) {
+            const FieldDesc& fd = F[fc];
+            if (wc.full) commit_block<ND, true>(q, pre, lm, wc);
+            else commit_block<ND, false>(q, pre, lm, wc);
+            // outliers (code 0) take their value from the output array, where
+            // the scatter step put them; rare, so one uniform test first
+            bool anyz = false;
+#pragma unroll
+            for (int k = 0; k < G::NPRE; ++k) anyz = anyz || pre[k] == 0u;
+            if (__any(anyz)) {
+                const SZI_G float* ob = gp((const float*)fd.out) + wc.gbase;
+#pragma unroll
+                for (int k = 0; k < G::NPRE; ++k) {
+                    uint32_t gg;
+                    int l;
+                    (void)lm.template slot<true>(k, wc, gg, l);
+                    if (pre[k] == 0u) v[l] = *at(ob, gg);
+                }
+            }
+            uint32_t ga;
+            int la;
+            if (anchor_slot<ND>(lane, fd, wc, ga, la)) v[la] = apre;
+        }
+        g += gs.step;
+        const bool more = g < gs.end;
+        if (more) fetch();   // in flight during the passes below
+        if (vc) {
+            wave_sync();
+            const FieldDesc& fd = F[fc];
+            const FieldPlan& pl = P[fc];
+            if (wc.full) {
+                run_levels<ND, false, true>(v, q, lane, pl, fd.R, wc);
+                write_values<ND, true>(v, lane, fd, wc);
+            } else {
+                run_levels<ND, false, false>(v, q, lane, pl, fd.R, wc);
+                write_values<ND, false>(v, lane, fd, wc);
+            }
+            wave_sync();
+        }
+        if (!more) break;
     }
 }
 
 // ------------------------------------------------------- launchers
 // The persistent grid is the number of workgroups resident at once
-// (occupancy from the runtime x compute units) unless per_cu overrides it.
+// (occupancy from the runtime x compute units) unless per_cu overrides it,
+// rounded to whole L2 domains.
 template <class K>
-static int resident_grid(K kernel, size_t lds, int num_cus, int per_cu) {
-    if (per_cu > 0) return num_cus * per_cu;
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, kThreads, lds) != hipSuccess ||
-        occ < 1) {
-        (void)hipGetLastError();
-        occ = 4;
+static uint64_t resident_grid(K kernel, size_t lds, int num_cus, int per_cu, uint64_t ngroups) {
+    int occ = per_cu;
+    if (occ <= 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, kThreads, lds) !=
+                hipSuccess ||
+            occ < 1) {
+            (void)hipGetLastError();
+            occ = 2;
+        }
     }
-    return num_cus * occ;
+    uint64_t grid = (uint64_t)num_cus * (uint64_t)occ;
+    if (grid > ngroups) grid = ngroups;
+    if (grid > (uint64_t)kXcds) grid -= grid % kXcds;
+    return grid;
 }
 
 hipError_t launch_compress(int ndim, const FieldDesc* d_fields, const FieldPlan* d_plans,
-                           int nfields, const uint64_t* d_item_off, uint64_t nitems,
-                           const uint16_t* d_ptab, const PassMeta* d_pmeta, int num_cus,
-                           int per_cu, int max_R, hipStream_t st) {
-    if (nitems == 0) return hipSuccess;
+                           const uint64_t* d_goff, uint64_t ngroups, int num_cus, int per_cu,
+                           int max_R, hipStream_t st) {
+    if (ngroups == 0) return hipSuccess;
     const size_t lds = (size_t)2 * max_R * sizeof(uint32_t);
     if (ndim == 3) {
-        auto k = k_compress<3, 32, 8, 8>;
-        uint64_t grid = (uint64_t)resident_grid(k, lds, num_cus, per_cu);
-        if (grid > nitems) grid = nitems;
+        auto k = k_compress<3>;
+        const uint64_t grid = resident_grid(k, lds, num_cus, per_cu, ngroups);
         hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kThreads), lds, st, d_fields, d_plans,
-                           d_item_off, nfields, nitems, d_ptab, d_pmeta);
+                           d_goff, ngroups);
     } else {
-        auto k = k_compress<2, 64, 16, 1>;
-        uint64_t grid = (uint64_t)resident_grid(k, lds, num_cus, per_cu);
-        if (grid > nitems) grid = nitems;
+        auto k = k_compress<2>;
+        const uint64_t grid = resident_grid(k, lds, num_cus, per_cu, ngroups);
         hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kThreads), lds, st, d_fields, d_plans,
-                           d_item_off, nfields, nitems, d_ptab, d_pmeta);
+                           d_goff, ngroups);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_decompress(int ndim, const FieldDesc* d_fields, const FieldPlan* d_plans,
-                             int nfields, const uint64_t* d_item_off, uint64_t nitems,
-                             const uint16_t* d_ptab, const PassMeta* d_pmeta, int num_cus,
-                             int per_cu, hipStream_t st) {
-    if (nitems == 0) return hipSuccess;
+                             const uint64_t* d_goff, uint64_t ngroups, int num_cus, int per_cu,
+                             hipStream_t st) {
+    if (ngroups == 0) return hipSuccess;
     if (ndim == 3) {
-        auto k = k_decompress<3, 32, 8, 8>;
-        uint64_t grid = (uint64_t)resident_grid(k, 0, num_cus, per_cu);
-        if (grid > nitems) grid = nitems;
+        auto k = k_decompress<3>;
+        const uint64_t grid = resident_grid(k, 0, num_cus, per_cu, ngroups);
         hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kThreads), 0, st, d_fields, d_plans,
-                           d_item_off, nfields, nitems, d_ptab, d_pmeta);
+                           d_goff, ngroups);
     } else {
-        auto k = k_decompress<2, 64, 16, 1>;
-        uint64_t grid = (uint64_t)resident_grid(k, 0, num_cus, per_cu);
-        if (grid > nitems) grid = nitems;
+        auto k = k_decompress<2>;
+        const uint64_t grid = resident_grid(k, 0, num_cus, per_cu, ngroups);
         hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kThreads), 0, st, d_fields, d_plans,
-                           d_item_off, nfields, nitems, d_ptab, d_pmeta);
+                           d_goff, ngroups);
     }
     return hipGetLastError();
 }

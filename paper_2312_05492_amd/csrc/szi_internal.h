@@ -67,21 +67,9 @@ struct FieldPlan {
     double prof[3][3];     // [dim][linear, NAK, natural] L1 errors
 };
 
-// Pass tables of a full window (block extents W+1 in every dimension): for
-// every processing order, the block points of each pass, i0 fastest.
-// Entry: u16 = li | m3 << 12 | p3 << 13 (li the LDS index, m3/p3 whether the
-// neighbours at -3s/+3s along the pass dimension lie in the window; the one
-// at +s always does in a full window).  Meta per order: offset and count of
-// each pass, passes numbered (L - lvl) * ND + k.  Within a pass the points
-// with all four neighbours (a cubic stencil) come first.
-constexpr int kMaxPasses = 9;
-struct PassMeta {
-    uint32_t off[kMaxPasses];
-    uint32_t cnt[kMaxPasses];
-    uint32_t ncub[kMaxPasses];   // leading entries with all four neighbours
-};
-// order id: 3D 2*o0 + (o1 > o2), 2D o0
-constexpr int kPerm3 = 6, kPerm2 = 2;
+// Windows are handed to the interpolation kernels in groups of this many,
+// one per wave of a workgroup; each field is padded to whole groups.
+constexpr int kWinPerGroup = 4;
 
 // Decode tables, one u32 array per field:
 //   [0, 1<<kLutBits)           LUT: len << 16 | symbol (len 0 = longer code)
@@ -93,7 +81,7 @@ constexpr int kDtOffset = kDtCount + kLmax + 1;
 constexpr int kDtSorted = kDtOffset + kLmax + 1;
 __host__ __device__ inline int dtab_words(int nsym) { return kDtSorted + nsym; }
 
-// ---- launchers (kernels.hip) ----
+// ---- launchers (k_plan.hip, k_interp.hip, k_huff.hip) ----
 hipError_t launch_range(const FieldDesc* d_fields, int nfields, float* d_part_min,
                         float* d_part_max, uint32_t* d_part_bad, hipStream_t st);
 hipError_t launch_profile(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
@@ -103,13 +91,11 @@ hipError_t launch_plan(const FieldDesc* d_fields, FieldPlan* d_plans, int nfield
                        const uint32_t* d_part_bad, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_compress(int ndim, const FieldDesc* d_fields, const FieldPlan* d_plans,
-                           int nfields, const uint64_t* d_item_off, uint64_t nitems,
-                           const uint16_t* d_ptab, const PassMeta* d_pmeta, int num_cus,
-                           int per_cu, int max_R, hipStream_t st);
+                           const uint64_t* d_goff, uint64_t ngroups, int num_cus, int per_cu,
+                           int max_R, hipStream_t st);
 hipError_t launch_decompress(int ndim, const FieldDesc* d_fields, const FieldPlan* d_plans,
-                             int nfields, const uint64_t* d_item_off, uint64_t nitems,
-                             const uint16_t* d_ptab, const PassMeta* d_pmeta, int num_cus,
-                             int per_cu, hipStream_t st);
+                             const uint64_t* d_goff, uint64_t ngroups, int num_cus, int per_cu,
+                             hipStream_t st);
 hipError_t launch_huff_stats(const FieldDesc* d_fields, int nfields, const uint64_t* d_boff,
                              uint64_t nblocks, int chunk, uint32_t* d_cwords, uint32_t* d_couts,
                              uint32_t* d_bw, uint32_t* d_bo, int max_nsym, hipStream_t st);
