@@ -368,7 +368,9 @@ static int quantize(float xv, float p, float el, float ebx2, float inv, int32_t 
     float qf, t, xr;
     int32_t q;
     if (el == 0.0f) {
-        if (diff == 0.0f) { *q_out = 0; *xr_out = p; return 0; }
+        /* only exact predictions; the decompressor rebuilds p + 0 * 2e_l,
+         * which is +0 where p is -0, so that is the value kept here */
+        if (diff == 0.0f) { *q_out = 0; *xr_out = p + 0.0f * ebx2; return 0; }
         return 1;
     }
     qf = diff * inv;

@@ -257,7 +257,18 @@ CASES = [
     ("clim2d", lambda: synth.climate_field(301, shape=(90, 180)), dict(eb=1e-3)),
     ("spec2d", lambda: synth.spectral_field((77, 131), beta=3.0, seed=5), dict(eb=1e-4)),
     ("front", lambda: synth.front_field((30, 40, 50), seed=6), dict(eb=1e-2)),
+    # +0 and -0 mixed: the closed loop must keep the sign of zero the
+    # decompressor rebuilds (p + 0 * 2e_l is +0 where p is -0)
+    ("signed_zeros_eb0", lambda: _signed_zeros((12, 20, 36), 7),
+     dict(eb=0.0, eb_mode=O.EB_ABS, interp=(O.NAT, O.NAK, O.NAT))),
+    ("signed_zeros_abs", lambda: _signed_zeros((12, 20, 36), 8),
+     dict(eb=0.25, eb_mode=O.EB_ABS, interp=(O.NAT, O.LIN, O.NAK))),
 ]
+
+
+def _signed_zeros(shape, seed):
+    rng = np.random.default_rng(seed)
+    return np.where(rng.random(shape) < 0.5, np.float32(-0.0), np.float32(0.0)).astype(np.float32)
 
 
 @pytest.mark.parametrize("name,gen,kw", CASES, ids=[c[0] for c in CASES])
