@@ -239,6 +239,74 @@ sz_status sz_result_read(sz_ctx* ctx, const sz_result* res, int32_t section, voi
  * other word-aligned.
  */
 
+/* ------------------------------------------------------------ serving
+ * A request server for a stream of compress and decompress jobs of uneven
+ * sizes (continuous batching).  It has `slots` workers, each with its own
+ * context (resident buffer pool) and HIP stream.  Requests wait in arrival
+ * order; a free worker admits the oldest one whose device-memory estimate
+ * fits what the HBM budget leaves, runs it as a plain sz_compress or
+ * sz_decompress on its stream, and posts a completion.  Requests in
+ * different slots overlap on the device, and the host codebook step of one
+ * compression overlaps other requests' kernels.  A request's result depends
+ * only on the request: the same as a plain call, alone or in any mix.
+ *
+ * The budget counts, for every running request, an upper bound of the
+ * device memory it can take (compression: codes 2 B, words kLmax bits and
+ * outliers 8 B per point, plus 1 MiB; decompression: codes 2 B per point
+ * plus 1 MiB), and for every compression result not yet freed its actual
+ * size.  0 = no limit.  The caller's input and output buffers are not
+ * counted.
+ *
+ * The server may be called from any host thread.  Inputs (the field of a
+ * compression, the result and output buffer of a decompression) must stay
+ * valid until the request's completion has been polled; a result must not be
+ * freed while a decompression of it is queued or running. */
+typedef struct sz_server sz_server;
+
+typedef enum { SZ_REQ_COMPRESS = 0, SZ_REQ_DECOMPRESS = 1 } sz_req_kind;
+
+typedef struct {
+    int32_t kind;            /* sz_req_kind */
+    int32_t reserved0;       /* 0 */
+    uint64_t tag;            /* the caller's id, echoed in the completion */
+    const float* d_in;       /* compression: the field (device) */
+    sz_dims dims;            /* compression: its shape */
+    sz_params params;        /* compression: its parameters */
+    const sz_result* src;    /* decompression: a result of this server or of any
+                                context on the same device */
+    float* d_out;            /* decompression: the output field (device) */
+} sz_request;
+
+typedef struct {
+    uint64_t tag;
+    int32_t status;          /* sz_status of the request */
+    int32_t slot;            /* the worker that ran it */
+    double t_submit;         /* seconds since the server was created: */
+    double t_start;          /*   submitted, admitted, finished (its stream */
+    double t_done;           /*   drained) */
+    sz_result result;        /* compression: free with sz_server_result_free */
+} sz_completion;
+
+/* Create a server with 1..64 worker slots on a device. */
+sz_status sz_server_create(sz_server** out, int device, int slots, uint64_t hbm_budget_bytes);
+/* Enqueue a copy of *req.  SZ_ERR_OOM if the request alone exceeds the
+ * budget; SZ_ERR_INVALID_ARG for a malformed request.  Errors of the work
+ * itself are reported in the completion's status. */
+sz_status sz_server_submit(sz_server* s, const sz_request* req);
+/* Move up to cap completions, oldest first, into out; *n receives the count.
+ * With wait != 0, block until at least one is available, or until nothing
+ * runs and nothing queued can be admitted (then *n = 0). */
+sz_status sz_server_poll(sz_server* s, sz_completion* out, uint32_t cap, uint32_t* n, int wait);
+/* Free a compression result of this server and return its bytes to the
+ * budget. */
+sz_status sz_server_result_free(sz_server* s, sz_result* res);
+/* Bytes charged against the budget, queued requests, running requests. */
+sz_status sz_server_stats(sz_server* s, uint64_t* charged, uint64_t* queued, uint64_t* running);
+const char* sz_server_last_error(const sz_server* s);
+/* Cancel queued requests, wait for running ones, release everything,
+ * including results not yet freed (their sz_result values become invalid). */
+sz_status sz_server_destroy(sz_server* s);
+
 #ifdef __cplusplus
 }
 #endif

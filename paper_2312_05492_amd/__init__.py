@@ -59,6 +59,21 @@ class SzResult(C.Structure):
                 ("internal", C.c_void_p)]
 
 
+class SzRequest(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved0", C.c_int32), ("tag", C.c_uint64),
+                ("d_in", C.c_void_p), ("dims", SzDims), ("params", SzParams),
+                ("src", C.POINTER(SzResult)), ("d_out", C.c_void_p)]
+
+
+class SzCompletion(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("status", C.c_int32), ("slot", C.c_int32),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
+                ("result", SzResult)]
+
+
+REQ_COMPRESS, REQ_DECOMPRESS = 0, 1
+
+
 class SzError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
@@ -112,6 +127,20 @@ def lib():
         L.sz_result_read.restype = C.c_int
         L.sz_result_read.argtypes = [vp, P(SzResult), C.c_int32, vp, C.c_uint64,
                                      P(C.c_uint64)]
+        L.sz_server_create.restype = C.c_int
+        L.sz_server_create.argtypes = [P(vp), C.c_int, C.c_int, C.c_uint64]
+        L.sz_server_submit.restype = C.c_int
+        L.sz_server_submit.argtypes = [vp, P(SzRequest)]
+        L.sz_server_poll.restype = C.c_int
+        L.sz_server_poll.argtypes = [vp, P(SzCompletion), C.c_uint32, P(C.c_uint32), C.c_int]
+        L.sz_server_result_free.restype = C.c_int
+        L.sz_server_result_free.argtypes = [vp, P(SzResult)]
+        L.sz_server_stats.restype = C.c_int
+        L.sz_server_stats.argtypes = [vp, P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
+        L.sz_server_last_error.restype = C.c_char_p
+        L.sz_server_last_error.argtypes = [vp]
+        L.sz_server_destroy.restype = C.c_int
+        L.sz_server_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -301,3 +330,108 @@ class Context:
             n = struct.unpack_from("<3Q", blob, 16)
             shape = tuple(reversed(n[:ndim]))
         return Result(self, r, shape)
+
+
+class ServerResult(Result):
+    """A compression result produced by a Server (freed through it)."""
+
+    def __init__(self, server: "Server", raw: SzResult, shape):
+        super().__init__(server.reader, raw, shape)
+        self.server = server
+
+    def free(self):
+        if self.raw.internal and self.server.h:
+            lib().sz_server_result_free(self.server.h, C.byref(self.raw))
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request server (continuous batching): `slots` workers with their own
+    context and stream admit queued compress/decompress requests in arrival
+    order as slots and the HBM budget allow.  Inputs stay referenced here
+    until their completion is polled."""
+
+    def __init__(self, device: int = 0, slots: int = 4, hbm_budget: int = 0):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.reader = Context(device)   # for reading results back
+        h = C.c_void_p()
+        rc = lib().sz_server_create(C.byref(h), device, slots, hbm_budget)
+        if rc != SZ_OK:
+            raise SzError(rc, "sz_server_create failed")
+        self.h = h
+        self._keep = {}   # tag -> objects that must outlive the request
+        self._shape = {}
+
+    def _check(self, rc):
+        if rc != SZ_OK:
+            raise SzError(rc, lib().sz_server_last_error(self.h).decode())
+
+    def submit_compress(self, x, tag: int, **kw):
+        x = self.reader._field(x)
+        r = SzRequest()
+        r.kind = REQ_COMPRESS
+        r.tag = tag
+        r.d_in = x.data_ptr()
+        r.dims = make_dims(x.shape)
+        r.params = make_params(x.dim(), **kw)
+        self._check(lib().sz_server_submit(self.h, C.byref(r)))
+        self._keep[tag] = x
+        self._shape[tag] = tuple(x.shape)
+
+    def submit_decompress(self, res: Result, out, tag: int):
+        if not (out.is_cuda and out.is_contiguous() and out.numel() == res.raw.n):
+            raise ValueError("output must be a contiguous CUDA tensor of the field's size")
+        r = SzRequest()
+        r.kind = REQ_DECOMPRESS
+        r.tag = tag
+        r.src = C.pointer(res.raw)
+        r.d_out = out.data_ptr()
+        self._check(lib().sz_server_submit(self.h, C.byref(r)))
+        self._keep[tag] = (res, out, r)
+
+    def poll(self, wait: bool = True, cap: int = 256) -> list:
+        """Completed requests, oldest first: dicts with tag, status, slot,
+        t_submit, t_start, t_done (seconds) and, for a compression, result."""
+        buf = (SzCompletion * cap)()
+        n = C.c_uint32(0)
+        self._check(lib().sz_server_poll(self.h, buf, cap, C.byref(n), 1 if wait else 0))
+        out = []
+        for i in range(n.value):
+            c = buf[i]
+            d = dict(tag=c.tag, status=c.status, slot=c.slot, t_submit=c.t_submit,
+                     t_start=c.t_start, t_done=c.t_done, result=None)
+            shape = self._shape.pop(c.tag, None)
+            if c.result.internal:
+                raw = SzResult()
+                C.pointer(raw)[0] = c.result
+                d["result"] = ServerResult(self, raw, shape)
+            self._keep.pop(c.tag, None)
+            out.append(d)
+        return out
+
+    def stats(self):
+        a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        self._check(lib().sz_server_stats(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return dict(charged=a.value, queued=b.value, running=c.value)
+
+    def close(self):
+        if self.h:
+            lib().sz_server_destroy(self.h)
+            self.h = None
+        self._keep.clear()
+        if self.reader is not None:
+            self.reader.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

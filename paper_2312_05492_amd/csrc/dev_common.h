@@ -81,6 +81,30 @@ __device__ __forceinline__ bool finite_bits(float v) {
     return (__float_as_uint(v) & 0x7f800000u) != 0x7f800000u;
 }
 
+// Window geometry of the interpolation kernels (Sec. V-D): the window a
+// wave owns, its block (window + far faces) and the block's LDS strides.
+template <int ND>
+struct Geo;
+template <>
+struct Geo<3> {
+    static constexpr int W0 = 32, W1 = 8, W2 = 8;   // window
+    static constexpr int B0 = 33, B1 = 9, B2 = 9;   // block (window + far faces)
+    static constexpr int SY = 33, SZ = 297;         // LDS strides
+    static constexpr int BN = B0 * B1 * B2;
+    static constexpr int SHS = 3;                   // log2 of the anchor stride
+    static constexpr int NPRE = 43;                 // block values per lane
+    static constexpr int NANCH = 20;                // anchors in a block
+};
+template <>
+struct Geo<2> {
+    static constexpr int W0 = 64, W1 = 16, W2 = 1;
+    static constexpr int B0 = 65, B1 = 17, B2 = 1;
+    static constexpr int SY = 65, SZ = 0;
+    static constexpr int BN = B0 * B1;
+    static constexpr int SHS = 4;
+    static constexpr int NPRE = 18;
+    static constexpr int NANCH = 10;
+};
 // spline kinds per dimension (include/szi.h sz_interp)
 enum { SPL_LIN = 0, SPL_NAK = 1, SPL_NAT = 2, SPL_AUTO = 3 };
 

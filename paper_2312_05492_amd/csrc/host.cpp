@@ -11,6 +11,10 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -25,6 +29,7 @@ struct sz_ctx {
     int num_cus = 256;
     uint64_t budget = 0;       // 0 = unlimited
     uint64_t held = 0;         // bytes obtained from hipMalloc and not freed
+    std::mutex pool_mu;        // pool calls may come from other threads (results freed by a server)
     std::multimap<size_t, void*> free_blocks;
     std::unordered_map<void*, size_t> block_size;
     std::string err;
@@ -68,6 +73,7 @@ size_t round_block(size_t b) { return (b + 511) & ~(size_t)511; }
 // Caching allocator: freed blocks are kept for reuse (every API call
 // synchronizes its stream before returning, so a freed block is idle).
 sz_status pool_alloc(sz_ctx* c, size_t bytes, void** out) {
+    std::lock_guard<std::mutex> lock(c->pool_mu);
     if (bytes == 0) bytes = 1;
     bytes = round_block(bytes);
     auto it = c->free_blocks.lower_bound(bytes);
@@ -113,6 +119,7 @@ sz_status pool_alloc(sz_ctx* c, size_t bytes, void** out) {
 
 void pool_free(sz_ctx* c, void* p) {
     if (!p) return;
+    std::lock_guard<std::mutex> lock(c->pool_mu);
     auto it = c->block_size.find(p);
     if (it == c->block_size.end()) return;
     c->free_blocks.emplace(it->second, p);
@@ -342,6 +349,7 @@ bool kraft_ok(const uint8_t* len, int nsym) {
 
 // ------------------------------------------------------------ bookkeeping
 struct ResultInternal {
+    sz_ctx* owner = nullptr;       // the context whose pool holds the blocks
     std::vector<void*> blocks;     // device blocks owned by the result
     FieldPlan plan;                // host copy
     sz_dims dims;
@@ -367,7 +375,8 @@ sz_status res_alloc(sz_ctx* c, ResultInternal* R, size_t count, T** out) {
 void release_result(sz_ctx* c, sz_result* r) {
     ResultInternal* R = ri(r);
     if (R) {
-        for (void* p : R->blocks) pool_free(c, p);
+        sz_ctx* o = R->owner ? R->owner : c;
+        for (void* p : R->blocks) pool_free(o, p);
         delete R;
     }
     std::memset(r, 0, sizeof(*r));
@@ -529,6 +538,120 @@ void make_header(const sz_result* r, const ResultInternal* R, uint8_t* h) {
 }  // namespace
 
 // ======================================================================
+// ------------------------------------------------------------ serving
+// A request server: slots worker threads, each with its own context and
+// stream; requests wait in arrival order and a free slot admits the oldest
+// one whose device-memory estimate fits the budget that admitted requests
+// and held results leave.
+struct sz_server {
+    int device = 0;
+    uint64_t budget = 0;     // 0 = unlimited
+    uint64_t charged = 0;    // estimates of running requests + bytes of held results
+    std::vector<sz_ctx*> ctx;
+    std::vector<hipStream_t> st;
+    std::vector<std::thread> th;
+    struct Item {
+        sz_request r;
+        uint64_t need;
+        double t_submit;
+    };
+    std::mutex m;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Item> q;
+    std::deque<sz_completion> done;
+    std::unordered_map<void*, uint64_t> held;   // result -> bytes charged
+    int running = 0;
+    bool stop = false;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    std::string err;
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+// Device memory a request may take while it runs: compression holds the
+// codes (2 B/point), the words (at most kLmax bits per point) and the
+// outlier lists (at most 8 B per point) plus per-field metadata; the replay
+// holds the codes.
+uint64_t request_need(const sz_request& r) {
+    if (r.kind == SZ_REQ_COMPRESS) {
+        uint64_t n = 1;
+        for (uint32_t k = 0; k < r.dims.ndim && k < 3; ++k) n *= r.dims.n[k];
+        return 2 * n + (n * kLmax + 7) / 8 + 8 * n + (1u << 20);
+    }
+    const sz_dims& d = r.src ? ri(r.src)->dims : r.dims;
+    uint64_t n = 1;
+    for (uint32_t k = 0; k < d.ndim && k < 3; ++k) n *= d.n[k];
+    return 2 * n + (1u << 20);
+}
+
+uint64_t result_bytes(sz_ctx* c, const sz_result* r) {
+    std::lock_guard<std::mutex> lock(c->pool_mu);
+    uint64_t b = 0;
+    for (void* p : ri(r)->blocks) {
+        auto it = c->block_size.find(p);
+        if (it != c->block_size.end()) b += it->second;
+    }
+    return b;
+}
+
+// index of the oldest queued request that fits, or -1
+long admissible(const sz_server* s) {
+    for (size_t i = 0; i < s->q.size(); ++i)
+        if (!s->budget || s->charged + s->q[i].need <= s->budget) return (long)i;
+    return -1;
+}
+
+void server_worker(sz_server* s, int slot) {
+    (void)hipSetDevice(s->device);
+    sz_ctx* c = s->ctx[slot];
+    for (;;) {
+        std::unique_lock<std::mutex> lk(s->m);
+        long pick = -1;
+        s->cv_work.wait(lk, [&] {
+            pick = admissible(s);
+            return pick >= 0 || (s->stop && s->q.empty());
+        });
+        if (pick < 0) return;   // stopped and drained
+        sz_server::Item it = s->q[(size_t)pick];
+        s->q.erase(s->q.begin() + pick);
+        s->charged += it.need;
+        ++s->running;
+        lk.unlock();
+        sz_completion cp;
+        std::memset(&cp, 0, sizeof cp);
+        cp.tag = it.r.tag;
+        cp.slot = slot;
+        cp.t_submit = it.t_submit;
+        cp.t_start = s->now();
+        sz_status rc;
+        // both calls return after their stream has finished the request
+        if (it.r.kind == SZ_REQ_COMPRESS)
+            rc = sz_compress(c, it.r.d_in, &it.r.dims, &it.r.params, s->st[slot], &cp.result);
+        else
+            rc = sz_decompress(c, it.r.src, it.r.d_out, s->st[slot]);
+        cp.t_done = s->now();
+        cp.status = rc;
+        const uint64_t keep =
+            (rc == SZ_OK && it.r.kind == SZ_REQ_COMPRESS) ? result_bytes(c, &cp.result) : 0;
+        lk.lock();
+        s->charged -= it.need;
+        if (keep) {
+            s->charged += keep;
+            s->held[cp.result.internal] = keep;
+        }
+        --s->running;
+        s->done.push_back(cp);
+        lk.unlock();
+        s->cv_done.notify_all();
+        s->cv_work.notify_all();
+    }
+}
+
+}  // namespace
+
 extern "C" {
 
 void sz_params_default(sz_params* p) {
@@ -649,6 +772,8 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
     int max_R = 0, max_chunk = 0;
     for (uint32_t i = 0; i < nf; ++i) {
         ResultInternal* R = new ResultInternal();
+    R->owner = c;
+        R->owner = c;
         res[i].internal = R;
         R->dims = dims[i];
         R->S = geo[i].S;
@@ -779,7 +904,7 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
         for (int sy = 0; sy < nsym; ++sy) bits += (uint64_t)hist[k][sy] * R->code_len[sy];
         const uint64_t nout = hist[k][0];
         const uint64_t wcap = bits / 32 + geo[i].nchunks + 1;
-        if ((s = res_alloc(c, R, wcap, &res[i].words))) return s;
+        if ((s = res_alloc(c, R, wcap + kWordPad, &res[i].words))) return s;
         if ((s = res_alloc(c, R, std::max<uint64_t>(nout, 1), &res[i].outlier_idx))) return s;
         if ((s = res_alloc(c, R, std::max<uint64_t>(nout, 1), &res[i].outlier_val))) return s;
         res[i].n_outliers = nout;
@@ -981,6 +1106,7 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         return s;
     HIP_TRY(c, hipMemcpyAsync(d_fd, fds.data(), sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
     HIP_TRY(c, hipMemcpyAsync(d_plan, plans.data(), sizeof(FieldPlan) * nf, hipMemcpyHostToDevice, st));
+    HIP_TRY(c, launch_pass_desc(d_fd, d_plan, (int)nf, st));
     HIP_TRY(c, hipMemcpyAsync(d_items, items.data(), sizeof(uint64_t) * items.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(c, hipMemcpyAsync(d_dboff, dboff.data(), sizeof(uint64_t) * (nf + 1), hipMemcpyHostToDevice, st));
     {
@@ -1184,7 +1310,7 @@ sz_status sz_upload(sz_ctx* c, const void* blob, uint64_t bytes, void* stream, s
     build_tables(R->code_len.data(), nsym, cbook.data(), dtab.data());
     if ((s = res_alloc(c, R, r.n_anchors, &r.anchors)) || (s = res_alloc(c, R, nsym, &r.code_len)) ||
         (s = res_alloc(c, R, std::max<uint64_t>(r.n_chunks, 1), &r.chunk_bits)) ||
-        (s = res_alloc(c, R, std::max<uint64_t>(r.n_words, 1), &r.words)) ||
+        (s = res_alloc(c, R, r.n_words + kWordPad, &r.words)) ||
         (s = res_alloc(c, R, std::max<uint64_t>(r.n_outliers, 1), &r.outlier_idx)) ||
         (s = res_alloc(c, R, std::max<uint64_t>(r.n_outliers, 1), &r.outlier_val)) ||
         (s = res_alloc(c, R, nsym, &R->d_cbook)) || (s = res_alloc(c, R, dtab.size(), &R->d_dtab))) {
@@ -1210,6 +1336,121 @@ sz_status sz_upload(sz_ctx* c, const void* blob, uint64_t bytes, void* stream, s
     std::memcpy(r.header, b, 256);
     r.compressed_bytes = bytes;
     *out = r;
+    return SZ_OK;
+}
+
+// ------------------------------------------------------------ serving
+sz_status sz_server_create(sz_server** out, int device, int slots, uint64_t hbm_budget_bytes) {
+    if (!out || slots < 1 || slots > 64) return SZ_ERR_INVALID_ARG;
+    *out = nullptr;
+    sz_server* s = new sz_server();
+    s->device = device;
+    s->budget = hbm_budget_bytes;
+    for (int i = 0; i < slots; ++i) {
+        sz_ctx* c = nullptr;
+        sz_status rc = sz_ctx_create(&c, device, 0);
+        hipStream_t st = nullptr;
+        if (rc == SZ_OK && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            sz_ctx_destroy(c);
+            rc = SZ_ERR_DEVICE;
+        }
+        if (rc != SZ_OK) {
+            for (size_t k = 0; k < s->ctx.size(); ++k) {
+                (void)hipStreamDestroy(s->st[k]);
+                sz_ctx_destroy(s->ctx[k]);
+            }
+            delete s;
+            return rc;
+        }
+        s->ctx.push_back(c);
+        s->st.push_back(st);
+    }
+    for (int i = 0; i < slots; ++i) s->th.emplace_back(server_worker, s, i);
+    *out = s;
+    return SZ_OK;
+}
+
+sz_status sz_server_submit(sz_server* s, const sz_request* req) {
+    if (!s || !req) return SZ_ERR_INVALID_ARG;
+    if (req->kind == SZ_REQ_COMPRESS ? !req->d_in : (req->kind != SZ_REQ_DECOMPRESS || !req->src ||
+                                                     !req->src->internal || !req->d_out))
+        return SZ_ERR_INVALID_ARG;
+    const uint64_t need = request_need(*req);
+    std::lock_guard<std::mutex> lk(s->m);
+    if (s->stop) return SZ_ERR_INVALID_ARG;
+    if (s->budget && need > s->budget) {
+        s->err = "request needs more device memory than the whole budget";
+        return SZ_ERR_OOM;
+    }
+    s->q.push_back({*req, need, s->now()});
+    s->cv_work.notify_one();
+    return SZ_OK;
+}
+
+sz_status sz_server_poll(sz_server* s, sz_completion* out, uint32_t cap, uint32_t* n, int wait) {
+    if (!s || !n || (cap && !out)) return SZ_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(s->m);
+    if (wait)
+        s->cv_done.wait(lk, [&] {
+            return !s->done.empty() || (s->running == 0 && (s->q.empty() || admissible(s) < 0));
+        });
+    uint32_t k = 0;
+    while (k < cap && !s->done.empty()) {
+        out[k++] = s->done.front();
+        s->done.pop_front();
+    }
+    *n = k;
+    return SZ_OK;
+}
+
+sz_status sz_server_result_free(sz_server* s, sz_result* res) {
+    if (!s || !res || !res->internal) return SZ_ERR_INVALID_ARG;
+    {
+        std::lock_guard<std::mutex> lk(s->m);
+        auto it = s->held.find(res->internal);
+        if (it == s->held.end()) return SZ_ERR_INVALID_ARG;
+        s->charged -= it->second;
+        s->held.erase(it);
+    }
+    release_result(ri(res)->owner, res);
+    std::memset(res, 0, sizeof *res);
+    s->cv_work.notify_all();
+    return SZ_OK;
+}
+
+sz_status sz_server_stats(sz_server* s, uint64_t* charged, uint64_t* queued, uint64_t* running) {
+    if (!s) return SZ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->m);
+    if (charged) *charged = s->charged;
+    if (queued) *queued = s->q.size();
+    if (running) *running = (uint64_t)s->running;
+    return SZ_OK;
+}
+
+const char* sz_server_last_error(const sz_server* s) { return s ? s->err.c_str() : ""; }
+
+sz_status sz_server_destroy(sz_server* s) {
+    if (!s) return SZ_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->m);
+        s->stop = true;
+        s->q.clear();   // requests not yet started are cancelled
+    }
+    s->cv_work.notify_all();
+    for (auto& t : s->th) t.join();   // running requests finish
+    for (auto& cp : s->done)
+        if (cp.result.internal) {
+            s->held.erase(cp.result.internal);
+            release_result(ri(&cp.result)->owner, &cp.result);
+        }
+    // results the caller did not free: their blocks go with the contexts
+    for (auto& kv : s->held) delete static_cast<ResultInternal*>(kv.first);
+    for (size_t k = 0; k < s->ctx.size(); ++k) {
+        (void)hipStreamDestroy(s->st[k]);
+        sz_ctx_destroy(s->ctx[k]);
+    }
+    delete s;
     return SZ_OK;
 }
 

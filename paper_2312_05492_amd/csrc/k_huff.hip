@@ -12,17 +12,15 @@
 // Decode: one lane per chunk, kDecChunks chunks per workgroup.
 //   k_chunk_words  word count of every chunk, sums per block
 //   k_scan_blocks  exclusive scan of the block sums
-//   k_huff_decode  in-block scan, then a table-driven canonical decode with
-//                  a prefetched word queue; symbols are staged in LDS and
-//                  written to global memory in coalesced rows
+//   k_huff_decode  in-block scan, then a table-driven canonical decode from
+//                  a 64-bit bit buffer and a prefetched word queue; eight
+//                  symbols per 16-byte store
 #include "dev_common.h"
 
 namespace szi {
 
 constexpr int kEncChunks = 16;
 constexpr int kDecChunks = 256;
-constexpr int kStage = 32;   // decoded symbols per lane staged in LDS
-constexpr int kStageRow = kStage + 2;   // u16 per staged row: 17 words, so rows spread over banks
 
 // symbols [s0, s0 + per) of the code array (all inside the field)
 template <int PER>
@@ -262,6 +260,25 @@ __global__ __launch_bounds__(kDecChunks) void k_chunk_words(const FieldDesc* __r
 
 // one lane decodes one chunk: canonical decode with a 2^kLutBits table for
 // short codes and a first-code search for longer ones
+// One lane per chunk.  The next bits sit most significant first in a 64-bit
+// buffer, topped up by one word whenever 32 or fewer remain (a lookup needs
+// at most kLmax = 24).  The words come from a 32-word ring per lane in LDS:
+// once per group of 8 symbols every lane requests its next 8 words from
+// global memory (two 16-byte loads, if the ring has room) and commits them
+// to the ring one group later, so global loads sit at fixed points and their
+// latency is covered by a group of decoding.  A group consumes at most 6
+// words and the ring always holds at least 7 ahead of the buffer.  Each
+// top-up also reads the following ring word, which LDS returns in order
+// ahead of the next table lookups.  Symbols leave 8 at a time in one 16-byte
+// store.
+constexpr int kRing = 32;   // ring words per lane (power of 2)
+
+__device__ __forceinline__ int ring_slot(uint32_t i, uint32_t sw) {
+    // 16-byte groups of the ring are permuted per lane, so that lanes at the
+    // same ring position hit different LDS banks
+    return (int)((((i >> 2) ^ sw) & (kRing / 4 - 1)) << 2 | (i & 3u));
+}
+
 __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __restrict__ F,
                                                             int nfields,
                                                             const uint64_t* __restrict__ boff,
@@ -271,9 +288,9 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
     const FieldDesc& fd = F[f];
     const int nsym = 2 * fd.R;
     const int ntab = dtab_words(nsym);
-    uint32_t* tab = smem;
-    uint32_t* scan = smem + ntab;                                     // kDecChunks
-    uint16_t* stage = reinterpret_cast<uint16_t*>(scan + kDecChunks);  // kDecChunks x kStageRow
+    uint32_t* scan = smem;                                   // kDecChunks / 64
+    uint32_t* rings = smem + kDecChunks / 64;                // kDecChunks x kRing, 16-byte aligned
+    uint32_t* tab = rings + kDecChunks * kRing;
     for (int k = threadIdx.x; k < ntab; k += blockDim.x) tab[k] = gp(fd.dtab)[k];
     const int tid = threadIdx.x;
     const uint64_t first = (blockIdx.x - boff[f]) * kDecChunks;
@@ -288,85 +305,112 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
     __syncthreads();
     uint32_t before = 0;
     for (int k = 0; k < (tid >> 6); ++k) before += scan[k];
-    __syncthreads();
     const uint64_t w0 = bwoff[blockIdx.x] - bwoff[boff[f]] + before + wx;
-    // never read past the field's word array, whatever the chunk sizes say
-    const uint64_t wend = w0 + nw < fd.words_cap ? w0 + nw : fd.words_cap;
-    const SZI_G uint32_t* words = gp(fd.words);
     const int C = fd.chunk;
     const uint64_t s0 = ch * (uint64_t)C;
     const int cnt = !live ? 0 : (s0 + C <= fd.npts ? C : (int)(fd.npts - s0));
-    // Words enter the 64-bit bit buffer from an 8-word queue.  The queue is
-    // reloaded at the start of every stage of kStage symbols with all eight
-    // loads in flight at once, so the decode loop itself never waits on
-    // memory unless a stage needs more than 8 words (long codes).
-    uint64_t wp = w0;          // next word not yet shifted into the bit buffer
-    uint64_t buf = 0;          // next bits, most significant first
-    int nb = 0;
-    const int rows_per_pass = kDecChunks * kStage;
-    for (int k0 = 0; k0 < C; k0 += kStage) {
-        uint32_t q0, q1, q2, q3, q4, q5, q6, q7;
-        q0 = wp + 0 < wend ? words[wp + 0] : 0u;
-        q1 = wp + 1 < wend ? words[wp + 1] : 0u;
-        q2 = wp + 2 < wend ? words[wp + 2] : 0u;
-        q3 = wp + 3 < wend ? words[wp + 3] : 0u;
-        q4 = wp + 4 < wend ? words[wp + 4] : 0u;
-        q5 = wp + 5 < wend ? words[wp + 5] : 0u;
-        q6 = wp + 6 < wend ? words[wp + 6] : 0u;
-        q7 = wp + 7 < wend ? words[wp + 7] : 0u;
-        int qn = 8;
-        for (int k = 0; k < kStage; ++k) {
-            if (k0 + k >= cnt) break;
-            if (nb <= 32) {
-                uint32_t nxt;
-                if (qn > 0) {
-                    nxt = q0;
-                    q0 = q1; q1 = q2; q2 = q3; q3 = q4; q4 = q5; q5 = q6; q6 = q7;
-                    --qn;
-                } else {
-                    nxt = wp < wend ? words[wp] : 0u;   // more than 8 words in one stage
-                }
-                ++wp;
-                buf |= (uint64_t)nxt << (32 - nb);
-                nb += 32;
-            }
-            const uint32_t e = tab[buf >> (64 - kLutBits)];
-            uint32_t len = e >> 16, sym = e & 0xFFFFu;
-            if (len == 0) {
-                for (int l = kLutBits + 1; l <= kLmax; ++l) {
-                    const uint32_t code = (uint32_t)(buf >> (64 - l));
-                    const uint32_t rel = code - tab[kDtFirst + l];
-                    if (rel < tab[kDtCount + l]) {
-                        sym = tab[kDtSorted + tab[kDtOffset + l] + rel];
-                        len = l;
-                        break;
-                    }
-                }
-                if (len == 0) len = 1;   // corrupt stream: consume a bit and go on
-            }
-            stage[tid * kStageRow + k] = (uint16_t)sym;
-            buf <<= len;
-            nb -= (int)len;
+    if (cnt == 0) return;
+    // requests start at the 4-aligned word at or below w0 and stop at the
+    // end of the field's words (the array has kWordPad words of slack, so
+    // the 8-word loads of the last request stay inside it)
+    const uint64_t wcap = fd.words_cap;
+    const SZI_G uint32_t* words = gp(fd.words);
+    uint32_t* ring = rings + tid * kRing;
+    const uint32_t sw = (uint32_t)tid & (kRing / 4 - 1);
+    uint64_t wr = w0 & ~(uint64_t)3;   // next word to request
+    uint64_t rd = w0;                  // next word to move into the buffer
+    auto put = [&](uint64_t at, vu4 a, vu4 b) {   // words [at, at + 8) into the ring
+        *reinterpret_cast<vu4*>(ring + ring_slot((uint32_t)at, sw)) = a;
+        *reinterpret_cast<vu4*>(ring + ring_slot((uint32_t)at + 4u, sw)) = b;
+    };
+    // prime the ring with 16 words
+    {
+        vu4 a = {0u, 0u, 0u, 0u}, b = a, c = a, d = a;
+        if (wr < wcap) {
+            a = *reinterpret_cast<const SZI_G vu4*>(words + wr);
+            b = *reinterpret_cast<const SZI_G vu4*>(words + wr + 4);
         }
-        // wp counts the words shifted into the bit buffer: the words left in
-        // the queue are reloaded by the next stage
-        __syncthreads();
-        // write the staged rows: row r holds kStage symbols of chunk first + r
-        const uint32_t* st32 = reinterpret_cast<const uint32_t*>(stage);
-        for (int e = tid; e < rows_per_pass / 2; e += kDecChunks) {
-            const int r = e / (kStage / 2), c2 = e % (kStage / 2);
-            const uint64_t chr = first + r;
-            if (chr >= fd.nchunks) continue;
-            const uint64_t sb = chr * (uint64_t)C + k0 + 2 * c2;
-            const int se = r * kStageRow + 2 * c2;   // staged symbol index
-            if (sb + 1 < fd.npts && ((sb & 1) == 0)) {
-                *reinterpret_cast<SZI_G uint32_t*>(gp(fd.codes) + sb) = st32[se / 2];
-            } else {
-                if (sb < fd.npts) gp(fd.codes)[sb] = stage[se];
-                if (sb + 1 < fd.npts) gp(fd.codes)[sb + 1] = stage[se + 1];
-            }
+        if (wr + 8 < wcap) {
+            c = *reinterpret_cast<const SZI_G vu4*>(words + wr + 8);
+            d = *reinterpret_cast<const SZI_G vu4*>(words + wr + 12);
         }
-        __syncthreads();
+        put(wr, a, b);
+        put(wr + 8, c, d);
+        wr += 16;
+    }
+    auto rword = [&](uint64_t i) { return ring[ring_slot((uint32_t)i, sw)]; };
+    uint64_t buf = ((uint64_t)rword(rd) << 32) | (uint64_t)rword(rd + 1);
+    rd += 2;
+    int nb = 64;
+    uint32_t nxw = rword(rd);   // the ring word the next top-up takes
+    auto decode_one = [&]() -> uint32_t {
+        if (nb <= 32) {
+            buf |= (uint64_t)nxw << (32 - nb);
+            nb += 32;
+            ++rd;
+            nxw = rword(rd);
+        }
+        const uint32_t e = tab[(uint32_t)(buf >> (64 - kLutBits))];
+        uint32_t len = e >> 16, sym = e & 0xFFFFu;
+        if (len == 0) {   // longer than the table: canonical decode
+#pragma unroll 1
+            for (int l = kLutBits + 1; l <= kLmax; ++l) {
+                const uint32_t code = (uint32_t)(buf >> (64 - l));
+                const uint32_t rel = code - tab[kDtFirst + l];
+                if (rel < tab[kDtCount + l]) {
+                    sym = tab[kDtSorted + tab[kDtOffset + l] + rel];
+                    len = l;
+                    break;
+                }
+            }
+            if (len == 0) len = 1;   // corrupt stream: consume a bit and go on
+        }
+        buf <<= len;
+        nb -= (int)len;
+        return sym;
+    };
+    SZI_G uint16_t* out = gp(fd.codes) + s0;
+    const bool vec = ((uintptr_t)fd.codes & 15u) == 0u;   // s0 and k are multiples of 8
+    // a group: commit the previous request, maybe request 8 more words,
+    // decode n <= 8 symbols
+    bool pend = false;
+    uint64_t pat = 0;
+    vu4 la = {0u, 0u, 0u, 0u}, lb = la;
+    int k = 0;
+#pragma unroll 1
+    while (k < cnt) {
+        if (pend) put(pat, la, lb);
+        // the ring holds [rd, wr) and a request adds 8; the prefetched word
+        // at rd is not overwritten because the ring keeps kRing - 8 >= 7
+        pend = wr < wcap && wr + 8 - rd <= (uint64_t)kRing;
+        if (pend) {
+            pat = wr;
+            la = *reinterpret_cast<const SZI_G vu4*>(words + wr);
+            lb = *reinterpret_cast<const SZI_G vu4*>(words + wr + 4);
+            wr += 8;
+        }
+        if (vec && k + 8 <= cnt) {
+            vu4 pk;
+            uint32_t lo, hi;
+            lo = decode_one();
+            hi = decode_one();
+            pk.x = lo | (hi << 16);
+            lo = decode_one();
+            hi = decode_one();
+            pk.y = lo | (hi << 16);
+            lo = decode_one();
+            hi = decode_one();
+            pk.z = lo | (hi << 16);
+            lo = decode_one();
+            hi = decode_one();
+            pk.w = lo | (hi << 16);
+            *reinterpret_cast<SZI_G vu4*>(out + k) = pk;
+            k += 8;
+        } else {
+            const int e = k + 8 < cnt ? k + 8 : cnt;
+#pragma unroll 1
+            for (; k < e; ++k) out[k] = (uint16_t)decode_one();
+        }
     }
 }
 
@@ -434,8 +478,8 @@ hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields, const uint
                               uint64_t nblocks, const uint64_t* d_bwoff, int max_nsym,
                               hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
-    const size_t lds = (size_t)(dtab_words(max_nsym) + kDecChunks) * sizeof(uint32_t) +
-                       (size_t)kDecChunks * kStageRow * sizeof(uint16_t);
+    const size_t lds =
+        (size_t)(kDecChunks / 64 + kDecChunks * kRing + dtab_words(max_nsym)) * sizeof(uint32_t);
     hipLaunchKernelGGL(k_huff_decode, dim3((unsigned)nblocks), dim3(kDecChunks), lds, st,
                        d_fields, nfields, d_dboff, d_bwoff);
     return hipGetLastError();

@@ -30,28 +30,6 @@ constexpr int kPad = 8;                 // guard floats on both sides of a block
 constexpr int kXcds = 8;                // L2 domains; workgroup i runs on domain i % kXcds
 
 template <int ND>
-struct Geo;
-template <>
-struct Geo<3> {
-    static constexpr int W0 = 32, W1 = 8, W2 = 8;   // window
-    static constexpr int B0 = 33, B1 = 9, B2 = 9;   // block (window + far faces)
-    static constexpr int SY = 33, SZ = 297;         // LDS strides
-    static constexpr int BN = B0 * B1 * B2;
-    static constexpr int SHS = 3;                   // log2 of the anchor stride
-    static constexpr int NPRE = 43;                 // block values per lane
-    static constexpr int NANCH = 20;                // anchors in a block
-};
-template <>
-struct Geo<2> {
-    static constexpr int W0 = 64, W1 = 16, W2 = 1;
-    static constexpr int B0 = 65, B1 = 17, B2 = 1;
-    static constexpr int SY = 65, SZ = 0;
-    static constexpr int BN = B0 * B1;
-    static constexpr int SHS = 4;
-    static constexpr int NPRE = 18;
-    static constexpr int NANCH = 10;
-};
-template <int ND>
 constexpr int vlen() { return kPad + Geo<ND>::BN + kPad; }
 template <int ND>
 constexpr int qlen() { return (Geo<ND>::BN + 2) & ~1; }
@@ -221,19 +199,42 @@ __device__ __forceinline__ bool anchor_slot(uint32_t lane, const FieldDesc& f, c
 }
 
 // ------------------------------------------------------------------ passes
+// Division by 40 in the natural cubic, as a multiply by RN(1/40) followed
+// by one fused multiply-add correction (Brisebarre, Muller and Raina,
+// "Accelerating correctly rounded floating-point division when the divisor
+// is known in advance", IEEE Trans. Computers 53(8), 2004).  Checked
+// exhaustively over all FP32 inputs: equal to the correctly rounded x / 40
+// for 2^-123 <= |x| < inf.  Other inputs take the division.
+__device__ __forceinline__ float div40_fast(float x) {
+    const float c = 0.025f;
+    const float q0 = x * c;
+    const float r = fmaf(-q0, 40.0f, x);
+    return fmaf(r, c, q0);
+}
+__device__ __forceinline__ bool div40_fast_ok(float x) {
+    const float ax = fabsf(x);
+    return ax >= 0x1p-123f && ax < INFINITY;
+}
+
 // Sec. V-B.1 splines by neighbour availability (a = x[-3s], b = x[-s],
-// c = x[+s], d = x[+3s]); with one neighbour the value of x[-s].
+// c = x[+s], d = x[+3s]); with one neighbour the value of x[-s].  For the
+// natural cubic, num receives the numerator and cub whether it was used.
 template <int SPL>
 __device__ __forceinline__ float predict(bool m3, bool p1, bool p3, float a, float b, float c,
-                                         float d) {
+                                         float d, float& num, bool& cub) {
     const float sbc = b + c;
     float p = sbc * 0.5f;
+    num = 0.0f;
+    cub = false;
     if (SPL != SPL_LIN) {
         if (m3 && p3) {
-            if (SPL == SPL_NAT)
-                p = (23.0f * sbc - 3.0f * (a + d)) / 40.0f;   // natural cubic
-            else
+            if (SPL == SPL_NAT) {
+                num = 23.0f * sbc - 3.0f * (a + d);           // natural cubic, / 40
+                p = div40_fast(num);
+                cub = p1;
+            } else {
                 p = (9.0f * sbc - (a + d)) * 0.0625f;         // not-a-knot cubic
+            }
         } else if (m3) {
             p = ((6.0f * b + 3.0f * c) - a) * 0.125f;         // quadratic on a, b, c
         } else if (p3) {
@@ -243,20 +244,27 @@ __device__ __forceinline__ float predict(bool m3, bool p1, bool p3, float a, flo
     return p1 ? p : b;
 }
 
-// Quantiser constants of one level (Sec. III-A, Eq. 1).
-struct LvlQ {
-    float ebx2, inv, Rf;
-    double eld;
-    int R;
-    bool zero;   // e_l == 0: only exact predictions are kept
+// LDS values of one task: K targets of one line (segment seg, starting at
+// LDS index base), the K + 3 knowns around them and the targets' original
+// values (compression) or quant-codes (decompression).
+template <int K>
+struct Task {
+    int base;
+    uint32_t seg;
+    float kn[K + 3];
+    float xt[K];
+    uint32_t ct[K];
 };
 
-// One pass: dimension D, stride 1 << SH, spline SPL, over ntask tasks of
-// K targets.  Line i0 + ne * i1 starts at LDS index i0 * le + i1 * lf.
+// One pass: dimension D, stride s = 1 << SH, spline SPL.  FULL: the window
+// interval along D is the whole block, so the stencil flags are constants.
+// Tasks are software-pipelined: the LDS reads of a lane's next task are
+// issued before the current one is computed.  Within a pass no task reads a
+// point another task writes (targets never neighbour each other along D and
+// knowns are not written), so the reordering is safe.
 template <int ND, int D, int SH, int SPL, bool COMP, bool FULL>
-__device__ __forceinline__ void pass_lines(float* v, uint16_t* q, uint32_t lane, uint32_t ntask,
-                                           uint32_t ne, FastDiv dvn, int le, int lf, int ed,
-                                           const LvlQ& lq) {
+__device__ __forceinline__ void pass_lines(float* v, uint16_t* q, uint32_t lane,
+                                           const PassDesc& pd, int ed, int R) {
     using G = Geo<ND>;
     constexpr int s = 1 << SH;
     constexpr int W = D == 0 ? G::W0 : (D == 1 ? G::W1 : G::W2);
@@ -266,84 +274,125 @@ __device__ __forceinline__ void pass_lines(float* v, uint16_t* q, uint32_t lane,
     constexpr int NSEG = T / K;
     static_assert(NSEG == 1 || D == 0, "lines split into segments run along x only");
     static_assert(NSEG == 1 || 2 * s <= kPad, "guard band narrower than the stencil");
-#pragma unroll 1
-    for (uint32_t t = lane; t < ntask; t += 64) {
-        const uint32_t seg = NSEG > 1 ? (t & (uint32_t)(NSEG - 1)) : 0u;
+    const uint32_t ntask = pd.nlines * (uint32_t)NSEG;
+    const uint32_t ne = pd.ne, magic = pd.magic;
+    const int le = pd.le, lf = pd.lf;
+    const float ebx2 = pd.ebx2, inv = pd.inv, Rf = (float)R;
+    const double eld = (double)pd.el;
+
+    auto fetch = [&](uint32_t t, Task<K>& tk) {
+        tk.seg = NSEG > 1 ? (t & (uint32_t)(NSEG - 1)) : 0u;
         const uint32_t ln = NSEG > 1 ? t / (uint32_t)NSEG : t;
-        const uint32_t i1 = dvn.div(ln);
+        const uint32_t i1 = __umulhi(ln, magic);   // ln / ne (ne >= 2, ln < 2^16)
         const uint32_t i0 = ln - i1 * ne;
-        const int p0 = (int)seg * (2 * K * s);   // segment start along D
-        const int base = (int)i0 * le + (int)i1 * lf + p0 * SD;
+        tk.base = (int)i0 * le + (int)i1 * lf + (int)tk.seg * (2 * K * s) * SD;
         // knowns at (2i - 2) s from the segment start; whole lines read only
         // the ones inside the block, split lines all of them (the guard band
         // and the neighbouring line absorb the ends; the flags drop them)
-        float kn[K + 3];
 #pragma unroll
         for (int i = 0; i < K + 3; ++i) {
             const int pos = (2 * i - 2) * s;
-            kn[i] = (NSEG > 1 || (pos >= 0 && pos <= W)) ? v[base + pos * SD] : 0.0f;
+            tk.kn[i] = (NSEG > 1 || (pos >= 0 && pos <= W)) ? v[tk.base + pos * SD] : 0.0f;
         }
-        float xt[K];
-        uint32_t ct[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const int li = base + (2 * j + 1) * s * SD;
+            const int li = tk.base + (2 * j + 1) * s * SD;
             if (COMP)
-                xt[j] = v[li];
+                tk.xt[j] = v[li];
             else
-                ct[j] = q[li];
+                tk.ct[j] = q[li];
         }
+    };
+
+    auto compute = [&](const Task<K>& tk) {
+        const int p0 = (int)tk.seg * (2 * K * s);   // segment start along D
+        float pr[K], nm[K];
+        bool cub[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int pos = (2 * j + 1) * s;   // target position in the segment
-            const bool m3 = NSEG > 1 ? (j >= 1 || seg > 0u) : (j >= 1);
-            bool p3 = NSEG > 1 ? (j <= K - 2 || seg < (uint32_t)(NSEG - 1))
+            const bool m3 = NSEG > 1 ? (j >= 1 || tk.seg > 0u) : (j >= 1);
+            bool p3 = NSEG > 1 ? (j <= K - 2 || tk.seg < (uint32_t)(NSEG - 1))
                                : ((2 * j + 4) * s <= W);
             bool p1 = true;
             if (!FULL) {   // the window interval ends at ed - 1
                 p1 = p0 + pos + s <= ed - 1;
                 p3 = p0 + pos + 3 * s <= ed - 1;
             }
-            const float p = predict<SPL>(m3, p1, p3, kn[j], kn[j + 1], kn[j + 2], kn[j + 3]);
-            const int li = base + pos * SD;
+            pr[j] = predict<SPL>(m3, p1, p3, tk.kn[j], tk.kn[j + 1], tk.kn[j + 2], tk.kn[j + 3],
+                                 nm[j], cub[j]);
+        }
+        if (SPL == SPL_NAT) {   // numerators outside the fast division's range: rare
+            bool need = false;
+#pragma unroll
+            for (int j = 0; j < K; ++j) need = need || (cub[j] && !div40_fast_ok(nm[j]));
+            if (__any(need)) {
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+                    if (cub[j] && !div40_fast_ok(nm[j])) pr[j] = nm[j] / 40.0f;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const float p = pr[j];
+            const int li = tk.base + (2 * j + 1) * s * SD;
             if (COMP) {
-                // closed-loop quantisation against e_l, with the exact check
-                const float xv = xt[j];
+                // closed-loop quantisation against e_l, with the exact check;
+                // with e_l = 0, inv = 0 gives q = 0 and xr = p + 0 (exact
+                // predictions only: xr == x iff diff == 0)
+                const float xv = tk.xt[j];
                 const float diff = xv - p;
-                const float qr = rintf(diff * lq.inv);   // round half to even
+                const float qr = rintf(diff * inv);   // round half to even
                 const int qi = (int)qr;
-                const float xr = lq.zero ? p : p + (float)qi * lq.ebx2;
+                const float xr = p + (float)qi * ebx2;
                 // |rint(qf)| < R holds iff |qf| < R and |q| < R; NaN fails it
-                const bool ok = fabsf(qr) < lq.Rf && fabs((double)xv - (double)xr) <= lq.eld;
+                const bool ok = fabsf(qr) < Rf && fabs((double)xv - (double)xr) <= eld;
                 v[li] = ok ? xr : xv;
-                q[li] = (uint16_t)(ok ? qi + lq.R : 0);
+                q[li] = (uint16_t)(ok ? qi + R : 0);
             } else {
-                const uint32_t code = ct[j];
-                const float tq = (float)((int)code - lq.R) * lq.ebx2;
+                const uint32_t code = tk.ct[j];
+                const float tq = (float)((int)code - R) * ebx2;
                 if (code != 0u) v[li] = p + tq;   // code 0: outlier, value already staged
             }
         }
+    };
+
+    // two task slots in turn, so that no values are copied between them
+    uint32_t t = lane;
+    if (t >= ntask) return;
+    Task<K> ta, tb;
+    fetch(t, ta);
+#pragma unroll 1
+    while (true) {
+        t += 64;
+        bool more = t < ntask;
+        if (more) fetch(t, tb);
+        compute(ta);
+        if (!more) break;
+        t += 64;
+        more = t < ntask;
+        if (more) fetch(t, ta);
+        compute(tb);
+        if (!more) break;
     }
 }
 
-template <int ND, int D, int SH, bool COMP, bool FULL>
-__device__ __forceinline__ void pass_spline(float* v, uint16_t* q, uint32_t lane, int spl,
-                                            uint32_t nlines, uint32_t ne, int le, int lf,
-                                            const Win& wi, const LvlQ& lq) {
+template <int ND, int D, int SH, bool COMP>
+__device__ __forceinline__ void run_pass(float* v, uint16_t* q, uint32_t lane, const PassDesc& pd,
+                                         const Win& wi, int R) {
     using G = Geo<ND>;
     constexpr int W = D == 0 ? G::W0 : (D == 1 ? G::W1 : G::W2);
-    constexpr int T = W / (2 << SH);
-    constexpr int NSEG = T > 8 ? T / 8 : 1;
-    const uint32_t ntask = nlines * (uint32_t)NSEG;
     const int ed = D == 0 ? wi.e0 : (D == 1 ? wi.e1 : wi.e2);
-    FastDiv dvn;
-    dvn.set(ne);
-    if (spl == SPL_LIN)
-        pass_lines<ND, D, SH, SPL_LIN, COMP, FULL>(v, q, lane, ntask, ne, dvn, le, lf, ed, lq);
-    else if (spl == SPL_NAT)
-        pass_lines<ND, D, SH, SPL_NAT, COMP, FULL>(v, q, lane, ntask, ne, dvn, le, lf, ed, lq);
-    else
-        pass_lines<ND, D, SH, SPL_NAK, COMP, FULL>(v, q, lane, ntask, ne, dvn, le, lf, ed, lq);
+    // the stencil flags depend on the extent along D only
+    if (ed == W + 1) {
+        if (pd.spl == SPL_LIN) pass_lines<ND, D, SH, SPL_LIN, COMP, true>(v, q, lane, pd, ed, R);
+        else if (pd.spl == SPL_NAT) pass_lines<ND, D, SH, SPL_NAT, COMP, true>(v, q, lane, pd, ed, R);
+        else pass_lines<ND, D, SH, SPL_NAK, COMP, true>(v, q, lane, pd, ed, R);
+    } else {
+        if (pd.spl == SPL_LIN) pass_lines<ND, D, SH, SPL_LIN, COMP, false>(v, q, lane, pd, ed, R);
+        else if (pd.spl == SPL_NAT) pass_lines<ND, D, SH, SPL_NAT, COMP, false>(v, q, lane, pd, ed, R);
+        else pass_lines<ND, D, SH, SPL_NAK, COMP, false>(v, q, lane, pd, ed, R);
+    }
 }
 
 // A wave's own LDS accesses execute in program order; this keeps the
@@ -354,69 +403,28 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The passes of one level (stride s = 1 << SH).  Along the pass dimension
-// the odd multiples of s; along dimensions already passed at this level the
-// multiples of s, along those still to come the multiples of 2s.
-template <int ND, int SH, bool COMP, bool FULL>
+// The passes of one level (stride 1 << SH), in the planned order.
+template <int ND, int SH, bool COMP>
 __device__ __forceinline__ void run_level(float* v, uint16_t* q, uint32_t lane,
                                           const FieldPlan& pl, int R, const Win& wi) {
-    using G = Geo<ND>;
-    constexpr int s = 1 << SH;
-    LvlQ lq;
-    const float el = pl.el[SH];
-    lq.zero = el == 0.0f;
-    lq.ebx2 = pl.ebx2[SH];
-    lq.inv = lq.zero ? 0.0f : pl.inv[SH];
-    lq.eld = (double)el;
-    lq.R = R;
-    lq.Rf = (float)R;
-    const int o0 = pl.order[0], o1 = pl.order[1];
+    constexpr int L = ND == 3 ? 3 : 4;
 #pragma unroll 1
     for (int k = 0; k < ND; ++k) {
-        const int d = k == 0 ? o0 : (k == 1 ? o1 : pl.order[2]);
-        auto step = [&](int j) {   // line spacing along dimension j
-            const int pj = o0 == j ? 0 : (o1 == j ? 1 : 2);
-            return pj < k ? s : 2 * s;
-        };
-        if constexpr (ND == 3) {
-            const int e = d == 0 ? 1 : 0, f = d == 2 ? 1 : 2;
-            const int se = step(e), sf = step(f);
-            const uint32_t ne = (uint32_t)((e == 0 ? G::W0 : G::W1) / se + 1);
-            const uint32_t nf = (uint32_t)((f == 1 ? G::W1 : G::W2) / sf + 1);
-            const int le = se * (e == 0 ? 1 : G::SY);
-            const int lf = sf * (f == 1 ? G::SY : G::SZ);
-            if (d == 0)
-                pass_spline<ND, 0, SH, COMP, FULL>(v, q, lane, pl.spline[0], ne * nf, ne, le, lf,
-                                                   wi, lq);
-            else if (d == 1)
-                pass_spline<ND, 1, SH, COMP, FULL>(v, q, lane, pl.spline[1], ne * nf, ne, le, lf,
-                                                   wi, lq);
-            else
-                pass_spline<ND, 2, SH, COMP, FULL>(v, q, lane, pl.spline[2], ne * nf, ne, le, lf,
-                                                   wi, lq);
-        } else {
-            const int e = 1 - d;
-            const int se = step(e);
-            const uint32_t ne = (uint32_t)((e == 0 ? G::W0 : G::W1) / se + 1);
-            const int le = se * (e == 0 ? 1 : G::SY);
-            if (d == 0)
-                pass_spline<ND, 0, SH, COMP, FULL>(v, q, lane, pl.spline[0], ne, ne, le, 0, wi,
-                                                   lq);
-            else
-                pass_spline<ND, 1, SH, COMP, FULL>(v, q, lane, pl.spline[1], ne, ne, le, 0, wi,
-                                                   lq);
-        }
+        const PassDesc pd = pl.pass[(L - 1 - SH) * ND + k];
+        if (pd.d == 0) run_pass<ND, 0, SH, COMP>(v, q, lane, pd, wi, R);
+        else if (ND == 2 || pd.d == 1) run_pass<ND, 1, SH, COMP>(v, q, lane, pd, wi, R);
+        else if constexpr (ND == 3) run_pass<ND, 2, SH, COMP>(v, q, lane, pd, wi, R);
         wave_sync();
     }
 }
 
-template <int ND, bool COMP, bool FULL>
+template <int ND, bool COMP>
 __device__ __forceinline__ void run_levels(float* v, uint16_t* q, uint32_t lane,
                                            const FieldPlan& pl, int R, const Win& wi) {
-    if constexpr (ND == 2) run_level<ND, 3, COMP, FULL>(v, q, lane, pl, R, wi);
-    run_level<ND, 2, COMP, FULL>(v, q, lane, pl, R, wi);
-    run_level<ND, 1, COMP, FULL>(v, q, lane, pl, R, wi);
-    run_level<ND, 0, COMP, FULL>(v, q, lane, pl, R, wi);
+    if constexpr (ND == 2) run_level<ND, 3, COMP>(v, q, lane, pl, R, wi);
+    run_level<ND, 2, COMP>(v, q, lane, pl, R, wi);
+    run_level<ND, 1, COMP>(v, q, lane, pl, R, wi);
+    run_level<ND, 0, COMP>(v, q, lane, pl, R, wi);
 }
 
 // ---------------------------------------------------------------- write-out
@@ -621,13 +629,9 @@ __global__ __launch_bounds__(kThreads) void k_compress(const FieldDesc* __restri
             wave_sync();
             const FieldDesc& fd = F[fc];
             const FieldPlan& pl = P[fc];
-            if (wc.full) {
-                run_levels<ND, true, true>(v, q, lane, pl, fd.R, wc);
-                write_codes<ND, true>(q, v, lane, fd, wc, hist, cntR);
-            } else {
-                run_levels<ND, true, false>(v, q, lane, pl, fd.R, wc);
-                write_codes<ND, false>(q, v, lane, fd, wc, hist, cntR);
-            }
+            run_levels<ND, true>(v, q, lane, pl, fd.R, wc);
+            if (wc.full) write_codes<ND, true>(q, v, lane, fd, wc, hist, cntR);
+            else write_codes<ND, false>(q, v, lane, fd, wc, hist, cntR);
             wave_sync();
         }
         if (!more) break;
@@ -709,13 +713,9 @@ __global__ __launch_bounds__(kThreads) void k_decompress(const FieldDesc* __rest
             wave_sync();
             const FieldDesc& fd = F[fc];
             const FieldPlan& pl = P[fc];
-            if (wc.full) {
-                run_levels<ND, false, true>(v, q, lane, pl, fd.R, wc);
-                write_values<ND, true>(v, lane, fd, wc);
-            } else {
-                run_levels<ND, false, false>(v, q, lane, pl, fd.R, wc);
-                write_values<ND, false>(v, lane, fd, wc);
-            }
+            run_levels<ND, false>(v, q, lane, pl, fd.R, wc);
+            if (wc.full) write_values<ND, true>(v, lane, fd, wc);
+            else write_values<ND, false>(v, lane, fd, wc);
             wave_sync();
         }
         if (!more) break;

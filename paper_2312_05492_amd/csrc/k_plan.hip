@@ -150,6 +150,66 @@ __device__ float floor_to_f32(double v) {
     return f;
 }
 
+// The passes of a window in execution order, from the plan's order, splines
+// and level bounds.  Along the pass dimension d the odd multiples of s;
+// along dimensions already passed at this level the multiples of s, along
+// those still to come the multiples of 2s (Sec. V-A).
+template <int ND>
+__device__ void make_passes(FieldPlan& p, int L) {
+    using G = Geo<ND>;
+    const int W[3] = {G::W0, G::W1, G::W2};
+    const int ST[3] = {1, G::SY, G::SZ};
+    int np = 0;
+    for (int lvl = L; lvl >= 1; --lvl) {
+        const int s = 1 << (lvl - 1);
+        for (int k = 0; k < ND; ++k, ++np) {
+            PassDesc& q = p.pass[np];
+            const int d = p.order[k];
+            int e = -1, g = -1;   // the other dimensions, ascending
+            for (int j = 0; j < ND; ++j) {
+                if (j == d) continue;
+                if (e < 0) e = j; else g = j;
+            }
+            auto step = [&](int j) {
+                int pj = 0;
+                while (p.order[pj] != j) ++pj;
+                return pj < k ? s : 2 * s;
+            };
+            const int se = step(e);
+            q.d = d;
+            q.spl = p.spline[d];
+            q.sh = lvl - 1;
+            q.ne = (uint32_t)(W[e] / se + 1);
+            q.le = se * ST[e];
+            if (g >= 0) {
+                const int sg = step(g);
+                q.nlines = q.ne * (uint32_t)(W[g] / sg + 1);
+                q.lf = sg * ST[g];
+            } else {
+                q.nlines = q.ne;
+                q.lf = 0;
+            }
+            q.magic = kMagic.v[q.ne];
+            q.el = p.el[lvl - 1];
+            q.ebx2 = p.ebx2[lvl - 1];
+            q.inv = q.el == 0.0f ? 0.0f : p.inv[lvl - 1];
+            q.pad = 0;
+        }
+    }
+    for (; np < kMaxPasses; ++np) p.pass[np] = PassDesc{};
+}
+
+__device__ void make_passes(const FieldDesc& f, FieldPlan& p) {
+    if (f.ndim == 3) make_passes<3>(p, f.L);
+    else make_passes<2>(p, f.L);
+}
+
+// pass descriptors of plans that came from the host (decompression)
+__global__ void k_pass_desc(const FieldDesc* __restrict__ F, FieldPlan* P, int nfields) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nfields) make_passes(F[i], P[i]);
+}
+
 __global__ __launch_bounds__(256) void k_plan(const FieldDesc* __restrict__ F, FieldPlan* P,
                                               const float* pmin, const float* pmax,
                                               const uint32_t* pbad) {
@@ -235,6 +295,7 @@ __global__ __launch_bounds__(256) void k_plan(const FieldDesc* __restrict__ F, F
             p.order[k] = best;
         }
     }
+    make_passes(f, p);
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
@@ -262,6 +323,14 @@ hipError_t launch_plan(const FieldDesc* d_fields, FieldPlan* d_plans, int nfield
                        const uint32_t* d_part_bad, hipStream_t st) {
     hipLaunchKernelGGL(k_plan, dim3(nfields), dim3(256), 0, st, d_fields, d_plans, d_part_min,
                        d_part_max, d_part_bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass_desc(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
+                            hipStream_t st) {
+    if (nfields <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pass_desc, dim3((unsigned)((nfields + 63) / 64)), dim3(64), 0, st,
+                       d_fields, d_plans, nfields);
     return hipGetLastError();
 }
 

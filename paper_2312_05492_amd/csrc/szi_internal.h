@@ -15,6 +15,7 @@ constexpr int kRangeBlocks = 1024; // partial min/max blocks per field
 constexpr int kThreads = 256;      // threads per interpolation workgroup
 constexpr int kEncBlockChunks = 16;   // Huffman chunks per encode workgroup
 constexpr int kDecBlockChunks = 256;  // Huffman chunks per decode workgroup
+constexpr int kWordPad = 8;        // allocated u32 past the end of every Huffman word array
 
 // Static description of one field, written by the host before launch.
 struct FieldDesc {
@@ -50,6 +51,20 @@ struct FieldDesc {
     const uint32_t* dtab;  // decode tables (see DecodeTables layout)
 };
 
+// One pass of the interpolation (Sec. V-A: levels from stride S/2 to 1, one
+// pass per dimension in the planned order), as the window kernels run it:
+// the points of the pass lie on nlines lines along dimension d, line
+// i0 + ne * i1 starting at LDS index i0 * le + i1 * lf of the block.
+constexpr int kMaxPasses = 12;
+struct PassDesc {
+    int32_t d, spl, sh;        // dimension, spline, log2 of the stride
+    uint32_t nlines, ne;
+    uint32_t magic;            // multiply-high constant for division by ne
+    int32_t le, lf;
+    float el, ebx2, inv;       // level bound, 2 e_l, 1 / (2 e_l) (0 when e_l = 0)
+    int32_t pad;
+};
+
 // Per-field plan computed on the device from the range and the profile.
 struct FieldPlan {
     float vmin, vmax;
@@ -65,6 +80,7 @@ struct FieldPlan {
     int32_t spline[3];
     int32_t order[3];
     double prof[3][3];     // [dim][linear, NAK, natural] L1 errors
+    PassDesc pass[kMaxPasses];   // derived from order, spline and e_l
 };
 
 // Windows are handed to the interpolation kernels in groups of this many,
@@ -89,6 +105,8 @@ hipError_t launch_profile(const FieldDesc* d_fields, FieldPlan* d_plans, int nfi
 hipError_t launch_plan(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
                        const float* d_part_min, const float* d_part_max,
                        const uint32_t* d_part_bad, hipStream_t st);
+hipError_t launch_pass_desc(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
+                            hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_compress(int ndim, const FieldDesc* d_fields, const FieldPlan* d_plans,
                            const uint64_t* d_goff, uint64_t ngroups, int num_cus, int per_cu,

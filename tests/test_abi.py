@@ -67,8 +67,10 @@ def test_struct_layouts_match_header():
 #include <stddef.h>
 #include "szi.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\n", sizeof(sz_dims), sizeof(sz_params), sizeof(sz_result),
-         offsetof(sz_result, header), offsetof(sz_result, internal));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(sz_dims), sizeof(sz_params),
+         sizeof(sz_result), offsetof(sz_result, header), offsetof(sz_result, internal),
+         sizeof(sz_request), offsetof(sz_request, src), offsetof(sz_request, d_out),
+         sizeof(sz_completion), offsetof(sz_completion, result));
   return 0;
 }
 '''
@@ -80,4 +82,6 @@ int main(void) {
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
         got = list(map(int, subprocess.run([exe], capture_output=True, text=True).stdout.split()))
     assert got == [C.sizeof(szi.SzDims), C.sizeof(szi.SzParams), C.sizeof(szi.SzResult),
-                   szi.SzResult.header.offset, szi.SzResult.internal.offset]
+                   szi.SzResult.header.offset, szi.SzResult.internal.offset,
+                   C.sizeof(szi.SzRequest), szi.SzRequest.src.offset, szi.SzRequest.d_out.offset,
+                   C.sizeof(szi.SzCompletion), szi.SzCompletion.result.offset]

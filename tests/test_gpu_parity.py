@@ -94,6 +94,13 @@ def _const(shape, v):
     return lambda: np.full(shape, v, dtype=np.float32)
 
 
+def _signed_zeros(shape, seed):
+    def gen():
+        rng = np.random.default_rng(seed)
+        return np.where(rng.random(shape) < 0.5, np.float32(-0.0), np.float32(0.0)).astype(np.float32)
+    return gen
+
+
 CASES = [
     ("small64_bumps", synth.workload_small, {}),
     ("odd_17_33_65", _spec((17, 33, 65), 3), {}),
@@ -126,6 +133,17 @@ CASES = [
     ("column_2d_300x1", _spec((300, 1), 20), {}),
     ("single_point_2d", _const((1, 1), -4.0), {}),
     ("linear_2d", _spec((65, 129), 21), dict(interp=(0, 0))),
+    # natural cubic on values near 1e-38: numerators below 2^-123 take the
+    # exact division instead of the reciprocal multiply
+    ("natural_tiny_values", lambda: synth.spectral_field((30, 40, 70), seed=22) * np.float32(1e-38),
+     dict(interp=(2, 2, 2), eb=2e-39, eb_mode=0)),
+    ("natural_tiny_2d", lambda: synth.spectral_field((70, 140), seed=24) * np.float32(3e-38),
+     dict(interp=(2, 2), eb=2e-39, eb_mode=0)),
+    # +0 and -0 mixed: the sign of zero survives prediction and quantisation
+    ("signed_zeros_zero_bound", _signed_zeros((20, 24, 40), 23),
+     dict(interp=(2, 2, 2), eb=0.0, eb_mode=0)),
+    ("signed_zeros_abs_bound", _signed_zeros((20, 24, 40), 25),
+     dict(interp=(1, 2, 0), eb=0.5, eb_mode=0)),
 ]
 
 
