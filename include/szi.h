@@ -129,6 +129,16 @@ uint64_t sz_ctx_bytes_in_use(const sz_ctx* ctx);
  * once.  Arithmetic-neutral: every setting gives byte-identical results; it
  * only trades occupancy against tail effects. */
 sz_status sz_ctx_set_grid(sz_ctx* ctx, int workgroups_per_cu);
+/* Graph mode (default off): the device work of a call is captured into a HIP
+ * graph once per launch signature (number of fields, their grids, the
+ * Huffman grouping, the launch shape) and replayed afterwards, on a stream of
+ * the context that first waits for the caller's stream; the call still
+ * returns after its work has finished.  Compression runs as two graphs
+ * around the host codebook step, decompression as one.  The kernel
+ * arguments of a graph live in a context-owned device arena filled from a
+ * pinned mirror by the graph's first node.  Results are identical to the
+ * default mode; per-stage timing is not recorded inside graphs. */
+sz_status sz_ctx_set_graphs(sz_ctx* ctx, int enable);
 
 /* Per-stage device timing.  When enabled, the context records a HIP event
  * pair around every kernel launch (on the stream the kernel runs on) and

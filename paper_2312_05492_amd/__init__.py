@@ -105,6 +105,8 @@ def lib():
         L.sz_ctx_bytes_in_use.argtypes = [vp]
         L.sz_ctx_set_grid.restype = C.c_int
         L.sz_ctx_set_grid.argtypes = [vp, C.c_int]
+        L.sz_ctx_set_graphs.restype = C.c_int
+        L.sz_ctx_set_graphs.argtypes = [vp, C.c_int]
         L.sz_ctx_set_timing.restype = C.c_int
         L.sz_ctx_set_timing.argtypes = [vp, C.c_int]
         L.sz_ctx_read_timing.restype = C.c_int
@@ -261,6 +263,9 @@ class Context:
 
     def set_grid(self, per_cu: int):
         self._check(lib().sz_ctx_set_grid(self.h, per_cu))
+
+    def set_graphs(self, on: bool):
+        self._check(lib().sz_ctx_set_graphs(self.h, 1 if on else 0))
 
     def set_timing(self, on: bool):
         self._check(lib().sz_ctx_set_timing(self.h, 1 if on else 0))

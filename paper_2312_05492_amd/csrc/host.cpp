@@ -36,6 +36,20 @@ struct sz_ctx {
     void* pinned = nullptr;    // host staging buffer
     size_t pinned_bytes = 0;
     int grid_per_cu = 0;       // persistent workgroups per CU; 0 = resident capacity
+    // graph mode: the device work of a call is captured once per launch
+    // signature and replayed; its kernel arguments live in a persistent
+    // device arena filled from a pinned mirror by the graph's first node
+    bool graphs = false;
+    hipStream_t gstream = nullptr;   // the library's stream for graph launches
+    hipEvent_t gjoin = nullptr;      // joins the caller's stream to it
+    void* arena = nullptr;           // device
+    void* parena = nullptr;          // pinned host mirror
+    size_t arena_bytes = 0;
+    struct Graph {
+        std::vector<uint64_t> sig;
+        hipGraphExec_t exec = nullptr;
+    };
+    Graph graph[3];                  // decompression; compression before / after the codebook
     // stage timing
     bool timing = false;
     std::vector<hipEvent_t> ev_free;
@@ -221,6 +235,95 @@ struct Scratch {
         return SZ_OK;
     }
 };
+
+// ------------------------------------------------------------ graph mode
+// arena layout: regions at 256-byte offsets
+struct Layout {
+    size_t off = 0;
+    template <class T>
+    size_t take(size_t count) {
+        const size_t o = (off + 255) & ~(size_t)255;
+        off = o + count * sizeof(T);
+        return o;
+    }
+};
+
+void graph_drop(sz_ctx* c) {
+    for (auto& g : c->graph) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
+        g.sig.clear();
+    }
+}
+
+// grow the arena (and its pinned mirror) to at least bytes; replayed graphs
+// hold its addresses, so growing drops them
+sz_status arena_reserve(sz_ctx* c, size_t bytes) {
+    if (!c->gstream) {
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->gjoin, hipEventDisableTiming));
+    }
+    if (bytes <= c->arena_bytes) return SZ_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->gstream));
+    graph_drop(c);
+    if (c->arena) (void)hipFree(c->arena);
+    if (c->parena) (void)hipHostFree(c->parena);
+    c->arena = c->parena = nullptr;
+    c->arena_bytes = 0;
+    const size_t nb = std::max(bytes + bytes / 2, (size_t)1 << 20);
+    HIP_TRY(c, hipMalloc(&c->arena, nb));
+    HIP_TRY(c, hipHostMalloc(&c->parena, nb, hipHostMallocDefault));
+    c->arena_bytes = nb;
+    return SZ_OK;
+}
+
+// run the launch sequence enqueue(stream) as graph g: captured on the
+// library's stream when the signature is new, then replayed there after the
+// caller's stream; the caller synchronizes the library's stream.  The bytes
+// [soff, soff + staged) of the pinned mirror are copied to the same place in
+// the arena by the graph's first node.
+template <class F>
+sz_status graph_run(sz_ctx* c, int g, std::vector<uint64_t> sig, size_t soff, size_t staged,
+                    hipStream_t user, F&& enqueue) {
+    sig.push_back(soff);
+    sig.push_back(staged);
+    sz_ctx::Graph& G = c->graph[g];
+    HIP_TRY(c, hipEventRecord(c->gjoin, user));
+    HIP_TRY(c, hipStreamWaitEvent(c->gstream, c->gjoin, 0));
+    if (!G.exec || G.sig != sig) {
+        if (G.exec) (void)hipGraphExecDestroy(G.exec);
+        G.exec = nullptr;
+        G.sig.clear();
+        const bool timing = c->timing;
+        c->timing = false;   // no stage events inside a graph
+        HIP_TRY(c, hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+        sz_status s = SZ_OK;
+        hipError_t e = hipSuccess;
+        if (staged)
+            e = hipMemcpyAsync(static_cast<char*>(c->arena) + soff,
+                               static_cast<char*>(c->parena) + soff, staged,
+                               hipMemcpyHostToDevice, c->gstream);
+        if (e == hipSuccess) s = enqueue(c->gstream);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(c->gstream, &graph);
+        c->timing = timing;
+        if (e != hipSuccess || e2 != hipSuccess || s != SZ_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            return s != SZ_OK ? s : fail(c, SZ_ERR_DEVICE, "graph capture failed");
+        }
+        const hipError_t e3 = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e3 != hipSuccess) {
+            G.exec = nullptr;
+            (void)hipGetLastError();
+            return fail(c, SZ_ERR_DEVICE, "graph instantiation failed");
+        }
+        G.sig = sig;
+    }
+    HIP_TRY(c, hipGraphLaunch(G.exec, c->gstream));
+    return SZ_OK;
+}
 
 // ------------------------------------------------------------ CRC-32 (IEEE)
 uint32_t crc32_update(uint32_t crc, const uint8_t* p, size_t n) {
@@ -701,7 +804,19 @@ sz_status sz_ctx_destroy(sz_ctx* c) {
     }
     for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->gstream) (void)hipStreamSynchronize(c->gstream);
+    graph_drop(c);
+    if (c->arena) (void)hipFree(c->arena);
+    if (c->parena) (void)hipHostFree(c->parena);
+    if (c->gjoin) (void)hipEventDestroy(c->gjoin);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
     delete c;
+    return SZ_OK;
+}
+
+sz_status sz_ctx_set_graphs(sz_ctx* c, int enable) {
+    if (!c) return SZ_ERR_INVALID_ARG;
+    c->graphs = enable != 0;
     return SZ_OK;
 }
 
@@ -772,7 +887,6 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
     int max_R = 0, max_chunk = 0;
     for (uint32_t i = 0; i < nf; ++i) {
         ResultInternal* R = new ResultInternal();
-    R->owner = c;
         R->owner = c;
         res[i].internal = R;
         R->dims = dims[i];
@@ -805,19 +919,8 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
         max_chunk = std::max(max_chunk, geo[i].chunk);
     }
     const uint64_t total_chunks = chunk_base;
-
     Scratch sc(c);
-    FieldDesc* d_fd;
-    FieldPlan* d_plan;
-    float *d_pmin, *d_pmax;
-    uint32_t* d_pbad;
-    uint64_t* d_items;
     sz_status s;
-    if ((s = sc.get(nf, &d_fd)) || (s = sc.get(nf, &d_plan)) ||
-        (s = sc.get((size_t)nf * kRangeBlocks, &d_pmin)) ||
-        (s = sc.get((size_t)nf * kRangeBlocks, &d_pmax)) ||
-        (s = sc.get((size_t)nf * kRangeBlocks, &d_pbad)) || (s = sc.get(2 * (nf + 1), &d_items)))
-        return s;
     // work lists: one per dimensionality, fields in input order
     std::vector<uint32_t> grp[2];
     for (uint32_t i = 0; i < nf; ++i) grp[geo[i].ndim == 3 ? 0 : 1].push_back(i);
@@ -839,50 +942,163 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
             nitems[gi] = grp[gi].empty() ? 0 : io[grp[gi].size()];
         }
     }
-    const size_t stage1 = sizeof(FieldDesc) * nf + sizeof(uint64_t) * items.size();
-    if ((s = pinned_reserve(c, std::max<size_t>(stage1, sizeof(FieldPlan) * nf +
-                                                           sizeof(uint32_t) * 2 * max_R * nf))))
+    // Huffman encode layout.  The encode kernels are specialised on the
+    // chunk size, so the fields are ordered by chunk size into contiguous
+    // groups; each group runs stats -> block scan -> encode over blocks of
+    // kEncBlockChunks chunks (blocks never straddle fields).
+    std::vector<uint32_t> hord(nf);
+    for (uint32_t k = 0; k < nf; ++k) hord[k] = k;
+    std::stable_sort(hord.begin(), hord.end(),
+                     [&](uint32_t x, uint32_t y) { return fds[x].chunk < fds[y].chunk; });
+    std::vector<uint64_t> hboff(nf + 1, 0);   // global block prefix in hord order
+    for (uint32_t j = 0; j < nf; ++j)
+        hboff[j + 1] = hboff[j] + (fds[hord[j]].nchunks + kEncBlockChunks - 1) / kEncBlockChunks;
+    struct Group {
+        uint32_t fs, fe;   // field slice in hord order
+    };
+    std::vector<Group> groups;
+    for (uint32_t j = 0; j < nf; ++j)
+        if (groups.empty() || fds[hord[groups.back().fs]].chunk != fds[hord[j]].chunk)
+            groups.push_back({j, j + 1});
+        else
+            groups.back().fe = j + 1;
+    const uint64_t total_blocks = hboff[nf];
+    // per group: block prefix (group-local) and offsets with one closing slot
+    std::vector<uint64_t> gboff;            // concatenated group-local prefixes
+    std::vector<uint64_t> gboff_at(groups.size()), goff_at(groups.size());
+    for (size_t g = 0; g < groups.size(); ++g) {
+        gboff_at[g] = gboff.size();
+        goff_at[g] = hboff[groups[g].fs] + g;
+        for (uint32_t j = groups[g].fs; j <= groups[g].fe; ++j)
+            gboff.push_back(hboff[j] - hboff[groups[g].fs]);
+    }
+    const uint64_t nbw = total_blocks + groups.size();
+
+    // device buffers of the launches: per-call scratch, or in graph mode the
+    // arena (descriptors and offsets staged from its pinned mirror)
+    FieldDesc *d_fd, *d_hfd;
+    FieldPlan* d_plan;
+    float *d_pmin, *d_pmax;
+    uint32_t *d_pbad, *d_hist = nullptr;
+    uint64_t *d_items, *d_gboff, *d_bwoff, *d_booff;
+    uint32_t *d_cwords, *d_couts, *d_bw, *d_bo;
+    const size_t hstride = 2 * (size_t)max_R;   // graph mode: histogram k at d_hist + k * hstride
+    Layout L;
+    const size_t o_fd = L.take<FieldDesc>(nf), o_items = L.take<uint64_t>(items.size());
+    const size_t end1 = L.off;
+    const size_t o_plan = L.take<FieldPlan>(nf), o_hist = L.take<uint32_t>(nf * hstride);
+    const size_t o_pmin = L.take<float>((size_t)nf * kRangeBlocks);
+    const size_t o_pmax = L.take<float>((size_t)nf * kRangeBlocks);
+    const size_t o_pbad = L.take<uint32_t>((size_t)nf * kRangeBlocks);
+    const size_t o_hfd = L.take<FieldDesc>(nf), o_gboff = L.take<uint64_t>(gboff.size());
+    const size_t end2 = L.off;
+    const size_t o_cwords = L.take<uint32_t>(std::max<uint64_t>(total_chunks, 1));
+    const size_t o_couts = L.take<uint32_t>(std::max<uint64_t>(total_chunks, 1));
+    const size_t o_bw = L.take<uint32_t>(std::max<uint64_t>(total_blocks, 1));
+    const size_t o_bo = L.take<uint32_t>(std::max<uint64_t>(total_blocks, 1));
+    const size_t o_bwoff = L.take<uint64_t>(nbw), o_booff = L.take<uint64_t>(nbw);
+    if (c->graphs) {
+        if ((s = arena_reserve(c, L.off))) return s;
+        char* d = static_cast<char*>(c->arena);
+        d_fd = reinterpret_cast<FieldDesc*>(d + o_fd);
+        d_items = reinterpret_cast<uint64_t*>(d + o_items);
+        d_plan = reinterpret_cast<FieldPlan*>(d + o_plan);
+        d_hist = reinterpret_cast<uint32_t*>(d + o_hist);
+        d_pmin = reinterpret_cast<float*>(d + o_pmin);
+        d_pmax = reinterpret_cast<float*>(d + o_pmax);
+        d_pbad = reinterpret_cast<uint32_t*>(d + o_pbad);
+        d_hfd = reinterpret_cast<FieldDesc*>(d + o_hfd);
+        d_gboff = reinterpret_cast<uint64_t*>(d + o_gboff);
+        d_cwords = reinterpret_cast<uint32_t*>(d + o_cwords);
+        d_couts = reinterpret_cast<uint32_t*>(d + o_couts);
+        d_bw = reinterpret_cast<uint32_t*>(d + o_bw);
+        d_bo = reinterpret_cast<uint32_t*>(d + o_bo);
+        d_bwoff = reinterpret_cast<uint64_t*>(d + o_bwoff);
+        d_booff = reinterpret_cast<uint64_t*>(d + o_booff);
+        for (uint32_t k = 0; k < nf; ++k) fds[k].hist = d_hist + k * hstride;
+    } else if ((s = sc.get(nf, &d_fd)) || (s = sc.get(items.size(), &d_items)) ||
+               (s = sc.get(nf, &d_plan)) || (s = sc.get((size_t)nf * kRangeBlocks, &d_pmin)) ||
+               (s = sc.get((size_t)nf * kRangeBlocks, &d_pmax)) ||
+               (s = sc.get((size_t)nf * kRangeBlocks, &d_pbad)) || (s = sc.get(nf, &d_hfd)) ||
+               (s = sc.get(gboff.size(), &d_gboff)) ||
+               (s = sc.get(std::max<uint64_t>(total_chunks, 1), &d_cwords)) ||
+               (s = sc.get(std::max<uint64_t>(total_chunks, 1), &d_couts)) ||
+               (s = sc.get(std::max<uint64_t>(total_blocks, 1), &d_bw)) ||
+               (s = sc.get(std::max<uint64_t>(total_blocks, 1), &d_bo)) ||
+               (s = sc.get(nbw, &d_bwoff)) || (s = sc.get(nbw, &d_booff))) {
         return s;
-    HIP_TRY(c, hipMemcpyAsync(d_fd, fds.data(), sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
-    HIP_TRY(c, hipMemcpyAsync(d_items, items.data(), sizeof(uint64_t) * items.size(),
-                              hipMemcpyHostToDevice, st));
-    for (uint32_t k = 0; k < nf; ++k)
-        HIP_TRY(c, launch_fill_u32(fds[k].hist, 2 * (uint64_t)fds[k].R, 0, st));
-    {
-        STAGE(c, SZ_STAGE_RANGE, st);
-        HIP_TRY(c, launch_range(d_fd, (int)nf, d_pmin, d_pmax, d_pbad, st));
     }
-    {
-        STAGE(c, SZ_STAGE_PROFILE, st);
-        HIP_TRY(c, launch_profile(d_fd, d_plan, (int)nf, st));
-    }
-    {
-        STAGE(c, SZ_STAGE_PLAN, st);
-        HIP_TRY(c, launch_plan(d_fd, d_plan, (int)nf, d_pmin, d_pmax, d_pbad, st));
-    }
-    {
+
+    // part 1: range, profile, plan, interpolation (with histogram)
+    auto enqueue1 = [&](hipStream_t q) -> sz_status {
+        HIP_TRY(c, launch_zero_hist(d_fd, (int)nf, q));
+        {
+            STAGE(c, SZ_STAGE_RANGE, q);
+            HIP_TRY(c, launch_range(d_fd, (int)nf, d_pmin, d_pmax, d_pbad, q));
+        }
+        {
+            STAGE(c, SZ_STAGE_PROFILE, q);
+            HIP_TRY(c, launch_profile(d_fd, d_plan, (int)nf, q));
+        }
+        {
+            STAGE(c, SZ_STAGE_PLAN, q);
+            HIP_TRY(c, launch_plan(d_fd, d_plan, (int)nf, d_pmin, d_pmax, d_pbad, q));
+        }
         uint32_t base = 0;
         for (int gi = 0; gi < 2; ++gi) {
             if (!grp[gi].empty()) {
-                STAGE(c, SZ_STAGE_INTERP, st);
+                STAGE(c, SZ_STAGE_INTERP, q);
                 HIP_TRY(c, launch_compress(gi == 0 ? 3 : 2, d_fd + base, d_plan + base,
                                            d_items + gi * (nf + 1), nitems[gi], c->num_cus,
-                                           c->grid_per_cu, max_R, st));
+                                           c->grid_per_cu, max_R, q));
             }
             base += (uint32_t)grp[gi].size();
         }
-    }
+        return SZ_OK;
+    };
     // sync 1: plans and histograms to the host
-    std::unique_ptr<StageMark> cb_mark(new StageMark(c, SZ_STAGE_CODEBOOK, st));
     std::vector<FieldPlan> plans(nf);
     std::vector<std::vector<uint32_t>> hist(nf);
-    HIP_TRY(c, hipMemcpyAsync(plans.data(), d_plan, sizeof(FieldPlan) * nf, hipMemcpyDeviceToHost, st));
-    for (uint32_t k = 0; k < nf; ++k) {
-        hist[k].resize(2 * fds[k].R);
-        HIP_TRY(c, hipMemcpyAsync(hist[k].data(), fds[k].hist, sizeof(uint32_t) * hist[k].size(),
+    for (uint32_t k = 0; k < nf; ++k) hist[k].resize(2 * fds[k].R);
+    if (c->graphs) {
+        char* h = static_cast<char*>(c->parena);
+        std::memcpy(h + o_fd, fds.data(), sizeof(FieldDesc) * nf);
+        std::memcpy(h + o_items, items.data(), sizeof(uint64_t) * items.size());
+        const std::vector<uint64_t> sig = {nf, nitems[0], nitems[1], grp[0].size(), (uint64_t)max_R,
+                                           (uint64_t)c->grid_per_cu, L.off};
+        char* d = static_cast<char*>(c->arena);
+        s = graph_run(c, 1, sig, o_fd, end1 - o_fd, st, [&](hipStream_t q) -> sz_status {
+            sz_status r = enqueue1(q);
+            if (r) return r;
+            HIP_TRY(c, hipMemcpyAsync(h + o_plan, d + o_plan, sizeof(FieldPlan) * nf,
+                                      hipMemcpyDeviceToHost, q));
+            HIP_TRY(c, hipMemcpyAsync(h + o_hist, d + o_hist, sizeof(uint32_t) * nf * hstride,
+                                      hipMemcpyDeviceToHost, q));
+            return SZ_OK;
+        });
+        if (s) return s;
+        HIP_TRY(c, hipStreamSynchronize(c->gstream));
+        std::memcpy(plans.data(), h + o_plan, sizeof(FieldPlan) * nf);
+        for (uint32_t k = 0; k < nf; ++k)
+            std::memcpy(hist[k].data(), h + o_hist + sizeof(uint32_t) * k * hstride,
+                        sizeof(uint32_t) * hist[k].size());
+    } else {
+        const size_t stage1 = sizeof(FieldDesc) * nf + sizeof(uint64_t) * items.size();
+        if ((s = pinned_reserve(c, std::max<size_t>(stage1, sizeof(FieldPlan) * nf +
+                                                               sizeof(uint32_t) * 2 * max_R * nf))))
+            return s;
+        HIP_TRY(c, hipMemcpyAsync(d_fd, fds.data(), sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(d_items, items.data(), sizeof(uint64_t) * items.size(),
+                                  hipMemcpyHostToDevice, st));
+        if ((s = enqueue1(st))) return s;
+        HIP_TRY(c, hipMemcpyAsync(plans.data(), d_plan, sizeof(FieldPlan) * nf,
                                   hipMemcpyDeviceToHost, st));
+        for (uint32_t k = 0; k < nf; ++k)
+            HIP_TRY(c, hipMemcpyAsync(hist[k].data(), fds[k].hist, sizeof(uint32_t) * hist[k].size(),
+                                      hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
     }
-    HIP_TRY(c, hipStreamSynchronize(st));
+    std::unique_ptr<StageMark> cb_mark(new StageMark(c, SZ_STAGE_CODEBOOK, st));
     for (uint32_t k = 0; k < nf; ++k)
         if (plans[k].status == -2)
             return fail(c, SZ_ERR_NONFINITE, "field %u holds %u non-finite values", perm[k],
@@ -914,89 +1130,85 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
         fds[k].n_outliers = nout;
         fds[k].words_cap = wcap;
         fds[k].dtab = R->d_dtab;
+        if (c->graphs)   // the result keeps its own histogram
+            HIP_TRY(c, hipMemcpyAsync(res[i].hist, fds[k].hist, sizeof(uint32_t) * nsym,
+                                      hipMemcpyDeviceToDevice, st));
         HIP_TRY(c, hipMemcpyAsync(res[i].code_len, R->code_len.data(), nsym, hipMemcpyHostToDevice, st));
         HIP_TRY(c, hipMemcpyAsync(R->d_cbook, cbook[k].data(), sizeof(uint32_t) * nsym,
                                   hipMemcpyHostToDevice, st));
         HIP_TRY(c, hipMemcpyAsync(R->d_dtab, dtab[k].data(), sizeof(uint32_t) * dtab[k].size(),
                                   hipMemcpyHostToDevice, st));
     }
-    // Huffman encode.  The encode kernels are specialised on the chunk size,
-    // so the fields are ordered by chunk size into contiguous groups; each
-    // group runs stats -> block scan -> encode over blocks of
-    // kEncBlockChunks chunks (blocks never straddle fields).
-    std::vector<uint32_t> hord(nf);
-    for (uint32_t k = 0; k < nf; ++k) hord[k] = k;
-    std::stable_sort(hord.begin(), hord.end(),
-                     [&](uint32_t x, uint32_t y) { return fds[x].chunk < fds[y].chunk; });
     std::vector<FieldDesc> hfd(nf);
-    std::vector<uint64_t> hboff(nf + 1, 0);   // global block prefix in hfd order
     {
         uint64_t cb = 0;
         for (uint32_t j = 0; j < nf; ++j) {
             hfd[j] = fds[hord[j]];
             hfd[j].chunk_base = cb;
             cb += hfd[j].nchunks;
-            hboff[j + 1] = hboff[j] + (hfd[j].nchunks + kEncBlockChunks - 1) / kEncBlockChunks;
         }
     }
-    struct Group {
-        uint32_t fs, fe;   // field slice in hfd
+    // part 2: Huffman stats, block scans, encode with outlier compaction
+    auto enqueue2 = [&](hipStream_t q) -> sz_status {
+        for (size_t g = 0; g < groups.size(); ++g) {
+            const uint32_t fs = groups[g].fs, nfg = groups[g].fe - groups[g].fs;
+            const uint64_t b0 = hboff[fs], nb = hboff[groups[g].fe] - b0;
+            const int chunk = hfd[fs].chunk;
+            {
+                STAGE(c, SZ_STAGE_HUFF_STATS, q);
+                HIP_TRY(c, launch_huff_stats(d_hfd + fs, (int)nfg, d_gboff + gboff_at[g], nb, chunk,
+                                             d_cwords, d_couts, d_bw + b0, d_bo + b0, 2 * max_R, q));
+            }
+            {
+                STAGE(c, SZ_STAGE_SCAN, q);
+                HIP_TRY(c, launch_scan_blocks(d_bw + b0, d_bo + b0, nb, d_bwoff + goff_at[g],
+                                              d_booff + goff_at[g], q));
+            }
+            {
+                STAGE(c, SZ_STAGE_ENCODE, q);
+                HIP_TRY(c, launch_huff_encode(d_hfd + fs, (int)nfg, d_gboff + gboff_at[g], nb, chunk,
+                                              d_cwords, d_couts, d_bwoff + goff_at[g],
+                                              d_booff + goff_at[g], 2 * max_R, q));
+            }
+        }
+        return SZ_OK;
     };
-    std::vector<Group> groups;
-    for (uint32_t j = 0; j < nf; ++j)
-        if (groups.empty() || hfd[groups.back().fs].chunk != hfd[j].chunk) groups.push_back({j, j + 1});
-        else groups.back().fe = j + 1;
-    const uint64_t total_blocks = hboff[nf];
-    // per group: block prefix (group-local) and offsets with one closing slot
-    std::vector<uint64_t> gboff;            // concatenated group-local prefixes
-    std::vector<uint64_t> gboff_at(groups.size()), goff_at(groups.size());
-    for (size_t g = 0; g < groups.size(); ++g) {
-        gboff_at[g] = gboff.size();
-        goff_at[g] = hboff[groups[g].fs] + g;
-        for (uint32_t j = groups[g].fs; j <= groups[g].fe; ++j)
-            gboff.push_back(hboff[j] - hboff[groups[g].fs]);
-    }
-    FieldDesc* d_hfd;
-    uint64_t *d_gboff, *d_bwoff, *d_booff;
-    uint32_t *d_cwords, *d_couts, *d_bw, *d_bo;
-    if ((s = sc.get(nf, &d_hfd)) || (s = sc.get(gboff.size(), &d_gboff)) ||
-        (s = sc.get(std::max<uint64_t>(total_chunks, 1), &d_cwords)) ||
-        (s = sc.get(std::max<uint64_t>(total_chunks, 1), &d_couts)) ||
-        (s = sc.get(std::max<uint64_t>(total_blocks, 1), &d_bw)) ||
-        (s = sc.get(std::max<uint64_t>(total_blocks, 1), &d_bo)) ||
-        (s = sc.get(total_blocks + groups.size(), &d_bwoff)) ||
-        (s = sc.get(total_blocks + groups.size(), &d_booff)))
-        return s;
-    HIP_TRY(c, hipMemcpyAsync(d_hfd, hfd.data(), sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
-    HIP_TRY(c, hipMemcpyAsync(d_gboff, gboff.data(), sizeof(uint64_t) * gboff.size(),
-                              hipMemcpyHostToDevice, st));
-    cb_mark.reset();
-    for (size_t g = 0; g < groups.size(); ++g) {
-        const uint32_t fs = groups[g].fs, nfg = groups[g].fe - groups[g].fs;
-        const uint64_t b0 = hboff[fs], nb = hboff[groups[g].fe] - b0;
-        const int chunk = hfd[fs].chunk;
-        {
-            STAGE(c, SZ_STAGE_HUFF_STATS, st);
-            HIP_TRY(c, launch_huff_stats(d_hfd + fs, (int)nfg, d_gboff + gboff_at[g], nb, chunk,
-                                         d_cwords, d_couts, d_bw + b0, d_bo + b0, 2 * max_R, st));
-        }
-        {
-            STAGE(c, SZ_STAGE_SCAN, st);
-            HIP_TRY(c, launch_scan_blocks(d_bw + b0, d_bo + b0, nb, d_bwoff + goff_at[g],
-                                          d_booff + goff_at[g], st));
-        }
-        {
-            STAGE(c, SZ_STAGE_ENCODE, st);
-            HIP_TRY(c, launch_huff_encode(d_hfd + fs, (int)nfg, d_gboff + gboff_at[g], nb, chunk,
-                                          d_cwords, d_couts, d_bwoff + goff_at[g],
-                                          d_booff + goff_at[g], 2 * max_R, st));
-        }
-    }
     // sync 2: block word offsets (small) to the host
-    std::vector<uint64_t> bwoff(total_blocks + groups.size());
-    HIP_TRY(c, hipMemcpyAsync(bwoff.data(), d_bwoff, sizeof(uint64_t) * bwoff.size(),
-                              hipMemcpyDeviceToHost, st));
-    HIP_TRY(c, hipStreamSynchronize(st));
+    std::vector<uint64_t> bwoff(nbw);
+    if (c->graphs) {
+        char* h = static_cast<char*>(c->parena);
+        char* d = static_cast<char*>(c->arena);
+        std::memcpy(h + o_hfd, hfd.data(), sizeof(FieldDesc) * nf);
+        std::memcpy(h + o_gboff, gboff.data(), sizeof(uint64_t) * gboff.size());
+        std::vector<uint64_t> sig = {nf, groups.size(), total_blocks, total_chunks, (uint64_t)max_R, L.off};
+        for (size_t g = 0; g < groups.size(); ++g) {
+            sig.push_back(groups[g].fs);
+            sig.push_back(groups[g].fe);
+            sig.push_back((uint64_t)hfd[groups[g].fs].chunk);
+            sig.push_back(hboff[groups[g].fe]);
+        }
+        cb_mark.reset();
+        s = graph_run(c, 2, sig, o_hfd, end2 - o_hfd, st, [&](hipStream_t q) -> sz_status {
+            sz_status r = enqueue2(q);
+            if (r) return r;
+            HIP_TRY(c, hipMemcpyAsync(h + o_bwoff, d + o_bwoff, sizeof(uint64_t) * nbw,
+                                      hipMemcpyDeviceToHost, q));
+            return SZ_OK;
+        });
+        if (s) return s;
+        HIP_TRY(c, hipStreamSynchronize(c->gstream));
+        HIP_TRY(c, hipStreamSynchronize(st));
+        std::memcpy(bwoff.data(), h + o_bwoff, sizeof(uint64_t) * nbw);
+    } else {
+        HIP_TRY(c, hipMemcpyAsync(d_hfd, hfd.data(), sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(d_gboff, gboff.data(), sizeof(uint64_t) * gboff.size(),
+                                  hipMemcpyHostToDevice, st));
+        cb_mark.reset();
+        if ((s = enqueue2(st))) return s;
+        HIP_TRY(c, hipMemcpyAsync(bwoff.data(), d_bwoff, sizeof(uint64_t) * nbw,
+                                  hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
+    }
     resolve_marks(c);
     for (size_t g = 0; g < groups.size(); ++g) {
         for (uint32_t j = groups[g].fs; j < groups[g].fe; ++j) {
@@ -1100,38 +1312,70 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
     uint64_t *d_items, *d_dboff, *d_bwoff;
     uint32_t* d_bsum;
     sz_status s;
+    // the device work of the call
+    auto enqueue = [&](hipStream_t q) -> sz_status {
+        HIP_TRY(c, launch_pass_desc(d_fd, d_plan, (int)nf, q));
+        {
+            STAGE(c, SZ_STAGE_SCAN, q);
+            HIP_TRY(c, launch_chunk_words(d_fd, (int)nf, d_dboff, nblocks, d_bsum, q));
+            HIP_TRY(c, launch_scan_blocks(d_bsum, nullptr, nblocks, d_bwoff, nullptr, q));
+        }
+        {
+            STAGE(c, SZ_STAGE_DECODE, q);
+            HIP_TRY(c, launch_huff_decode(d_fd, (int)nf, d_dboff, nblocks, d_bwoff, 2 * max_R, q));
+        }
+        {
+            STAGE(c, SZ_STAGE_SCATTER, q);
+            HIP_TRY(c, launch_scatter_outliers(d_fd, (int)nf, q));
+        }
+        uint32_t base = 0;
+        for (int gi = 0; gi < 2; ++gi) {
+            if (!grp[gi].empty()) {
+                STAGE(c, SZ_STAGE_REPLAY, q);
+                HIP_TRY(c, launch_decompress(gi == 0 ? 3 : 2, d_fd + base, d_plan + base,
+                                             d_items + gi * (nf + 1), nitems[gi], c->num_cus,
+                                             c->grid_per_cu, q));
+            }
+            base += (uint32_t)grp[gi].size();
+        }
+        return SZ_OK;
+    };
+    if (c->graphs) {
+        Layout L;
+        const size_t o_fd = L.take<FieldDesc>(nf), o_plan = L.take<FieldPlan>(nf);
+        const size_t o_items = L.take<uint64_t>(items.size()), o_dboff = L.take<uint64_t>(nf + 1);
+        const size_t staged = L.off;
+        const size_t o_bwoff = L.take<uint64_t>(nblocks + 1);
+        const size_t o_bsum = L.take<uint32_t>(std::max<uint64_t>(nblocks, 1));
+        if ((s = arena_reserve(c, L.off))) return s;
+        char* h = static_cast<char*>(c->parena);
+        char* d = static_cast<char*>(c->arena);
+        std::memcpy(h + o_fd, fds.data(), sizeof(FieldDesc) * nf);
+        std::memcpy(h + o_plan, plans.data(), sizeof(FieldPlan) * nf);
+        std::memcpy(h + o_items, items.data(), sizeof(uint64_t) * items.size());
+        std::memcpy(h + o_dboff, dboff.data(), sizeof(uint64_t) * (nf + 1));
+        d_fd = reinterpret_cast<FieldDesc*>(d + o_fd);
+        d_plan = reinterpret_cast<FieldPlan*>(d + o_plan);
+        d_items = reinterpret_cast<uint64_t*>(d + o_items);
+        d_dboff = reinterpret_cast<uint64_t*>(d + o_dboff);
+        d_bwoff = reinterpret_cast<uint64_t*>(d + o_bwoff);
+        d_bsum = reinterpret_cast<uint32_t*>(d + o_bsum);
+        // everything the launches' arguments depend on
+        const std::vector<uint64_t> sig = {nf, nblocks, nitems[0], nitems[1], grp[0].size(),
+                                           (uint64_t)max_R, (uint64_t)c->grid_per_cu, L.off};
+        if ((s = graph_run(c, 0, sig, 0, staged, st, enqueue))) return s;
+        HIP_TRY(c, hipStreamSynchronize(c->gstream));
+        return SZ_OK;
+    }
     if ((s = sc.get(nf, &d_fd)) || (s = sc.get(nf, &d_plan)) || (s = sc.get(items.size(), &d_items)) ||
         (s = sc.get(nf + 1, &d_dboff)) || (s = sc.get(nblocks + 1, &d_bwoff)) ||
         (s = sc.get(std::max<uint64_t>(nblocks, 1), &d_bsum)))
         return s;
     HIP_TRY(c, hipMemcpyAsync(d_fd, fds.data(), sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
     HIP_TRY(c, hipMemcpyAsync(d_plan, plans.data(), sizeof(FieldPlan) * nf, hipMemcpyHostToDevice, st));
-    HIP_TRY(c, launch_pass_desc(d_fd, d_plan, (int)nf, st));
     HIP_TRY(c, hipMemcpyAsync(d_items, items.data(), sizeof(uint64_t) * items.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(c, hipMemcpyAsync(d_dboff, dboff.data(), sizeof(uint64_t) * (nf + 1), hipMemcpyHostToDevice, st));
-    {
-        STAGE(c, SZ_STAGE_SCAN, st);
-        HIP_TRY(c, launch_chunk_words(d_fd, (int)nf, d_dboff, nblocks, d_bsum, st));
-        HIP_TRY(c, launch_scan_blocks(d_bsum, nullptr, nblocks, d_bwoff, nullptr, st));
-    }
-    {
-        STAGE(c, SZ_STAGE_DECODE, st);
-        HIP_TRY(c, launch_huff_decode(d_fd, (int)nf, d_dboff, nblocks, d_bwoff, 2 * max_R, st));
-    }
-    {
-        STAGE(c, SZ_STAGE_SCATTER, st);
-        HIP_TRY(c, launch_scatter_outliers(d_fd, (int)nf, st));
-    }
-    uint32_t base = 0;
-    for (int gi = 0; gi < 2; ++gi) {
-        if (!grp[gi].empty()) {
-            STAGE(c, SZ_STAGE_REPLAY, st);
-            HIP_TRY(c, launch_decompress(gi == 0 ? 3 : 2, d_fd + base, d_plan + base,
-                                         d_items + gi * (nf + 1), nitems[gi], c->num_cus,
-                                         c->grid_per_cu, st));
-        }
-        base += (uint32_t)grp[gi].size();
-    }
+    if ((s = enqueue(st))) return s;
     HIP_TRY(c, hipStreamSynchronize(st));
     resolve_marks(c);
     return SZ_OK;
@@ -1270,6 +1514,7 @@ sz_status sz_upload(sz_ctx* c, const void* blob, uint64_t bytes, void* stream, s
                 return fail(c, SZ_ERR_CORRUPT, "outlier index outside the field");
     }
     ResultInternal* R = new ResultInternal();
+    R->owner = c;
     r.internal = R;
     R->dims = d;
     R->S = g.S;

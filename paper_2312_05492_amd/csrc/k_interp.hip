@@ -22,6 +22,9 @@
 // rounding per operation (the library is built with -ffp-contract=off).
 #include "dev_common.h"
 
+#include <map>
+#include <mutex>
+
 namespace szi {
 
 constexpr int kWaves = kWinPerGroup;    // windows in flight per workgroup, one per wave
@@ -726,17 +729,28 @@ __global__ __launch_bounds__(kThreads) void k_decompress(const FieldDesc* __rest
 // The persistent grid is the number of workgroups resident at once
 // (occupancy from the runtime x compute units) unless per_cu overrides it,
 // rounded to whole L2 domains.
+// occupancy of a kernel at an LDS size, asked of the runtime once per process
+template <class K>
+static int resident_per_cu(K kernel, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::pair<const void*, size_t>, int> known;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_pair(reinterpret_cast<const void*>(kernel), lds);
+    auto it = known.find(key);
+    if (it != known.end()) return it->second;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, kThreads, lds) != hipSuccess ||
+        occ < 1) {
+        (void)hipGetLastError();
+        occ = 2;
+    }
+    known[key] = occ;
+    return occ;
+}
+
 template <class K>
 static uint64_t resident_grid(K kernel, size_t lds, int num_cus, int per_cu, uint64_t ngroups) {
-    int occ = per_cu;
-    if (occ <= 0) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, kThreads, lds) !=
-                hipSuccess ||
-            occ < 1) {
-            (void)hipGetLastError();
-            occ = 2;
-        }
-    }
+    const int occ = per_cu > 0 ? per_cu : resident_per_cu(kernel, lds);
     uint64_t grid = (uint64_t)num_cus * (uint64_t)occ;
     if (grid > ngroups) grid = ngroups;
     if (grid > (uint64_t)kXcds) grid -= grid % kXcds;

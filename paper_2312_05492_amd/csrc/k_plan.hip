@@ -298,6 +298,13 @@ __global__ __launch_bounds__(256) void k_plan(const FieldDesc* __restrict__ F, F
     make_passes(f, p);
 }
 
+// zero the histogram of every field (one y-row of workgroups per field)
+__global__ void k_zero_hist(const FieldDesc* __restrict__ F) {
+    const FieldDesc& f = F[blockIdx.y];
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < 2 * f.R; b += gridDim.x * blockDim.x)
+        gp(f.hist)[b] = 0u;
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
@@ -323,6 +330,12 @@ hipError_t launch_plan(const FieldDesc* d_fields, FieldPlan* d_plans, int nfield
                        const uint32_t* d_part_bad, hipStream_t st) {
     hipLaunchKernelGGL(k_plan, dim3(nfields), dim3(256), 0, st, d_fields, d_plans, d_part_min,
                        d_part_max, d_part_bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_hist(const FieldDesc* d_fields, int nfields, hipStream_t st) {
+    if (nfields <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_hist, dim3(4, (unsigned)nfields), dim3(256), 0, st, d_fields);
     return hipGetLastError();
 }
 

@@ -105,6 +105,7 @@ hipError_t launch_profile(const FieldDesc* d_fields, FieldPlan* d_plans, int nfi
 hipError_t launch_plan(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
                        const float* d_part_min, const float* d_part_max,
                        const uint32_t* d_part_bad, hipStream_t st);
+hipError_t launch_zero_hist(const FieldDesc* d_fields, int nfields, hipStream_t st);
 hipError_t launch_pass_desc(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
                             hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);

@@ -243,3 +243,47 @@ def test_full_size_512_cube(ctx):
     y = ctx.decompress(res).cpu().numpy()
     assert np.array_equal(_bits(y), _bits(ref.recon))
     res.free()
+
+
+def test_graph_mode_replays_equal_eager(ctx):
+    # graph mode against the default mode: several replays of the same
+    # signature with eager work and synchronizations between them, a new
+    # signature (re-capture) in the middle, and a batch
+    import torch
+    a = synth.spectral_field((40, 50, 90), seed=81)
+    b = synth.climate_field(381, shape=(120, 250))
+    fields = [synth.spectral_field((20, 30, 70), seed=82), synth.climate_field(382, shape=(60, 130))]
+    print("\n[graphs] replays vs eager", flush=True)
+    ctx.set_graphs(False)
+    ref = {}
+    for name, x, kw in (("a", a, {}), ("b", b, dict(eb=1e-4))):
+        r = ctx.compress(_to_gpu(x), **kw)
+        ref[name] = (r.blob(), _bits(ctx.decompress(r).cpu().numpy()), kw)
+        r.free()
+    rb = ctx.compress_batch([_to_gpu(f) for f in fields])
+    ref_batch = [r.blob() for r in rb]
+    ref_batch_y = [_bits(y.cpu().numpy()) for y in ctx.decompress_batch(rb)]
+    for r in rb:
+        r.free()
+    ctx.set_graphs(True)
+    try:
+        for rep, name in enumerate(["a", "a", "a", "b", "b", "a", "a"]):
+            x = a if name == "a" else b
+            g = _to_gpu(x)
+            g2 = g * 2.0   # eager work on the caller's stream between replays
+            r = ctx.compress(g, **ref[name][2])
+            assert r.blob() == ref[name][0], "compression replay %d (%s)" % (rep, name)
+            y = ctx.decompress(r)
+            assert np.array_equal(_bits(y.cpu().numpy()), ref[name][1]), "decompression replay %d" % rep
+            torch.cuda.synchronize()
+            del g2
+            r.free()
+        for rep in range(3):
+            rb = ctx.compress_batch([_to_gpu(f) for f in fields])
+            assert [r.blob() for r in rb] == ref_batch, "batch replay %d" % rep
+            ys = ctx.decompress_batch(rb)
+            assert all(np.array_equal(_bits(y.cpu().numpy()), e) for y, e in zip(ys, ref_batch_y))
+            for r in rb:
+                r.free()
+    finally:
+        ctx.set_graphs(False)
