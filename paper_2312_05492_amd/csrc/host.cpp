@@ -1033,12 +1033,8 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
     auto enqueue1 = [&](hipStream_t q) -> sz_status {
         HIP_TRY(c, launch_zero_hist(d_fd, (int)nf, q));
         {
-            STAGE(c, SZ_STAGE_RANGE, q);
-            HIP_TRY(c, launch_range(d_fd, (int)nf, d_pmin, d_pmax, d_pbad, q));
-        }
-        {
-            STAGE(c, SZ_STAGE_PROFILE, q);
-            HIP_TRY(c, launch_profile(d_fd, d_plan, (int)nf, q));
+            STAGE(c, SZ_STAGE_RANGE, q);   // with the profiling
+            HIP_TRY(c, launch_range(d_fd, d_plan, (int)nf, d_pmin, d_pmax, d_pbad, q));
         }
         {
             STAGE(c, SZ_STAGE_PLAN, q);

@@ -13,8 +13,8 @@
 //   k_chunk_words  word count of every chunk, sums per block
 //   k_scan_blocks  exclusive scan of the block sums
 //   k_huff_decode  in-block scan, then a table-driven canonical decode from
-//                  a 64-bit bit buffer and a prefetched word queue; eight
-//                  symbols per 16-byte store
+//                  a 64-bit bit buffer fed by a per-lane LDS word ring; 32
+//                  symbols per lane stored at once
 #include "dev_common.h"
 
 namespace szi {
@@ -269,8 +269,8 @@ __global__ __launch_bounds__(kDecChunks) void k_chunk_words(const FieldDesc* __r
 // latency is covered by a group of decoding.  A group consumes at most 6
 // words and the ring always holds at least 7 ahead of the buffer.  Each
 // top-up also reads the following ring word, which LDS returns in order
-// ahead of the next table lookups.  Symbols leave 8 at a time in one 16-byte
-// store.
+// ahead of the next table lookups.  Symbols leave 32 at a time per lane in
+// four back-to-back 16-byte stores.
 constexpr int kRing = 32;   // ring words per lane (power of 2)
 
 __device__ __forceinline__ int ring_slot(uint32_t i, uint32_t sw) {
@@ -372,13 +372,11 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
     SZI_G uint16_t* out = gp(fd.codes) + s0;
     const bool vec = ((uintptr_t)fd.codes & 15u) == 0u;   // s0 and k are multiples of 8
     // a group: commit the previous request, maybe request 8 more words,
-    // decode n <= 8 symbols
+    // then decode up to 8 symbols
     bool pend = false;
     uint64_t pat = 0;
     vu4 la = {0u, 0u, 0u, 0u}, lb = la;
-    int k = 0;
-#pragma unroll 1
-    while (k < cnt) {
+    auto refill = [&]() {
         if (pend) put(pat, la, lb);
         // the ring holds [rd, wr) and a request adds 8; the prefetched word
         // at rd is not overwritten because the ring keeps kRing - 8 >= 7
@@ -389,28 +387,48 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
             lb = *reinterpret_cast<const SZI_G vu4*>(words + wr + 4);
             wr += 8;
         }
-        if (vec && k + 8 <= cnt) {
-            vu4 pk;
-            uint32_t lo, hi;
-            lo = decode_one();
-            hi = decode_one();
-            pk.x = lo | (hi << 16);
-            lo = decode_one();
-            hi = decode_one();
-            pk.y = lo | (hi << 16);
-            lo = decode_one();
-            hi = decode_one();
-            pk.z = lo | (hi << 16);
-            lo = decode_one();
-            hi = decode_one();
-            pk.w = lo | (hi << 16);
-            *reinterpret_cast<SZI_G vu4*>(out + k) = pk;
-            k += 8;
-        } else {
-            const int e = k + 8 < cnt ? k + 8 : cnt;
+    };
+    auto group8 = [&]() -> vu4 {
+        refill();
+        vu4 pk;
+        uint32_t lo, hi;
+        lo = decode_one();
+        hi = decode_one();
+        pk.x = lo | (hi << 16);
+        lo = decode_one();
+        hi = decode_one();
+        pk.y = lo | (hi << 16);
+        lo = decode_one();
+        hi = decode_one();
+        pk.z = lo | (hi << 16);
+        lo = decode_one();
+        hi = decode_one();
+        pk.w = lo | (hi << 16);
+        return pk;
+    };
+    int k = 0;
+    // 32 symbols of a lane leave as four back-to-back 16-byte stores, so
+    // that a lane fills half a cache line at once
+    if (vec) {
 #pragma unroll 1
-            for (; k < e; ++k) out[k] = (uint16_t)decode_one();
+        for (; k + 32 <= cnt; k += 32) {
+            const vu4 p0 = group8();
+            const vu4 p1 = group8();
+            const vu4 p2 = group8();
+            const vu4 p3 = group8();
+            SZI_G vu4* o = reinterpret_cast<SZI_G vu4*>(out + k);
+            o[0] = p0;
+            o[1] = p1;
+            o[2] = p2;
+            o[3] = p3;
         }
+    }
+#pragma unroll 1
+    while (k < cnt) {
+        refill();
+        const int e = k + 8 < cnt ? k + 8 : cnt;
+#pragma unroll 1
+        for (; k < e; ++k) out[k] = (uint16_t)decode_one();
     }
 }
 

@@ -160,10 +160,134 @@ struct LaneMap<2> {
     }
 };
 
+// 16-byte staging of a whole FP32 block whose rows are 16-byte aligned
+// (n[0] a multiple of 4): lane = (quad q of x, row).  3D: slots 0-8 hold
+// planes z = 0-8 at rows y = lane / 8, slot 9 rows y = 8 of planes lane / 8,
+// slot 10 row (8, 8); then the x = 32 column in two scalar slots.  2D: slots
+// 0-4 rows 4k + lane / 16, then the x = 64 column.  NQ quads and NC column
+// values per lane, the quads first in the register array.
+template <int ND>
+struct QuadMap;
+
+template <>
+struct QuadMap<3> {
+    static constexpr int NQ = 11, NC = 2, N = 4 * NQ + NC;
+    uint32_t gq, gy8, gc0, gc1;   // per-lane global offsets
+    int lq, ly8;                  // per-lane LDS offsets
+    bool c1v;
+    __device__ __forceinline__ void init(uint32_t lane, uint32_t n0, uint32_t n01) {
+        const uint32_t q = lane & 7u, r = lane >> 3;
+        gq = 4u * q + r * n0;
+        lq = 4 * (int)q + 33 * (int)r;
+        gy8 = 4u * q + 8u * n0 + r * n01;
+        ly8 = 4 * (int)q + 8 * 33 + 297 * (int)r;
+        gc0 = 32u + (lane % 9u) * n0 + (lane / 9u) * n01;
+        gc1 = 32u + ((lane + 64u) % 9u) * n0 + ((lane + 64u) / 9u) * n01;
+        c1v = lane + 64u < 81u;
+    }
+    // quad slot k: global offset and LDS index of its first value
+    __device__ __forceinline__ bool quad(int k, uint32_t lane, uint32_t n01, uint32_t& g,
+                                         int& l) const {
+        if (k < 9) {
+            g = gq + (uint32_t)k * n01;
+            l = lq + 297 * k;
+            return true;
+        }
+        if (k == 9) {
+            g = gy8;
+            l = ly8;
+            return true;
+        }
+        g = gy8 + 8u * n01 - (lane >> 3) * n01;   // row (8, 8)
+        l = 4 * (int)(lane & 7u) + 8 * 33 + 8 * 297;
+        return lane < 8u;
+    }
+    __device__ __forceinline__ bool col(int k, uint32_t lane, uint32_t& g, int& l) const {
+        g = k == 0 ? gc0 : gc1;
+        l = 32 + 33 * ((int)lane + 64 * k);
+        return k == 0 || c1v;
+    }
+};
+
+template <>
+struct QuadMap<2> {
+    static constexpr int NQ = 5, NC = 1, N = 4 * NQ + NC;
+    uint32_t gq, gc0, n0;
+    int lq;
+    uint32_t r;
+    __device__ __forceinline__ void init(uint32_t lane, uint32_t nn0, uint32_t) {
+        const uint32_t q = lane & 15u;
+        r = lane >> 4;
+        n0 = nn0;
+        gq = 4u * q + r * nn0;
+        lq = 4 * (int)q + 65 * (int)r;
+        gc0 = 64u + lane * nn0;
+    }
+    __device__ __forceinline__ bool quad(int k, uint32_t lane, uint32_t, uint32_t& g,
+                                         int& l) const {
+        g = gq + (uint32_t)(4 * k) * n0;
+        l = lq + 65 * 4 * k;
+        return 4 * k + (int)r < 17;
+    }
+    __device__ __forceinline__ bool col(int, uint32_t lane, uint32_t& g, int& l) const {
+        g = gc0;
+        l = 64 + 65 * (int)lane;
+        return lane < 17u;
+    }
+};
+
+template <int ND>
+__device__ __forceinline__ void load_quads(float* pre, const SZI_G float* wb, const QuadMap<ND>& qm,
+                                           uint32_t lane, uint32_t n01) {
+    using Q = QuadMap<ND>;
+#pragma unroll
+    for (int k = 0; k < Q::NQ; ++k) {
+        uint32_t g;
+        int l;
+        vf4 t = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (qm.quad(k, lane, n01, g, l)) t = *at((const SZI_G vf4*)wb, g >> 2);
+        pre[4 * k] = t.x;
+        pre[4 * k + 1] = t.y;
+        pre[4 * k + 2] = t.z;
+        pre[4 * k + 3] = t.w;
+    }
+#pragma unroll
+    for (int k = 0; k < Q::NC; ++k) {
+        uint32_t g;
+        int l;
+        float t = 0.0f;
+        if (qm.col(k, lane, g, l)) t = *at(wb, g);
+        pre[4 * Q::NQ + k] = t;
+    }
+}
+
+template <int ND>
+__device__ __forceinline__ void commit_quads(float* v, const float* pre, const QuadMap<ND>& qm,
+                                             uint32_t lane, uint32_t n01) {
+    using Q = QuadMap<ND>;
+#pragma unroll
+    for (int k = 0; k < Q::NQ; ++k) {
+        uint32_t g;
+        int l;
+        if (qm.quad(k, lane, n01, g, l)) {
+            v[l] = pre[4 * k];
+            v[l + 1] = pre[4 * k + 1];
+            v[l + 2] = pre[4 * k + 2];
+            v[l + 3] = pre[4 * k + 3];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < Q::NC; ++k) {
+        uint32_t g;
+        int l;
+        if (qm.col(k, lane, g, l)) v[l] = pre[4 * Q::NQ + k];
+    }
+}
+
 // Slots a lane does not load keep the value fill.
 template <int ND, bool FULL, class T, class U>
-__device__ __forceinline__ void load_block(U (&pre)[Geo<ND>::NPRE], const SZI_G T* wb,
-                                           const LaneMap<ND>& lm, const Win& wi, U fill) {
+__device__ __forceinline__ void load_block(U* pre, const SZI_G T* wb, const LaneMap<ND>& lm,
+                                           const Win& wi, U fill) {
 #pragma unroll
     for (int k = 0; k < Geo<ND>::NPRE; ++k) {
         uint32_t g;
@@ -175,8 +299,8 @@ __device__ __forceinline__ void load_block(U (&pre)[Geo<ND>::NPRE], const SZI_G 
 }
 
 template <int ND, bool FULL, class T, class U>
-__device__ __forceinline__ void commit_block(T* dst, const U (&pre)[Geo<ND>::NPRE],
-                                             const LaneMap<ND>& lm, const Win& wi) {
+__device__ __forceinline__ void commit_block(T* dst, const U* pre, const LaneMap<ND>& lm,
+                                             const Win& wi) {
 #pragma unroll
     for (int k = 0; k < Geo<ND>::NPRE; ++k) {
         uint32_t g;
@@ -585,10 +709,14 @@ __global__ __launch_bounds__(kThreads) void k_compress(const FieldDesc* __restri
     uint64_t g = gs.cur;
     if (g >= gs.end) return;
     int f = 0;
-    float pre[G::NPRE];   // block of the next window
+    // block of the next window: 16-byte slots for a whole window with
+    // aligned rows, else dword slots
+    constexpr int NP = QuadMap<ND>::N > G::NPRE ? QuadMap<ND>::N : G::NPRE;
+    float pre[NP];
     LaneMap<ND> lm;
+    QuadMap<ND> qm;
     Win wn;
-    bool valid;
+    bool valid, quads = false;
     // window of group g for this wave, and the start of its block load
     auto fetch = [&]() {
         while (g >= goff[f + 1]) ++f;
@@ -596,10 +724,16 @@ __global__ __launch_bounds__(kThreads) void k_compress(const FieldDesc* __restri
         valid = w < (uint32_t)(F[f].nwin[0] * F[f].nwin[1] * F[f].nwin[2]);
         if (valid) {
             wn = make_win<ND>(F[f], w);
-            lm.init(lane, wn.n0, wn.n01);
             const SZI_G float* wb = gp(F[f].in) + wn.gbase;
-            if (wn.full) load_block<ND, true>(pre, wb, lm, wn, 0.0f);
-            else load_block<ND, false>(pre, wb, lm, wn, 0.0f);
+            quads = wn.full && (wn.n0 & 3u) == 0u && ((uintptr_t)F[f].in & 15u) == 0u;
+            if (quads) {
+                qm.init(lane, wn.n0, wn.n01);
+                load_quads<ND>(pre, wb, qm, lane, wn.n01);
+            } else {
+                lm.init(lane, wn.n0, wn.n01);
+                if (wn.full) load_block<ND, true>(pre, wb, lm, wn, 0.0f);
+                else load_block<ND, false>(pre, wb, lm, wn, 0.0f);
+            }
         }
     };
     fetch();
@@ -608,7 +742,7 @@ __global__ __launch_bounds__(kThreads) void k_compress(const FieldDesc* __restri
     while (true) {
         const int fc = f;
         const Win wc = wn;
-        const bool vc = valid;
+        const bool vc = valid, qc = quads;
         if (fc != hf) {   // uniform over the workgroup: groups never span fields
             if (hf >= 0) flush_hist(hist, cntR, F[hf]);
 #pragma unroll 1
@@ -622,7 +756,8 @@ __global__ __launch_bounds__(kThreads) void k_compress(const FieldDesc* __restri
             hf = fc;
         }
         if (vc) {
-            if (wc.full) commit_block<ND, true>(v, pre, lm, wc);
+            if (qc) commit_quads<ND>(v, pre, qm, lane, wc.n01);
+            else if (wc.full) commit_block<ND, true>(v, pre, lm, wc);
             else commit_block<ND, false>(v, pre, lm, wc);
         }
         g += gs.step;

@@ -5,50 +5,58 @@
 namespace szi {
 
 // ------------------------------------------------------- value range
-// Partial min / max / non-finite counts: kRangeBlocks blocks per field.
+// Partial min / max / non-finite counts: kRangeBlocks blocks per field; the
+// extra block x = 0 of each field runs its profiling (first, so that its
+// serial work overlaps the streaming blocks).
+__device__ void profile_field(const FieldDesc& f, FieldPlan& P);
+
 __global__ __launch_bounds__(256) void k_range(const FieldDesc* __restrict__ F, float* pmin,
-                                               float* pmax, uint32_t* pbad) {
+                                               float* pmax, uint32_t* pbad, FieldPlan* P) {
     const FieldDesc& f = F[blockIdx.y];
+    if (blockIdx.x == 0) {
+        profile_field(f, P[blockIdx.y]);
+        return;
+    }
+    const uint32_t blk = blockIdx.x - 1;
     const SZI_G float* in = gp(f.in);
     const uint64_t n = f.npts;
     float mn = INFINITY, mx = -INFINITY;
     uint32_t bad = 0;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)kRangeBlocks * blockDim.x;
+    uint64_t tid = (uint64_t)blk * blockDim.x + threadIdx.x;
     uint64_t head = 0;
+    auto take = [&](float v) {
+        mn = fminf(mn, v);
+        mx = fmaxf(mx, v);
+        bad += finite_bits(v) ? 0u : 1u;
+    };
     if ((reinterpret_cast<uintptr_t>(in) & 15) == 0) {
         const SZI_G vf4* in4 = reinterpret_cast<const SZI_G vf4*>(in);
         const uint64_t n4 = n / 4;
         uint64_t i = tid;
-        for (; i + 3 * stride < n4; i += 4 * stride) {
-            const vf4 a = in4[i], b = in4[i + stride], c = in4[i + 2 * stride], d = in4[i + 3 * stride];
-            float vv[16] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w,
-                            c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w};
+        // eight 16-byte loads in flight per lane
+        for (; i + 7 * stride < n4; i += 8 * stride) {
+            vf4 a[8];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                mn = fminf(mn, vv[k]);
-                mx = fmaxf(mx, vv[k]);
-                bad += finite_bits(vv[k]) ? 0u : 1u;
+            for (int k = 0; k < 8; ++k) a[k] = __builtin_nontemporal_load(in4 + i + k * stride);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                take(a[k].x);
+                take(a[k].y);
+                take(a[k].z);
+                take(a[k].w);
             }
         }
         for (; i < n4; i += stride) {
             const vf4 a = in4[i];
-            float vv[4] = {a.x, a.y, a.z, a.w};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                mn = fminf(mn, vv[k]);
-                mx = fmaxf(mx, vv[k]);
-                bad += finite_bits(vv[k]) ? 0u : 1u;
-            }
+            take(a.x);
+            take(a.y);
+            take(a.z);
+            take(a.w);
         }
         head = n4 * 4;
     }
-    for (uint64_t i = head + tid; i < n; i += stride) {
-        float v = in[i];
-        mn = fminf(mn, v);
-        mx = fmaxf(mx, v);
-        bad += finite_bits(v) ? 0u : 1u;
-    }
+    for (uint64_t i = head + tid; i < n; i += stride) take(in[i]);
     __shared__ float smn[4], smx[4];
     __shared__ uint32_t sbad[4];
     mn = wave_min(mn);
@@ -67,7 +75,7 @@ __global__ __launch_bounds__(256) void k_range(const FieldDesc* __restrict__ F, 
             mx = fmaxf(mx, smx[k]);
             bad += sbad[k];
         }
-        const uint64_t o = (uint64_t)blockIdx.y * gridDim.x + blockIdx.x;
+        const uint64_t o = (uint64_t)blockIdx.y * kRangeBlocks + blk;
         pmin[o] = mn;
         pmax[o] = mx;
         pbad[o] = bad;
@@ -87,10 +95,11 @@ __device__ __forceinline__ int sample_pos(int nd, int t) {
     return v;
 }
 
-__global__ __launch_bounds__(64) void k_profile(const FieldDesc* __restrict__ F, FieldPlan* P) {
-    const FieldDesc& f = F[blockIdx.x];
+// Sec. V-C.1 profiling of one field by threads 0-63 of a workgroup.
+__device__ void profile_field(const FieldDesc& f, FieldPlan& P) {
     __shared__ double err[64][3][3];
     const int t = threadIdx.x;
+    if (t >= 64) return;
     const int D = f.ndim;
     const int ns = D == 3 ? 64 : 16;
     for (int d = 0; d < 3; ++d)
@@ -116,7 +125,9 @@ __global__ __launch_bounds__(64) void k_profile(const FieldDesc* __restrict__ F,
             err[t][d][2] = fabs((double)x - (double)pn);
         }
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();   // one wave: threads 0-63
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     if (t == 0) {
         double s[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
         if (f.need_prof)
@@ -125,7 +136,7 @@ __global__ __launch_bounds__(64) void k_profile(const FieldDesc* __restrict__ F,
                     if (f.n[d] >= 7)
                         for (int e = 0; e < 3; ++e) s[d][e] = s[d][e] + err[k][d][e];
         for (int d = 0; d < 3; ++d)
-            for (int e = 0; e < 3; ++e) P[blockIdx.x].prof[d][e] = s[d][e];
+            for (int e = 0; e < 3; ++e) P.prof[d][e] = s[d][e];
     }
 }
 
@@ -312,16 +323,11 @@ __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
 }
 
 // ------------------------------------------------------- launchers
-hipError_t launch_range(const FieldDesc* d_fields, int nfields, float* d_part_min,
-                        float* d_part_max, uint32_t* d_part_bad, hipStream_t st) {
-    hipLaunchKernelGGL(k_range, dim3(kRangeBlocks, nfields), dim3(256), 0, st, d_fields,
-                       d_part_min, d_part_max, d_part_bad);
-    return hipGetLastError();
-}
-
-hipError_t launch_profile(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
-                          hipStream_t st) {
-    hipLaunchKernelGGL(k_profile, dim3(nfields), dim3(64), 0, st, d_fields, d_plans);
+hipError_t launch_range(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
+                        float* d_part_min, float* d_part_max, uint32_t* d_part_bad,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_range, dim3(kRangeBlocks + 1, nfields), dim3(256), 0, st, d_fields,
+                       d_part_min, d_part_max, d_part_bad, d_plans);
     return hipGetLastError();
 }
 

@@ -11,7 +11,7 @@ constexpr int kMaxLevels = 8;
 constexpr int kLmax = 24;          // Huffman length limit
 constexpr int kLutBits = 10;       // decode look-up table width
 constexpr int kMaxRadius = 1024;   // LDS histogram holds 2R <= 2048 bins
-constexpr int kRangeBlocks = 1024; // partial min/max blocks per field
+constexpr int kRangeBlocks = 2048; // partial min/max blocks per field
 constexpr int kThreads = 256;      // threads per interpolation workgroup
 constexpr int kEncBlockChunks = 16;   // Huffman chunks per encode workgroup
 constexpr int kDecBlockChunks = 256;  // Huffman chunks per decode workgroup
@@ -98,10 +98,10 @@ constexpr int kDtSorted = kDtOffset + kLmax + 1;
 __host__ __device__ inline int dtab_words(int nsym) { return kDtSorted + nsym; }
 
 // ---- launchers (k_plan.hip, k_interp.hip, k_huff.hip) ----
-hipError_t launch_range(const FieldDesc* d_fields, int nfields, float* d_part_min,
-                        float* d_part_max, uint32_t* d_part_bad, hipStream_t st);
-hipError_t launch_profile(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
-                          hipStream_t st);
+// range partials and, in one extra block per field, the profiling (Sec. V-C.1)
+hipError_t launch_range(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
+                        float* d_part_min, float* d_part_max, uint32_t* d_part_bad,
+                        hipStream_t st);
 hipError_t launch_plan(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
                        const float* d_part_min, const float* d_part_max,
                        const uint32_t* d_part_bad, hipStream_t st);
