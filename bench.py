@@ -359,6 +359,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--eb", type=float, default=1e-3)
+    ap.add_argument("--chunk", type=int, default=1024, choices=(256, 512, 1024, 2048),
+                    help="Huffman chunk length in symbols")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain device copy of the input (4n bytes read, 4n written) "
@@ -405,7 +407,7 @@ def main():
     d_x = torch.from_numpy(x).to(dev)
     out = torch.empty_like(d_x)
     ctx = szi.Context(0)
-    kw = dict(eb=args.eb)
+    kw = dict(eb=args.eb, chunk=args.chunk)
 
     if args.calibrate_copy:
         out.copy_(d_x)
@@ -502,7 +504,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "shape": list(wl["shape"]), "eb_rel": args.eb,
                    "interp": "cubic auto (profiled)", "anchor_stride": 8, "radius": 512,
-                   "huffman_chunk": 1024},
+                   "huffman_chunk": args.chunk},
         "compress_GBps": round(in_bytes / float(np.median(t_c)) / 1e9, 2),
         "decompress_GBps": round(in_bytes / float(np.median(t_d)) / 1e9, 2),
         "compress_kernel_GBps": round(in_bytes / (comp_kernel_ms * 1e-3) / 1e9, 2),

@@ -34,8 +34,6 @@ constexpr int kXcds = 8;                // L2 domains; workgroup i runs on domai
 
 template <int ND>
 constexpr int vlen() { return kPad + Geo<ND>::BN + kPad; }
-template <int ND>
-constexpr int qlen() { return (Geo<ND>::BN + 2) & ~1; }
 
 // The window a wave works on.  Every member is wave-uniform.
 struct Win {
@@ -376,11 +374,22 @@ __device__ __forceinline__ float predict(bool m3, bool p1, bool p3, float a, flo
 // values (compression) or quant-codes (decompression).
 template <int K>
 struct Task {
-    int base;
+    int base;       // LDS index of the segment start
+    uint32_t gl;    // its global offset from the window origin
     uint32_t seg;
+    bool own;       // the line lies in the window's owned part
     float kn[K + 3];
     float xt[K];
     uint32_t ct[K];
+};
+
+// Where a pass leaves its results besides the block: compression stores
+// the quant-code of every owned target in the codes array and counts it in
+// the histogram; the replay finds outliers' values in the output array.
+struct PassOut {
+    SZI_G uint16_t* cb;       // the window's codes (compression)
+    const SZI_G float* ob;    // the window's output values (replay)
+    uint32_t* hist;           // LDS histogram (compression)
 };
 
 // One pass: dimension D, stride s = 1 << SH, spline SPL.  FULL: the window
@@ -389,9 +398,14 @@ struct Task {
 // issued before the current one is computed.  Within a pass no task reads a
 // point another task writes (targets never neighbour each other along D and
 // knowns are not written), so the reordering is safe.
+//
+// The block holds a value at every known point.  In the replay a point not
+// yet reconstructed holds its quant-code instead (as the bits of the
+// float), which the pass reading it as a target replaces by the value.
 template <int ND, int D, int SH, int SPL, bool COMP, bool FULL>
-__device__ __forceinline__ void pass_lines(float* v, uint16_t* q, uint32_t lane,
-                                           const PassDesc& pd, int ed, int R) {
+__device__ __forceinline__ void pass_lines(float* v, uint32_t lane, const PassDesc& pd,
+                                           const Win& wi, int ed, int R, const PassOut& po,
+                                           uint32_t& cntR) {
     using G = Geo<ND>;
     constexpr int s = 1 << SH;
     constexpr int W = D == 0 ? G::W0 : (D == 1 ? G::W1 : G::W2);
@@ -406,6 +420,18 @@ __device__ __forceinline__ void pass_lines(float* v, uint16_t* q, uint32_t lane,
     const int le = pd.le, lf = pd.lf;
     const float ebx2 = pd.ebx2, inv = pd.inv, Rf = (float)R;
     const double eld = (double)pd.el;
+    const uint32_t ge = pd.ge, gf = pd.gf;
+    const uint32_t gsd = D == 0 ? 1u : (D == 1 ? wi.n0 : wi.n01);   // global stride along D
+    // owned lines: i0 << she below the owned extent along de, i1 << shg
+    // below the one along dg
+    // (the extent is picked arithmetically: a select between members would
+    // become an indexed load, which keeps the window record in memory)
+    auto owned_count = [&](int dim, int sh) {
+        const int o = wi.o0 * (dim == 0) + wi.o1 * (dim == 1) + wi.o2 * (dim == 2);
+        return (o + (1 << sh) - 1) >> sh;
+    };
+    const int own0 = owned_count(pd.de, pd.she);
+    const int own1 = ND == 2 ? 1 : owned_count(pd.dg, pd.shg);
 
     auto fetch = [&](uint32_t t, Task<K>& tk) {
         tk.seg = NSEG > 1 ? (t & (uint32_t)(NSEG - 1)) : 0u;
@@ -413,6 +439,8 @@ __device__ __forceinline__ void pass_lines(float* v, uint16_t* q, uint32_t lane,
         const uint32_t i1 = __umulhi(ln, magic);   // ln / ne (ne >= 2, ln < 2^16)
         const uint32_t i0 = ln - i1 * ne;
         tk.base = (int)i0 * le + (int)i1 * lf + (int)tk.seg * (2 * K * s) * SD;
+        tk.gl = i0 * ge + i1 * gf + tk.seg * (uint32_t)(2 * K * s) * gsd;
+        if (COMP) tk.own = (int)i0 < own0 && (int)i1 < own1;
         // knowns at (2i - 2) s from the segment start; whole lines read only
         // the ones inside the block, split lines all of them (the guard band
         // and the neighbouring line absorb the ends; the flags drop them)
@@ -427,7 +455,7 @@ __device__ __forceinline__ void pass_lines(float* v, uint16_t* q, uint32_t lane,
             if (COMP)
                 tk.xt[j] = v[li];
             else
-                tk.ct[j] = q[li];
+                tk.ct[j] = __float_as_uint(v[li]);
         }
     };
 
@@ -462,7 +490,9 @@ __device__ __forceinline__ void pass_lines(float* v, uint16_t* q, uint32_t lane,
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const float p = pr[j];
-            const int li = tk.base + (2 * j + 1) * s * SD;
+            const int pos = (2 * j + 1) * s;
+            const int li = tk.base + pos * SD;
+            const uint32_t gi = tk.gl + (uint32_t)pos * gsd;
             if (COMP) {
                 // closed-loop quantisation against e_l, with the exact check;
                 // with e_l = 0, inv = 0 gives q = 0 and xr = p + 0 (exact
@@ -475,11 +505,21 @@ __device__ __forceinline__ void pass_lines(float* v, uint16_t* q, uint32_t lane,
                 // |rint(qf)| < R holds iff |qf| < R and |q| < R; NaN fails it
                 const bool ok = fabsf(qr) < Rf && fabs((double)xv - (double)xr) <= eld;
                 v[li] = ok ? xr : xv;
-                q[li] = (uint16_t)(ok ? qi + R : 0);
+                // owned targets: the window interval along D ends at ed - 1
+                if (tk.own && (FULL || p0 + pos < ed)) {
+                    const uint32_t code = ok ? (uint32_t)(qi + R) : 0u;
+                    *at(po.cb, gi) = (uint16_t)code;
+                    if (code == (uint32_t)R) ++cntR;
+                    else atomicAdd(&po.hist[code], 1u);
+                }
             } else {
+                // code 0: an outlier, whose value the scatter step put in the
+                // output array (points outside the field hold a code no
+                // point takes, so the load stays inside it)
                 const uint32_t code = tk.ct[j];
                 const float tq = (float)((int)code - R) * ebx2;
-                if (code != 0u) v[li] = p + tq;   // code 0: outlier, value already staged
+                if (code != 0u) v[li] = p + tq;
+                else v[li] = *at(po.ob, gi);
             }
         }
     };
@@ -505,20 +545,26 @@ __device__ __forceinline__ void pass_lines(float* v, uint16_t* q, uint32_t lane,
 }
 
 template <int ND, int D, int SH, bool COMP>
-__device__ __forceinline__ void run_pass(float* v, uint16_t* q, uint32_t lane, const PassDesc& pd,
-                                         const Win& wi, int R) {
+__device__ __forceinline__ void run_pass(float* v, uint32_t lane, const PassDesc& pd, const Win& wi,
+                                         int R, const PassOut& po, uint32_t& cntR) {
     using G = Geo<ND>;
     constexpr int W = D == 0 ? G::W0 : (D == 1 ? G::W1 : G::W2);
     const int ed = D == 0 ? wi.e0 : (D == 1 ? wi.e1 : wi.e2);
     // the stencil flags depend on the extent along D only
     if (ed == W + 1) {
-        if (pd.spl == SPL_LIN) pass_lines<ND, D, SH, SPL_LIN, COMP, true>(v, q, lane, pd, ed, R);
-        else if (pd.spl == SPL_NAT) pass_lines<ND, D, SH, SPL_NAT, COMP, true>(v, q, lane, pd, ed, R);
-        else pass_lines<ND, D, SH, SPL_NAK, COMP, true>(v, q, lane, pd, ed, R);
+        if (pd.spl == SPL_LIN)
+            pass_lines<ND, D, SH, SPL_LIN, COMP, true>(v, lane, pd, wi, ed, R, po, cntR);
+        else if (pd.spl == SPL_NAT)
+            pass_lines<ND, D, SH, SPL_NAT, COMP, true>(v, lane, pd, wi, ed, R, po, cntR);
+        else
+            pass_lines<ND, D, SH, SPL_NAK, COMP, true>(v, lane, pd, wi, ed, R, po, cntR);
     } else {
-        if (pd.spl == SPL_LIN) pass_lines<ND, D, SH, SPL_LIN, COMP, false>(v, q, lane, pd, ed, R);
-        else if (pd.spl == SPL_NAT) pass_lines<ND, D, SH, SPL_NAT, COMP, false>(v, q, lane, pd, ed, R);
-        else pass_lines<ND, D, SH, SPL_NAK, COMP, false>(v, q, lane, pd, ed, R);
+        if (pd.spl == SPL_LIN)
+            pass_lines<ND, D, SH, SPL_LIN, COMP, false>(v, lane, pd, wi, ed, R, po, cntR);
+        else if (pd.spl == SPL_NAT)
+            pass_lines<ND, D, SH, SPL_NAT, COMP, false>(v, lane, pd, wi, ed, R, po, cntR);
+        else
+            pass_lines<ND, D, SH, SPL_NAK, COMP, false>(v, lane, pd, wi, ed, R, po, cntR);
     }
 }
 
@@ -532,26 +578,26 @@ __device__ __forceinline__ void wave_sync() {
 
 // The passes of one level (stride 1 << SH), in the planned order.
 template <int ND, int SH, bool COMP>
-__device__ __forceinline__ void run_level(float* v, uint16_t* q, uint32_t lane,
-                                          const FieldPlan& pl, int R, const Win& wi) {
+__device__ __forceinline__ void run_level(float* v, uint32_t lane, const FieldPlan& pl, int R,
+                                          const Win& wi, const PassOut& po, uint32_t& cntR) {
     constexpr int L = ND == 3 ? 3 : 4;
 #pragma unroll 1
     for (int k = 0; k < ND; ++k) {
         const PassDesc pd = pl.pass[(L - 1 - SH) * ND + k];
-        if (pd.d == 0) run_pass<ND, 0, SH, COMP>(v, q, lane, pd, wi, R);
-        else if (ND == 2 || pd.d == 1) run_pass<ND, 1, SH, COMP>(v, q, lane, pd, wi, R);
-        else if constexpr (ND == 3) run_pass<ND, 2, SH, COMP>(v, q, lane, pd, wi, R);
+        if (pd.d == 0) run_pass<ND, 0, SH, COMP>(v, lane, pd, wi, R, po, cntR);
+        else if (ND == 2 || pd.d == 1) run_pass<ND, 1, SH, COMP>(v, lane, pd, wi, R, po, cntR);
+        else if constexpr (ND == 3) run_pass<ND, 2, SH, COMP>(v, lane, pd, wi, R, po, cntR);
         wave_sync();
     }
 }
 
 template <int ND, bool COMP>
-__device__ __forceinline__ void run_levels(float* v, uint16_t* q, uint32_t lane,
-                                           const FieldPlan& pl, int R, const Win& wi) {
-    if constexpr (ND == 2) run_level<ND, 3, COMP>(v, q, lane, pl, R, wi);
-    run_level<ND, 2, COMP>(v, q, lane, pl, R, wi);
-    run_level<ND, 1, COMP>(v, q, lane, pl, R, wi);
-    run_level<ND, 0, COMP>(v, q, lane, pl, R, wi);
+__device__ __forceinline__ void run_levels(float* v, uint32_t lane, const FieldPlan& pl, int R,
+                                           const Win& wi, const PassOut& po, uint32_t& cntR) {
+    if constexpr (ND == 2) run_level<ND, 3, COMP>(v, lane, pl, R, wi, po, cntR);
+    run_level<ND, 2, COMP>(v, lane, pl, R, wi, po, cntR);
+    run_level<ND, 1, COMP>(v, lane, pl, R, wi, po, cntR);
+    run_level<ND, 0, COMP>(v, lane, pl, R, wi, po, cntR);
 }
 
 // ---------------------------------------------------------------- write-out
@@ -566,55 +612,22 @@ struct OutMap {
     static constexpr int z0(int k) { return (k * RPS) / G::W1; }
 };
 
-// Owned quant-codes (anchors carry R), owned anchors, and the histogram of
-// the owned codes (Sec. VI-A; the centre code R is counted in a register).
-template <int ND, bool FULL>
-__device__ __forceinline__ void write_codes(const uint16_t* q, const float* v, uint32_t lane,
-                                            const FieldDesc& f, const Win& wi, uint32_t* hist,
-                                            uint32_t& cntR) {
+// Owned anchors: x = 0, S, 2S, 3S of row 0.  Their values go to the anchor
+// array (Sec. V-A: stored losslessly); their quant-code is R (counted in
+// the histogram like every owned code, Sec. VI-A).  The passes store the
+// codes of all other owned points.
+template <int ND>
+__device__ __forceinline__ void write_anchors(const float* v, uint32_t lane, const FieldDesc& f,
+                                              const Win& wi, uint32_t& cntR) {
     using G = Geo<ND>;
-    using M = OutMap<ND, G::W0 / 2>;    // x-pairs
-    const uint32_t R = (uint32_t)f.R;
-    SZI_G uint16_t* cb = gp(f.codes) + wi.gbase;
-    const uint32_t sub = lane / (uint32_t)(G::W0 / 2);
-    const int x = 2 * (int)(lane % (uint32_t)(G::W0 / 2));
-    const int lq = x + (int)sub * G::SY;
-    const uint32_t gq = (uint32_t)x + sub * wi.n0;
-    if (FULL && (wi.n0 & 1u) == 0u) {
-        // one 32-bit store per pair (window origins and rows are even)
-#pragma unroll
-        for (int k = 0; k < M::NS; ++k) {
-            const int l = lq + M::y0(k) * G::SY + M::z0(k) * G::SZ;
-            const uint32_t c0 = q[l], c1 = q[l + 1];
-            const uint32_t g = gq + (uint32_t)M::y0(k) * wi.n0 + (uint32_t)M::z0(k) * wi.n01;
-            *at((SZI_G uint32_t*)cb, g >> 1) = c0 | (c1 << 16);
-            if (c0 == R) ++cntR; else atomicAdd(&hist[c0], 1u);
-            if (c1 == R) ++cntR; else atomicAdd(&hist[c1], 1u);
-        }
-    } else {
-#pragma unroll 1
-        for (int k = 0; k < M::NS; ++k) {
-            const int y = M::y0(k) + (int)sub, z = M::z0(k);
-            if (y >= wi.o1 || z >= wi.o2) continue;
-            const int l = x + y * G::SY + z * G::SZ;
-            const uint32_t g = (uint32_t)x + (uint32_t)y * wi.n0 + (uint32_t)z * wi.n01;
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                if (x + i < wi.o0) {
-                    const uint32_t c = q[l + i];
-                    *at(cb, g + (uint32_t)i) = (uint16_t)c;
-                    if (c == R) ++cntR; else atomicAdd(&hist[c], 1u);
-                }
-            }
-        }
-    }
-    // owned anchors: x = 0, S, 2S, 3S of row 0
     constexpr int S = 1 << G::SHS;
     if (lane < (uint32_t)(G::W0 / S) && (int)lane * S < wi.o0) {
         const uint32_t ai = (uint32_t)(wi.lo0 >> G::SHS) + lane +
                             (uint32_t)f.na[0] * ((uint32_t)(wi.lo1 >> G::SHS) +
                                                  (uint32_t)f.na[1] * (uint32_t)(wi.lo2 >> G::SHS));
         gp(f.anchors)[ai] = v[(int)lane * S];
+        *at(gp(f.codes) + wi.gbase, lane * (uint32_t)S) = (uint16_t)f.R;
+        ++cntR;
     }
 }
 
@@ -692,31 +705,29 @@ __device__ __forceinline__ void flush_hist(uint32_t* hist, uint32_t& cntR, const
     __syncthreads();
 }
 
+// Three waves per SIMD: the register budget that leaves (168 VGPRs) is
+// what the kernels are compiled for; with the block alone in LDS (and the
+// histogram of compression), three workgroups of four windows fit a CU.
+#define SZI_WINDOW_KERNEL \
+    __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
+
 template <int ND>
-__global__ __launch_bounds__(kThreads) void k_compress(const FieldDesc* __restrict__ F,
-                                                       const FieldPlan* __restrict__ P,
-                                                       const uint64_t* __restrict__ goff,
-                                                       uint64_t ngroups) {
+SZI_WINDOW_KERNEL void k_compress(const FieldDesc* __restrict__ F, const FieldPlan* __restrict__ P,
+                                  const uint64_t* __restrict__ goff, uint64_t ngroups) {
     using G = Geo<ND>;
     __shared__ float vbuf[kWaves][vlen<ND>()];
-    __shared__ uint16_t qbuf[kWaves][qlen<ND>()];
     extern __shared__ uint32_t hist[];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lane = threadIdx.x & 63u;
     float* v = vbuf[wave] + kPad;
-    uint16_t* q = qbuf[wave];
     const GroupSeq gs = group_seq(ngroups);
     uint64_t g = gs.cur;
     if (g >= gs.end) return;
     int f = 0;
-    // block of the next window: 16-byte slots for a whole window with
-    // aligned rows, else dword slots
-    constexpr int NP = QuadMap<ND>::N > G::NPRE ? QuadMap<ND>::N : G::NPRE;
-    float pre[NP];
+    float pre[G::NPRE];   // block of the next window
     LaneMap<ND> lm;
-    QuadMap<ND> qm;
     Win wn;
-    bool valid, quads = false;
+    bool valid;
     // window of group g for this wave, and the start of its block load
     auto fetch = [&]() {
         while (g >= goff[f + 1]) ++f;
@@ -724,16 +735,10 @@ __global__ __launch_bounds__(kThreads) void k_compress(const FieldDesc* __restri
         valid = w < (uint32_t)(F[f].nwin[0] * F[f].nwin[1] * F[f].nwin[2]);
         if (valid) {
             wn = make_win<ND>(F[f], w);
+            lm.init(lane, wn.n0, wn.n01);
             const SZI_G float* wb = gp(F[f].in) + wn.gbase;
-            quads = wn.full && (wn.n0 & 3u) == 0u && ((uintptr_t)F[f].in & 15u) == 0u;
-            if (quads) {
-                qm.init(lane, wn.n0, wn.n01);
-                load_quads<ND>(pre, wb, qm, lane, wn.n01);
-            } else {
-                lm.init(lane, wn.n0, wn.n01);
-                if (wn.full) load_block<ND, true>(pre, wb, lm, wn, 0.0f);
-                else load_block<ND, false>(pre, wb, lm, wn, 0.0f);
-            }
+            if (wn.full) load_block<ND, true>(pre, wb, lm, wn, 0.0f);
+            else load_block<ND, false>(pre, wb, lm, wn, 0.0f);
         }
     };
     fetch();
@@ -742,22 +747,16 @@ __global__ __launch_bounds__(kThreads) void k_compress(const FieldDesc* __restri
     while (true) {
         const int fc = f;
         const Win wc = wn;
-        const bool vc = valid, qc = quads;
+        const bool vc = valid;
         if (fc != hf) {   // uniform over the workgroup: groups never span fields
             if (hf >= 0) flush_hist(hist, cntR, F[hf]);
 #pragma unroll 1
             for (int b = threadIdx.x; b < 2 * F[fc].R; b += kThreads) hist[b] = 0;
-            // anchors never become targets: their codes stay R
-            uint32_t ga;
-            int la;
-            (void)anchor_slot<ND>(lane, F[fc], wc, ga, la);
-            if (lane < (uint32_t)G::NANCH) q[la] = (uint16_t)F[fc].R;
             __syncthreads();
             hf = fc;
         }
         if (vc) {
-            if (qc) commit_quads<ND>(v, pre, qm, lane, wc.n01);
-            else if (wc.full) commit_block<ND, true>(v, pre, lm, wc);
+            if (wc.full) commit_block<ND, true>(v, pre, lm, wc);
             else commit_block<ND, false>(v, pre, lm, wc);
         }
         g += gs.step;
@@ -766,10 +765,9 @@ __global__ __launch_bounds__(kThreads) void k_compress(const FieldDesc* __restri
         if (vc) {
             wave_sync();
             const FieldDesc& fd = F[fc];
-            const FieldPlan& pl = P[fc];
-            run_levels<ND, true>(v, q, lane, pl, fd.R, wc);
-            if (wc.full) write_codes<ND, true>(q, v, lane, fd, wc, hist, cntR);
-            else write_codes<ND, false>(q, v, lane, fd, wc, hist, cntR);
+            const PassOut po{gp(fd.codes) + wc.gbase, nullptr, hist};
+            run_levels<ND, true>(v, lane, P[fc], fd.R, wc, po, cntR);
+            write_anchors<ND>(v, lane, fd, wc, cntR);
             wave_sync();
         }
         if (!more) break;
@@ -778,23 +776,20 @@ __global__ __launch_bounds__(kThreads) void k_compress(const FieldDesc* __restri
 }
 
 template <int ND>
-__global__ __launch_bounds__(kThreads) void k_decompress(const FieldDesc* __restrict__ F,
-                                                         const FieldPlan* __restrict__ P,
-                                                         const uint64_t* __restrict__ goff,
-                                                         uint64_t ngroups) {
+SZI_WINDOW_KERNEL void k_decompress(const FieldDesc* __restrict__ F,
+                                    const FieldPlan* __restrict__ P,
+                                    const uint64_t* __restrict__ goff, uint64_t ngroups) {
     using G = Geo<ND>;
     __shared__ float vbuf[kWaves][vlen<ND>()];
-    __shared__ uint16_t qbuf[kWaves][qlen<ND>()];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lane = threadIdx.x & 63u;
     float* v = vbuf[wave] + kPad;
-    uint16_t* q = qbuf[wave];
     const GroupSeq gs = group_seq(ngroups);
     uint64_t g = gs.cur;
     if (g >= gs.end) return;
     int f = 0;
-    // codes of the next window's block; slots outside it hold a value no
-    // code takes
+    // codes of the next window's block; block points outside the field
+    // hold a value no code takes
     constexpr uint32_t kNone = 0xFFFFFFFFu;
     uint32_t pre[G::NPRE];
     float apre = 0.0f;   // one anchor per lane
@@ -817,32 +812,23 @@ __global__ __launch_bounds__(kThreads) void k_decompress(const FieldDesc* __rest
         }
     };
     fetch();
+    uint32_t unused = 0;
     while (true) {
         const int fc = f;
         const Win wc = wn;
         const bool vc = valid;
         if (vc) {
-            const FieldDesc& fd = F[fc];
-            if (wc.full) commit_block<ND, true>(q, pre, lm, wc);
-            else commit_block<ND, false>(q, pre, lm, wc);
-            // outliers (code 0) take their value from the output array, where
-            // the scatter step put them; rare, so one uniform test first
-            bool anyz = false;
+            // every point of the block takes its code (as float bits), those
+            // outside the field the value kNone; the anchors then their values
 #pragma unroll
-            for (int k = 0; k < G::NPRE; ++k) anyz = anyz || pre[k] == 0u;
-            if (__any(anyz)) {
-                const SZI_G float* ob = gp((const float*)fd.out) + wc.gbase;
-#pragma unroll
-                for (int k = 0; k < G::NPRE; ++k) {
-                    uint32_t gg;
-                    int l;
-                    (void)lm.template slot<true>(k, wc, gg, l);
-                    if (pre[k] == 0u) v[l] = *at(ob, gg);
-                }
+            for (int k = 0; k < G::NPRE; ++k) {
+                uint32_t gg;
+                int l;
+                if (lm.template slot<true>(k, wc, gg, l)) v[l] = __uint_as_float(pre[k]);
             }
             uint32_t ga;
             int la;
-            if (anchor_slot<ND>(lane, fd, wc, ga, la)) v[la] = apre;
+            if (anchor_slot<ND>(lane, F[fc], wc, ga, la)) v[la] = apre;
         }
         g += gs.step;
         const bool more = g < gs.end;
@@ -850,8 +836,8 @@ __global__ __launch_bounds__(kThreads) void k_decompress(const FieldDesc* __rest
         if (vc) {
             wave_sync();
             const FieldDesc& fd = F[fc];
-            const FieldPlan& pl = P[fc];
-            run_levels<ND, false>(v, q, lane, pl, fd.R, wc);
+            const PassOut po{nullptr, gp((const float*)fd.out) + wc.gbase, nullptr};
+            run_levels<ND, false>(v, lane, P[fc], fd.R, wc, po, unused);
             if (wc.full) write_values<ND, true>(v, lane, fd, wc);
             else write_values<ND, false>(v, lane, fd, wc);
             wave_sync();

@@ -166,10 +166,11 @@ __device__ float floor_to_f32(double v) {
 // along dimensions already passed at this level the multiples of s, along
 // those still to come the multiples of 2s (Sec. V-A).
 template <int ND>
-__device__ void make_passes(FieldPlan& p, int L) {
+__device__ void make_passes(FieldPlan& p, int L, uint32_t n0, uint32_t n01) {
     using G = Geo<ND>;
     const int W[3] = {G::W0, G::W1, G::W2};
     const int ST[3] = {1, G::SY, G::SZ};
+    const uint32_t GS[3] = {1u, n0, n01};
     int np = 0;
     for (int lvl = L; lvl >= 1; --lvl) {
         const int s = 1 << (lvl - 1);
@@ -181,38 +182,49 @@ __device__ void make_passes(FieldPlan& p, int L) {
                 if (j == d) continue;
                 if (e < 0) e = j; else g = j;
             }
-            auto step = [&](int j) {
+            // lines sit at multiples of s along dimensions this level has
+            // already passed over, of 2 s along the others
+            auto shift = [&](int j) {
                 int pj = 0;
                 while (p.order[pj] != j) ++pj;
-                return pj < k ? s : 2 * s;
+                return pj < k ? lvl - 1 : lvl;
             };
-            const int se = step(e);
+            const int she = shift(e);
             q.d = d;
             q.spl = p.spline[d];
             q.sh = lvl - 1;
-            q.ne = (uint32_t)(W[e] / se + 1);
-            q.le = se * ST[e];
+            q.ne = (uint32_t)((W[e] >> she) + 1);
+            q.le = ST[e] << she;
+            q.de = e;
+            q.she = she;
+            q.ge = GS[e] << she;
             if (g >= 0) {
-                const int sg = step(g);
-                q.nlines = q.ne * (uint32_t)(W[g] / sg + 1);
-                q.lf = sg * ST[g];
+                const int shg = shift(g);
+                q.nlines = q.ne * (uint32_t)((W[g] >> shg) + 1);
+                q.lf = ST[g] << shg;
+                q.dg = g;
+                q.shg = shg;
+                q.gf = GS[g] << shg;
             } else {
                 q.nlines = q.ne;
                 q.lf = 0;
+                q.dg = e;
+                q.shg = 0;
+                q.gf = 0;
             }
             q.magic = kMagic.v[q.ne];
             q.el = p.el[lvl - 1];
             q.ebx2 = p.ebx2[lvl - 1];
             q.inv = q.el == 0.0f ? 0.0f : p.inv[lvl - 1];
-            q.pad = 0;
         }
     }
     for (; np < kMaxPasses; ++np) p.pass[np] = PassDesc{};
 }
 
 __device__ void make_passes(const FieldDesc& f, FieldPlan& p) {
-    if (f.ndim == 3) make_passes<3>(p, f.L);
-    else make_passes<2>(p, f.L);
+    const uint32_t n0 = (uint32_t)f.n[0], n01 = n0 * (uint32_t)f.n[1];
+    if (f.ndim == 3) make_passes<3>(p, f.L, n0, n01);
+    else make_passes<2>(p, f.L, n0, n01);
 }
 
 // pass descriptors of plans that came from the host (decompression)

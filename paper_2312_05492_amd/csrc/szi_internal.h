@@ -56,13 +56,19 @@ struct FieldDesc {
 // the points of the pass lie on nlines lines along dimension d, line
 // i0 + ne * i1 starting at LDS index i0 * le + i1 * lf of the block.
 constexpr int kMaxPasses = 12;
+// Lines of a pass are numbered i0 + ne * i1 over the two other dimensions
+// e < g (i1 = 0 in 2D); line (i0, i1) lies at coordinate i0 << she along e
+// and i1 << shg along g, at LDS offset i0 le + i1 lf and global offset
+// i0 ge + i1 gf from the window origin.
 struct PassDesc {
     int32_t d, spl, sh;        // dimension, spline, log2 of the stride
     uint32_t nlines, ne;
     uint32_t magic;            // multiply-high constant for division by ne
     int32_t le, lf;
     float el, ebx2, inv;       // level bound, 2 e_l, 1 / (2 e_l) (0 when e_l = 0)
-    int32_t pad;
+    int32_t de, dg;            // the other dimensions (dg = de in 2D)
+    int32_t she, shg;          // log2 of the line spacing along de and dg
+    uint32_t ge, gf;
 };
 
 // Per-field plan computed on the device from the range and the profile.
