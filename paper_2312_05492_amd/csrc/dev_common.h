@@ -13,6 +13,8 @@ namespace szi {
 // also counts against the LDS wait counter.  Casting them to the global
 // address space gives global_* instructions with a scalar base.
 #define SZI_G __attribute__((address_space(1)))
+// for lambdas in kernels: their bodies must not become calls
+#define SZI_INLINE __attribute__((always_inline))
 template <class T>
 __device__ __forceinline__ SZI_G T* gp(T* p) {
     return (SZI_G T*)p;

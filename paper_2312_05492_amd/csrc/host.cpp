@@ -427,13 +427,11 @@ void build_tables(const uint8_t* len, int nsym, uint32_t* cbook, uint32_t* dtab)
         for (uint32_t e = lo; e < hi; ++e) dtab[e] = ((uint32_t)l << 16) | (uint32_t)s;
     }
     uint32_t off = 0;
-    for (int l = 0; l <= kLmax; ++l) {
-        dtab[kDtFirst + l] = first[l];
-        dtab[kDtCount + l] = l == 0 ? 0 : count[l];
-        dtab[kDtOffset + l] = off;
-        if (l > 0)
-            for (int s = 0; s < nsym; ++s)
-                if (len[s] == l) dtab[kDtSorted + off++] = (uint32_t)s;
+    for (int l = 1; l <= kLmax; ++l) {
+        dtab[kDtLimit + l] = (first[l] + count[l]) << (kLmax - l);
+        dtab[kDtBase + l] = off - first[l];
+        for (int s = 0; s < nsym; ++s)
+            if (len[s] == l) dtab[kDtSorted + off++] = (uint32_t)s;
     }
 }
 

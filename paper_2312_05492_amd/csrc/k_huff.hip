@@ -258,8 +258,9 @@ __global__ __launch_bounds__(kDecChunks) void k_chunk_words(const FieldDesc* __r
     }
 }
 
-// one lane decodes one chunk: canonical decode with a 2^kLutBits table for
-// short codes and a first-code search for longer ones
+// One lane decodes one chunk: canonical decode with a 2^kLutBits table for
+// short codes; a longer code's length comes from comparing the next bits
+// with the per-length limits, without a loop or a data-dependent branch.
 // One lane per chunk.  The next bits sit most significant first in a 64-bit
 // buffer, topped up by one word whenever 32 or fewer remain (a lookup needs
 // at most kLmax = 24).  The words come from a 32-word ring per lane in LDS:
@@ -292,6 +293,11 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
     uint32_t* rings = smem + kDecChunks / 64;                // kDecChunks x kRing, 16-byte aligned
     uint32_t* tab = rings + kDecChunks * kRing;
     for (int k = threadIdx.x; k < ntab; k += blockDim.x) tab[k] = gp(fd.dtab)[k];
+    // length limits of the codes longer than the LUT, in scalar registers
+    uint32_t lim[kLmax - kLutBits - 1];
+#pragma unroll
+    for (int l = kLutBits + 1; l < kLmax; ++l)
+        lim[l - kLutBits - 1] = __builtin_amdgcn_readfirstlane(gp(fd.dtab)[kDtLimit + l]);
     const int tid = threadIdx.x;
     const uint64_t first = (blockIdx.x - boff[f]) * kDecChunks;
     const uint64_t ch = first + tid;
@@ -319,7 +325,7 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
     const uint32_t sw = (uint32_t)tid & (kRing / 4 - 1);
     uint64_t wr = w0 & ~(uint64_t)3;   // next word to request
     uint64_t rd = w0;                  // next word to move into the buffer
-    auto put = [&](uint64_t at, vu4 a, vu4 b) {   // words [at, at + 8) into the ring
+    auto put = [&](uint64_t at, vu4 a, vu4 b) SZI_INLINE {   // words [at, at + 8) into the ring
         *reinterpret_cast<vu4*>(ring + ring_slot((uint32_t)at, sw)) = a;
         *reinterpret_cast<vu4*>(ring + ring_slot((uint32_t)at + 4u, sw)) = b;
     };
@@ -338,12 +344,12 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
         put(wr + 8, c, d);
         wr += 16;
     }
-    auto rword = [&](uint64_t i) { return ring[ring_slot((uint32_t)i, sw)]; };
+    auto rword = [&](uint64_t i) SZI_INLINE { return ring[ring_slot((uint32_t)i, sw)]; };
     uint64_t buf = ((uint64_t)rword(rd) << 32) | (uint64_t)rword(rd + 1);
     rd += 2;
     int nb = 64;
     uint32_t nxw = rword(rd);   // the ring word the next top-up takes
-    auto decode_one = [&]() -> uint32_t {
+    auto decode_one = [&]() SZI_INLINE -> uint32_t {
         if (nb <= 32) {
             buf |= (uint64_t)nxw << (32 - nb);
             nb += 32;
@@ -352,18 +358,16 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
         }
         const uint32_t e = tab[(uint32_t)(buf >> (64 - kLutBits))];
         uint32_t len = e >> 16, sym = e & 0xFFFFu;
-        if (len == 0) {   // longer than the table: canonical decode
-#pragma unroll 1
-            for (int l = kLutBits + 1; l <= kLmax; ++l) {
-                const uint32_t code = (uint32_t)(buf >> (64 - l));
-                const uint32_t rel = code - tab[kDtFirst + l];
-                if (rel < tab[kDtCount + l]) {
-                    sym = tab[kDtSorted + tab[kDtOffset + l] + rel];
-                    len = l;
-                    break;
-                }
-            }
-            if (len == 0) len = 1;   // corrupt stream: consume a bit and go on
+        if (len == 0) {
+            // longer than the table: the length is one more than the number
+            // of length limits at or below the next kLmax bits (canonical
+            // codes grow with their length), then one look-up
+            const uint32_t w = (uint32_t)(buf >> (64 - kLmax));
+            len = kLutBits + 1;
+#pragma unroll
+            for (int l = kLutBits + 1; l < kLmax; ++l) len += w >= lim[l - kLutBits - 1] ? 1u : 0u;
+            const uint32_t i = tab[kDtBase + len] + (w >> (kLmax - len));
+            sym = tab[kDtSorted + (i < (uint32_t)nsym ? i : 0u)];   // a corrupt stream stays inside
         }
         buf <<= len;
         nb -= (int)len;
@@ -376,7 +380,7 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
     bool pend = false;
     uint64_t pat = 0;
     vu4 la = {0u, 0u, 0u, 0u}, lb = la;
-    auto refill = [&]() {
+    auto refill = [&]() SZI_INLINE {
         if (pend) put(pat, la, lb);
         // the ring holds [rd, wr) and a request adds 8; the prefetched word
         // at rd is not overwritten because the ring keeps kRing - 8 >= 7
@@ -388,7 +392,7 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
             wr += 8;
         }
     };
-    auto group8 = [&]() -> vu4 {
+    auto group8 = [&]() SZI_INLINE -> vu4 {
         refill();
         vu4 pk;
         uint32_t lo, hi;

@@ -94,13 +94,15 @@ struct FieldPlan {
 constexpr int kWinPerGroup = 4;
 
 // Decode tables, one u32 array per field:
-//   [0, 1<<kLutBits)           LUT: len << 16 | symbol (len 0 = longer code)
-//   first[kLmax+1], count[kLmax+1], offset[kLmax+1]
+//   [0, 1<<kLutBits)   LUT: len << 16 | symbol (len 0 = longer code)
+//   limit[kLmax+1]     limit[l]: the codes of length <= l, left-justified to
+//                      kLmax bits, lie below it ((first + count) << (kLmax - l))
+//   base[kLmax+1]      base[l]: position of length l among the sorted
+//                      symbols minus the first code of length l
 //   sorted symbols (nsym entries, by (length, symbol))
-constexpr int kDtFirst = 1 << kLutBits;
-constexpr int kDtCount = kDtFirst + kLmax + 1;
-constexpr int kDtOffset = kDtCount + kLmax + 1;
-constexpr int kDtSorted = kDtOffset + kLmax + 1;
+constexpr int kDtLimit = 1 << kLutBits;
+constexpr int kDtBase = kDtLimit + kLmax + 1;
+constexpr int kDtSorted = kDtBase + kLmax + 1;
 __host__ __device__ inline int dtab_words(int nsym) { return kDtSorted + nsym; }
 
 // ---- launchers (k_plan.hip, k_interp.hip, k_huff.hip) ----

@@ -114,6 +114,26 @@ def front_field(shape, seed, width=2.0) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- workloads
+def fib_spikes(shape, n=24, seed=26) -> np.ndarray:
+    """Zeros with spikes of height k at F(k) points (F the Fibonacci numbers
+    1, 1, 2, 3, ..., k = 1..n), placed at seeded random points whose
+    coordinates are all odd."""
+    x = np.zeros(shape, np.float32)
+    idx = np.stack(np.meshgrid(*[np.arange(1, s, 2) for s in shape], indexing="ij"),
+                   -1).reshape(-1, len(shape))
+    np.random.default_rng(seed).shuffle(idx)
+    f = [1, 1]
+    while len(f) < n:
+        f.append(f[-1] + f[-2])
+    if sum(f) > len(idx):
+        raise ValueError("shape %s has too few all-odd points for %d spike heights" % (shape, n))
+    k0 = 0
+    for k, c in enumerate(f, 1):
+        x[tuple(idx[k0:k0 + c].T)] = np.float32(k)
+        k0 += c
+    return x
+
+
 def workload_small(seed=1):
     """64^3 smooth field: bumps + sinusoids + N(0, 1e-4)."""
     return bumps_field((64, 64, 64), seed=seed)

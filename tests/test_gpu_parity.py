@@ -144,6 +144,13 @@ CASES = [
      dict(interp=(2, 2, 2), eb=0.0, eb_mode=0)),
     ("signed_zeros_abs_bound", _signed_zeros((20, 24, 40), 25),
      dict(interp=(1, 2, 0), eb=0.5, eb_mode=0)),
+    # Huffman codes up to the 24-bit length limit, decoded past the look-up
+    # table (Fibonacci code counts give the deepest tree; the oracle pins
+    # check the lengths)
+    ("long_codes_3d", lambda: synth.fib_spikes((100, 100, 100)),
+     dict(interp=(0, 0, 0), eb=0.5, eb_mode=0)),
+    ("long_codes_2d", lambda: synth.fib_spikes((700, 700), seed=27),
+     dict(interp=(0, 0), eb=0.5, eb_mode=0)),
 ]
 
 

@@ -472,6 +472,23 @@ def test_huffman_length_limit_binds():
     assert ln2.max() <= 3 and _cost(h2, ln2) == _brute_optimal(list(map(int, h2)), 3)
 
 
+@pytest.mark.parametrize("shape,seed", [((100, 100, 100), 26), ((700, 700), 27)])
+def test_fib_spikes_codes_and_depth(shape, seed):
+    # a spike of height k at a point with all coordinates odd is a target of
+    # the last pass and nobody's neighbour: under linear interpolation its
+    # prediction is 0 and, with 2 e = 1, its code is R + k; every other
+    # point predicts 0 exactly (code R).  The counts F(k) then drive the
+    # code lengths to the 24-bit limit.
+    x = synth.fib_spikes(shape, seed=seed)
+    p = O.Params(shape=shape, eb=0.5, eb_mode=0, interp=(0,) * len(shape))
+    res = O.compress(x, p)
+    R = p.R
+    assert np.array_equal(res.codes, (R + x).astype(res.codes.dtype))
+    assert res.outlier_idx.size == 0
+    assert res.code_len.max() == 24
+    assert np.array_equal(res.recon, x)
+
+
 def test_huffman_single_symbol():
     h = np.zeros(1024, dtype=np.uint32)
     h[512] = 77
