@@ -418,38 +418,57 @@ def main():
         r.free()
     torch.cuda.synchronize()
 
-    ctx.set_timing(True)
-    comp_stages, decomp_stages = {}, {}
-    t_c, t_d = [], []
-    last = None
+    def run_steps(k, keep_last, collect=None):
+        tc, td, r_last = [], [], None
+        for i in range(k):
+            a = time.perf_counter()
+            r = ctx.compress(d_x, **kw)
+            b = time.perf_counter()
+            if collect:
+                collect[0]()
+            b2 = time.perf_counter()
+            ctx.decompress(r, out)
+            c = time.perf_counter()
+            if collect:
+                collect[1]()
+            tc.append(b - a)
+            td.append(c - b2)
+            if keep_last and i == k - 1:
+                r_last = r
+            else:
+                r.free()
+        return tc, td, r_last
+
+    # the timed steps: the plain one-field-per-call path, no instrumentation
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    def collect(tgt):
-        # host bookkeeping only: totals accumulated by the library's events
-        for k, (ms, cnt) in ctx.read_timing(reset=True).items():
-            if cnt:
-                acc = tgt.setdefault(k, [0.0, 0])
-                acc[0] += ms
-                acc[1] += cnt
-
-    for i in range(args.steps):
-        a = time.perf_counter()
-        r = ctx.compress(d_x, **kw)
-        b = time.perf_counter()
-        collect(comp_stages)
-        b2 = time.perf_counter()
-        ctx.decompress(r, out)
-        c = time.perf_counter()
-        collect(decomp_stages)
-        t_c.append(b - a)
-        t_d.append(c - b2)
-        if i == args.steps - 1:
-            last = r
-        else:
-            r.free()
+    t_c, t_d, last = run_steps(args.steps, True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     step_s = (t1 - t0) / args.steps
+
+    # untimed: per-stage device time from the library's events
+    comp_stages, decomp_stages = {}, {}
+
+    def collector(tgt):
+        def f():
+            for k, (ms, cnt) in ctx.read_timing(reset=True).items():
+                if cnt:
+                    acc = tgt.setdefault(k, [0.0, 0])
+                    acc[0] += ms
+                    acc[1] += cnt
+        return f
+
+    ctx.set_timing(True)
+    ctx.read_timing(reset=True)
+    run_steps(max(1, min(args.steps, 5)), False, (collector(comp_stages), collector(decomp_stages)))
+    ctx.set_timing(False)
+    # untimed: the same calls through the library's captured graphs
+    ctx.set_graphs(True)
+    run_steps(2, False)
+    g_c, g_d, _ = run_steps(max(1, min(args.steps, 5)), False)
+    ctx.set_graphs(False)
+    torch.cuda.synchronize()
 
     # quality metrics of the last step (untimed)
     cr = 4.0 * n / last.compressed_bytes
@@ -513,6 +532,8 @@ def main():
                        "compress_p99": round(pct(t_c, 99) * 1e3, 3),
                        "decompress_p50": round(pct(t_d, 50) * 1e3, 3),
                        "decompress_p99": round(pct(t_d, 99) * 1e3, 3)},
+        "graph_latency_ms": {"compress_p50": round(pct(g_c, 50) * 1e3, 3),
+                             "decompress_p50": round(pct(g_d, 50) * 1e3, 3)},
         "kernels": {"compress": comp_rep, "decompress": decomp_rep},
         "ratio": round(cr, 3),
         "bitrate": round(32.0 / cr, 4),

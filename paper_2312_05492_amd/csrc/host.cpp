@@ -342,58 +342,109 @@ uint32_t crc32_update(uint32_t crc, const uint8_t* p, size_t n) {
 }
 
 // ------------------------------------------------------------ codebook
+// One package-merge round: merge the sorted leaf weights lw[0, m) (lw[m] a
+// sentinel) with the packages pk(j) = pw[2j] + pw[2j+1], j < np, a leaf
+// first on equal weight; out[o] gets the merged weights and leaf[o] whether
+// item o is a leaf.  The output is cut into four parts at their merge-path
+// split points (the number of leaves among the first k items, found by
+// bisection), and the four merges advance together, which gives the CPU
+// four independent dependency chains instead of one.
+static void merge_round(const uint64_t* lw, size_t m, const uint64_t* pw, size_t np, uint64_t* out,
+                        uint8_t* leaf) {
+    const size_t n = m + np;
+    auto pk = [&](size_t j) { return pw[2 * j] + pw[2 * j + 1]; };
+    auto corank = [&](size_t k) {
+        size_t lo = k > np ? k - np : 0, hi = k < m ? k : m;
+        while (lo < hi) {
+            const size_t i = (lo + hi) / 2, j = k - i;
+            if (j > 0 && lw[i] <= pk(j - 1)) lo = i + 1;   // leaf i precedes package j - 1
+            else hi = i;
+        }
+        return lo;
+    };
+    constexpr int P = 4;
+    size_t k[P + 1], i[P], j[P], ie[P], je[P];
+    for (int p = 0; p <= P; ++p) k[p] = n * (size_t)p / P;
+    for (int p = 0; p < P; ++p) {
+        i[p] = p == 0 ? 0 : corank(k[p]);
+        j[p] = k[p] - i[p];
+    }
+    for (int p = 0; p < P; ++p) {
+        ie[p] = p + 1 < P ? i[p + 1] : m;
+        je[p] = k[p + 1] - ie[p];
+    }
+    auto step = [&](int p, size_t o) {
+        const uint64_t a = lw[i[p]];
+        const uint64_t b = j[p] < je[p] ? pk(j[p]) : UINT64_MAX;
+        const bool tl = i[p] < ie[p] && a <= b;
+        out[o] = tl ? a : b;
+        leaf[o] = tl;
+        i[p] += tl;
+        j[p] += !tl;
+    };
+    size_t len = n;
+    for (int p = 0; p < P; ++p) len = std::min(len, k[p + 1] - k[p]);
+    for (size_t o = 0; o < len; ++o)
+        for (int p = 0; p < P; ++p) step(p, k[p] + o);
+    for (int p = 0; p < P; ++p)   // parts longer than the shortest
+        for (size_t o = k[p] + len; o < k[p + 1]; ++o) step(p, o);
+}
+
 // Length-limited Huffman lengths by package-merge, with the tie-breaking
 // fixed so that the lengths are unique: leaves ordered by (count, symbol);
 // each round pairs consecutive items of the previous round's list and
 // merges the pairs into the leaves, a leaf first on equal weight; the first
-// 2m-2 items of the last round decide the lengths.
+// 2m-2 items of the last round decide the lengths.  The leaves in a
+// round's selected prefix are always the lightest ones, so a leaf's length
+// is the number of rounds whose prefix holds more leaves than its rank.
 void huffman_lengths(const uint32_t* h, int nsym, int lmax, uint8_t* len) {
     std::memset(len, 0, nsym);
-    std::vector<std::pair<uint64_t, int>> leaf;
+    std::vector<uint64_t> key;   // count << 32 | symbol
+    key.reserve(nsym);
     for (int s = 0; s < nsym; ++s)
-        if (h[s]) leaf.emplace_back(h[s], s);
-    const size_t m = leaf.size();
+        if (h[s]) key.push_back((uint64_t)h[s] << 32 | (uint32_t)s);
+    const size_t m = key.size();
     if (m == 0) return;
     if (m == 1) {
-        len[leaf[0].second] = 1;
+        len[key[0] & 0xFFFFFFFFu] = 1;
         return;
     }
-    std::sort(leaf.begin(), leaf.end());
-    std::vector<std::vector<uint64_t>> wt(lmax);
-    std::vector<std::vector<int>> sym(lmax);   // -1 marks a package
-    for (auto& l : leaf) {
-        wt[0].push_back(l.first);
-        sym[0].push_back(l.second);
+    std::sort(key.begin(), key.end());
+    std::vector<uint64_t> lw(m + 1);
+    for (size_t i = 0; i < m; ++i) lw[i] = key[i] >> 32;
+    lw[m] = UINT64_MAX;
+    const size_t cap = 2 * m;
+    std::vector<uint64_t> wprev(cap), wcur(cap);
+    std::vector<uint8_t> leafbit((size_t)lmax * cap);
+    std::vector<size_t> lsize(lmax);
+    for (size_t i = 0; i < m; ++i) {
+        wprev[i] = lw[i];
+        leafbit[i] = 1;
     }
+    lsize[0] = m;
     for (int lv = 1; lv < lmax; ++lv) {
-        const std::vector<uint64_t>& pw = wt[lv - 1];
-        const size_t npk = pw.size() / 2;
-        size_t i = 0, j = 0;
-        while (i < m || j < npk) {
-            const bool take_leaf =
-                j >= npk || (i < m && leaf[i].first <= pw[2 * j] + pw[2 * j + 1]);
-            if (take_leaf) {
-                wt[lv].push_back(leaf[i].first);
-                sym[lv].push_back(leaf[i].second);
-                ++i;
-            } else {
-                wt[lv].push_back(pw[2 * j] + pw[2 * j + 1]);
-                sym[lv].push_back(-1);
-                ++j;
-            }
-        }
+        const size_t np = lsize[lv - 1] / 2;
+        merge_round(lw.data(), m, wprev.data(), np, wcur.data(), &leafbit[(size_t)lv * cap]);
+        lsize[lv] = m + np;
+        std::swap(wprev, wcur);
     }
+    // rounds from the last down: the leaves among the first take items, and
+    // the packages among them set the next round's take
+    std::vector<int32_t> diff(m + 1, 0);
     size_t take = 2 * m - 2;
     for (int lv = lmax - 1; lv >= 0; --lv) {
-        size_t pk = 0;
-        const size_t lim = std::min(take, sym[lv].size());
-        for (size_t k = 0; k < lim; ++k) {
-            if (sym[lv][k] >= 0)
-                len[sym[lv][k]]++;
-            else
-                ++pk;
-        }
-        take = 2 * pk;
+        const size_t lim = std::min(take, lsize[lv]);
+        const uint8_t* lb = &leafbit[(size_t)lv * cap];
+        size_t nl = 0;
+        for (size_t k = 0; k < lim; ++k) nl += lb[k];
+        diff[0] += 1;
+        diff[nl] -= 1;
+        take = 2 * (lim - nl);
+    }
+    int32_t acc = 0;
+    for (size_t i = 0; i < m; ++i) {
+        acc += diff[i];
+        len[key[i] & 0xFFFFFFFFu] = (uint8_t)acc;
     }
 }
 
@@ -426,13 +477,14 @@ void build_tables(const uint8_t* len, int nsym, uint32_t* cbook, uint32_t* dtab)
         const uint32_t lo = code[s] << (kLutBits - l), hi = (code[s] + 1) << (kLutBits - l);
         for (uint32_t e = lo; e < hi; ++e) dtab[e] = ((uint32_t)l << 16) | (uint32_t)s;
     }
-    uint32_t off = 0;
+    uint32_t off[kLmax + 2] = {0};   // first position of each length among the sorted symbols
     for (int l = 1; l <= kLmax; ++l) {
+        off[l + 1] = off[l] + count[l];
         dtab[kDtLimit + l] = (first[l] + count[l]) << (kLmax - l);
-        dtab[kDtBase + l] = off - first[l];
-        for (int s = 0; s < nsym; ++s)
-            if (len[s] == l) dtab[kDtSorted + off++] = (uint32_t)s;
+        dtab[kDtBase + l] = off[l] - first[l];
     }
+    for (int s = 0; s < nsym; ++s)
+        if (len[s]) dtab[kDtSorted + off[len[s]]++] = (uint32_t)s;
 }
 
 bool kraft_ok(const uint8_t* len, int nsym) {

@@ -513,14 +513,26 @@ __device__ __forceinline__ void pass_lines(float* v, uint32_t lane, const PassDe
                     else atomicAdd(&po.hist[code], 1u);
                 }
             } else {
-                // code 0: an outlier, whose value the scatter step put in the
-                // output array (points outside the field hold a code no
-                // point takes, so the load stays inside it)
                 const uint32_t code = tk.ct[j];
-                const float tq = (float)((int)code - R) * ebx2;
-                if (code != 0u) v[li] = p + tq;
-                else v[li] = *at(po.ob, gi);
+                pr[j] = p + (float)((int)code - R) * ebx2;
             }
+        }
+        if (!COMP) {
+            // code 0: an outlier, whose value the scatter step put in the
+            // output array (points outside the field hold a code no point
+            // takes, so the load stays inside it); rare, so one uniform test
+            bool out = false;
+#pragma unroll
+            for (int j = 0; j < K; ++j) out = out || tk.ct[j] == 0u;
+            if (__any(out)) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const int pos = (2 * j + 1) * s;
+                    if (tk.ct[j] == 0u) pr[j] = *at(po.ob, tk.gl + (uint32_t)pos * gsd);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j) v[tk.base + (2 * j + 1) * s * SD] = pr[j];
         }
     };
 
