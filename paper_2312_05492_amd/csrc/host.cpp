@@ -1047,8 +1047,24 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
     const size_t o_bw = L.take<uint32_t>(std::max<uint64_t>(total_blocks, 1));
     const size_t o_bo = L.take<uint32_t>(std::max<uint64_t>(total_blocks, 1));
     const size_t o_bwoff = L.take<uint64_t>(nbw), o_booff = L.take<uint64_t>(nbw);
+    // host staging in pinned memory (copies from it are asynchronous): the
+    // arena's layout, then each field's code lengths, codebook and decode
+    // tables
+    std::vector<size_t> o_cb(nf + 1);
+    o_cb[0] = (L.off + 255) & ~(size_t)255;
+    for (uint32_t k = 0; k < nf; ++k) {
+        const size_t nsym = 2 * (size_t)fds[k].R;
+        o_cb[k + 1] = o_cb[k] + ((nsym + 4 * nsym + 4 * (size_t)dtab_words((int)nsym) + 255) & ~(size_t)255);
+    }
+    char* hs;   // the staging base
     if (c->graphs) {
-        if ((s = arena_reserve(c, L.off))) return s;
+        if ((s = arena_reserve(c, o_cb[nf]))) return s;
+        hs = static_cast<char*>(c->parena);
+    } else {
+        if ((s = pinned_reserve(c, o_cb[nf]))) return s;
+        hs = static_cast<char*>(c->pinned);
+    }
+    if (c->graphs) {
         char* d = static_cast<char*>(c->arena);
         d_fd = reinterpret_cast<FieldDesc*>(d + o_fd);
         d_items = reinterpret_cast<uint64_t*>(d + o_items);
@@ -1129,20 +1145,22 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
             std::memcpy(hist[k].data(), h + o_hist + sizeof(uint32_t) * k * hstride,
                         sizeof(uint32_t) * hist[k].size());
     } else {
-        const size_t stage1 = sizeof(FieldDesc) * nf + sizeof(uint64_t) * items.size();
-        if ((s = pinned_reserve(c, std::max<size_t>(stage1, sizeof(FieldPlan) * nf +
-                                                               sizeof(uint32_t) * 2 * max_R * nf))))
-            return s;
-        HIP_TRY(c, hipMemcpyAsync(d_fd, fds.data(), sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(d_items, items.data(), sizeof(uint64_t) * items.size(),
+        std::memcpy(hs + o_fd, fds.data(), sizeof(FieldDesc) * nf);
+        std::memcpy(hs + o_items, items.data(), sizeof(uint64_t) * items.size());
+        HIP_TRY(c, hipMemcpyAsync(d_fd, hs + o_fd, sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(d_items, hs + o_items, sizeof(uint64_t) * items.size(),
                                   hipMemcpyHostToDevice, st));
         if ((s = enqueue1(st))) return s;
-        HIP_TRY(c, hipMemcpyAsync(plans.data(), d_plan, sizeof(FieldPlan) * nf,
-                                  hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipMemcpyAsync(hs + o_plan, d_plan, sizeof(FieldPlan) * nf, hipMemcpyDeviceToHost,
+                                  st));
         for (uint32_t k = 0; k < nf; ++k)
-            HIP_TRY(c, hipMemcpyAsync(hist[k].data(), fds[k].hist, sizeof(uint32_t) * hist[k].size(),
-                                      hipMemcpyDeviceToHost, st));
+            HIP_TRY(c, hipMemcpyAsync(hs + o_hist + sizeof(uint32_t) * k * hstride, fds[k].hist,
+                                      sizeof(uint32_t) * hist[k].size(), hipMemcpyDeviceToHost, st));
         HIP_TRY(c, hipStreamSynchronize(st));
+        std::memcpy(plans.data(), hs + o_plan, sizeof(FieldPlan) * nf);
+        for (uint32_t k = 0; k < nf; ++k)
+            std::memcpy(hist[k].data(), hs + o_hist + sizeof(uint32_t) * k * hstride,
+                        sizeof(uint32_t) * hist[k].size());
     }
     std::unique_ptr<StageMark> cb_mark(new StageMark(c, SZ_STAGE_CODEBOOK, st));
     for (uint32_t k = 0; k < nf; ++k)
@@ -1151,7 +1169,6 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
                         plans[k].nonfinite);
 
     // host codebooks (Sec. VI-A), exact buffer sizes from the histogram
-    std::vector<std::vector<uint32_t>> cbook(nf), dtab(nf);
     for (uint32_t k = 0; k < nf; ++k) {
         const uint32_t i = perm[k];
         ResultInternal* R = ri(&res[i]);
@@ -1159,9 +1176,11 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
         const int nsym = 2 * fds[k].R;
         R->code_len.assign(nsym, 0);
         huffman_lengths(hist[k].data(), nsym, kLmax, R->code_len.data());
-        cbook[k].resize(nsym);
-        dtab[k].resize(dtab_words(nsym));
-        build_tables(R->code_len.data(), nsym, cbook[k].data(), dtab[k].data());
+        uint8_t* h_len = reinterpret_cast<uint8_t*>(hs + o_cb[k]);
+        uint32_t* h_cbook = reinterpret_cast<uint32_t*>(h_len + nsym);
+        uint32_t* h_dtab = h_cbook + nsym;
+        std::memcpy(h_len, R->code_len.data(), nsym);
+        build_tables(R->code_len.data(), nsym, h_cbook, h_dtab);
         uint64_t bits = 0;
         for (int sy = 0; sy < nsym; ++sy) bits += (uint64_t)hist[k][sy] * R->code_len[sy];
         const uint64_t nout = hist[k][0];
@@ -1179,10 +1198,10 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
         if (c->graphs)   // the result keeps its own histogram
             HIP_TRY(c, hipMemcpyAsync(res[i].hist, fds[k].hist, sizeof(uint32_t) * nsym,
                                       hipMemcpyDeviceToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(res[i].code_len, R->code_len.data(), nsym, hipMemcpyHostToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(R->d_cbook, cbook[k].data(), sizeof(uint32_t) * nsym,
+        HIP_TRY(c, hipMemcpyAsync(res[i].code_len, h_len, nsym, hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(R->d_cbook, h_cbook, sizeof(uint32_t) * nsym,
                                   hipMemcpyHostToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(R->d_dtab, dtab[k].data(), sizeof(uint32_t) * dtab[k].size(),
+        HIP_TRY(c, hipMemcpyAsync(R->d_dtab, h_dtab, sizeof(uint32_t) * dtab_words(nsym),
                                   hipMemcpyHostToDevice, st));
     }
     std::vector<FieldDesc> hfd(nf);
@@ -1246,14 +1265,17 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
         HIP_TRY(c, hipStreamSynchronize(st));
         std::memcpy(bwoff.data(), h + o_bwoff, sizeof(uint64_t) * nbw);
     } else {
-        HIP_TRY(c, hipMemcpyAsync(d_hfd, hfd.data(), sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(d_gboff, gboff.data(), sizeof(uint64_t) * gboff.size(),
+        std::memcpy(hs + o_hfd, hfd.data(), sizeof(FieldDesc) * nf);
+        std::memcpy(hs + o_gboff, gboff.data(), sizeof(uint64_t) * gboff.size());
+        HIP_TRY(c, hipMemcpyAsync(d_hfd, hs + o_hfd, sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(d_gboff, hs + o_gboff, sizeof(uint64_t) * gboff.size(),
                                   hipMemcpyHostToDevice, st));
         cb_mark.reset();
         if ((s = enqueue2(st))) return s;
-        HIP_TRY(c, hipMemcpyAsync(bwoff.data(), d_bwoff, sizeof(uint64_t) * nbw,
+        HIP_TRY(c, hipMemcpyAsync(hs + o_bwoff, d_bwoff, sizeof(uint64_t) * nbw,
                                   hipMemcpyDeviceToHost, st));
         HIP_TRY(c, hipStreamSynchronize(st));
+        std::memcpy(bwoff.data(), hs + o_bwoff, sizeof(uint64_t) * nbw);
     }
     resolve_marks(c);
     for (size_t g = 0; g < groups.size(); ++g) {
@@ -1417,10 +1439,24 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         (s = sc.get(nf + 1, &d_dboff)) || (s = sc.get(nblocks + 1, &d_bwoff)) ||
         (s = sc.get(std::max<uint64_t>(nblocks, 1), &d_bsum)))
         return s;
-    HIP_TRY(c, hipMemcpyAsync(d_fd, fds.data(), sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
-    HIP_TRY(c, hipMemcpyAsync(d_plan, plans.data(), sizeof(FieldPlan) * nf, hipMemcpyHostToDevice, st));
-    HIP_TRY(c, hipMemcpyAsync(d_items, items.data(), sizeof(uint64_t) * items.size(), hipMemcpyHostToDevice, st));
-    HIP_TRY(c, hipMemcpyAsync(d_dboff, dboff.data(), sizeof(uint64_t) * (nf + 1), hipMemcpyHostToDevice, st));
+    // descriptors staged in pinned memory, one asynchronous copy each
+    {
+        Layout L;
+        const size_t o_fd = L.take<FieldDesc>(nf), o_plan = L.take<FieldPlan>(nf);
+        const size_t o_items = L.take<uint64_t>(items.size()), o_dboff = L.take<uint64_t>(nf + 1);
+        if ((s = pinned_reserve(c, L.off))) return s;
+        char* h = static_cast<char*>(c->pinned);
+        std::memcpy(h + o_fd, fds.data(), sizeof(FieldDesc) * nf);
+        std::memcpy(h + o_plan, plans.data(), sizeof(FieldPlan) * nf);
+        std::memcpy(h + o_items, items.data(), sizeof(uint64_t) * items.size());
+        std::memcpy(h + o_dboff, dboff.data(), sizeof(uint64_t) * (nf + 1));
+        HIP_TRY(c, hipMemcpyAsync(d_fd, h + o_fd, sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(d_plan, h + o_plan, sizeof(FieldPlan) * nf, hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(d_items, h + o_items, sizeof(uint64_t) * items.size(),
+                                  hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(d_dboff, h + o_dboff, sizeof(uint64_t) * (nf + 1),
+                                  hipMemcpyHostToDevice, st));
+    }
     if ((s = enqueue(st))) return s;
     HIP_TRY(c, hipStreamSynchronize(st));
     resolve_marks(c);
