@@ -192,7 +192,13 @@ def run_batch(args):
         return float(np.median(ts))
 
     t_single = timed(per_field)
+    t_batch_untuned = timed(batched)
+    # the launch-shape tuner: the first call per (kind, ndim, radius) times
+    # the candidate shapes and keeps the fastest (results unchanged)
+    ctx.set_tuning(True)
     t_batch = timed(batched)
+    nd = xs[0].dim()
+    shapes = {k: ctx.shape(i, nd)[:2] for i, k in enumerate(("interp", "replay"))}
     # identity: the batched results equal the per-field ones, bit for bit
     rs1 = per_field()
     y1 = [o.clone() for o in outs]
@@ -209,6 +215,8 @@ def run_batch(args):
         "per_field_call_GBps": round(in_bytes / t_single / 1e9, 2),
         "speedup": round(t_single / t_batch, 3),
         "ms_batched": round(t_batch * 1e3, 3), "ms_per_field_calls": round(t_single * 1e3, 3),
+        "ms_batched_default_shape": round(t_batch_untuned * 1e3, 3),
+        "tuned_shapes": {k: {"variant": v[0], "workgroups_per_cu": v[1]} for k, v in shapes.items()},
         "steps": args.steps, "fields": len(xs), "input_bytes": in_bytes,
         "ratio": round(in_bytes / comp, 3), "identical": bool(same),
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",

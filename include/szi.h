@@ -129,6 +129,25 @@ uint64_t sz_ctx_bytes_in_use(const sz_ctx* ctx);
  * once.  Arithmetic-neutral: every setting gives byte-identical results; it
  * only trades occupancy against tail effects. */
 sz_status sz_ctx_set_grid(sz_ctx* ctx, int workgroups_per_cu);
+/* Launch-shape tuner for the interpolation kernels (compression, kind 0)
+ * and the replay (kind 1), the batched launches of Sec. V-D included.  A
+ * shape is a kernel variant (0: compiled for three waves per SIMD; 1: for
+ * four, 2D only) and a grid (workgroups per compute unit, 0 = resident
+ * capacity).  Every shape gives byte-identical results.
+ *
+ * sz_ctx_set_tuning(ctx, 1): a plain (non-graph) call that meets a
+ * (kind, ndim, radius) with no shape yet times each candidate shape on its
+ * own data, keeps the fastest for the context and uses it from then on;
+ * the call's results do not change.  sz_ctx_set_grid(ctx, n > 0) takes
+ * precedence over the tuner's grid and turns tuning off.
+ * sz_ctx_set_shape pins a shape for a key (SZ_ERR_INVALID_ARG for a
+ * variant that does not exist for ndim).  sz_ctx_get_shape reports the
+ * shape in use for a key and whether one was tuned or pinned (*known). */
+sz_status sz_ctx_set_tuning(sz_ctx* ctx, int on);
+sz_status sz_ctx_set_shape(sz_ctx* ctx, int kind, int ndim, int radius, int variant,
+                           int workgroups_per_cu);
+sz_status sz_ctx_get_shape(sz_ctx* ctx, int kind, int ndim, int radius, int* variant,
+                           int* workgroups_per_cu, int* known);
 /* Graph mode (default off): the device work of a call is captured into a HIP
  * graph once per launch signature (number of fields, their grids, the
  * Huffman grouping, the launch shape) and replayed afterwards, on a stream of

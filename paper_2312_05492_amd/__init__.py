@@ -107,6 +107,13 @@ def lib():
         L.sz_ctx_set_grid.argtypes = [vp, C.c_int]
         L.sz_ctx_set_graphs.restype = C.c_int
         L.sz_ctx_set_graphs.argtypes = [vp, C.c_int]
+        L.sz_ctx_set_tuning.restype = C.c_int
+        L.sz_ctx_set_tuning.argtypes = [vp, C.c_int]
+        L.sz_ctx_set_shape.restype = C.c_int
+        L.sz_ctx_set_shape.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.sz_ctx_get_shape.restype = C.c_int
+        L.sz_ctx_get_shape.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int),
+                                       C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.sz_ctx_set_timing.restype = C.c_int
         L.sz_ctx_set_timing.argtypes = [vp, C.c_int]
         L.sz_ctx_read_timing.restype = C.c_int
@@ -263,6 +270,22 @@ class Context:
 
     def set_grid(self, per_cu: int):
         self._check(lib().sz_ctx_set_grid(self.h, per_cu))
+
+    def set_tuning(self, on: bool):
+        """Launch-shape tuning of the window kernels on the first plain call
+        per (kind, ndim, radius); results are unchanged."""
+        self._check(lib().sz_ctx_set_tuning(self.h, 1 if on else 0))
+
+    def set_shape(self, kind: int, ndim: int, radius: int, variant: int, per_cu: int):
+        """Pin the launch shape of a window kernel (kind 0 compression, 1 replay)."""
+        self._check(lib().sz_ctx_set_shape(self.h, kind, ndim, radius, variant, per_cu))
+
+    def shape(self, kind: int, ndim: int, radius: int = 512):
+        """(variant, workgroups per CU, known) in use for a key."""
+        v, g, k = C.c_int(), C.c_int(), C.c_int()
+        self._check(lib().sz_ctx_get_shape(self.h, kind, ndim, radius, C.byref(v), C.byref(g),
+                                           C.byref(k)))
+        return v.value, g.value, bool(k.value)
 
     def set_graphs(self, on: bool):
         self._check(lib().sz_ctx_set_graphs(self.h, 1 if on else 0))

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <array>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -36,6 +37,11 @@ struct sz_ctx {
     void* pinned = nullptr;    // host staging buffer
     size_t pinned_bytes = 0;
     int grid_per_cu = 0;       // persistent workgroups per CU; 0 = resident capacity
+    // launch-shape tuner: the shape of each window kernel, per (kind 0 =
+    // compression / 1 = replay, ndim, radius); tuned by timing the
+    // candidates on the first plain call that meets a key while on
+    bool tuning = false;
+    std::map<std::array<int, 3>, LaunchShape> shapes;
     // graph mode: the device work of a call is captured once per launch
     // signature and replayed; its kernel arguments live in a persistent
     // device arena filled from a pinned mirror by the graph's first node
@@ -805,6 +811,67 @@ void server_worker(sz_server* s, int slot) {
 
 }  // namespace
 
+namespace {
+
+// the launch shape for a window kernel: a tuned or pinned one, else the
+// default; sz_ctx_set_grid overrides the grid
+LaunchShape shape_for(const sz_ctx* c, int kind, int ndim, int radius) {
+    auto it = c->shapes.find({kind, ndim, radius});
+    LaunchShape sh = it != c->shapes.end() ? it->second : LaunchShape{};
+    if (c->grid_per_cu > 0) sh.per_cu = c->grid_per_cu;
+    return sh;
+}
+
+bool needs_tuning(const sz_ctx* c, int kind, int ndim, int radius) {
+    return c->tuning && !c->graphs && c->grid_per_cu == 0 &&
+           c->shapes.find({kind, ndim, radius}) == c->shapes.end();
+}
+
+// the candidates the tuner times: the resident grid and a smaller one; in
+// 2D also the four-waves-per-SIMD variant
+std::vector<LaunchShape> shape_candidates(int ndim) {
+    if (ndim == 3) return {{0, 0}, {0, 2}};
+    return {{0, 0}, {1, 0}, {1, 3}};
+}
+
+// Times launch(shape) for each candidate (two runs each, the faster
+// counts) on stream st and returns the fastest.  The launches repeat work
+// whose results the caller restores or that rewrites the same values.
+template <class Launch>
+sz_status tune_shapes(sz_ctx* c, int ndim, hipStream_t st, LaunchShape* best, Launch&& launch) {
+    const std::vector<LaunchShape> cand = shape_candidates(ndim);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(c, SZ_ERR_DEVICE, "hipEventCreate");
+    }
+    float best_ms = 0;
+    sz_status s = SZ_OK;
+    for (size_t i = 0; i < cand.size() && !s; ++i) {
+        float ms_min = 0;
+        for (int rep = 0; rep < 2 && !s; ++rep) {
+            float ms = 0;
+            if (hipEventRecord(e0, st) != hipSuccess || (s = launch(cand[i])) ||
+                hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                if (!s) s = fail(c, SZ_ERR_DEVICE, "timing a launch shape");
+                break;
+            }
+            if (rep == 0 || ms < ms_min) ms_min = ms;
+        }
+        if (!s && (i == 0 || ms_min < best_ms)) {
+            best_ms = ms_min;
+            *best = cand[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return s;
+}
+
+}  // namespace
+
 extern "C" {
 
 void sz_params_default(sz_params* p) {
@@ -903,6 +970,34 @@ sz_status sz_ctx_set_grid(sz_ctx* c, int workgroups_per_cu) {
     c->grid_per_cu = workgroups_per_cu;
     return SZ_OK;
 }
+
+sz_status sz_ctx_set_tuning(sz_ctx* c, int on) {
+    if (!c) return SZ_ERR_INVALID_ARG;
+    c->tuning = on != 0;
+    return SZ_OK;
+}
+
+sz_status sz_ctx_set_shape(sz_ctx* c, int kind, int ndim, int radius, int variant,
+                           int workgroups_per_cu) {
+    if (!c || (kind != 0 && kind != 1) || (ndim != 2 && ndim != 3) || radius < 2 ||
+        radius > kMaxRadius || variant < 0 || variant >= kShapeVariants ||
+        (ndim == 3 && variant != 0) || workgroups_per_cu < 0 || workgroups_per_cu > 64)
+        return SZ_ERR_INVALID_ARG;
+    c->shapes[{kind, ndim, radius}] = LaunchShape{variant, workgroups_per_cu};
+    return SZ_OK;
+}
+
+sz_status sz_ctx_get_shape(sz_ctx* c, int kind, int ndim, int radius, int* variant,
+                           int* workgroups_per_cu, int* known) {
+    if (!c || !variant || !workgroups_per_cu || !known) return SZ_ERR_INVALID_ARG;
+    auto it = c->shapes.find({kind, ndim, radius});
+    *known = it != c->shapes.end();
+    const LaunchShape sh = *known ? it->second : LaunchShape{};
+    *variant = sh.variant;
+    *workgroups_per_cu = sh.per_cu;
+    return SZ_OK;
+}
+
 
 sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, const sz_dims* dims,
                             const sz_params* params, void* stream, sz_result* outs) {
@@ -1112,7 +1207,7 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
                 STAGE(c, SZ_STAGE_INTERP, q);
                 HIP_TRY(c, launch_compress(gi == 0 ? 3 : 2, d_fd + base, d_plan + base,
                                            d_items + gi * (nf + 1), nitems[gi], c->num_cus,
-                                           c->grid_per_cu, max_R, q));
+                                           shape_for(c, 0, gi == 0 ? 3 : 2, max_R), max_R, q));
             }
             base += (uint32_t)grp[gi].size();
         }
@@ -1126,8 +1221,10 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
         char* h = static_cast<char*>(c->parena);
         std::memcpy(h + o_fd, fds.data(), sizeof(FieldDesc) * nf);
         std::memcpy(h + o_items, items.data(), sizeof(uint64_t) * items.size());
+        const LaunchShape s3 = shape_for(c, 0, 3, max_R), s2 = shape_for(c, 0, 2, max_R);
         const std::vector<uint64_t> sig = {nf, nitems[0], nitems[1], grp[0].size(), (uint64_t)max_R,
-                                           (uint64_t)c->grid_per_cu, L.off};
+                                           (uint64_t)s3.per_cu, (uint64_t)s2.variant,
+                                           (uint64_t)s2.per_cu, L.off};
         char* d = static_cast<char*>(c->arena);
         s = graph_run(c, 1, sig, o_fd, end1 - o_fd, st, [&](hipStream_t q) -> sz_status {
             sz_status r = enqueue1(q);
@@ -1161,6 +1258,38 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
         for (uint32_t k = 0; k < nf; ++k)
             std::memcpy(hist[k].data(), hs + o_hist + sizeof(uint32_t) * k * hstride,
                         sizeof(uint32_t) * hist[k].size());
+        // launch-shape tuning: the interpolation launch of a group again per
+        // candidate (same codes and anchors; the histograms gain counts),
+        // then the histograms rebuilt with the chosen shapes
+        bool tuned = false;
+        uint32_t base = 0;
+        for (int gi = 0; gi < 2; ++gi) {
+            const int nd = gi == 0 ? 3 : 2;
+            if (!grp[gi].empty() && needs_tuning(c, 0, nd, max_R)) {
+                LaunchShape best;
+                s = tune_shapes(c, nd, st, &best, [&](LaunchShape sh) -> sz_status {
+                    HIP_TRY(c, launch_compress(nd, d_fd + base, d_plan + base, d_items + gi * (nf + 1),
+                                               nitems[gi], c->num_cus, sh, max_R, st));
+                    return SZ_OK;
+                });
+                if (s) return s;
+                c->shapes[{0, nd, max_R}] = best;
+                tuned = true;
+            }
+            base += (uint32_t)grp[gi].size();
+        }
+        if (tuned) {
+            HIP_TRY(c, launch_zero_hist(d_fd, (int)nf, st));
+            base = 0;
+            for (int gi = 0; gi < 2; ++gi) {
+                const int nd = gi == 0 ? 3 : 2;
+                if (!grp[gi].empty())
+                    HIP_TRY(c, launch_compress(nd, d_fd + base, d_plan + base, d_items + gi * (nf + 1),
+                                               nitems[gi], c->num_cus, shape_for(c, 0, nd, max_R),
+                                               max_R, st));
+                base += (uint32_t)grp[gi].size();
+            }
+        }
     }
     std::unique_ptr<StageMark> cb_mark(new StageMark(c, SZ_STAGE_CODEBOOK, st));
     for (uint32_t k = 0; k < nf; ++k)
@@ -1402,7 +1531,7 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
                 STAGE(c, SZ_STAGE_REPLAY, q);
                 HIP_TRY(c, launch_decompress(gi == 0 ? 3 : 2, d_fd + base, d_plan + base,
                                              d_items + gi * (nf + 1), nitems[gi], c->num_cus,
-                                             c->grid_per_cu, q));
+                                             shape_for(c, 1, gi == 0 ? 3 : 2, max_R), q));
             }
             base += (uint32_t)grp[gi].size();
         }
@@ -1429,8 +1558,10 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         d_bwoff = reinterpret_cast<uint64_t*>(d + o_bwoff);
         d_bsum = reinterpret_cast<uint32_t*>(d + o_bsum);
         // everything the launches' arguments depend on
+        const LaunchShape s3 = shape_for(c, 1, 3, max_R), s2 = shape_for(c, 1, 2, max_R);
         const std::vector<uint64_t> sig = {nf, nblocks, nitems[0], nitems[1], grp[0].size(),
-                                           (uint64_t)max_R, (uint64_t)c->grid_per_cu, L.off};
+                                           (uint64_t)max_R, (uint64_t)s3.per_cu,
+                                           (uint64_t)s2.variant, (uint64_t)s2.per_cu, L.off};
         if ((s = graph_run(c, 0, sig, 0, staged, st, enqueue))) return s;
         HIP_TRY(c, hipStreamSynchronize(c->gstream));
         return SZ_OK;
@@ -1458,6 +1589,22 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
                                   hipMemcpyHostToDevice, st));
     }
     if ((s = enqueue(st))) return s;
+    // launch-shape tuning: the replay rewrites the same values
+    uint32_t base = 0;
+    for (int gi = 0; gi < 2; ++gi) {
+        const int nd = gi == 0 ? 3 : 2;
+        if (!grp[gi].empty() && needs_tuning(c, 1, nd, max_R)) {
+            LaunchShape best;
+            s = tune_shapes(c, nd, st, &best, [&](LaunchShape sh) -> sz_status {
+                HIP_TRY(c, launch_decompress(nd, d_fd + base, d_plan + base, d_items + gi * (nf + 1),
+                                             nitems[gi], c->num_cus, sh, st));
+                return SZ_OK;
+            });
+            if (s) return s;
+            c->shapes[{1, nd, max_R}] = best;
+        }
+        base += (uint32_t)grp[gi].size();
+    }
     HIP_TRY(c, hipStreamSynchronize(st));
     resolve_marks(c);
     return SZ_OK;

@@ -717,13 +717,14 @@ __device__ __forceinline__ void flush_hist(uint32_t* hist, uint32_t& cntR, const
     __syncthreads();
 }
 
-// Three waves per SIMD: the register budget that leaves (168 VGPRs) is
-// what the kernels are compiled for; with the block alone in LDS (and the
-// histogram of compression), three workgroups of four windows fit a CU.
+// WPE waves per SIMD: the register budget that leaves (3: 168 VGPRs, 4:
+// 128) is what a kernel variant is compiled for.  With the block alone in
+// LDS (and the histogram of compression), three workgroups of four 3D
+// windows fit a CU; 2D blocks are small enough for four.
 #define SZI_WINDOW_KERNEL \
-    __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
+    __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
 
-template <int ND>
+template <int ND, int WPE>
 SZI_WINDOW_KERNEL void k_compress(const FieldDesc* __restrict__ F, const FieldPlan* __restrict__ P,
                                   const uint64_t* __restrict__ goff, uint64_t ngroups) {
     using G = Geo<ND>;
@@ -787,7 +788,7 @@ SZI_WINDOW_KERNEL void k_compress(const FieldDesc* __restrict__ F, const FieldPl
     flush_hist(hist, cntR, F[hf]);
 }
 
-template <int ND>
+template <int ND, int WPE>
 SZI_WINDOW_KERNEL void k_decompress(const FieldDesc* __restrict__ F,
                                     const FieldPlan* __restrict__ P,
                                     const uint64_t* __restrict__ goff, uint64_t ngroups) {
@@ -891,39 +892,33 @@ static uint64_t resident_grid(K kernel, size_t lds, int num_cus, int per_cu, uin
 }
 
 hipError_t launch_compress(int ndim, const FieldDesc* d_fields, const FieldPlan* d_plans,
-                           const uint64_t* d_goff, uint64_t ngroups, int num_cus, int per_cu,
-                           int max_R, hipStream_t st) {
+                           const uint64_t* d_goff, uint64_t ngroups, int num_cus,
+                           LaunchShape shape, int max_R, hipStream_t st) {
     if (ngroups == 0) return hipSuccess;
     const size_t lds = (size_t)2 * max_R * sizeof(uint32_t);
-    if (ndim == 3) {
-        auto k = k_compress<3>;
-        const uint64_t grid = resident_grid(k, lds, num_cus, per_cu, ngroups);
+    auto go = [&](auto k) {
+        const uint64_t grid = resident_grid(k, lds, num_cus, shape.per_cu, ngroups);
         hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kThreads), lds, st, d_fields, d_plans,
                            d_goff, ngroups);
-    } else {
-        auto k = k_compress<2>;
-        const uint64_t grid = resident_grid(k, lds, num_cus, per_cu, ngroups);
-        hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kThreads), lds, st, d_fields, d_plans,
-                           d_goff, ngroups);
-    }
+    };
+    if (ndim == 3) go(k_compress<3, 3>);
+    else if (shape.variant == 1) go(k_compress<2, 4>);
+    else go(k_compress<2, 3>);
     return hipGetLastError();
 }
 
 hipError_t launch_decompress(int ndim, const FieldDesc* d_fields, const FieldPlan* d_plans,
-                             const uint64_t* d_goff, uint64_t ngroups, int num_cus, int per_cu,
-                             hipStream_t st) {
+                             const uint64_t* d_goff, uint64_t ngroups, int num_cus,
+                             LaunchShape shape, hipStream_t st) {
     if (ngroups == 0) return hipSuccess;
-    if (ndim == 3) {
-        auto k = k_decompress<3>;
-        const uint64_t grid = resident_grid(k, 0, num_cus, per_cu, ngroups);
+    auto go = [&](auto k) {
+        const uint64_t grid = resident_grid(k, 0, num_cus, shape.per_cu, ngroups);
         hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kThreads), 0, st, d_fields, d_plans,
                            d_goff, ngroups);
-    } else {
-        auto k = k_decompress<2>;
-        const uint64_t grid = resident_grid(k, 0, num_cus, per_cu, ngroups);
-        hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kThreads), 0, st, d_fields, d_plans,
-                           d_goff, ngroups);
-    }
+    };
+    if (ndim == 3) go(k_decompress<3, 3>);
+    else if (shape.variant == 1) go(k_decompress<2, 4>);
+    else go(k_decompress<2, 3>);
     return hipGetLastError();
 }
 

@@ -117,12 +117,21 @@ hipError_t launch_zero_hist(const FieldDesc* d_fields, int nfields, hipStream_t 
 hipError_t launch_pass_desc(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
                             hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
+// Launch shape of a window kernel; every shape gives the same results.
+// variant 0: compiled for three waves per SIMD (168 VGPRs); variant 1: for
+// four (128 VGPRs; 2D only, whose smaller blocks leave LDS for 16 windows
+// per CU).  per_cu: persistent workgroups per CU, 0 = resident capacity.
+struct LaunchShape {
+    int variant = 0;
+    int per_cu = 0;
+};
+constexpr int kShapeVariants = 2;
 hipError_t launch_compress(int ndim, const FieldDesc* d_fields, const FieldPlan* d_plans,
-                           const uint64_t* d_goff, uint64_t ngroups, int num_cus, int per_cu,
-                           int max_R, hipStream_t st);
+                           const uint64_t* d_goff, uint64_t ngroups, int num_cus,
+                           LaunchShape shape, int max_R, hipStream_t st);
 hipError_t launch_decompress(int ndim, const FieldDesc* d_fields, const FieldPlan* d_plans,
-                             const uint64_t* d_goff, uint64_t ngroups, int num_cus, int per_cu,
-                             hipStream_t st);
+                             const uint64_t* d_goff, uint64_t ngroups, int num_cus,
+                             LaunchShape shape, hipStream_t st);
 hipError_t launch_huff_stats(const FieldDesc* d_fields, int nfields, const uint64_t* d_boff,
                              uint64_t nblocks, int chunk, uint32_t* d_cwords, uint32_t* d_couts,
                              uint32_t* d_bw, uint32_t* d_bo, int max_nsym, hipStream_t st);

@@ -190,6 +190,45 @@ def test_launch_shape_is_arithmetic_neutral(ctx):
     assert all(b == blobs[0] for b in blobs)
 
 
+def test_tuned_shapes_are_arithmetic_neutral():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    plain = szi.Context(0)
+    tuned = szi.Context(0)
+    tuned.set_tuning(True)
+    cases = [synth.spectral_field((70, 90, 130), seed=81), synth.climate_field(351, shape=(300, 500))]
+    for x in cases:
+        nd = x.ndim
+        print("\n[parity] tuner, %dD %s" % (nd, x.shape), flush=True)
+        d = _to_gpu(x)
+        a = plain.compress(d)
+        ya = plain.decompress(a)
+        b = tuned.compress(d)   # times the candidate shapes on this call
+        assert b.blob() == a.blob()
+        yb = tuned.decompress(b)
+        assert torch.equal(yb.view(torch.int32), ya.view(torch.int32))
+        assert tuned.shape(0, nd)[2] and tuned.shape(1, nd)[2]
+        b.free()
+        # every candidate, pinned, gives the same bytes
+        cands = [(0, 0), (0, 2)] if nd == 3 else [(0, 0), (1, 0), (1, 3)]
+        for v, g in cands:
+            p = szi.Context(0)
+            p.set_shape(0, nd, 512, v, g)
+            p.set_shape(1, nd, 512, v, g)
+            r = p.compress(d)
+            assert r.blob() == a.blob(), "shape %s" % ((v, g),)
+            y = p.decompress(r)
+            assert torch.equal(y.view(torch.int32), ya.view(torch.int32)), "shape %s" % ((v, g),)
+            r.free()
+            p.close()
+        a.free()
+    with pytest.raises(szi.SzError):
+        tuned.set_shape(0, 3, 512, 1, 0)   # no four-wave variant in 3D
+    tuned.close()
+    plain.close()
+
+
 def test_repeat_is_deterministic(ctx):
     x = synth.bumps_field((64, 64, 64), seed=3)
     print("\n[parity] repeat", flush=True)
