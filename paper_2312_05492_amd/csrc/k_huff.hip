@@ -116,42 +116,82 @@ __global__ __launch_bounds__(256) void k_huff_stats(const FieldDesc* __restrict_
 }
 
 // Exclusive scan of up to two u32 arrays of length n into u64 offsets; one
-// workgroup of 1024 threads, contiguous runs per thread.  off[n] receives
-// the total.
+// workgroup of 1024 threads, a contiguous run per thread: run sums, wave
+// scans, the 16 wave totals through LDS (one barrier), then the run's
+// offsets.  off[n] receives the total.
 __global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t* __restrict__ a,
                                                       const uint32_t* __restrict__ b, uint64_t n,
                                                       uint64_t* aoff, uint64_t* boff) {
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const uint64_t per = (n + 1023) / 1024;
-    const uint64_t beg = t * per, end = beg + per < n ? beg + per : n;
+    const uint64_t beg = (uint64_t)t * per < n ? (uint64_t)t * per : n;
+    const uint64_t end = beg + per < n ? beg + per : n;
+    // runs of up to kRun elements sit in registers, all loads issued at once
+    constexpr int kRun = 16;
+    const bool regs = per <= (uint64_t)kRun;
+    uint32_t va[kRun], vb[kRun];
     uint64_t sa = 0, sb = 0;
-    for (uint64_t i = beg; i < end; ++i) {
-        sa += a[i];
-        if (b) sb += b[i];
+    if (regs) {
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            const uint64_t i = beg + k;
+            va[k] = i < end ? a[i] : 0u;
+            vb[k] = (b && i < end) ? b[i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            sa += va[k];
+            sb += vb[k];
+        }
+    } else {
+        for (uint64_t i = beg; i < end; ++i) {
+            sa += a[i];
+            if (b) sb += b[i];
+        }
     }
-    __shared__ uint64_t xa[1024], xb[1024];
-    xa[t] = sa;
-    xb[t] = sb;
+    uint64_t xa = sa, xb = sb;   // inclusive scans over the wave's lanes
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t ya = __shfl_up(xa, o), yb = __shfl_up(xb, o);
+        if (lane >= o) {
+            xa += ya;
+            xb += yb;
+        }
+    }
+    __shared__ uint64_t wa[16], wb[16];
+    if (lane == 63) {
+        wa[wave] = xa;
+        wb[wave] = xb;
+    }
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const uint64_t ya = t >= o ? xa[t - o] : 0, yb = t >= o ? xb[t - o] : 0;
-        __syncthreads();
-        xa[t] += ya;
-        xb[t] += yb;
-        __syncthreads();
+    for (int k = 0; k < wave; ++k) {
+        xa += wa[k];
+        xb += wb[k];
     }
-    uint64_t ra = xa[t] - sa, rb = xb[t] - sb;
-    for (uint64_t i = beg; i < end; ++i) {
-        aoff[i] = ra;
-        ra += a[i];
-        if (b) {
-            boff[i] = rb;
-            rb += b[i];
+    uint64_t ra = xa - sa, rb = xb - sb;
+    if (regs) {
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            const uint64_t i = beg + k;
+            if (i < end) {
+                aoff[i] = ra;
+                if (b) boff[i] = rb;
+            }
+            ra += va[k];
+            rb += vb[k];
+        }
+    } else {
+        for (uint64_t i = beg; i < end; ++i) {
+            aoff[i] = ra;
+            ra += a[i];
+            if (b) {
+                boff[i] = rb;
+                rb += b[i];
+            }
         }
     }
     if (t == 1023) {
-        aoff[n] = xa[1023];
-        if (b) boff[n] = xb[1023];
+        aoff[n] = xa;
+        if (b) boff[n] = xb;
     }
 }
 
