@@ -92,8 +92,12 @@ def pmc_summary(fetch_csv, write_csv, n, cmd, out_path):
     def short(k):
         k = k.replace("void ", "").replace("szi::", "")
         k = k[:k.index("(")] if "(" in k else k
-        # the window kernels keep their dimensionality, the rest their base name
-        return k if k.startswith(("k_compress", "k_decompress")) else k.split("<")[0]
+        # the window kernels keep their dimensionality (not the register
+        # variant), the rest their base name
+        base = k.split("<")[0]
+        if k.startswith(("k_compress", "k_decompress")) and "<" in k:
+            return base + "<" + k.split("<")[1].split(",")[0].split(">")[0].strip() + ">"
+        return base
 
     fe, wr = load(fetch_csv), load(write_csv)
     copy = max((k for k in fe if "copyBuffer" in k), key=lambda k: max(fe[k]))
