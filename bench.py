@@ -313,6 +313,20 @@ def run_serve(args):
 
     def served(at):
         srv = szi.Server(0, slots=slots, hbm_budget=200 * 10 ** 9)
+        # warm-up like the plain calls': the slots' pools and caches fill
+        for i in range(min(250, nreq)):
+            kind, f, e = reqs[i]
+            if kind == "c":
+                srv.submit_compress(pool[f], tag=i, eb=e)
+            else:
+                srv.submit_decompress(src[(f, e)], outs[f][i % nout], tag=i)
+        left = min(250, nreq)
+        while left:
+            for c in srv.poll(wait=True):
+                assert c["status"] == 0, c
+                if c["result"] is not None:
+                    c["result"].free()
+                left -= 1
         lat = [None] * nreq
         t_first = [None]
 
