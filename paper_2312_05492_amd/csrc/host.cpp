@@ -477,11 +477,13 @@ void build_tables(const uint8_t* len, int nsym, uint32_t* cbook, uint32_t* dtab)
     canonical(len, nsym, code.data(), first, count);
     for (int s = 0; s < nsym; ++s) cbook[s] = ((uint32_t)len[s] << 24) | code[s];
     std::memset(dtab, 0, sizeof(uint32_t) * dtab_words(nsym));
+    uint16_t* lut = reinterpret_cast<uint16_t*>(dtab);   // little-endian u16 view
     for (int s = 0; s < nsym; ++s) {
         const int l = len[s];
         if (l == 0 || l > kLutBits) continue;
         const uint32_t lo = code[s] << (kLutBits - l), hi = (code[s] + 1) << (kLutBits - l);
-        for (uint32_t e = lo; e < hi; ++e) dtab[e] = ((uint32_t)l << 16) | (uint32_t)s;
+        const uint16_t e = (uint16_t)(((uint32_t)l << kLutSymBits) | (uint32_t)s);
+        for (uint32_t j = lo; j < hi; ++j) lut[j] = e;
     }
     uint32_t off[kLmax + 2] = {0};   // first position of each length among the sorted symbols
     for (int l = 1; l <= kLmax; ++l) {

@@ -298,20 +298,20 @@ __global__ __launch_bounds__(kDecChunks) void k_chunk_words(const FieldDesc* __r
     }
 }
 
-// One lane decodes one chunk: canonical decode with a 2^kLutBits table for
-// short codes; a longer code's length comes from comparing the next bits
-// with the per-length limits, without a loop or a data-dependent branch.
-// One lane per chunk.  The next bits sit most significant first in a 64-bit
-// buffer, topped up by one word whenever 32 or fewer remain (a lookup needs
-// at most kLmax = 24).  The words come from a 32-word ring per lane in LDS:
-// once per group of 8 symbols every lane requests its next 8 words from
-// global memory (two 16-byte loads, if the ring has room) and commits them
-// to the ring one group later, so global loads sit at fixed points and their
-// latency is covered by a group of decoding.  A group consumes at most 6
-// words and the ring always holds at least 7 ahead of the buffer.  Each
-// top-up also reads the following ring word, which LDS returns in order
-// ahead of the next table lookups.  Symbols leave 32 at a time per lane in
-// four back-to-back 16-byte stores.
+// One lane decodes one chunk: canonical decode with a 2^kLutBits table of
+// u16 entries for short codes; a longer code's length comes from comparing
+// the next bits with the per-length limits, without a loop or a
+// data-dependent branch.  The next bits sit most significant first in a
+// 64-bit buffer, topped up (without a branch) by one word whenever 32 or
+// fewer remain (a lookup needs at most kLmax = 24).  The words come from a
+// 32-word ring per lane in LDS: once per group of 8 symbols every lane
+// requests its next 8 words from global memory (two 16-byte loads, if the
+// ring has room) and commits them to the ring one group later, so global
+// loads sit at fixed points and their latency is covered by a group of
+// decoding.  A group consumes at most 6 words and the ring always holds at
+// least 7 ahead of the buffer.  Every step also reads the ring word the
+// next top-up takes, off the critical path of the table lookups.  Symbols
+// leave 64 at a time per lane in eight back-to-back 16-byte stores.
 constexpr int kRing = 32;   // ring words per lane (power of 2)
 
 __device__ __forceinline__ int ring_slot(uint32_t i, uint32_t sw) {
@@ -332,6 +332,7 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
     uint32_t* scan = smem;                                   // kDecChunks / 64
     uint32_t* rings = smem + kDecChunks / 64;                // kDecChunks x kRing, 16-byte aligned
     uint32_t* tab = rings + kDecChunks * kRing;
+    const uint16_t* lut = reinterpret_cast<const uint16_t*>(tab);
     for (int k = threadIdx.x; k < ntab; k += blockDim.x) tab[k] = gp(fd.dtab)[k];
     // length limits of the codes longer than the LUT, in scalar registers
     uint32_t lim[kLmax - kLutBits - 1];
@@ -390,14 +391,8 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
     int nb = 64;
     uint32_t nxw = rword(rd);   // the ring word the next top-up takes
     auto decode_one = [&]() SZI_INLINE -> uint32_t {
-        if (nb <= 32) {
-            buf |= (uint64_t)nxw << (32 - nb);
-            nb += 32;
-            ++rd;
-            nxw = rword(rd);
-        }
-        const uint32_t e = tab[(uint32_t)(buf >> (64 - kLutBits))];
-        uint32_t len = e >> 16, sym = e & 0xFFFFu;
+        const uint32_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
+        uint32_t len = e >> kLutSymBits, sym = e & ((1u << kLutSymBits) - 1u);
         if (len == 0) {
             // longer than the table: the length is one more than the number
             // of length limits at or below the next kLmax bits (canonical
@@ -411,6 +406,14 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
         }
         buf <<= len;
         nb -= (int)len;
+        // top-up without a branch: with 32 or fewer bits left (never fewer
+        // than 64 - 2 kLmax) the next word goes in below them; the ring
+        // word at rd is read every time, so the next one is on its way
+        const bool t = nb <= 32;
+        buf |= (uint64_t)(t ? nxw : 0u) << ((32 - nb) & 63);
+        nb += t ? 32 : 0;
+        rd += t ? 1u : 0u;
+        nxw = rword(rd);
         return sym;
     };
     SZI_G uint16_t* out = gp(fd.codes) + s0;
@@ -451,20 +454,18 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
         return pk;
     };
     int k = 0;
-    // 32 symbols of a lane leave as four back-to-back 16-byte stores, so
-    // that a lane fills half a cache line at once
+    // 64 symbols of a lane leave as eight back-to-back 16-byte stores, so
+    // that a lane writes a whole 128-byte cache line at once (half lines
+    // written far apart in time cost 15 % more decode time)
     if (vec) {
 #pragma unroll 1
-        for (; k + 32 <= cnt; k += 32) {
-            const vu4 p0 = group8();
-            const vu4 p1 = group8();
-            const vu4 p2 = group8();
-            const vu4 p3 = group8();
+        for (; k + 64 <= cnt; k += 64) {
+            vu4 p[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) p[j] = group8();
             SZI_G vu4* o = reinterpret_cast<SZI_G vu4*>(out + k);
-            o[0] = p0;
-            o[1] = p1;
-            o[2] = p2;
-            o[3] = p3;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) o[j] = p[j];
         }
     }
 #pragma unroll 1

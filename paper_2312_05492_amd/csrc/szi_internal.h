@@ -9,7 +9,7 @@ namespace szi {
 
 constexpr int kMaxLevels = 8;
 constexpr int kLmax = 24;          // Huffman length limit
-constexpr int kLutBits = 10;       // decode look-up table width
+constexpr int kLutBits = 12;       // decode look-up table width (bits)
 constexpr int kMaxRadius = 1024;   // LDS histogram holds 2R <= 2048 bins
 constexpr int kRangeBlocks = 2048; // partial min/max blocks per field
 constexpr int kThreads = 256;      // threads per interpolation workgroup
@@ -94,15 +94,20 @@ struct FieldPlan {
 constexpr int kWinPerGroup = 4;
 
 // Decode tables, one u32 array per field:
-//   [0, 1<<kLutBits)   LUT: len << 16 | symbol (len 0 = longer code)
+//   LUT, 1<<kLutBits u16 entries in (1<<kLutBits)/2 words: len << 11 | symbol
+//                      for the codes of at most kLutBits bits (symbols < 2048;
+//                      len 0 = longer code)
 //   limit[kLmax+1]     limit[l]: the codes of length <= l, left-justified to
 //                      kLmax bits, lie below it ((first + count) << (kLmax - l))
 //   base[kLmax+1]      base[l]: position of length l among the sorted
 //                      symbols minus the first code of length l
 //   sorted symbols (nsym entries, by (length, symbol))
-constexpr int kDtLimit = 1 << kLutBits;
+constexpr int kLutSymBits = 11;
+constexpr int kDtLimit = (1 << kLutBits) / 2;
 constexpr int kDtBase = kDtLimit + kLmax + 1;
 constexpr int kDtSorted = kDtBase + kLmax + 1;
+static_assert(2 * kMaxRadius <= (1 << kLutSymBits) && kLutBits < (1 << (16 - kLutSymBits)),
+              "LUT entries hold a symbol and a length in 16 bits");
 __host__ __device__ inline int dtab_words(int nsym) { return kDtSorted + nsym; }
 
 // ---- launchers (k_plan.hip, k_interp.hip, k_huff.hip) ----
