@@ -1508,7 +1508,7 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
     const uint64_t nblocks = dboff[nf];
     FieldDesc* d_fd;
     FieldPlan* d_plan;
-    uint64_t *d_items, *d_dboff, *d_bwoff;
+    uint64_t *d_items, *d_dboff;
     uint32_t* d_bsum;
     sz_status s;
     // the device work of the call
@@ -1517,11 +1517,10 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         {
             STAGE(c, SZ_STAGE_SCAN, q);
             HIP_TRY(c, launch_chunk_words(d_fd, (int)nf, d_dboff, nblocks, d_bsum, q));
-            HIP_TRY(c, launch_scan_blocks(d_bsum, nullptr, nblocks, d_bwoff, nullptr, q));
         }
         {
             STAGE(c, SZ_STAGE_DECODE, q);
-            HIP_TRY(c, launch_huff_decode(d_fd, (int)nf, d_dboff, nblocks, d_bwoff, 2 * max_R, q));
+            HIP_TRY(c, launch_huff_decode(d_fd, (int)nf, d_dboff, nblocks, d_bsum, 2 * max_R, q));
         }
         {
             STAGE(c, SZ_STAGE_SCATTER, q);
@@ -1544,7 +1543,6 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         const size_t o_fd = L.take<FieldDesc>(nf), o_plan = L.take<FieldPlan>(nf);
         const size_t o_items = L.take<uint64_t>(items.size()), o_dboff = L.take<uint64_t>(nf + 1);
         const size_t staged = L.off;
-        const size_t o_bwoff = L.take<uint64_t>(nblocks + 1);
         const size_t o_bsum = L.take<uint32_t>(std::max<uint64_t>(nblocks, 1));
         if ((s = arena_reserve(c, L.off))) return s;
         char* h = static_cast<char*>(c->parena);
@@ -1557,7 +1555,6 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         d_plan = reinterpret_cast<FieldPlan*>(d + o_plan);
         d_items = reinterpret_cast<uint64_t*>(d + o_items);
         d_dboff = reinterpret_cast<uint64_t*>(d + o_dboff);
-        d_bwoff = reinterpret_cast<uint64_t*>(d + o_bwoff);
         d_bsum = reinterpret_cast<uint32_t*>(d + o_bsum);
         // everything the launches' arguments depend on
         const LaunchShape s3 = shape_for(c, 1, 3, max_R), s2 = shape_for(c, 1, 2, max_R);
@@ -1569,8 +1566,7 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         return SZ_OK;
     }
     if ((s = sc.get(nf, &d_fd)) || (s = sc.get(nf, &d_plan)) || (s = sc.get(items.size(), &d_items)) ||
-        (s = sc.get(nf + 1, &d_dboff)) || (s = sc.get(nblocks + 1, &d_bwoff)) ||
-        (s = sc.get(std::max<uint64_t>(nblocks, 1), &d_bsum)))
+        (s = sc.get(nf + 1, &d_dboff)) || (s = sc.get(std::max<uint64_t>(nblocks, 1), &d_bsum)))
         return s;
     // descriptors staged in pinned memory, one asynchronous copy each
     {

@@ -195,6 +195,19 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t* __restrict
     }
 }
 
+// Orders the LDS accesses of one wave around this point (a wave's LDS
+// instructions execute in issue order, so only the compiler needs holding).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// One wave per chunk, PER consecutive symbols per lane: the wave scans the
+// lanes' bit counts, ORs every code MSB first into the chunk's words in LDS
+// and copies them out contiguously.  The waves of a workgroup share only
+// the code book, so they synchronise among their own lanes.  (Packing a
+// lane's codes in registers with plain stores for the words it owns, and
+// loading the next chunk ahead, were both slower.)
 template <int PER>
 __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict__ F, int nfields,
                                                      const uint64_t* __restrict__ boff,
@@ -212,7 +225,6 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     uint32_t* wbuf = smem + nsym + wave * MCW;
     for (int s = threadIdx.x; s < nsym; s += blockDim.x) cb[s] = gp(fd.cbook)[s];
-    __syncthreads();
     const uint64_t blk_local = blockIdx.x - boff[f];
     const uint64_t first = blk_local * kEncChunks;
     // this field's sections start at 0: subtract the offsets of its first block
@@ -227,42 +239,48 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
     uint32_t tw, to;
     const uint32_t pw = wave_excl_scan(cw, &tw);
     const uint32_t po = wave_excl_scan(co, &to);
-    for (int j0 = 0; j0 < kEncChunks; j0 += 4) {
-        const int j = j0 + wave;
+    __syncthreads();   // the code book is in LDS
+    for (int j = wave; j < kEncChunks; j += 4) {
         const uint64_t ch = first + j;
-        const bool live = ch < fd.nchunks;   // uniform across the wave
+        if (ch >= fd.nchunks) break;   // uniform across the wave
         uint32_t sym[PER];
         int ns = 0;
-        if (live) lane_syms<PER>(fd, ch, lane, sym, ns);
+        lane_syms<PER>(fd, ch, lane, sym, ns);
+        uint32_t e[PER];
         uint32_t bits = 0, zeros = 0;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const bool on = k < ns;
-            bits += on ? cb[sym[k]] >> 24 : 0u;
+            e[k] = on ? cb[sym[k]] : 0u;
+            bits += e[k] >> 24;
             zeros += (on && sym[k] == 0) ? 1u : 0u;
         }
-        uint32_t tb, tz;
-        const uint32_t boffl = wave_excl_scan(bits, &tb);
-        const uint32_t zoffl = wave_excl_scan(zeros, &tz);
-        const int nw = live ? (int)((tb + 31) >> 5) : 0;
-        for (int k = lane; k < nw; k += 64) wbuf[k] = 0;
-        __syncthreads();
-        const uint64_t ow = bw0 + __shfl(pw, j);
-        const uint64_t oo = bo0 + __shfl(po, j);
-        uint32_t pos = boffl;
-        uint32_t zo = zoffl;
-        const uint64_t s0 = ch * (uint64_t)C + (uint64_t)lane * PER;
+        uint32_t tb;
+        const uint32_t pos = wave_excl_scan(bits, &tb);
+        const uint32_t nw = (tb + 31) >> 5;
+        for (uint32_t k = lane; k < nw; k += 64) wbuf[k] = 0;
+        wave_lds_sync();
+        {
+            uint32_t p = pos;
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            if (k < ns) {
-                const uint32_t e = cb[sym[k]];
-                const uint32_t len = e >> 24, code = e & 0xFFFFFFu;
-                const uint32_t wi = pos >> 5, bo = pos & 31;
-                const uint64_t sh = (uint64_t)code << (64 - len - bo);   // MSB first
-                atomicOr(&wbuf[wi], (uint32_t)(sh >> 32));
-                if (bo + len > 32) atomicOr(&wbuf[wi + 1], (uint32_t)sh);
-                pos += len;
-                if (sym[k] == 0) {
+            for (int k = 0; k < PER; ++k) {
+                const uint32_t len = e[k] >> 24;
+                if (len) {
+                    const uint32_t wi = p >> 5, bo = p & 31;
+                    const uint64_t sh = (uint64_t)(e[k] & 0xFFFFFFu) << (64 - len - bo);   // MSB first
+                    atomicOr(&wbuf[wi], (uint32_t)(sh >> 32));
+                    if (bo + len > 32) atomicOr(&wbuf[wi + 1], (uint32_t)sh);
+                    p += len;
+                }
+            }
+        }
+        if (wave_sum(zeros)) {   // uniform: outliers in this chunk
+            uint32_t tz, zo = wave_excl_scan(zeros, &tz);
+            const uint64_t oo = bo0 + __shfl(po, j);
+            const uint64_t s0 = ch * (uint64_t)C + (uint64_t)lane * PER;
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                if (k < ns && sym[k] == 0) {
                     if (oo + zo < fd.n_outliers) {   // the histogram sized the list
                         gp(fd.outlier_idx)[oo + zo] = (uint32_t)(s0 + k);
                         gp(fd.outlier_val)[oo + zo] = gp(fd.in)[s0 + k];
@@ -271,10 +289,11 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
                 }
             }
         }
-        __syncthreads();
-        for (int k = lane; k < nw; k += 64)
+        wave_lds_sync();
+        const uint64_t ow = bw0 + __shfl(pw, j);
+        for (uint32_t k = lane; k < nw; k += 64)
             if (ow + k < fd.words_cap) gp(fd.words)[ow + k] = wbuf[k];
-        __syncthreads();
+        wave_lds_sync();
     }
 }
 
@@ -323,14 +342,15 @@ __device__ __forceinline__ int ring_slot(uint32_t i, uint32_t sw) {
 __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __restrict__ F,
                                                             int nfields,
                                                             const uint64_t* __restrict__ boff,
-                                                            const uint64_t* __restrict__ bwoff) {
+                                                            const uint32_t* __restrict__ bsum) {
     extern __shared__ uint32_t smem[];
     const int f = block_field(boff, nfields, blockIdx.x);
     const FieldDesc& fd = F[f];
     const int nsym = 2 * fd.R;
     const int ntab = dtab_words(nsym);
     uint32_t* scan = smem;                                   // kDecChunks / 64
-    uint32_t* rings = smem + kDecChunks / 64;                // kDecChunks x kRing, 16-byte aligned
+    uint64_t* pre = reinterpret_cast<uint64_t*>(smem + kDecChunks / 64);   // kDecChunks / 64
+    uint32_t* rings = smem + 3 * (kDecChunks / 64);          // kDecChunks x kRing, 16-byte aligned
     uint32_t* tab = rings + kDecChunks * kRing;
     const uint16_t* lut = reinterpret_cast<const uint16_t*>(tab);
     for (int k = threadIdx.x; k < ntab; k += blockDim.x) tab[k] = gp(fd.dtab)[k];
@@ -345,14 +365,22 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
     const bool live = ch < fd.nchunks;
     const uint32_t cbits = live ? (uint32_t)gp(fd.chunk_bits)[ch] : 0u;
     const uint32_t nw = (cbits + 31) >> 5;
-    // in-block exclusive scan of the word counts
+    // words of the field's earlier blocks (the sum of their word counts)
+    // and the in-block exclusive scan of the chunks' word counts
+    uint64_t pb = 0;
+    for (uint64_t i = boff[f] + (uint64_t)tid; i < blockIdx.x; i += kDecChunks) pb += bsum[i];
+    for (int o = 32; o > 0; o >>= 1) pb += __shfl_xor(pb, o);
     uint32_t tot;
     const uint32_t wx = wave_excl_scan(nw, &tot);
-    if ((tid & 63) == 0) scan[tid >> 6] = tot;
+    if ((tid & 63) == 0) {
+        scan[tid >> 6] = tot;
+        pre[tid >> 6] = pb;
+    }
     __syncthreads();
-    uint32_t before = 0;
+    uint64_t before = 0;
+    for (int k = 0; k < kDecChunks / 64; ++k) before += pre[k];
     for (int k = 0; k < (tid >> 6); ++k) before += scan[k];
-    const uint64_t w0 = bwoff[blockIdx.x] - bwoff[boff[f]] + before + wx;
+    const uint64_t w0 = before + wx;
     const int C = fd.chunk;
     const uint64_t s0 = ch * (uint64_t)C;
     const int cnt = !live ? 0 : (s0 + C <= fd.npts ? C : (int)(fd.npts - s0));
@@ -538,13 +566,13 @@ hipError_t launch_chunk_words(const FieldDesc* d_fields, int nfields, const uint
 }
 
 hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields, const uint64_t* d_dboff,
-                              uint64_t nblocks, const uint64_t* d_bwoff, int max_nsym,
+                              uint64_t nblocks, const uint32_t* d_bsum, int max_nsym,
                               hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
-    const size_t lds =
-        (size_t)(kDecChunks / 64 + kDecChunks * kRing + dtab_words(max_nsym)) * sizeof(uint32_t);
+    const size_t lds = (size_t)(3 * (kDecChunks / 64) + kDecChunks * kRing + dtab_words(max_nsym)) *
+                       sizeof(uint32_t);
     hipLaunchKernelGGL(k_huff_decode, dim3((unsigned)nblocks), dim3(kDecChunks), lds, st,
-                       d_fields, nfields, d_dboff, d_bwoff);
+                       d_fields, nfields, d_dboff, d_bsum);
     return hipGetLastError();
 }
 

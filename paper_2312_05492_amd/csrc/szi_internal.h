@@ -148,8 +148,9 @@ hipError_t launch_huff_encode(const FieldDesc* d_fields, int nfields, const uint
                               const uint64_t* d_booff, int max_nsym, hipStream_t st);
 hipError_t launch_chunk_words(const FieldDesc* d_fields, int nfields, const uint64_t* d_dboff,
                               uint64_t nblocks, uint32_t* d_bsum, hipStream_t st);
+// d_bsum: the word count of every decode block (launch_chunk_words)
 hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields, const uint64_t* d_dboff,
-                              uint64_t nblocks, const uint64_t* d_bwoff, int max_nsym,
+                              uint64_t nblocks, const uint32_t* d_bsum, int max_nsym,
                               hipStream_t st);
 hipError_t launch_scatter_outliers(const FieldDesc* d_fields, int nfields, hipStream_t st);
 
