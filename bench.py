@@ -237,6 +237,7 @@ def run_serve(args):
     overlapping on the device, HBM admission) and through sequential plain
     calls, at 0.8 of the sequential capacity (latency) and saturated (all
     requests queued at once: throughput).  Prints one JSON line."""
+    import gc
     import threading
 
     import numpy as np
@@ -365,7 +366,14 @@ def run_serve(args):
            "plain_call_mean_ms": round(svc * 1e3, 3), "offered_rate_per_s": round(rate, 1)}
     for name, at in (("load0.8", arrive), ("saturated", np.zeros(nreq))):
         for mode, fn in (("server", served), ("sequential", sequential)):
-            span, lat = fn(at)
+            # no cyclic garbage collection inside a timed run: its pauses
+            # (tens of ms) would hold up the submitting thread
+            gc.collect()
+            gc.disable()
+            try:
+                span, lat = fn(at)
+            finally:
+                gc.enable()
             lat = sorted(lat)
             out["%s_%s" % (mode, name)] = {
                 "GBps": round(total / span / 1e9, 2),

@@ -396,6 +396,7 @@ class Server:
         self.h = h
         self._keep = {}   # tag -> objects that must outlive the request
         self._shape = {}
+        self._bufs = {}   # poll's completion arrays (poll from one thread at a time)
 
     def _check(self, rc):
         if rc != SZ_OK:
@@ -427,7 +428,9 @@ class Server:
     def poll(self, wait: bool = True, cap: int = 256) -> list:
         """Completed requests, oldest first: dicts with tag, status, slot,
         t_submit, t_start, t_done (seconds) and, for a compression, result."""
-        buf = (SzCompletion * cap)()
+        buf = self._bufs.get(cap)
+        if buf is None:   # one completion array per size, reused
+            buf = self._bufs[cap] = (SzCompletion * cap)()
         n = C.c_uint32(0)
         self._check(lib().sz_server_poll(self.h, buf, cap, C.byref(n), 1 if wait else 0))
         out = []
