@@ -82,15 +82,18 @@ __global__ __launch_bounds__(256) void k_huff_stats(const FieldDesc* __restrict_
             uint32_t sym[PER];
             int ns;
             lane_syms<PER>(fd, ch, lane, sym, ns);
-            uint32_t bits = 0;
+            // bits (< 2^16 per chunk) and outliers (<= 2048) summed as one
+            // word: outliers in the high half
+            static_assert(PER * 64 * kLmax < 65536, "chunk bits fit 16 bits");
+            uint32_t bz = 0;
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 const bool live = k < ns;
-                bits += live ? cb[sym[k]] >> 24 : 0u;
-                zeros += (live && sym[k] == 0) ? 1u : 0u;
+                bz += live ? (cb[sym[k]] >> 24) + (sym[k] == 0 ? 0x10000u : 0u) : 0u;
             }
-            bits = wave_sum(bits);
-            zeros = wave_sum(zeros);
+            bz = wave_sum(bz);
+            const uint32_t bits = bz & 0xFFFFu;
+            zeros = bz >> 16;
             words = (bits + 31) >> 5;
             if (lane == 0) {
                 gp(fd.chunk_bits)[ch] = (uint16_t)bits;
@@ -246,17 +249,20 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
         uint32_t sym[PER];
         int ns = 0;
         lane_syms<PER>(fd, ch, lane, sym, ns);
+        // bits (< 2^16 per chunk) in the low half, outliers in the high half:
+        // one scan gives both offsets
+        static_assert(PER * 64 * kLmax < 65536, "chunk bits fit 16 bits");
         uint32_t e[PER];
-        uint32_t bits = 0, zeros = 0;
+        uint32_t bz = 0;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const bool on = k < ns;
             e[k] = on ? cb[sym[k]] : 0u;
-            bits += e[k] >> 24;
-            zeros += (on && sym[k] == 0) ? 1u : 0u;
+            bz += (e[k] >> 24) + ((on && sym[k] == 0) ? 0x10000u : 0u);
         }
-        uint32_t tb;
-        const uint32_t pos = wave_excl_scan(bits, &tb);
+        uint32_t tbz;
+        const uint32_t pbz = wave_excl_scan(bz, &tbz);
+        const uint32_t pos = pbz & 0xFFFFu, tb = tbz & 0xFFFFu;
         const uint32_t nw = (tb + 31) >> 5;
         for (uint32_t k = lane; k < nw; k += 64) wbuf[k] = 0;
         wave_lds_sync();
@@ -274,8 +280,8 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
                 }
             }
         }
-        if (wave_sum(zeros)) {   // uniform: outliers in this chunk
-            uint32_t tz, zo = wave_excl_scan(zeros, &tz);
+        if (tbz >> 16) {   // uniform: outliers in this chunk
+            uint32_t zo = pbz >> 16;
             const uint64_t oo = bo0 + __shfl(po, j);
             const uint64_t s0 = ch * (uint64_t)C + (uint64_t)lane * PER;
 #pragma unroll
