@@ -42,19 +42,28 @@ __device__ __forceinline__ float wave_max(float v) {
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
     return v;
 }
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+// Inclusive prefix sum across the 64 lanes of a wave (all lanes active)
+// with DPP lane moves: shifts by 1, 2, 4 and 8 within each row of 16 lanes,
+// then the last lane of each row added to the next row (row_bcast:15 into
+// rows 1 and 3) and lane 31 added to rows 2 and 3 (row_bcast:31).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    constexpr int kRowShr = 0x110, kBcast15 = 0x142, kBcast31 = 0x143;
+    const int x = (int)v;
+    int s = x + __builtin_amdgcn_update_dpp(0, x, kRowShr + 1, 0xF, 0xF, false);
+    s += __builtin_amdgcn_update_dpp(0, s, kRowShr + 2, 0xF, 0xF, false);
+    s += __builtin_amdgcn_update_dpp(0, s, kRowShr + 4, 0xF, 0xF, false);
+    s += __builtin_amdgcn_update_dpp(0, s, kRowShr + 8, 0xF, 0xF, false);
+    s += __builtin_amdgcn_update_dpp(0, s, kBcast15, 0xA, 0xF, false);
+    s += __builtin_amdgcn_update_dpp(0, s, kBcast31, 0xC, 0xF, false);
+    return (uint32_t)s;
 }
-// exclusive prefix sum across the 64 lanes of a wave
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(v), 63);
+}
+// exclusive prefix sum across the 64 lanes of a wave (all lanes active)
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total) {
-    const int lane = threadIdx.x & 63;
-    uint32_t x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
-    *total = __shfl(x, 63);
+    const uint32_t x = wave_incl_scan(v);
+    *total = (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
     return x - v;
 }
 
