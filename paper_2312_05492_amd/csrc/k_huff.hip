@@ -282,7 +282,7 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
         }
         if (tbz >> 16) {   // uniform: outliers in this chunk
             uint32_t zo = pbz >> 16;
-            const uint64_t oo = bo0 + __shfl(po, j);
+            const uint64_t oo = bo0 + (uint32_t)__builtin_amdgcn_readlane((int)po, j);
             const uint64_t s0 = ch * (uint64_t)C + (uint64_t)lane * PER;
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
             }
         }
         wave_lds_sync();
-        const uint64_t ow = bw0 + __shfl(pw, j);
+        const uint64_t ow = bw0 + (uint32_t)__builtin_amdgcn_readlane((int)pw, j);   // j is uniform
         for (uint32_t k = lane; k < nw; k += 64)
             if (ow + k < fd.words_cap) gp(fd.words)[ow + k] = wbuf[k];
         wave_lds_sync();
