@@ -11,10 +11,10 @@
 //                  (index, original value) in ascending index order
 // Decode: one lane per chunk, kDecChunks chunks per workgroup.
 //   k_chunk_words  word count of every chunk, sums per block
-//   k_scan_blocks  exclusive scan of the block sums
-//   k_huff_decode  in-block scan, then a table-driven canonical decode from
-//                  a 64-bit bit buffer fed by a per-lane LDS word ring; 32
-//                  symbols per lane stored at once
+//   k_huff_decode  sum of the field's earlier block sums and an in-block
+//                  scan, then a table-driven canonical decode from a 64-bit
+//                  bit buffer fed by a per-lane LDS word ring; 64 symbols
+//                  per lane stored at once
 #include "dev_common.h"
 
 namespace szi {
