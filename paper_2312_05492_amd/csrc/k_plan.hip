@@ -164,34 +164,43 @@ __device__ float floor_to_f32(double v) {
 // The passes of a window in execution order, from the plan's order, splines
 // and level bounds.  Along the pass dimension d the odd multiples of s;
 // along dimensions already passed at this level the multiples of s, along
-// those still to come the multiples of 2s (Sec. V-A).
+// those still to come the multiples of 2s (Sec. V-A).  The window kernels
+// run the default anchor stride only, so the level count is a constant and
+// every input sits in registers: the plan in global memory is only written.
+struct PlanIn {
+    int order[3], spline[3];
+    float el[kMaxLevels], ebx2[kMaxLevels], inv[kMaxLevels];
+};
+
 template <int ND>
-__device__ void make_passes(FieldPlan& p, int L, uint32_t n0, uint32_t n01) {
+__device__ void make_passes(FieldPlan& p, const PlanIn& in, uint32_t n0, uint32_t n01) {
     using G = Geo<ND>;
+    constexpr int L = G::SHS;
     const int W[3] = {G::W0, G::W1, G::W2};
     const int ST[3] = {1, G::SY, G::SZ};
     const uint32_t GS[3] = {1u, n0, n01};
+    int pos[3] = {0, 0, 0};   // place of each dimension in the order
+#pragma unroll
+    for (int k = 0; k < ND; ++k)
+#pragma unroll
+        for (int j = 0; j < ND; ++j)
+            if (in.order[k] == j) pos[j] = k;
     int np = 0;
+#pragma unroll
     for (int lvl = L; lvl >= 1; --lvl) {
-        const int s = 1 << (lvl - 1);
+#pragma unroll
         for (int k = 0; k < ND; ++k, ++np) {
-            PassDesc& q = p.pass[np];
-            const int d = p.order[k];
-            int e = -1, g = -1;   // the other dimensions, ascending
-            for (int j = 0; j < ND; ++j) {
-                if (j == d) continue;
-                if (e < 0) e = j; else g = j;
-            }
+            PassDesc q{};
+            const int d = in.order[k];
+            // the other dimensions, ascending
+            const int e = d == 0 ? 1 : 0;
+            const int g = ND == 2 ? -1 : (d == 2 ? 1 : 2);
             // lines sit at multiples of s along dimensions this level has
             // already passed over, of 2 s along the others
-            auto shift = [&](int j) {
-                int pj = 0;
-                while (p.order[pj] != j) ++pj;
-                return pj < k ? lvl - 1 : lvl;
-            };
+            auto shift = [&](int j) { return pos[j] < k ? lvl - 1 : lvl; };
             const int she = shift(e);
             q.d = d;
-            q.spl = p.spline[d];
+            q.spl = in.spline[d];
             q.sh = lvl - 1;
             q.ne = (uint32_t)((W[e] >> she) + 1);
             q.le = ST[e] << she;
@@ -213,24 +222,40 @@ __device__ void make_passes(FieldPlan& p, int L, uint32_t n0, uint32_t n01) {
                 q.gf = 0;
             }
             q.magic = kMagic.v[q.ne];
-            q.el = p.el[lvl - 1];
-            q.ebx2 = p.ebx2[lvl - 1];
-            q.inv = q.el == 0.0f ? 0.0f : p.inv[lvl - 1];
+            q.el = in.el[lvl - 1];
+            q.ebx2 = in.ebx2[lvl - 1];
+            q.inv = q.el == 0.0f ? 0.0f : in.inv[lvl - 1];
+            p.pass[np] = q;
         }
     }
-    for (; np < kMaxPasses; ++np) p.pass[np] = PassDesc{};
+#pragma unroll
+    for (int k = L * ND; k < kMaxPasses; ++k) p.pass[k] = PassDesc{};
 }
 
-__device__ void make_passes(const FieldDesc& f, FieldPlan& p) {
+__device__ void make_passes(const FieldDesc& f, FieldPlan& p, const PlanIn& in) {
     const uint32_t n0 = (uint32_t)f.n[0], n01 = n0 * (uint32_t)f.n[1];
-    if (f.ndim == 3) make_passes<3>(p, f.L, n0, n01);
-    else make_passes<2>(p, f.L, n0, n01);
+    if (f.ndim == 3) make_passes<3>(p, in, n0, n01);
+    else make_passes<2>(p, in, n0, n01);
 }
 
 // pass descriptors of plans that came from the host (decompression)
 __global__ void k_pass_desc(const FieldDesc* __restrict__ F, FieldPlan* P, int nfields) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nfields) make_passes(F[i], P[i]);
+    if (i >= nfields) return;
+    const FieldPlan& p = P[i];
+    PlanIn in;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        in.order[k] = p.order[k];
+        in.spline[k] = p.spline[k];
+    }
+#pragma unroll
+    for (int l = 0; l < kMaxLevels; ++l) {
+        in.el[l] = p.el[l];
+        in.ebx2[l] = p.ebx2[l];
+        in.inv[l] = p.inv[l];
+    }
+    make_passes(F[i], P[i], in);
 }
 
 __global__ __launch_bounds__(256) void k_plan(const FieldDesc* __restrict__ F, FieldPlan* P,
@@ -278,47 +303,59 @@ __global__ __launch_bounds__(256) void k_plan(const FieldDesc* __restrict__ F, F
     p.e = floor_to_f32(p.e_abs);
     p.alpha = f.alpha_req > 0.0 ? f.alpha_req : eq1_alpha(p.eps);
     p.levels = f.L;
+    PlanIn in;
     double apow = 1.0;
+#pragma unroll
     for (int l = 0; l < kMaxLevels; ++l) {
         if (l < f.L) {
-            p.el[l] = floor_to_f32(p.e_abs / apow);
-            p.ebx2[l] = 2.0f * p.el[l];
-            p.inv[l] = 1.0f / p.ebx2[l];
+            in.el[l] = floor_to_f32(p.e_abs / apow);
+            in.ebx2[l] = 2.0f * in.el[l];
+            in.inv[l] = 1.0f / in.ebx2[l];
             apow = apow * p.alpha;
         } else {
-            p.el[l] = 0.0f;
-            p.ebx2[l] = 0.0f;
-            p.inv[l] = 0.0f;
+            in.el[l] = 0.0f;
+            in.ebx2[l] = 0.0f;
+            in.inv[l] = 0.0f;
         }
+        p.el[l] = in.el[l];
+        p.ebx2[l] = in.ebx2[l];
+        p.inv[l] = in.inv[l];
     }
     const int D = f.ndim;
     double score[3] = {0.0, 0.0, 0.0};
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
         int s = d < D ? f.interp[d] : SPL_LIN;
         if (s == SPL_AUTO) s = p.prof[d][2] < p.prof[d][1] ? SPL_NAT : SPL_NAK;
+        in.spline[d] = s;
         p.spline[d] = s;
         score[d] = p.prof[d][s];
     }
     if (f.order_req[0] >= 0) {
-        for (int k = 0; k < 3; ++k) p.order[k] = k < D ? f.order_req[k] : -1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) in.order[k] = k < D ? f.order_req[k] : -1;
     } else {
         // least smooth first; a strictly larger error wins, else the slower
         bool used[3] = {false, false, false};
+#pragma unroll
         for (int k = 0; k < 3; ++k) {
             if (k >= D) {
-                p.order[k] = -1;
+                in.order[k] = -1;
                 continue;
             }
             int best = -1;
-            for (int d = D - 1; d >= 0; --d) {
-                if (used[d]) continue;
+#pragma unroll
+            for (int d = 2; d >= 0; --d) {
+                if (d >= D || used[d]) continue;
                 if (best < 0 || score[d] > score[best]) best = d;
             }
             used[best] = true;
-            p.order[k] = best;
+            in.order[k] = best;
         }
     }
-    make_passes(f, p);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) p.order[k] = in.order[k];
+    make_passes(f, p, in);
 }
 
 // zero the histogram of every field (one y-row of workgroups per field)
