@@ -36,7 +36,6 @@ def algorithmic_bytes(stage, n, n_anchors, n_out, n_words, n_chunks):
         "huff_stats": 2 * n + 2 * n_chunks,
         "encode": 2 * n + 4 * n_words + 8 * n_out + 4 * n_out,
         "decode": 4 * n_words + 2 * n_chunks + 2 * n,
-        "scatter": 8 * n_out + 4 * n_out,
         "replay": 2 * n + 4 * n_anchors + 4 * n + 4 * n_out,
     }.get(stage)
 
@@ -46,7 +45,7 @@ def algorithmic_bytes(stage, n, n_anchors, n_out, n_words, n_chunks):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_512cube_rel1e-3.md")
 STAGE_KERNELS = {"range": "k_range", "interp": "k_compress<3>", "huff_stats": "k_huff_stats",
                  "encode": "k_huff_encode", "decode": "k_huff_decode",
-                 "scatter": "k_scatter_outliers", "replay": "k_decompress<3>"}
+                 "replay": "k_decompress<3>"}
 
 
 def kernel_source_hash():

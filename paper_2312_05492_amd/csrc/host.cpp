@@ -1192,9 +1192,9 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
         return s;
     }
 
-    // part 1: range, profile, plan, interpolation (with histogram)
+    // part 1: range, profile, plan (which also zeroes the histograms),
+    // interpolation (with histogram)
     auto enqueue1 = [&](hipStream_t q) -> sz_status {
-        HIP_TRY(c, launch_zero_hist(d_fd, (int)nf, q));
         {
             STAGE(c, SZ_STAGE_RANGE, q);   // with the profiling
             HIP_TRY(c, launch_range(d_fd, d_plan, (int)nf, d_pmin, d_pmax, d_pbad, q));
@@ -1513,18 +1513,14 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
     sz_status s;
     // the device work of the call
     auto enqueue = [&](hipStream_t q) -> sz_status {
-        HIP_TRY(c, launch_pass_desc(d_fd, d_plan, (int)nf, q));
         {
+            // block word counts, the outlier scatter and the pass descriptors
             STAGE(c, SZ_STAGE_SCAN, q);
-            HIP_TRY(c, launch_chunk_words(d_fd, (int)nf, d_dboff, nblocks, d_bsum, q));
+            HIP_TRY(c, launch_dec_prep(d_fd, d_plan, (int)nf, d_dboff, nblocks, d_bsum, q));
         }
         {
             STAGE(c, SZ_STAGE_DECODE, q);
             HIP_TRY(c, launch_huff_decode(d_fd, (int)nf, d_dboff, nblocks, d_bsum, 2 * max_R, q));
-        }
-        {
-            STAGE(c, SZ_STAGE_SCATTER, q);
-            HIP_TRY(c, launch_scatter_outliers(d_fd, (int)nf, q));
         }
         uint32_t base = 0;
         for (int gi = 0; gi < 2; ++gi) {

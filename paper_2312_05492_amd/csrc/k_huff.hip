@@ -10,7 +10,7 @@
 //                  codewords MSB-first through LDS and writes the outliers
 //                  (index, original value) in ascending index order
 // Decode: one lane per chunk, kDecChunks chunks per workgroup.
-//   k_chunk_words  word count of every chunk, sums per block
+//   k_dec_prep     (k_plan.hip) word count of every decode block
 //   k_huff_decode  sum of the field's earlier block sums and an in-block
 //                  scan, then a table-driven canonical decode from a 64-bit
 //                  bit buffer fed by a per-lane LDS word ring; 64 symbols
@@ -21,6 +21,8 @@ namespace szi {
 
 constexpr int kEncChunks = 16;
 constexpr int kDecChunks = 256;
+static_assert(kEncChunks == kEncBlockChunks && kDecChunks == kDecBlockChunks,
+              "the host sizes the Huffman grids with the same chunk counts");
 
 // symbols [s0, s0 + per) of the code array (all inside the field)
 template <int PER>
@@ -303,26 +305,6 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
     }
 }
 
-// word count of every chunk and their sums per decode block
-__global__ __launch_bounds__(kDecChunks) void k_chunk_words(const FieldDesc* __restrict__ F,
-                                                            int nfields,
-                                                            const uint64_t* __restrict__ boff,
-                                                            uint32_t* bsum) {
-    const int f = block_field(boff, nfields, blockIdx.x);
-    const FieldDesc& fd = F[f];
-    const uint64_t ch = (blockIdx.x - boff[f]) * kDecChunks + threadIdx.x;
-    uint32_t w = ch < fd.nchunks ? ((uint32_t)gp(fd.chunk_bits)[ch] + 31u) >> 5 : 0u;
-    w = wave_sum(w);
-    __shared__ uint32_t s[kDecChunks / 64];
-    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = w;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t a = 0;
-        for (int k = 0; k < kDecChunks / 64; ++k) a += s[k];
-        bsum[blockIdx.x] = a;
-    }
-}
-
 // One lane decodes one chunk: canonical decode with a 2^kLutBits table of
 // u16 entries for short codes; a longer code's length comes from comparing
 // the next bits with the per-length limits, without a loop or a
@@ -511,17 +493,6 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
     }
 }
 
-__global__ __launch_bounds__(256) void k_scatter_outliers(const FieldDesc* __restrict__ F) {
-    const FieldDesc& fd = F[blockIdx.y];
-    const uint64_t n = fd.npts;
-    const uint64_t no = fd.n_outliers;
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < no;
-         k += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t idx = gp(fd.outlier_idx)[k];
-        if (idx < n) gp(fd.out)[idx] = gp(fd.outlier_val)[k];
-    }
-}
-
 // ------------------------------------------------------- launchers
 hipError_t launch_huff_stats(const FieldDesc* d_fields, int nfields, const uint64_t* d_boff,
                              uint64_t nblocks, int chunk, uint32_t* d_cwords, uint32_t* d_couts,
@@ -563,13 +534,6 @@ hipError_t launch_huff_encode(const FieldDesc* d_fields, int nfields, const uint
     return hipGetLastError();
 }
 
-hipError_t launch_chunk_words(const FieldDesc* d_fields, int nfields, const uint64_t* d_dboff,
-                              uint64_t nblocks, uint32_t* d_bsum, hipStream_t st) {
-    if (nblocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_chunk_words, dim3((unsigned)nblocks), dim3(kDecChunks), 0, st, d_fields,
-                       nfields, d_dboff, d_bsum);
-    return hipGetLastError();
-}
 
 hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields, const uint64_t* d_dboff,
                               uint64_t nblocks, const uint32_t* d_bsum, int max_nsym,
@@ -582,9 +546,5 @@ hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields, const uint
     return hipGetLastError();
 }
 
-hipError_t launch_scatter_outliers(const FieldDesc* d_fields, int nfields, hipStream_t st) {
-    hipLaunchKernelGGL(k_scatter_outliers, dim3(256, nfields), dim3(256), 0, st, d_fields);
-    return hipGetLastError();
-}
 
 }  // namespace szi

@@ -238,24 +238,50 @@ __device__ void make_passes(const FieldDesc& f, FieldPlan& p, const PlanIn& in) 
     else make_passes<2>(p, in, n0, n01);
 }
 
-// pass descriptors of plans that came from the host (decompression)
-__global__ void k_pass_desc(const FieldDesc* __restrict__ F, FieldPlan* P, int nfields) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nfields) return;
-    const FieldPlan& p = P[i];
-    PlanIn in;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        in.order[k] = p.order[k];
-        in.spline[k] = p.spline[k];
+// Decompression prologue, one workgroup of kDecBlockChunks threads per
+// Huffman decode block: the block's word count (the decoder's offsets come
+// from these sums), a share of the field's outlier values scattered into
+// the output (where the replay reads them), and, in the field's first
+// block, the pass descriptors of the plan the header carried.
+__global__ __launch_bounds__(kDecBlockChunks) void k_dec_prep(const FieldDesc* __restrict__ F,
+                                                             FieldPlan* P, int nfields,
+                                                             const uint64_t* __restrict__ boff,
+                                                             uint32_t* bsum) {
+    const int f = block_field(boff, nfields, blockIdx.x);
+    const FieldDesc& fd = F[f];
+    const uint64_t b = blockIdx.x - boff[f], nb = boff[f + 1] - boff[f];
+    const uint64_t ch = b * kDecBlockChunks + threadIdx.x;
+    uint32_t w = ch < fd.nchunks ? ((uint32_t)gp(fd.chunk_bits)[ch] + 31u) >> 5 : 0u;
+    w = wave_sum(w);
+    __shared__ uint32_t s[kDecBlockChunks / 64];
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = w;
+    for (uint64_t k = b * kDecBlockChunks + threadIdx.x; k < fd.n_outliers;
+         k += nb * kDecBlockChunks) {
+        const uint32_t idx = gp(fd.outlier_idx)[k];
+        if (idx < fd.npts) gp(fd.out)[idx] = gp(fd.outlier_val)[k];
     }
+    if (b == 0 && threadIdx.x == 0) {
+        const FieldPlan& p = P[f];
+        PlanIn in;
 #pragma unroll
-    for (int l = 0; l < kMaxLevels; ++l) {
-        in.el[l] = p.el[l];
-        in.ebx2[l] = p.ebx2[l];
-        in.inv[l] = p.inv[l];
+        for (int k = 0; k < 3; ++k) {
+            in.order[k] = p.order[k];
+            in.spline[k] = p.spline[k];
+        }
+#pragma unroll
+        for (int l = 0; l < kMaxLevels; ++l) {
+            in.el[l] = p.el[l];
+            in.ebx2[l] = p.ebx2[l];
+            in.inv[l] = p.inv[l];
+        }
+        make_passes(fd, P[f], in);
     }
-    make_passes(F[i], P[i], in);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t a = 0;
+        for (int k = 0; k < kDecBlockChunks / 64; ++k) a += s[k];
+        bsum[blockIdx.x] = a;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_plan(const FieldDesc* __restrict__ F, FieldPlan* P,
@@ -281,6 +307,8 @@ __global__ __launch_bounds__(256) void k_plan(const FieldDesc* __restrict__ F, F
         smx[threadIdx.x >> 6] = mx;
         sbad[threadIdx.x >> 6] = bad;
     }
+    // the histogram the interpolation accumulates starts at zero
+    for (int b = threadIdx.x; b < 2 * f.R; b += blockDim.x) gp(f.hist)[b] = 0u;
     __syncthreads();
     if (threadIdx.x != 0) return;
     for (int k = 1; k < 4; ++k) {
@@ -394,11 +422,12 @@ hipError_t launch_zero_hist(const FieldDesc* d_fields, int nfields, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_pass_desc(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
-                            hipStream_t st) {
-    if (nfields <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pass_desc, dim3((unsigned)((nfields + 63) / 64)), dim3(64), 0, st,
-                       d_fields, d_plans, nfields);
+hipError_t launch_dec_prep(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
+                           const uint64_t* d_dboff, uint64_t nblocks, uint32_t* d_bsum,
+                           hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dec_prep, dim3((unsigned)nblocks), dim3(kDecBlockChunks), 0, st, d_fields,
+                       d_plans, nfields, d_dboff, d_bsum);
     return hipGetLastError();
 }
 

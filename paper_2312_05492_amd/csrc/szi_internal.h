@@ -119,8 +119,10 @@ hipError_t launch_plan(const FieldDesc* d_fields, FieldPlan* d_plans, int nfield
                        const float* d_part_min, const float* d_part_max,
                        const uint32_t* d_part_bad, hipStream_t st);
 hipError_t launch_zero_hist(const FieldDesc* d_fields, int nfields, hipStream_t st);
-hipError_t launch_pass_desc(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
-                            hipStream_t st);
+// decompression prologue: block word counts, outlier scatter, pass descriptors
+hipError_t launch_dec_prep(const FieldDesc* d_fields, FieldPlan* d_plans, int nfields,
+                           const uint64_t* d_dboff, uint64_t nblocks, uint32_t* d_bsum,
+                           hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
 // Launch shape of a window kernel; every shape gives the same results.
 // variant 0: compiled for three waves per SIMD (168 VGPRs); variant 1: for
@@ -146,12 +148,9 @@ hipError_t launch_huff_encode(const FieldDesc* d_fields, int nfields, const uint
                               uint64_t nblocks, int chunk, const uint32_t* d_cwords,
                               const uint32_t* d_couts, const uint64_t* d_bwoff,
                               const uint64_t* d_booff, int max_nsym, hipStream_t st);
-hipError_t launch_chunk_words(const FieldDesc* d_fields, int nfields, const uint64_t* d_dboff,
-                              uint64_t nblocks, uint32_t* d_bsum, hipStream_t st);
-// d_bsum: the word count of every decode block (launch_chunk_words)
+// d_bsum: the word count of every decode block (launch_dec_prep)
 hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields, const uint64_t* d_dboff,
                               uint64_t nblocks, const uint32_t* d_bsum, int max_nsym,
                               hipStream_t st);
-hipError_t launch_scatter_outliers(const FieldDesc* d_fields, int nfields, hipStream_t st);
 
 }  // namespace szi
