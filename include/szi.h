@@ -201,6 +201,29 @@ sz_status sz_compress_batch(sz_ctx* ctx, uint32_t nfields, const float* const* d
                             const sz_dims* dims, const sz_params* params, void* stream,
                             sz_result* outs);
 
+/* Compress with a code book the caller gives instead of one built from this
+ * field's histogram (Sec. VI-A builds it on the host between the histogram
+ * and the encoding; reusing one, e.g. across the time steps of a
+ * simulation, removes that host round trip).  code_len: host array of 2R
+ * canonical code lengths, every symbol 1..24 bits with Kraft sum <= 1, so
+ * that any quant-code can be encoded (sz_code_lengths makes one from a
+ * histogram).  The pipeline is enqueued at once and the call waits once,
+ * at the end; the result's histogram is this field's, its code lengths the
+ * given ones, and the blob decodes like any other.  The Huffman words are
+ * allocated for 24 bits per point, the outlier lists for a guess that the
+ * call enlarges (running the encode again) when the field has more.
+ * Errors: as sz_compress; INVALID_ARG for a code book that misses a symbol,
+ * exceeds 24 bits or breaks the Kraft inequality. */
+sz_status sz_compress_with_code(sz_ctx* ctx, const float* d_in, const sz_dims* dims,
+                                const sz_params* params, const uint8_t* code_len, void* stream,
+                                sz_result* out);
+
+/* Code lengths for sz_compress_with_code from a histogram of nsym = 2R
+ * bins (host memory): the length-limited Huffman lengths of the counts
+ * plus one, so that every symbol gets a code.  Host only, no context.
+ * Errors: INVALID_ARG (null pointer, nsym outside 2..2048). */
+sz_status sz_code_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* code_len);
+
 /* Decompress a device-resident result into d_out (n floats), replaying the
  * predictions (Sec. V-B.1).  Returns after the stream has completed.
  * Errors: INVALID_ARG, OOM, DEVICE, CORRUPT. */

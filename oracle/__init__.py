@@ -300,8 +300,13 @@ class Compressed:
         return serialize(self)
 
 
-def compress(x: np.ndarray, p: Params, want_cls: bool = False, cfg: Config = None) -> Compressed:
-    """Whole pipeline: plan, traversal, histogram, codebook, chunked encode."""
+def compress(x: np.ndarray, p: Params, want_cls: bool = False, cfg: Config = None,
+             lengths: np.ndarray = None) -> Compressed:
+    """Whole pipeline: plan, traversal, histogram, codebook, chunked encode.
+
+    lengths: a code book to use instead of the one the histogram gives
+    (Sec. VI-A builds it from the histogram; any prefix code whose lengths
+    cover every symbol encodes the same quant-codes)."""
     x = _check_field(x, p)
     cp = p.c_struct()
     if cfg is None:
@@ -323,7 +328,15 @@ def compress(x: np.ndarray, p: Params, want_cls: bool = False, cfg: Config = Non
     m = nout.value
     nsym = 2 * p.R
     h = histogram(codes, nsym)
-    ln = huffman_lengths(h)
+    if lengths is None:
+        ln = huffman_lengths(h)
+    else:
+        ln = np.ascontiguousarray(lengths, dtype=np.uint8)
+        used = ln[ln > 0].astype(np.int64)
+        if ln.size != nsym or np.any(ln[h > 0] == 0) or ln.max() > LMAX or \
+                float(np.sum(np.ldexp(1.0, -used))) > 1.0:
+            raise ValueError("code book: %d lengths of at most %d bits, one for every symbol "
+                             "that occurs, with Kraft sum <= 1 needed" % (nsym, LMAX))
     cw = canonical_codes(ln)
     cb, words = encode(codes, ln, cw, p.chunk)
     return Compressed(params=p, config=cfg, anchors=anchors, codes=codes, recon=recon,

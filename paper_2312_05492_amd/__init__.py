@@ -120,6 +120,10 @@ def lib():
         L.sz_ctx_read_timing.argtypes = [vp, P(C.c_double), P(C.c_uint64), C.c_int]
         L.sz_compress.restype = C.c_int
         L.sz_compress.argtypes = [vp, vp, P(SzDims), P(SzParams), vp, P(SzResult)]
+        L.sz_compress_with_code.restype = C.c_int
+        L.sz_compress_with_code.argtypes = [vp, vp, P(SzDims), P(SzParams), vp, vp, P(SzResult)]
+        L.sz_code_lengths.restype = C.c_int
+        L.sz_code_lengths.argtypes = [vp, C.c_uint32, vp]
         L.sz_compress_batch.restype = C.c_int
         L.sz_compress_batch.argtypes = [vp, C.c_uint32, P(vp), P(SzDims), P(SzParams), vp,
                                         P(SzResult)]
@@ -180,6 +184,18 @@ def make_params(ndim, eb=1e-3, eb_mode=EB_REL, interp=None, order=None, alpha=0.
     p.radius = int(radius)
     p.huff_chunk = int(chunk)
     return p
+
+
+def code_lengths(hist) -> np.ndarray:
+    """Code lengths for Context.compress_with_code from a histogram of 2R
+    bins: the length-limited Huffman lengths of the counts plus one, so that
+    every symbol has a code (host only)."""
+    h = np.ascontiguousarray(hist, dtype=np.uint32)
+    out = np.zeros(h.size, dtype=np.uint8)
+    rc = lib().sz_code_lengths(h.ctypes.data_as(C.c_void_p), h.size, out.ctypes.data_as(C.c_void_p))
+    if rc != SZ_OK:
+        raise SzError(rc, "sz_code_lengths: histogram of %d bins" % h.size)
+    return out
 
 
 def _stream(torch, device):
@@ -314,6 +330,21 @@ class Context:
         r = SzResult()
         self._check(lib().sz_compress(self.h, C.c_void_p(x.data_ptr()), C.byref(d), C.byref(p),
                                       _stream(self.torch, x.device), C.byref(r)))
+        return Result(self, r, x.shape)
+
+    def compress_with_code(self, x, code_len, **kw) -> Result:
+        """Compression with a given code book: 2R code lengths (uint8, each
+        1..24, Kraft sum <= 1), e.g. code_lengths(earlier.read(SEC_HIST))."""
+        x = self._field(x)
+        d = make_dims(x.shape)
+        p = make_params(x.dim(), **kw)
+        cl = np.ascontiguousarray(code_len, dtype=np.uint8)
+        if cl.size != 2 * p.radius:
+            raise ValueError("code_len needs %d entries (2R), got %d" % (2 * p.radius, cl.size))
+        r = SzResult()
+        self._check(lib().sz_compress_with_code(self.h, C.c_void_p(x.data_ptr()), C.byref(d),
+                                                C.byref(p), cl.ctypes.data_as(C.c_void_p),
+                                                _stream(self.torch, x.device), C.byref(r)))
         return Result(self, r, x.shape)
 
     def compress_batch(self, xs, params=None) -> list:

@@ -1001,8 +1001,15 @@ sz_status sz_ctx_get_shape(sz_ctx* c, int kind, int ndim, int radius, int* varia
 }
 
 
-sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, const sz_dims* dims,
-                            const sz_params* params, void* stream, sz_result* outs) {
+namespace {
+
+// Compression of nf fields.  given: per field the caller's code lengths
+// (2R entries), or null for code books built from the histograms.  With
+// given code books the whole pipeline is enqueued at once and the host
+// waits once, at the end, for the sizes.
+sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, const sz_dims* dims,
+                          const sz_params* params, const uint8_t* const* given, void* stream,
+                          sz_result* outs) {
     if (!c) return SZ_ERR_INVALID_ARG;
     if (nf == 0 || !d_in || !dims || !params || !outs)
         return fail(c, SZ_ERR_INVALID_ARG, "empty batch or null argument");
@@ -1017,7 +1024,20 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
         if (s) return s;
         fill_desc(geo[i], &params[i], fd[i]);
         fd[i].in = d_in[i];
+        if (given) {
+            const uint8_t* gl = given[i];
+            const int nsym = 2 * geo[i].R;
+            bool ok = gl != nullptr;
+            for (int sy = 0; ok && sy < nsym; ++sy) ok = gl[sy] >= 1 && gl[sy] <= kLmax;
+            if (!ok || !kraft_ok(gl, nsym))
+                return fail(c, SZ_ERR_INVALID_ARG,
+                            "field %u: the code book must give each of the %d symbols a length "
+                            "of 1..%d bits, with Kraft sum <= 1", i, nsym, kLmax);
+        }
     }
+    // graphs and launch-shape tuning need the host round trip after the
+    // interpolation, which a given code book does without
+    const bool graphs = c->graphs && !given;
     // results (released on any error below)
     std::vector<sz_result> res(nf);
     std::memset(res.data(), 0, sizeof(sz_result) * nf);
@@ -1154,14 +1174,14 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
         o_cb[k + 1] = o_cb[k] + ((nsym + 4 * nsym + 4 * (size_t)dtab_words((int)nsym) + 255) & ~(size_t)255);
     }
     char* hs;   // the staging base
-    if (c->graphs) {
+    if (graphs) {
         if ((s = arena_reserve(c, o_cb[nf]))) return s;
         hs = static_cast<char*>(c->parena);
     } else {
         if ((s = pinned_reserve(c, o_cb[nf]))) return s;
         hs = static_cast<char*>(c->pinned);
     }
-    if (c->graphs) {
+    if (graphs) {
         char* d = static_cast<char*>(c->arena);
         d_fd = reinterpret_cast<FieldDesc*>(d + o_fd);
         d_items = reinterpret_cast<uint64_t*>(d + o_items);
@@ -1219,7 +1239,15 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
     std::vector<FieldPlan> plans(nf);
     std::vector<std::vector<uint32_t>> hist(nf);
     for (uint32_t k = 0; k < nf; ++k) hist[k].resize(2 * fds[k].R);
-    if (c->graphs) {
+    if (given) {
+        // no round trip: part 1 now, its plans and histograms read at the end
+        std::memcpy(hs + o_fd, fds.data(), sizeof(FieldDesc) * nf);
+        std::memcpy(hs + o_items, items.data(), sizeof(uint64_t) * items.size());
+        HIP_TRY(c, hipMemcpyAsync(d_fd, hs + o_fd, sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(d_items, hs + o_items, sizeof(uint64_t) * items.size(),
+                                  hipMemcpyHostToDevice, st));
+        if ((s = enqueue1(st))) return s;
+    } else if (c->graphs) {
         char* h = static_cast<char*>(c->parena);
         std::memcpy(h + o_fd, fds.data(), sizeof(FieldDesc) * nf);
         std::memcpy(h + o_items, items.data(), sizeof(uint64_t) * items.size());
@@ -1293,28 +1321,38 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
             }
         }
     }
-    std::unique_ptr<StageMark> cb_mark(new StageMark(c, SZ_STAGE_CODEBOOK, st));
-    for (uint32_t k = 0; k < nf; ++k)
+    std::unique_ptr<StageMark> cb_mark(given ? nullptr : new StageMark(c, SZ_STAGE_CODEBOOK, st));
+    for (uint32_t k = 0; k < nf && !given; ++k)
         if (plans[k].status == -2)
             return fail(c, SZ_ERR_NONFINITE, "field %u holds %u non-finite values", perm[k],
                         plans[k].nonfinite);
 
-    // host codebooks (Sec. VI-A), exact buffer sizes from the histogram
+    // host codebooks (Sec. VI-A), exact buffer sizes from the histogram;
+    // with a given code book the words take their largest size and the
+    // outlier lists a guess that the end checks
+    auto outlier_guess = [](uint64_t n) { return std::min<uint64_t>(n, std::max<uint64_t>(n / 32, 4096)); };
     for (uint32_t k = 0; k < nf; ++k) {
         const uint32_t i = perm[k];
         ResultInternal* R = ri(&res[i]);
-        R->plan = plans[k];
         const int nsym = 2 * fds[k].R;
-        R->code_len.assign(nsym, 0);
-        huffman_lengths(hist[k].data(), nsym, kLmax, R->code_len.data());
+        if (given) {
+            R->code_len.assign(given[i], given[i] + nsym);
+        } else {
+            R->plan = plans[k];
+            R->code_len.assign(nsym, 0);
+            huffman_lengths(hist[k].data(), nsym, kLmax, R->code_len.data());
+        }
         uint8_t* h_len = reinterpret_cast<uint8_t*>(hs + o_cb[k]);
         uint32_t* h_cbook = reinterpret_cast<uint32_t*>(h_len + nsym);
         uint32_t* h_dtab = h_cbook + nsym;
         std::memcpy(h_len, R->code_len.data(), nsym);
         build_tables(R->code_len.data(), nsym, h_cbook, h_dtab);
         uint64_t bits = 0;
-        for (int sy = 0; sy < nsym; ++sy) bits += (uint64_t)hist[k][sy] * R->code_len[sy];
-        const uint64_t nout = hist[k][0];
+        if (given)
+            bits = geo[i].npts * (uint64_t)kLmax;
+        else
+            for (int sy = 0; sy < nsym; ++sy) bits += (uint64_t)hist[k][sy] * R->code_len[sy];
+        const uint64_t nout = given ? outlier_guess(geo[i].npts) : hist[k][0];
         const uint64_t wcap = bits / 32 + geo[i].nchunks + 1;
         if ((s = res_alloc(c, R, wcap + kWordPad, &res[i].words))) return s;
         if ((s = res_alloc(c, R, std::max<uint64_t>(nout, 1), &res[i].outlier_idx))) return s;
@@ -1326,7 +1364,7 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
         fds[k].n_outliers = nout;
         fds[k].words_cap = wcap;
         fds[k].dtab = R->d_dtab;
-        if (c->graphs)   // the result keeps its own histogram
+        if (graphs)   // the result keeps its own histogram
             HIP_TRY(c, hipMemcpyAsync(res[i].hist, fds[k].hist, sizeof(uint32_t) * nsym,
                                       hipMemcpyDeviceToDevice, st));
         HIP_TRY(c, hipMemcpyAsync(res[i].code_len, h_len, nsym, hipMemcpyHostToDevice, st));
@@ -1405,8 +1443,53 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
         if ((s = enqueue2(st))) return s;
         HIP_TRY(c, hipMemcpyAsync(hs + o_bwoff, d_bwoff, sizeof(uint64_t) * nbw,
                                   hipMemcpyDeviceToHost, st));
+        if (given) {
+            HIP_TRY(c, hipMemcpyAsync(hs + o_plan, d_plan, sizeof(FieldPlan) * nf,
+                                      hipMemcpyDeviceToHost, st));
+            for (uint32_t k = 0; k < nf; ++k)
+                HIP_TRY(c, hipMemcpyAsync(hs + o_hist + sizeof(uint32_t) * k * hstride, fds[k].hist,
+                                          sizeof(uint32_t) * hist[k].size(), hipMemcpyDeviceToHost, st));
+        }
         HIP_TRY(c, hipStreamSynchronize(st));
         std::memcpy(bwoff.data(), hs + o_bwoff, sizeof(uint64_t) * nbw);
+        if (given) {
+            std::memcpy(plans.data(), hs + o_plan, sizeof(FieldPlan) * nf);
+            for (uint32_t k = 0; k < nf; ++k)
+                std::memcpy(hist[k].data(), hs + o_hist + sizeof(uint32_t) * k * hstride,
+                            sizeof(uint32_t) * hist[k].size());
+            for (uint32_t k = 0; k < nf; ++k) {
+                if (plans[k].status == -2)
+                    return fail(c, SZ_ERR_NONFINITE, "field %u holds %u non-finite values", perm[k],
+                                plans[k].nonfinite);
+                ri(&res[perm[k]])->plan = plans[k];
+            }
+            // more outliers than the guess: exact lists, and the encode again
+            bool again = false;
+            for (uint32_t j = 0; j < nf; ++j) {
+                const uint32_t k = hord[j], i = perm[k];
+                const uint64_t nout = hist[k][0];
+                if (nout > fds[k].n_outliers) {
+                    ResultInternal* R = ri(&res[i]);
+                    if ((s = res_alloc(c, R, nout, &res[i].outlier_idx))) return s;
+                    if ((s = res_alloc(c, R, nout, &res[i].outlier_val))) return s;
+                    fds[k].outlier_idx = hfd[j].outlier_idx = res[i].outlier_idx;
+                    fds[k].outlier_val = hfd[j].outlier_val = res[i].outlier_val;
+                    fds[k].n_outliers = hfd[j].n_outliers = nout;
+                    again = true;
+                }
+                res[i].n_outliers = nout;
+            }
+            if (again) {
+                std::memcpy(hs + o_hfd, hfd.data(), sizeof(FieldDesc) * nf);
+                HIP_TRY(c, hipMemcpyAsync(d_hfd, hs + o_hfd, sizeof(FieldDesc) * nf,
+                                          hipMemcpyHostToDevice, st));
+                if ((s = enqueue2(st))) return s;
+                HIP_TRY(c, hipMemcpyAsync(hs + o_bwoff, d_bwoff, sizeof(uint64_t) * nbw,
+                                          hipMemcpyDeviceToHost, st));
+                HIP_TRY(c, hipStreamSynchronize(st));
+                std::memcpy(bwoff.data(), hs + o_bwoff, sizeof(uint64_t) * nbw);
+            }
+        }
     }
     resolve_marks(c);
     for (size_t g = 0; g < groups.size(); ++g) {
@@ -1416,7 +1499,7 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
             const uint32_t k = hord[j];
             const uint32_t i = perm[k];
             res[i].n_words = bwoff[goff_at[g] + hi] - bwoff[goff_at[g] + lo];
-            if (res[i].n_words > fds[k].words_cap)   // the histogram sized the stream
+            if (res[i].n_words > fds[k].words_cap)   // sized from the histogram or the largest
                 return fail(c, SZ_ERR_DEVICE, "field %u: %llu Huffman words exceed the %llu sized "
                             "from the histogram", i, (unsigned long long)res[i].n_words,
                             (unsigned long long)fds[k].words_cap);
@@ -1429,12 +1512,39 @@ sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, co
     return SZ_OK;
 }
 
+}  // namespace
+
+sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, const sz_dims* dims,
+                            const sz_params* params, void* stream, sz_result* outs) {
+    return compress_fields(c, nf, d_in, dims, params, nullptr, stream, outs);
+}
+
 sz_status sz_compress(sz_ctx* c, const float* d_in, const sz_dims* dims, const sz_params* params,
                       void* stream, sz_result* out) {
     if (!c) return SZ_ERR_INVALID_ARG;
     if (!out) return fail(c, SZ_ERR_INVALID_ARG, "null result");
     const float* ins[1] = {d_in};
-    return sz_compress_batch(c, 1, ins, dims, params, stream, out);
+    return compress_fields(c, 1, ins, dims, params, nullptr, stream, out);
+}
+
+sz_status sz_compress_with_code(sz_ctx* c, const float* d_in, const sz_dims* dims,
+                                const sz_params* params, const uint8_t* code_len, void* stream,
+                                sz_result* out) {
+    if (!c) return SZ_ERR_INVALID_ARG;
+    if (!out || !code_len) return fail(c, SZ_ERR_INVALID_ARG, "null result or code book");
+    const float* ins[1] = {d_in};
+    const uint8_t* lens[1] = {code_len};
+    return compress_fields(c, 1, ins, dims, params, lens, stream, out);
+}
+
+sz_status sz_code_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* code_len) {
+    if (!hist || !code_len || nsym < 2 || nsym > 2 * (uint32_t)kMaxRadius)
+        return SZ_ERR_INVALID_ARG;
+    // every symbol counted once more, so that each gets a code
+    std::vector<uint32_t> h(nsym);
+    for (uint32_t s = 0; s < nsym; ++s) h[s] = hist[s] == UINT32_MAX ? hist[s] : hist[s] + 1u;
+    huffman_lengths(h.data(), (int)nsym, kLmax, code_len);
+    return SZ_OK;
 }
 
 sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, float* const* d_out,
