@@ -1001,6 +1001,8 @@ sz_status sz_ctx_get_shape(sz_ctx* c, int kind, int ndim, int radius, int* varia
 }
 
 
+}  // extern "C"
+
 namespace {
 
 // Compression of nf fields.  given: per field the caller's code lengths
@@ -1513,6 +1515,8 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
 }
 
 }  // namespace
+
+extern "C" {
 
 sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, const sz_dims* dims,
                             const sz_params* params, void* stream, sz_result* outs) {
