@@ -380,13 +380,56 @@ def _pad8(b: bytes) -> bytes:
     return b + b"\0" * ((-len(b)) % 8)
 
 
+FLAG_WORDS_ELIDED = 1
+
+
+def elide_zero_words(words: np.ndarray):
+    """The Huffman words without their zero words: a bitmap of u32 words,
+    bit k % 32 of bitmap word k // 32 set when word k is non-zero, followed
+    by the non-zero words in order.  Returns that array when it is shorter
+    than the words themselves, else None (the words are stored as they are).
+    An open stand-in for the closed de-redundancy pass that follows Huffman
+    coding in the paper (Sec. VI-B); runs of zero words are what a smooth
+    field's one-bit centre code leaves."""
+    w = np.ascontiguousarray(words, dtype=np.uint32)
+    nbm = (w.size + 31) // 32
+    nz = w != 0
+    if nbm + int(nz.sum()) >= w.size:
+        return None
+    flags = np.zeros(nbm * 32, dtype=np.uint64)
+    flags[:w.size] = nz
+    weights = np.left_shift(np.uint64(1), np.arange(32, dtype=np.uint64))
+    bitmap = (flags.reshape(nbm, 32) * weights).sum(axis=1).astype(np.uint32)
+    return np.concatenate([bitmap, w[nz]])
+
+
+def restore_zero_words(section: np.ndarray, n_words: int) -> np.ndarray:
+    """Inverse of elide_zero_words; raises on a malformed section."""
+    sec = np.ascontiguousarray(section, dtype=np.uint32)
+    nbm = (n_words + 31) // 32
+    if sec.size < nbm:
+        raise OracleError(-5, "restore_zero_words (bitmap)")
+    bits = ((sec[:nbm, None] >> np.arange(32, dtype=np.uint32)) & 1).astype(bool).ravel()
+    if bits[n_words:].any():
+        raise OracleError(-5, "restore_zero_words (bits past the words)")
+    pos = np.flatnonzero(bits[:n_words])
+    vals = sec[nbm:]
+    if vals.size != pos.size or (vals == 0).any():
+        raise OracleError(-5, "restore_zero_words (values)")
+    w = np.zeros(n_words, dtype=np.uint32)
+    w[pos] = vals
+    return w
+
+
 def serialize(c: Compressed) -> bytes:
     p, cfg = c.params, c.config
     cp = p.c_struct()
     D = p.ndim()
     el = list(cfg.el) + [0.0] * (16 - cfg.levels)
+    elided = elide_zero_words(c.words)
+    wsec = c.words if elided is None else elided
     sections = [c.anchors.astype("<f4").tobytes(), c.code_len.astype(np.uint8).tobytes(),
-                c.chunk_bits.astype("<u2").tobytes(), c.words.astype("<u4").tobytes(),
+                c.chunk_bits.astype("<u2").tobytes(), wsec.astype("<u4").tobytes(),
                 c.outlier_idx.astype("<u4").tobytes(), c.outlier_val.astype("<f4").tobytes()]
     crcs = [zlib.crc32(s) & 0xFFFFFFFF for s in sections]
     spline = list(cfg.spline) + [0] * (3 - D)
@@ -394,7 +437,8 @@ def serialize(c: Compressed) -> bytes:
     fields = ([MAGIC, VERSION, D, cp.S] + [cp.n[i] for i in range(3)] +
               [cp.w[i] for i in range(3)] + [p.R, LMAX, p.chunk, p.eb_mode, cfg.levels] +
               [float(p.eb), float(cfg.alpha), cfg.vmin, cfg.vmax, cfg.e] + spline + order +
-              [0] + el + [c.anchors.size, c.chunk_bits.size, c.words.size,
+              [0 if elided is None else FLAG_WORDS_ELIDED] + el +
+              [c.anchors.size, c.chunk_bits.size, c.words.size,
                           c.outlier_idx.size] + crcs + [0, 0])
     head = bytearray(_HEADER.pack(*fields))
     struct.pack_into("<I", head, 252, zlib.crc32(bytes(head[:252])) & 0xFFFFFFFF)
@@ -411,7 +455,8 @@ def parse(blob: bytes) -> dict:
     f = _HEADER.unpack(head)
     if f[0] != MAGIC or f[1] != VERSION:
         raise OracleError(-5, "parse (magic)")
-    if struct.unpack_from("<I", head, 124)[0] or struct.unpack_from("<I", head, 248)[0]:
+    flags = struct.unpack_from("<I", head, 124)[0]
+    if flags & ~FLAG_WORDS_ELIDED or struct.unpack_from("<I", head, 248)[0]:
         raise OracleError(-5, "parse (reserved words)")
     i = 0
     out = {}
@@ -427,6 +472,13 @@ def parse(blob: bytes) -> dict:
     pos = 256
     secs = []
     for k, (cnt, dt) in enumerate(sizes):
+        if k == 3 and flags & FLAG_WORDS_ELIDED:
+            # bitmap, then one word per set bit
+            nbm = (int(cnt) + 31) // 32
+            bm = np.frombuffer(blob[pos:pos + 4 * nbm], dtype="<u4")
+            if bm.size != nbm:
+                raise OracleError(-5, "parse (bitmap)")
+            cnt = nbm + int(sum(bin(int(v)).count("1") for v in bm))
         nb = int(cnt) * np.dtype(dt).itemsize
         raw = blob[pos:pos + nb]
         if len(raw) != nb or zlib.crc32(raw) & 0xFFFFFFFF != out["crc%d" % k]:
@@ -437,8 +489,11 @@ def parse(blob: bytes) -> dict:
         pos += nb + ((-nb) % 8)
     if pos != len(blob):
         raise OracleError(-5, "parse (length)")
+    if flags & FLAG_WORDS_ELIDED:
+        secs[3] = restore_zero_words(secs[3], int(out["n_words"]))
     out["anchors"], out["code_len"], out["chunk_bits"], out["words"], out["outlier_idx"], \
         out["outlier_val"] = secs
+    out["flags"] = flags
     return out
 
 

@@ -519,6 +519,7 @@ struct ResultInternal {
     std::vector<uint8_t> code_len; // host copy
     uint32_t* d_cbook = nullptr;
     uint32_t* d_dtab = nullptr;
+    uint64_t nzw = UINT64_MAX;     // non-zero Huffman words; UINT64_MAX: unknown
 };
 
 ResultInternal* ri(const sz_result* r) { return static_cast<ResultInternal*>(r->internal); }
@@ -658,9 +659,21 @@ double getd(const uint8_t* h, int off) { double v; std::memcpy(&v, h + off, 8); 
 
 uint64_t pad8(uint64_t b) { return (b + 7) & ~(uint64_t)7; }
 
-uint64_t blob_bytes(const sz_result* r, int R) {
+// Zero-word elision of the words section (the blob's de-redundancy step
+// after Huffman coding): a bitmap, bit k % 32 of bitmap word k / 32 set for
+// a non-zero word k, then the non-zero words in order; used when shorter.
+constexpr uint32_t kFlagWordsElided = 1;
+uint64_t elided_words(uint64_t n_words, uint64_t nzw) { return (n_words + 31) / 32 + nzw; }
+bool words_elided(const sz_result* r, const ResultInternal* R) {
+    return R->nzw != UINT64_MAX && elided_words(r->n_words, R->nzw) < r->n_words;
+}
+uint64_t words_section_bytes(const sz_result* r, const ResultInternal* R) {
+    return 4 * (words_elided(r, R) ? elided_words(r->n_words, R->nzw) : r->n_words);
+}
+
+uint64_t blob_bytes(const sz_result* r, int R, uint64_t words_bytes) {
     return 256 + pad8(r->n_anchors * 4) + pad8((uint64_t)2 * R) + pad8(r->n_chunks * 2) +
-           pad8(r->n_words * 4) + pad8(r->n_outliers * 4) + pad8(r->n_outliers * 4);
+           pad8(words_bytes) + pad8(r->n_outliers * 4) + pad8(r->n_outliers * 4);
 }
 
 // header without CRCs (they are filled by sz_serialize)
@@ -689,6 +702,7 @@ void make_header(const sz_result* r, const ResultInternal* R, uint8_t* h) {
         put32(h, 100 + 4 * k, used ? (uint32_t)R->plan.spline[k] : 0u);
         put32(h, 112 + 4 * k, used ? (uint32_t)R->plan.order[k] : 0xFFFFFFFFu);
     }
+    put32(h, 124, words_elided(r, R) ? kFlagWordsElided : 0u);
     for (int l = 0; l < 16; ++l) putf(h, 128 + 4 * l, l < R->plan.levels ? R->plan.el[l] : 0.0f);
     put64(h, 192, r->n_anchors);
     put64(h, 200, r->n_chunks);
@@ -1148,7 +1162,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     FieldDesc *d_fd, *d_hfd;
     FieldPlan* d_plan;
     float *d_pmin, *d_pmax;
-    uint32_t *d_pbad, *d_hist = nullptr;
+    uint32_t *d_pbad, *d_hist = nullptr, *d_nzw;
     uint64_t *d_items, *d_gboff, *d_bwoff, *d_booff;
     uint32_t *d_cwords, *d_couts, *d_bw, *d_bo;
     const size_t hstride = 2 * (size_t)max_R;   // graph mode: histogram k at d_hist + k * hstride
@@ -1166,6 +1180,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     const size_t o_bw = L.take<uint32_t>(std::max<uint64_t>(total_blocks, 1));
     const size_t o_bo = L.take<uint32_t>(std::max<uint64_t>(total_blocks, 1));
     const size_t o_bwoff = L.take<uint64_t>(nbw), o_booff = L.take<uint64_t>(nbw);
+    const size_t o_nzw = L.take<uint32_t>(nf);
     // host staging in pinned memory (copies from it are asynchronous): the
     // arena's layout, then each field's code lengths, codebook and decode
     // tables
@@ -1200,6 +1215,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         d_bo = reinterpret_cast<uint32_t*>(d + o_bo);
         d_bwoff = reinterpret_cast<uint64_t*>(d + o_bwoff);
         d_booff = reinterpret_cast<uint64_t*>(d + o_booff);
+        d_nzw = reinterpret_cast<uint32_t*>(d + o_nzw);
         for (uint32_t k = 0; k < nf; ++k) fds[k].hist = d_hist + k * hstride;
     } else if ((s = sc.get(nf, &d_fd)) || (s = sc.get(items.size(), &d_items)) ||
                (s = sc.get(nf, &d_plan)) || (s = sc.get((size_t)nf * kRangeBlocks, &d_pmin)) ||
@@ -1210,9 +1226,11 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
                (s = sc.get(std::max<uint64_t>(total_chunks, 1), &d_couts)) ||
                (s = sc.get(std::max<uint64_t>(total_blocks, 1), &d_bw)) ||
                (s = sc.get(std::max<uint64_t>(total_blocks, 1), &d_bo)) ||
-               (s = sc.get(nbw, &d_bwoff)) || (s = sc.get(nbw, &d_booff))) {
+               (s = sc.get(nbw, &d_bwoff)) || (s = sc.get(nbw, &d_booff)) ||
+               (s = sc.get(nf, &d_nzw))) {
         return s;
     }
+    for (uint32_t k = 0; k < nf; ++k) fds[k].nzw = d_nzw + k;
 
     // part 1: range, profile, plan (which also zeroes the histograms),
     // interpolation (with histogram)
@@ -1409,8 +1427,9 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         }
         return SZ_OK;
     };
-    // sync 2: block word offsets (small) to the host
+    // sync 2: block word offsets and non-zero word counts (small) to the host
     std::vector<uint64_t> bwoff(nbw);
+    std::vector<uint32_t> nzw(nf);
     if (c->graphs) {
         char* h = static_cast<char*>(c->parena);
         char* d = static_cast<char*>(c->arena);
@@ -1429,12 +1448,15 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
             if (r) return r;
             HIP_TRY(c, hipMemcpyAsync(h + o_bwoff, d + o_bwoff, sizeof(uint64_t) * nbw,
                                       hipMemcpyDeviceToHost, q));
+            HIP_TRY(c, hipMemcpyAsync(h + o_nzw, d + o_nzw, sizeof(uint32_t) * nf,
+                                      hipMemcpyDeviceToHost, q));
             return SZ_OK;
         });
         if (s) return s;
         HIP_TRY(c, hipStreamSynchronize(c->gstream));
         HIP_TRY(c, hipStreamSynchronize(st));
         std::memcpy(bwoff.data(), h + o_bwoff, sizeof(uint64_t) * nbw);
+        std::memcpy(nzw.data(), h + o_nzw, sizeof(uint32_t) * nf);
     } else {
         std::memcpy(hs + o_hfd, hfd.data(), sizeof(FieldDesc) * nf);
         std::memcpy(hs + o_gboff, gboff.data(), sizeof(uint64_t) * gboff.size());
@@ -1445,6 +1467,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         if ((s = enqueue2(st))) return s;
         HIP_TRY(c, hipMemcpyAsync(hs + o_bwoff, d_bwoff, sizeof(uint64_t) * nbw,
                                   hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipMemcpyAsync(hs + o_nzw, d_nzw, sizeof(uint32_t) * nf, hipMemcpyDeviceToHost, st));
         if (given) {
             HIP_TRY(c, hipMemcpyAsync(hs + o_plan, d_plan, sizeof(FieldPlan) * nf,
                                       hipMemcpyDeviceToHost, st));
@@ -1454,6 +1477,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         }
         HIP_TRY(c, hipStreamSynchronize(st));
         std::memcpy(bwoff.data(), hs + o_bwoff, sizeof(uint64_t) * nbw);
+        std::memcpy(nzw.data(), hs + o_nzw, sizeof(uint32_t) * nf);
         if (given) {
             std::memcpy(plans.data(), hs + o_plan, sizeof(FieldPlan) * nf);
             for (uint32_t k = 0; k < nf; ++k)
@@ -1485,11 +1509,15 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
                 std::memcpy(hs + o_hfd, hfd.data(), sizeof(FieldDesc) * nf);
                 HIP_TRY(c, hipMemcpyAsync(d_hfd, hs + o_hfd, sizeof(FieldDesc) * nf,
                                           hipMemcpyHostToDevice, st));
+                HIP_TRY(c, launch_fill_u32(d_nzw, nf, 0u, st));   // counted again
                 if ((s = enqueue2(st))) return s;
                 HIP_TRY(c, hipMemcpyAsync(hs + o_bwoff, d_bwoff, sizeof(uint64_t) * nbw,
                                           hipMemcpyDeviceToHost, st));
+                HIP_TRY(c, hipMemcpyAsync(hs + o_nzw, d_nzw, sizeof(uint32_t) * nf,
+                                          hipMemcpyDeviceToHost, st));
                 HIP_TRY(c, hipStreamSynchronize(st));
                 std::memcpy(bwoff.data(), hs + o_bwoff, sizeof(uint64_t) * nbw);
+                std::memcpy(nzw.data(), hs + o_nzw, sizeof(uint32_t) * nf);
             }
         }
     }
@@ -1505,7 +1533,9 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
                 return fail(c, SZ_ERR_DEVICE, "field %u: %llu Huffman words exceed the %llu sized "
                             "from the histogram", i, (unsigned long long)res[i].n_words,
                             (unsigned long long)fds[k].words_cap);
-            res[i].compressed_bytes = blob_bytes(&res[i], fds[k].R);
+            ri(&res[i])->nzw = nzw[k];
+            res[i].compressed_bytes =
+                blob_bytes(&res[i], fds[k].R, words_section_bytes(&res[i], ri(&res[i])));
             make_header(&res[i], ri(&res[i]), res[i].header);
         }
     }
@@ -1759,7 +1789,7 @@ sz_status sz_result_read(sz_ctx* c, const sz_result* r, int32_t section, void* d
 sz_status sz_serialize(sz_ctx* c, const sz_result* r, void* dst, uint64_t cap, uint64_t* written) {
     if (!c || !r || !r->internal) return fail(c, SZ_ERR_INVALID_ARG, "empty result");
     const ResultInternal* R = ri(r);
-    const uint64_t total = blob_bytes(r, R->R);
+    const uint64_t total = blob_bytes(r, R->R, words_section_bytes(r, R));
     if (written) *written = total;
     if (cap < total) return fail(c, SZ_ERR_CAPACITY, "blob needs %llu bytes", (unsigned long long)total);
     if (!dst) return fail(c, SZ_ERR_INVALID_ARG, "null destination");
@@ -1776,6 +1806,25 @@ sz_status sz_serialize(sz_ctx* c, const sz_result* r, void* dst, uint64_t cap, u
                  {r->outlier_idx, r->n_outliers * 4}, {r->outlier_val, r->n_outliers * 4}};
     uint64_t pos = 256;
     for (int k = 0; k < 6; ++k) {
+        if (k == 3 && words_elided(r, R)) {
+            // the words without their zero words: bitmap, then the others
+            std::vector<uint32_t> w(r->n_words);
+            HIP_TRY(c, hipMemcpy(w.data(), r->words, r->n_words * 4, hipMemcpyDeviceToHost));
+            const uint64_t nbm = (r->n_words + 31) / 32;
+            std::vector<uint32_t> sec(elided_words(r->n_words, R->nzw), 0u);
+            uint64_t o = nbm;
+            for (uint64_t j = 0; j < r->n_words; ++j)
+                if (w[j]) {
+                    if (o == sec.size()) return fail(c, SZ_ERR_DEVICE, "non-zero word count changed");
+                    sec[j / 32] |= 1u << (j % 32);
+                    sec[o++] = w[j];
+                }
+            if (o != sec.size()) return fail(c, SZ_ERR_DEVICE, "non-zero word count changed");
+            std::memcpy(out + pos, sec.data(), sec.size() * 4);
+            put32(h, 224 + 4 * k, crc32_update(0, out + pos, sec.size() * 4));
+            pos += pad8(sec.size() * 4);
+            continue;
+        }
         if (secs[k].bytes) HIP_TRY(c, hipMemcpy(out + pos, secs[k].src, secs[k].bytes, hipMemcpyDeviceToHost));
         put32(h, 224 + 4 * k, crc32_update(0, out + pos, secs[k].bytes));
         pos += pad8(secs[k].bytes);
@@ -1822,9 +1871,26 @@ sz_status sz_upload(sz_ctx* c, const void* blob, uint64_t bytes, void* stream, s
         r.n_words > (g.npts * kLmax) / 32 + g.nchunks + 1)
         return fail(c, SZ_ERR_CORRUPT, "header: section sizes");
     const int nsym = 2 * g.R;
-    if (blob_bytes(&r, g.R) != bytes) return fail(c, SZ_ERR_CORRUPT, "blob length %llu", (unsigned long long)bytes);
+    const uint32_t flags = get32(b, 124);
+    if ((flags & ~kFlagWordsElided) || get32(b, 248))
+        return fail(c, SZ_ERR_CORRUPT, "reserved header words are not zero");
+    const bool elided = flags & kFlagWordsElided;
+    // an elided words section: its bitmap tells how many words follow
+    uint64_t wsec = r.n_words, nzw = 0;
+    {
+        const uint64_t at = 256 + pad8(r.n_anchors * 4) + pad8((uint64_t)nsym) + pad8(r.n_chunks * 2);
+        const uint64_t nbm = (r.n_words + 31) / 32;
+        if (elided) {
+            if (at + 4 * nbm > bytes) return fail(c, SZ_ERR_CORRUPT, "blob length %llu", (unsigned long long)bytes);
+            for (uint64_t j = 0; j < nbm; ++j) nzw += (uint64_t)__builtin_popcount(get32(b + at, 4 * j));
+            wsec = nbm + nzw;
+            if (wsec >= r.n_words) return fail(c, SZ_ERR_CORRUPT, "elided words are not shorter");
+        }
+    }
+    if (blob_bytes(&r, g.R, 4 * wsec) != bytes)
+        return fail(c, SZ_ERR_CORRUPT, "blob length %llu", (unsigned long long)bytes);
     const uint64_t secb[6] = {r.n_anchors * 4, (uint64_t)nsym, r.n_chunks * 2,
-                              r.n_words * 4, r.n_outliers * 4, r.n_outliers * 4};
+                              wsec * 4, r.n_outliers * 4, r.n_outliers * 4};
     uint64_t off[6], pos = 256;
     for (int k = 0; k < 6; ++k) {
         off[k] = pos;
@@ -1834,8 +1900,24 @@ sz_status sz_upload(sz_ctx* c, const void* blob, uint64_t bytes, void* stream, s
             if (b[q]) return fail(c, SZ_ERR_CORRUPT, "section %d padding is not zero", k);
         pos += pad8(secb[k]);
     }
-    if (get32(b, 124) || get32(b, 248))
-        return fail(c, SZ_ERR_CORRUPT, "reserved header words are not zero");
+    // the raw words: the words section itself, or its zero words restored
+    std::vector<uint32_t> words_host;
+    const uint8_t* words_src = b + off[3];
+    if (elided) {
+        const uint64_t nbm = (r.n_words + 31) / 32;
+        words_host.assign(r.n_words, 0u);
+        uint64_t o = nbm;
+        for (uint64_t j = 0; j < nbm * 32; ++j) {
+            if (!((get32(b + off[3], 4 * (j / 32)) >> (j % 32)) & 1u)) continue;
+            const uint32_t v = get32(b + off[3], 4 * o++);
+            if (j >= r.n_words || v == 0)
+                return fail(c, SZ_ERR_CORRUPT, "elided words: bit past the end or a zero word");
+            words_host[j] = v;
+        }
+        words_src = reinterpret_cast<const uint8_t*>(words_host.data());
+    } else {
+        for (uint64_t j = 0; j < r.n_words; ++j) nzw += get32(b + off[3], 4 * j) != 0u;
+    }
     {
         // the chunk bit counts must account for exactly the stored words, and
         // outlier indices must lie inside the field
@@ -1860,6 +1942,7 @@ sz_status sz_upload(sz_ctx* c, const void* blob, uint64_t bytes, void* stream, s
     R->chunk = g.chunk;
     R->eb_mode = p.eb_mode;
     R->eb = p.eb;
+    R->nzw = nzw;
     R->code_len.assign(b + off[1], b + off[1] + nsym);
     if (!kraft_ok(R->code_len.data(), nsym) && r.n > 0) {
         release_result(c, &r);
@@ -1900,9 +1983,11 @@ sz_status sz_upload(sz_ctx* c, const void* blob, uint64_t bytes, void* stream, s
         return s;
     }
     void* dsts[6] = {r.anchors, r.code_len, r.chunk_bits, r.words, r.outlier_idx, r.outlier_val};
+    const uint64_t upb[6] = {secb[0], secb[1], secb[2], r.n_words * 4, secb[4], secb[5]};
     for (int k = 0; k < 6; ++k)
-        if (secb[k]) {
-            hipError_t e = hipMemcpyAsync(dsts[k], b + off[k], secb[k], hipMemcpyHostToDevice, st);
+        if (upb[k]) {
+            const uint8_t* src = k == 3 ? words_src : b + off[k];
+            hipError_t e = hipMemcpyAsync(dsts[k], src, upb[k], hipMemcpyHostToDevice, st);
             if (e != hipSuccess) {
                 release_result(c, &r);
                 return fail(c, SZ_ERR_DEVICE, "upload copy: %s", hipGetErrorString(e));

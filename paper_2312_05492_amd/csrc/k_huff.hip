@@ -299,8 +299,14 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
         }
         wave_lds_sync();
         const uint64_t ow = bw0 + (uint32_t)__builtin_amdgcn_readlane((int)pw, j);   // j is uniform
-        for (uint32_t k = lane; k < nw; k += 64)
-            if (ow + k < fd.words_cap) gp(fd.words)[ow + k] = wbuf[k];
+        uint32_t nz = 0;   // non-zero words, for the zero-word elision of the blob
+        for (uint32_t k = lane; k < nw; k += 64) {
+            const uint32_t w = wbuf[k];
+            nz += w != 0u;
+            if (ow + k < fd.words_cap) gp(fd.words)[ow + k] = w;
+        }
+        nz = wave_sum(nz);
+        if (lane == 0 && nz && fd.nzw) atomicAdd(fd.nzw, nz);
         wave_lds_sync();
     }
 }

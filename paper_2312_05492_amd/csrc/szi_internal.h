@@ -49,6 +49,7 @@ struct FieldDesc {
     uint32_t* outlier_idx;
     float* outlier_val;
     const uint32_t* dtab;  // decode tables (see DecodeTables layout)
+    uint32_t* nzw;         // count of non-zero Huffman words (encode; zeroed by the plan)
 };
 
 // One pass of the interpolation (Sec. V-A: levels from stride S/2 to 1, one

@@ -543,12 +543,44 @@ def test_blob_crc_detects_corruption_and_truncation():
         O.parse(bytes(b[:-8]))
 
 
-def test_compression_ratio_below_one_bit_ceiling():
-    # >= 1 bit per symbol plus 32 bits per anchor: CR <= 32 / (1 + 32/S^D)
+def _pad8n(b):
+    return b + (-b) % 8
+
+
+def test_huffman_stream_below_one_bit_ceiling():
+    # Huffman codes take >= 1 bit per symbol and anchors 32 bits: with the
+    # words stored as they are, CR <= 32 / (1 + 32/S^D)
     x = synth.bumps_field((64, 64, 64), seed=1)
     c = O.compress(x, O.Params(shape=x.shape, eb=1e-2))
-    cr = x.nbytes / len(c.blob())
+    assert 32 * c.words.size >= x.size
+    raw = (256 + _pad8n(4 * c.anchors.size) + _pad8n(c.code_len.size) +
+           _pad8n(2 * c.chunk_bits.size) + _pad8n(4 * c.words.size) +
+           2 * _pad8n(4 * c.outlier_idx.size))
+    cr = x.nbytes / raw
     assert 20 < cr < 32 / (1 + 32 / 512)
+    # the zero-word elision after Huffman coding goes below that floor,
+    # and the blob still decodes to the reconstruction
+    blob = c.blob()
+    assert O.parse(blob)["flags"] == O.FLAG_WORDS_ELIDED and len(blob) < raw
+    assert np.array_equal(O.decompress_blob(blob).view(np.uint32), c.recon.view(np.uint32))
+
+
+def test_zero_word_elision_layout():
+    # bit k % 32 of bitmap word k // 32 marks non-zero word k; the non-zero
+    # words follow in order; used only when shorter
+    w = np.zeros(100, dtype=np.uint32)
+    w[[0, 31, 32, 70, 99]] = [5, 6, 7, 8, 9]
+    e = O.elide_zero_words(w)
+    assert e.tolist() == [(1 << 0) | (1 << 31), 1, (1 << 6), (1 << 3), 5, 6, 7, 8, 9]
+    assert np.array_equal(O.restore_zero_words(e, 100), w)
+    assert O.elide_zero_words(np.arange(1, 40, dtype=np.uint32)) is None   # no zero word
+    assert O.elide_zero_words(np.zeros(0, dtype=np.uint32)) is None
+    one = np.zeros(33, dtype=np.uint32)
+    assert O.elide_zero_words(one).tolist() == [0, 0]                       # 2 < 33
+    with pytest.raises(O.OracleError):
+        O.restore_zero_words(np.array([0, 2], dtype=np.uint32), 33)          # bit past the end
+    with pytest.raises(O.OracleError):
+        O.restore_zero_words(np.array([1, 0, 0], dtype=np.uint32), 33)       # a zero listed
 
 
 def test_psnr_closed_form():
