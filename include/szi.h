@@ -276,7 +276,7 @@ sz_status sz_result_read(sz_ctx* ctx, const sz_result* res, int32_t section, voi
  *    88    12  f32 vmin, vmax, e (absolute bound, rounded down to FP32)
  *   100    12  i32 spline per dimension (0 linear, 1 NAK, 2 natural)
  *   112    12  i32 order (unused -1)
- *   124     4  reserved 0
+ *   124     4  u32 flags: bit 0 = words section zero-elided (below); other bits 0
  *   128    64  f32 e_l for l = 1..16 (l = 1 is stride 1; unused 0)
  *   192    32  u64 n_anchors, n_chunks, n_words, n_outliers
  *   224    24  u32 CRC-32 of each section (unpadded)
@@ -289,6 +289,12 @@ sz_status sz_result_read(sz_ctx* ctx, const sz_result* res, int32_t section, voi
  * [jC, min((j+1)C, n)), its codewords packed most-significant bit first
  * from bit 31 of its first word, zero-padded to a word; chunks follow each
  * other word-aligned.
+ * Zero-word elision (the de-redundancy step after Huffman coding, in the
+ * role Sec. VI-B gives a closed library): when it is shorter than the
+ * n_words words, the words section holds instead a bitmap of
+ * ceil(n_words / 32) u32 (bit k % 32 of bitmap word k / 32 set when word k
+ * is non-zero) followed by the non-zero words in order, and flags bit 0 is
+ * set.  n_words still counts all words.
  */
 
 /* ------------------------------------------------------------ serving

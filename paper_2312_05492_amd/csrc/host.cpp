@@ -1162,7 +1162,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     FieldDesc *d_fd, *d_hfd;
     FieldPlan* d_plan;
     float *d_pmin, *d_pmax;
-    uint32_t *d_pbad, *d_hist = nullptr, *d_nzw;
+    uint32_t *d_pbad, *d_hist = nullptr, *d_bnz;
     uint64_t *d_items, *d_gboff, *d_bwoff, *d_booff;
     uint32_t *d_cwords, *d_couts, *d_bw, *d_bo;
     const size_t hstride = 2 * (size_t)max_R;   // graph mode: histogram k at d_hist + k * hstride
@@ -1180,7 +1180,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     const size_t o_bw = L.take<uint32_t>(std::max<uint64_t>(total_blocks, 1));
     const size_t o_bo = L.take<uint32_t>(std::max<uint64_t>(total_blocks, 1));
     const size_t o_bwoff = L.take<uint64_t>(nbw), o_booff = L.take<uint64_t>(nbw);
-    const size_t o_nzw = L.take<uint32_t>(nf);
+    const size_t o_bnz = L.take<uint32_t>(std::max<uint64_t>(total_blocks, 1));
     // host staging in pinned memory (copies from it are asynchronous): the
     // arena's layout, then each field's code lengths, codebook and decode
     // tables
@@ -1215,7 +1215,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         d_bo = reinterpret_cast<uint32_t*>(d + o_bo);
         d_bwoff = reinterpret_cast<uint64_t*>(d + o_bwoff);
         d_booff = reinterpret_cast<uint64_t*>(d + o_booff);
-        d_nzw = reinterpret_cast<uint32_t*>(d + o_nzw);
+        d_bnz = reinterpret_cast<uint32_t*>(d + o_bnz);
         for (uint32_t k = 0; k < nf; ++k) fds[k].hist = d_hist + k * hstride;
     } else if ((s = sc.get(nf, &d_fd)) || (s = sc.get(items.size(), &d_items)) ||
                (s = sc.get(nf, &d_plan)) || (s = sc.get((size_t)nf * kRangeBlocks, &d_pmin)) ||
@@ -1227,10 +1227,9 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
                (s = sc.get(std::max<uint64_t>(total_blocks, 1), &d_bw)) ||
                (s = sc.get(std::max<uint64_t>(total_blocks, 1), &d_bo)) ||
                (s = sc.get(nbw, &d_bwoff)) || (s = sc.get(nbw, &d_booff)) ||
-               (s = sc.get(nf, &d_nzw))) {
+               (s = sc.get(std::max<uint64_t>(total_blocks, 1), &d_bnz))) {
         return s;
     }
-    for (uint32_t k = 0; k < nf; ++k) fds[k].nzw = d_nzw + k;
 
     // part 1: range, profile, plan (which also zeroes the histograms),
     // interpolation (with histogram)
@@ -1422,14 +1421,14 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
                 STAGE(c, SZ_STAGE_ENCODE, q);
                 HIP_TRY(c, launch_huff_encode(d_hfd + fs, (int)nfg, d_gboff + gboff_at[g], nb, chunk,
                                               d_cwords, d_couts, d_bwoff + goff_at[g],
-                                              d_booff + goff_at[g], 2 * max_R, q));
+                                              d_booff + goff_at[g], d_bnz + b0, 2 * max_R, q));
             }
         }
         return SZ_OK;
     };
     // sync 2: block word offsets and non-zero word counts (small) to the host
     std::vector<uint64_t> bwoff(nbw);
-    std::vector<uint32_t> nzw(nf);
+    std::vector<uint32_t> bnz(std::max<uint64_t>(total_blocks, 1));
     if (c->graphs) {
         char* h = static_cast<char*>(c->parena);
         char* d = static_cast<char*>(c->arena);
@@ -1448,7 +1447,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
             if (r) return r;
             HIP_TRY(c, hipMemcpyAsync(h + o_bwoff, d + o_bwoff, sizeof(uint64_t) * nbw,
                                       hipMemcpyDeviceToHost, q));
-            HIP_TRY(c, hipMemcpyAsync(h + o_nzw, d + o_nzw, sizeof(uint32_t) * nf,
+            HIP_TRY(c, hipMemcpyAsync(h + o_bnz, d + o_bnz, sizeof(uint32_t) * total_blocks,
                                       hipMemcpyDeviceToHost, q));
             return SZ_OK;
         });
@@ -1456,7 +1455,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         HIP_TRY(c, hipStreamSynchronize(c->gstream));
         HIP_TRY(c, hipStreamSynchronize(st));
         std::memcpy(bwoff.data(), h + o_bwoff, sizeof(uint64_t) * nbw);
-        std::memcpy(nzw.data(), h + o_nzw, sizeof(uint32_t) * nf);
+        std::memcpy(bnz.data(), h + o_bnz, sizeof(uint32_t) * total_blocks);
     } else {
         std::memcpy(hs + o_hfd, hfd.data(), sizeof(FieldDesc) * nf);
         std::memcpy(hs + o_gboff, gboff.data(), sizeof(uint64_t) * gboff.size());
@@ -1467,7 +1466,8 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         if ((s = enqueue2(st))) return s;
         HIP_TRY(c, hipMemcpyAsync(hs + o_bwoff, d_bwoff, sizeof(uint64_t) * nbw,
                                   hipMemcpyDeviceToHost, st));
-        HIP_TRY(c, hipMemcpyAsync(hs + o_nzw, d_nzw, sizeof(uint32_t) * nf, hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipMemcpyAsync(hs + o_bnz, d_bnz, sizeof(uint32_t) * total_blocks,
+                                  hipMemcpyDeviceToHost, st));
         if (given) {
             HIP_TRY(c, hipMemcpyAsync(hs + o_plan, d_plan, sizeof(FieldPlan) * nf,
                                       hipMemcpyDeviceToHost, st));
@@ -1477,7 +1477,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         }
         HIP_TRY(c, hipStreamSynchronize(st));
         std::memcpy(bwoff.data(), hs + o_bwoff, sizeof(uint64_t) * nbw);
-        std::memcpy(nzw.data(), hs + o_nzw, sizeof(uint32_t) * nf);
+        std::memcpy(bnz.data(), hs + o_bnz, sizeof(uint32_t) * total_blocks);
         if (given) {
             std::memcpy(plans.data(), hs + o_plan, sizeof(FieldPlan) * nf);
             for (uint32_t k = 0; k < nf; ++k)
@@ -1509,15 +1509,14 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
                 std::memcpy(hs + o_hfd, hfd.data(), sizeof(FieldDesc) * nf);
                 HIP_TRY(c, hipMemcpyAsync(d_hfd, hs + o_hfd, sizeof(FieldDesc) * nf,
                                           hipMemcpyHostToDevice, st));
-                HIP_TRY(c, launch_fill_u32(d_nzw, nf, 0u, st));   // counted again
                 if ((s = enqueue2(st))) return s;
                 HIP_TRY(c, hipMemcpyAsync(hs + o_bwoff, d_bwoff, sizeof(uint64_t) * nbw,
                                           hipMemcpyDeviceToHost, st));
-                HIP_TRY(c, hipMemcpyAsync(hs + o_nzw, d_nzw, sizeof(uint32_t) * nf,
+                HIP_TRY(c, hipMemcpyAsync(hs + o_bnz, d_bnz, sizeof(uint32_t) * total_blocks,
                                           hipMemcpyDeviceToHost, st));
                 HIP_TRY(c, hipStreamSynchronize(st));
                 std::memcpy(bwoff.data(), hs + o_bwoff, sizeof(uint64_t) * nbw);
-                std::memcpy(nzw.data(), hs + o_nzw, sizeof(uint32_t) * nf);
+                std::memcpy(bnz.data(), hs + o_bnz, sizeof(uint32_t) * total_blocks);
             }
         }
     }
@@ -1533,7 +1532,9 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
                 return fail(c, SZ_ERR_DEVICE, "field %u: %llu Huffman words exceed the %llu sized "
                             "from the histogram", i, (unsigned long long)res[i].n_words,
                             (unsigned long long)fds[k].words_cap);
-            ri(&res[i])->nzw = nzw[k];
+            uint64_t nz = 0;   // non-zero words of the field's encode blocks
+            for (uint64_t b = hboff[j]; b < hboff[j + 1]; ++b) nz += bnz[b];
+            ri(&res[i])->nzw = nz;
             res[i].compressed_bytes =
                 blob_bytes(&res[i], fds[k].R, words_section_bytes(&res[i], ri(&res[i])));
             make_header(&res[i], ri(&res[i]), res[i].header);

@@ -219,8 +219,10 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
                                                      const uint32_t* __restrict__ cwords,
                                                      const uint32_t* __restrict__ couts,
                                                      const uint64_t* __restrict__ bwoff,
-                                                     const uint64_t* __restrict__ booff) {
+                                                     const uint64_t* __restrict__ booff,
+                                                     uint32_t* __restrict__ bnz) {
     extern __shared__ uint32_t smem[];
+    __shared__ uint32_t wnz[4];
     constexpr int C = PER * 64;
     constexpr int MCW = (C * kLmax + 31) / 32 + 1;   // words of the longest chunk
     const int f = block_field(boff, nfields, blockIdx.x);
@@ -245,6 +247,7 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
     const uint32_t pw = wave_excl_scan(cw, &tw);
     const uint32_t po = wave_excl_scan(co, &to);
     __syncthreads();   // the code book is in LDS
+    uint32_t nz = 0;   // non-zero words written, for the zero-word elision of the blob
     for (int j = wave; j < kEncChunks; j += 4) {
         const uint64_t ch = first + j;
         if (ch >= fd.nchunks) break;   // uniform across the wave
@@ -299,16 +302,18 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
         }
         wave_lds_sync();
         const uint64_t ow = bw0 + (uint32_t)__builtin_amdgcn_readlane((int)pw, j);   // j is uniform
-        uint32_t nz = 0;   // non-zero words, for the zero-word elision of the blob
         for (uint32_t k = lane; k < nw; k += 64) {
             const uint32_t w = wbuf[k];
             nz += w != 0u;
             if (ow + k < fd.words_cap) gp(fd.words)[ow + k] = w;
         }
-        nz = wave_sum(nz);
-        if (lane == 0 && nz && fd.nzw) atomicAdd(fd.nzw, nz);
         wave_lds_sync();
     }
+    // one count per block (no atomics on a shared counter)
+    nz = wave_sum(nz);
+    if (lane == 0) wnz[wave] = nz;
+    __syncthreads();
+    if (threadIdx.x == 0) bnz[blockIdx.x] = wnz[0] + wnz[1] + wnz[2] + wnz[3];
 }
 
 // One lane decodes one chunk: canonical decode with a 2^kLutBits table of
@@ -525,16 +530,17 @@ hipError_t launch_scan_blocks(const uint32_t* d_a, const uint32_t* d_b, uint64_t
 hipError_t launch_huff_encode(const FieldDesc* d_fields, int nfields, const uint64_t* d_boff,
                               uint64_t nblocks, int chunk, const uint32_t* d_cwords,
                               const uint32_t* d_couts, const uint64_t* d_bwoff,
-                              const uint64_t* d_booff, int max_nsym, hipStream_t st) {
+                              const uint64_t* d_booff, uint32_t* d_bnz, int max_nsym,
+                              hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
     const int mcw = (chunk * kLmax + 31) / 32 + 1;
     const size_t lds = ((size_t)max_nsym + 4 * (size_t)mcw) * sizeof(uint32_t);
     const dim3 g((unsigned)nblocks), b(256);
     switch (chunk) {
-    case 256: hipLaunchKernelGGL(k_huff_encode<4>, g, b, lds, st, d_fields, nfields, d_boff, d_cwords, d_couts, d_bwoff, d_booff); break;
-    case 512: hipLaunchKernelGGL(k_huff_encode<8>, g, b, lds, st, d_fields, nfields, d_boff, d_cwords, d_couts, d_bwoff, d_booff); break;
-    case 1024: hipLaunchKernelGGL(k_huff_encode<16>, g, b, lds, st, d_fields, nfields, d_boff, d_cwords, d_couts, d_bwoff, d_booff); break;
-    case 2048: hipLaunchKernelGGL(k_huff_encode<32>, g, b, lds, st, d_fields, nfields, d_boff, d_cwords, d_couts, d_bwoff, d_booff); break;
+    case 256: hipLaunchKernelGGL(k_huff_encode<4>, g, b, lds, st, d_fields, nfields, d_boff, d_cwords, d_couts, d_bwoff, d_booff, d_bnz); break;
+    case 512: hipLaunchKernelGGL(k_huff_encode<8>, g, b, lds, st, d_fields, nfields, d_boff, d_cwords, d_couts, d_bwoff, d_booff, d_bnz); break;
+    case 1024: hipLaunchKernelGGL(k_huff_encode<16>, g, b, lds, st, d_fields, nfields, d_boff, d_cwords, d_couts, d_bwoff, d_booff, d_bnz); break;
+    case 2048: hipLaunchKernelGGL(k_huff_encode<32>, g, b, lds, st, d_fields, nfields, d_boff, d_cwords, d_couts, d_bwoff, d_booff, d_bnz); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -307,10 +307,8 @@ __global__ __launch_bounds__(256) void k_plan(const FieldDesc* __restrict__ F, F
         smx[threadIdx.x >> 6] = mx;
         sbad[threadIdx.x >> 6] = bad;
     }
-    // the histogram the interpolation accumulates, and the count of
-    // non-zero words the encoding accumulates, start at zero
+    // the histogram the interpolation accumulates starts at zero
     for (int b = threadIdx.x; b < 2 * f.R; b += blockDim.x) gp(f.hist)[b] = 0u;
-    if (threadIdx.x == 0 && f.nzw) *gp(f.nzw) = 0u;
     __syncthreads();
     if (threadIdx.x != 0) return;
     for (int k = 1; k < 4; ++k) {

@@ -49,7 +49,6 @@ struct FieldDesc {
     uint32_t* outlier_idx;
     float* outlier_val;
     const uint32_t* dtab;  // decode tables (see DecodeTables layout)
-    uint32_t* nzw;         // count of non-zero Huffman words (encode; zeroed by the plan)
 };
 
 // One pass of the interpolation (Sec. V-A: levels from stride S/2 to 1, one
@@ -145,10 +144,12 @@ hipError_t launch_huff_stats(const FieldDesc* d_fields, int nfields, const uint6
                              uint32_t* d_bw, uint32_t* d_bo, int max_nsym, hipStream_t st);
 hipError_t launch_scan_blocks(const uint32_t* d_a, const uint32_t* d_b, uint64_t n,
                               uint64_t* d_aoff, uint64_t* d_boff, hipStream_t st);
+// d_bnz: per encode block, the number of non-zero words it wrote
 hipError_t launch_huff_encode(const FieldDesc* d_fields, int nfields, const uint64_t* d_boff,
                               uint64_t nblocks, int chunk, const uint32_t* d_cwords,
                               const uint32_t* d_couts, const uint64_t* d_bwoff,
-                              const uint64_t* d_booff, int max_nsym, hipStream_t st);
+                              const uint64_t* d_booff, uint32_t* d_bnz, int max_nsym,
+                              hipStream_t st);
 // d_bsum: the word count of every decode block (launch_dec_prep)
 hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields, const uint64_t* d_dboff,
                               uint64_t nblocks, const uint32_t* d_bsum, int max_nsym,
