@@ -422,8 +422,9 @@ def main():
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], n, args.pmc_command, TRAFFIC_FILE)
         return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; the compressor's path is single-GPU "
-              "(see the sharding note in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py: measures one GPU only (windows are independent, so a field would "
+              "shard into slabs with one borrowed plane each, which is not built); "
+              "run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
