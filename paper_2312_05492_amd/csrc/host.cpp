@@ -671,6 +671,13 @@ uint64_t words_section_bytes(const sz_result* r, const ResultInternal* R) {
     return 4 * (words_elided(r, R) ? elided_words(r->n_words, R->nzw) : r->n_words);
 }
 
+// A result's code tables in one device block, laid out like their host
+// staging: code lengths (nsym bytes, padded to 16), codebook, decode tables.
+size_t tables_len_bytes(int nsym) { return ((size_t)nsym + 15) & ~(size_t)15; }
+size_t tables_bytes(int nsym) {
+    return tables_len_bytes(nsym) + 4 * (size_t)nsym + 4 * (size_t)dtab_words(nsym);
+}
+
 uint64_t blob_bytes(const sz_result* r, int R, uint64_t words_bytes) {
     return 256 + pad8(r->n_anchors * 4) + pad8((uint64_t)2 * R) + pad8(r->n_chunks * 2) +
            pad8(words_bytes) + pad8(r->n_outliers * 4) + pad8(r->n_outliers * 4);
@@ -1084,9 +1091,11 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         if ((s = res_alloc(c, R, geo[i].nanch, &res[i].anchors))) return s;
         if ((s = res_alloc(c, R, geo[i].npts, &res[i].codes))) return s;
         if ((s = res_alloc(c, R, nsym, &res[i].hist))) return s;
-        if ((s = res_alloc(c, R, nsym, &res[i].code_len))) return s;
-        if ((s = res_alloc(c, R, nsym, &R->d_cbook))) return s;
-        if ((s = res_alloc(c, R, dtab_words(nsym), &R->d_dtab))) return s;
+        uint8_t* tabs;   // code lengths, codebook and decode tables together
+        if ((s = res_alloc(c, R, tables_bytes(nsym), &tabs))) return s;
+        res[i].code_len = tabs;
+        R->d_cbook = reinterpret_cast<uint32_t*>(tabs + tables_len_bytes(nsym));
+        R->d_dtab = R->d_cbook + nsym;
         if ((s = res_alloc(c, R, geo[i].nchunks, &res[i].chunk_bits))) return s;
         res[i].n = geo[i].npts;
         res[i].n_anchors = geo[i].nanch;
@@ -1188,7 +1197,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     o_cb[0] = (L.off + 255) & ~(size_t)255;
     for (uint32_t k = 0; k < nf; ++k) {
         const size_t nsym = 2 * (size_t)fds[k].R;
-        o_cb[k + 1] = o_cb[k] + ((nsym + 4 * nsym + 4 * (size_t)dtab_words((int)nsym) + 255) & ~(size_t)255);
+        o_cb[k + 1] = o_cb[k] + ((tables_bytes((int)nsym) + 255) & ~(size_t)255);
     }
     char* hs;   // the staging base
     if (graphs) {
@@ -1350,7 +1359,10 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     // with a given code book the words take their largest size and the
     // outlier lists a guess that the end checks
     auto outlier_guess = [](uint64_t n) { return std::min<uint64_t>(n, std::max<uint64_t>(n / 32, 4096)); };
-    for (uint32_t k = 0; k < nf; ++k) {
+    // the code books and tables of the fields are independent: a batch
+    // spreads them over a few host threads (about 35 us each at 2R = 1024)
+    std::vector<uint64_t> wbits(nf);
+    auto make_codes = [&](uint32_t k) {
         const uint32_t i = perm[k];
         ResultInternal* R = ri(&res[i]);
         const int nsym = 2 * fds[k].R;
@@ -1362,17 +1374,38 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
             huffman_lengths(hist[k].data(), nsym, kLmax, R->code_len.data());
         }
         uint8_t* h_len = reinterpret_cast<uint8_t*>(hs + o_cb[k]);
-        uint32_t* h_cbook = reinterpret_cast<uint32_t*>(h_len + nsym);
-        uint32_t* h_dtab = h_cbook + nsym;
+        uint32_t* h_cbook = reinterpret_cast<uint32_t*>(h_len + tables_len_bytes(nsym));
+        std::memset(h_len, 0, tables_len_bytes(nsym));
         std::memcpy(h_len, R->code_len.data(), nsym);
-        build_tables(R->code_len.data(), nsym, h_cbook, h_dtab);
+        build_tables(R->code_len.data(), nsym, h_cbook, h_cbook + nsym);
         uint64_t bits = 0;
         if (given)
             bits = geo[i].npts * (uint64_t)kLmax;
         else
             for (int sy = 0; sy < nsym; ++sy) bits += (uint64_t)hist[k][sy] * R->code_len[sy];
+        wbits[k] = bits;
+    };
+    {
+        const uint32_t nt = std::min<uint32_t>(nf / 2, 8);
+        if (nt >= 2) {
+            std::vector<std::thread> th;
+            for (uint32_t t = 1; t < nt; ++t)
+                th.emplace_back([&, t] {
+                    for (uint32_t k = t; k < nf; k += nt) make_codes(k);
+                });
+            for (uint32_t k = 0; k < nf; k += nt) make_codes(k);
+            for (auto& x : th) x.join();
+        } else {
+            for (uint32_t k = 0; k < nf; ++k) make_codes(k);
+        }
+    }
+    for (uint32_t k = 0; k < nf; ++k) {
+        const uint32_t i = perm[k];
+        ResultInternal* R = ri(&res[i]);
+        const int nsym = 2 * fds[k].R;
+        const uint8_t* h_tabs = reinterpret_cast<const uint8_t*>(hs + o_cb[k]);
         const uint64_t nout = given ? outlier_guess(geo[i].npts) : hist[k][0];
-        const uint64_t wcap = bits / 32 + geo[i].nchunks + 1;
+        const uint64_t wcap = wbits[k] / 32 + geo[i].nchunks + 1;
         if ((s = res_alloc(c, R, wcap + kWordPad, &res[i].words))) return s;
         if ((s = res_alloc(c, R, std::max<uint64_t>(nout, 1), &res[i].outlier_idx))) return s;
         if ((s = res_alloc(c, R, std::max<uint64_t>(nout, 1), &res[i].outlier_val))) return s;
@@ -1386,10 +1419,8 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         if (graphs)   // the result keeps its own histogram
             HIP_TRY(c, hipMemcpyAsync(res[i].hist, fds[k].hist, sizeof(uint32_t) * nsym,
                                       hipMemcpyDeviceToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(res[i].code_len, h_len, nsym, hipMemcpyHostToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(R->d_cbook, h_cbook, sizeof(uint32_t) * nsym,
-                                  hipMemcpyHostToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(R->d_dtab, h_dtab, sizeof(uint32_t) * dtab_words(nsym),
+        // lengths, codebook and decode tables in one copy
+        HIP_TRY(c, hipMemcpyAsync(res[i].code_len, h_tabs, tables_bytes(nsym),
                                   hipMemcpyHostToDevice, st));
     }
     std::vector<FieldDesc> hfd(nf);
