@@ -1386,18 +1386,23 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         wbits[k] = bits;
     };
     {
-        const uint32_t nt = std::min<uint32_t>(nf / 2, 8);
-        if (nt >= 2) {
-            std::vector<std::thread> th;
-            for (uint32_t t = 1; t < nt; ++t)
+        // field k goes to thread k % nt; fields of threads that could not be
+        // started run here
+        const uint32_t nt = std::max<uint32_t>(1, std::min<uint32_t>(nf / 2, 8));
+        std::vector<std::thread> th;
+        uint32_t started = 1;
+        for (uint32_t t = 1; t < nt; ++t, ++started) {
+            try {
                 th.emplace_back([&, t] {
                     for (uint32_t k = t; k < nf; k += nt) make_codes(k);
                 });
-            for (uint32_t k = 0; k < nf; k += nt) make_codes(k);
-            for (auto& x : th) x.join();
-        } else {
-            for (uint32_t k = 0; k < nf; ++k) make_codes(k);
+            } catch (...) {
+                break;
+            }
         }
+        for (uint32_t k = 0; k < nf; ++k)
+            if (k % nt == 0 || k % nt >= started) make_codes(k);
+        for (auto& x : th) x.join();
     }
     for (uint32_t k = 0; k < nf; ++k) {
         const uint32_t i = perm[k];
