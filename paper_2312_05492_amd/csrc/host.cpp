@@ -1226,19 +1226,29 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         d_booff = reinterpret_cast<uint64_t*>(d + o_booff);
         d_bnz = reinterpret_cast<uint32_t*>(d + o_bnz);
         for (uint32_t k = 0; k < nf; ++k) fds[k].hist = d_hist + k * hstride;
-    } else if ((s = sc.get(nf, &d_fd)) || (s = sc.get(items.size(), &d_items)) ||
-               (s = sc.get(nf, &d_plan)) || (s = sc.get((size_t)nf * kRangeBlocks, &d_pmin)) ||
-               (s = sc.get((size_t)nf * kRangeBlocks, &d_pmax)) ||
-               (s = sc.get((size_t)nf * kRangeBlocks, &d_pbad)) || (s = sc.get(nf, &d_hfd)) ||
-               (s = sc.get(gboff.size(), &d_gboff)) ||
-               (s = sc.get(std::max<uint64_t>(total_chunks, 1), &d_cwords)) ||
-               (s = sc.get(std::max<uint64_t>(total_chunks, 1), &d_couts)) ||
-               (s = sc.get(std::max<uint64_t>(total_blocks, 1), &d_bw)) ||
-               (s = sc.get(std::max<uint64_t>(total_blocks, 1), &d_bo)) ||
-               (s = sc.get(nbw, &d_bwoff)) || (s = sc.get(nbw, &d_booff)) ||
-               (s = sc.get(std::max<uint64_t>(total_blocks, 1), &d_bnz))) {
-        return s;
+    } else {
+        // one scratch block in the arena's layout, so that the staged
+        // regions go over in one copy each (the histograms stay in the results)
+        char* d;
+        if ((s = sc.get(L.off, &d))) return s;
+        d_fd = reinterpret_cast<FieldDesc*>(d + o_fd);
+        d_items = reinterpret_cast<uint64_t*>(d + o_items);
+        d_plan = reinterpret_cast<FieldPlan*>(d + o_plan);
+        d_pmin = reinterpret_cast<float*>(d + o_pmin);
+        d_pmax = reinterpret_cast<float*>(d + o_pmax);
+        d_pbad = reinterpret_cast<uint32_t*>(d + o_pbad);
+        d_hfd = reinterpret_cast<FieldDesc*>(d + o_hfd);
+        d_gboff = reinterpret_cast<uint64_t*>(d + o_gboff);
+        d_cwords = reinterpret_cast<uint32_t*>(d + o_cwords);
+        d_couts = reinterpret_cast<uint32_t*>(d + o_couts);
+        d_bw = reinterpret_cast<uint32_t*>(d + o_bw);
+        d_bo = reinterpret_cast<uint32_t*>(d + o_bo);
+        d_bwoff = reinterpret_cast<uint64_t*>(d + o_bwoff);
+        d_booff = reinterpret_cast<uint64_t*>(d + o_booff);
+        d_bnz = reinterpret_cast<uint32_t*>(d + o_bnz);
     }
+    // the offsets and per-block counts read back at the end, one region
+    const size_t o_back = o_bwoff, n_back = o_bnz + sizeof(uint32_t) * total_blocks - o_bwoff;
 
     // part 1: range, profile, plan (which also zeroes the histograms),
     // interpolation (with histogram)
@@ -1271,9 +1281,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         // no round trip: part 1 now, its plans and histograms read at the end
         std::memcpy(hs + o_fd, fds.data(), sizeof(FieldDesc) * nf);
         std::memcpy(hs + o_items, items.data(), sizeof(uint64_t) * items.size());
-        HIP_TRY(c, hipMemcpyAsync(d_fd, hs + o_fd, sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(d_items, hs + o_items, sizeof(uint64_t) * items.size(),
-                                  hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(d_fd, hs + o_fd, end1 - o_fd, hipMemcpyHostToDevice, st));
         if ((s = enqueue1(st))) return s;
     } else if (c->graphs) {
         char* h = static_cast<char*>(c->parena);
@@ -1302,9 +1310,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     } else {
         std::memcpy(hs + o_fd, fds.data(), sizeof(FieldDesc) * nf);
         std::memcpy(hs + o_items, items.data(), sizeof(uint64_t) * items.size());
-        HIP_TRY(c, hipMemcpyAsync(d_fd, hs + o_fd, sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(d_items, hs + o_items, sizeof(uint64_t) * items.size(),
-                                  hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(d_fd, hs + o_fd, end1 - o_fd, hipMemcpyHostToDevice, st));
         if ((s = enqueue1(st))) return s;
         HIP_TRY(c, hipMemcpyAsync(hs + o_plan, d_plan, sizeof(FieldPlan) * nf, hipMemcpyDeviceToHost,
                                   st));
@@ -1495,15 +1501,10 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     } else {
         std::memcpy(hs + o_hfd, hfd.data(), sizeof(FieldDesc) * nf);
         std::memcpy(hs + o_gboff, gboff.data(), sizeof(uint64_t) * gboff.size());
-        HIP_TRY(c, hipMemcpyAsync(d_hfd, hs + o_hfd, sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(d_gboff, hs + o_gboff, sizeof(uint64_t) * gboff.size(),
-                                  hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(d_hfd, hs + o_hfd, end2 - o_hfd, hipMemcpyHostToDevice, st));
         cb_mark.reset();
         if ((s = enqueue2(st))) return s;
-        HIP_TRY(c, hipMemcpyAsync(hs + o_bwoff, d_bwoff, sizeof(uint64_t) * nbw,
-                                  hipMemcpyDeviceToHost, st));
-        HIP_TRY(c, hipMemcpyAsync(hs + o_bnz, d_bnz, sizeof(uint32_t) * total_blocks,
-                                  hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipMemcpyAsync(hs + o_back, d_bwoff, n_back, hipMemcpyDeviceToHost, st));
         if (given) {
             HIP_TRY(c, hipMemcpyAsync(hs + o_plan, d_plan, sizeof(FieldPlan) * nf,
                                       hipMemcpyDeviceToHost, st));
@@ -1546,10 +1547,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
                 HIP_TRY(c, hipMemcpyAsync(d_hfd, hs + o_hfd, sizeof(FieldDesc) * nf,
                                           hipMemcpyHostToDevice, st));
                 if ((s = enqueue2(st))) return s;
-                HIP_TRY(c, hipMemcpyAsync(hs + o_bwoff, d_bwoff, sizeof(uint64_t) * nbw,
-                                          hipMemcpyDeviceToHost, st));
-                HIP_TRY(c, hipMemcpyAsync(hs + o_bnz, d_bnz, sizeof(uint32_t) * total_blocks,
-                                          hipMemcpyDeviceToHost, st));
+                HIP_TRY(c, hipMemcpyAsync(hs + o_back, d_bwoff, n_back, hipMemcpyDeviceToHost, st));
                 HIP_TRY(c, hipStreamSynchronize(st));
                 std::memcpy(bwoff.data(), hs + o_bwoff, sizeof(uint64_t) * nbw);
                 std::memcpy(bnz.data(), hs + o_bnz, sizeof(uint32_t) * total_blocks);
@@ -1742,26 +1740,28 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         HIP_TRY(c, hipStreamSynchronize(c->gstream));
         return SZ_OK;
     }
-    if ((s = sc.get(nf, &d_fd)) || (s = sc.get(nf, &d_plan)) || (s = sc.get(items.size(), &d_items)) ||
-        (s = sc.get(nf + 1, &d_dboff)) || (s = sc.get(std::max<uint64_t>(nblocks, 1), &d_bsum)))
-        return s;
-    // descriptors staged in pinned memory, one asynchronous copy each
+    // descriptors staged in pinned memory and sent in one asynchronous copy
+    // to one scratch block of the same layout
     {
         Layout L;
         const size_t o_fd = L.take<FieldDesc>(nf), o_plan = L.take<FieldPlan>(nf);
         const size_t o_items = L.take<uint64_t>(items.size()), o_dboff = L.take<uint64_t>(nf + 1);
-        if ((s = pinned_reserve(c, L.off))) return s;
+        const size_t staged = L.off;
+        const size_t o_bsum = L.take<uint32_t>(std::max<uint64_t>(nblocks, 1));
+        char* d;
+        if ((s = sc.get(L.off, &d))) return s;
+        if ((s = pinned_reserve(c, staged))) return s;
+        d_fd = reinterpret_cast<FieldDesc*>(d + o_fd);
+        d_plan = reinterpret_cast<FieldPlan*>(d + o_plan);
+        d_items = reinterpret_cast<uint64_t*>(d + o_items);
+        d_dboff = reinterpret_cast<uint64_t*>(d + o_dboff);
+        d_bsum = reinterpret_cast<uint32_t*>(d + o_bsum);
         char* h = static_cast<char*>(c->pinned);
         std::memcpy(h + o_fd, fds.data(), sizeof(FieldDesc) * nf);
         std::memcpy(h + o_plan, plans.data(), sizeof(FieldPlan) * nf);
         std::memcpy(h + o_items, items.data(), sizeof(uint64_t) * items.size());
         std::memcpy(h + o_dboff, dboff.data(), sizeof(uint64_t) * (nf + 1));
-        HIP_TRY(c, hipMemcpyAsync(d_fd, h + o_fd, sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(d_plan, h + o_plan, sizeof(FieldPlan) * nf, hipMemcpyHostToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(d_items, h + o_items, sizeof(uint64_t) * items.size(),
-                                  hipMemcpyHostToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(d_dboff, h + o_dboff, sizeof(uint64_t) * (nf + 1),
-                                  hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(d, h, staged, hipMemcpyHostToDevice, st));
     }
     if ((s = enqueue(st))) return s;
     // launch-shape tuning: the replay rewrites the same values
