@@ -1172,6 +1172,8 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     FieldPlan* d_plan;
     float *d_pmin, *d_pmax;
     uint32_t *d_pbad, *d_hist = nullptr, *d_bnz;
+    char* d_scr = nullptr;   // the plain calls' scratch block
+    const bool many = !graphs && nf >= 2;   // batch: gathered histograms, scattered tables
     uint64_t *d_items, *d_gboff, *d_bwoff, *d_booff;
     uint32_t *d_cwords, *d_couts, *d_bw, *d_bo;
     const size_t hstride = 2 * (size_t)max_R;   // graph mode: histogram k at d_hist + k * hstride
@@ -1228,9 +1230,12 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         for (uint32_t k = 0; k < nf; ++k) fds[k].hist = d_hist + k * hstride;
     } else {
         // one scratch block in the arena's layout, so that the staged
-        // regions go over in one copy each (the histograms stay in the results)
+        // regions go over in one copy each (the histograms stay in the
+        // results; a batch gathers them into the block to read them back,
+        // and scatters its staged code tables from the block)
         char* d;
-        if ((s = sc.get(L.off, &d))) return s;
+        if ((s = sc.get(o_cb[nf], &d))) return s;
+        d_scr = d;
         d_fd = reinterpret_cast<FieldDesc*>(d + o_fd);
         d_items = reinterpret_cast<uint64_t*>(d + o_items);
         d_plan = reinterpret_cast<FieldPlan*>(d + o_plan);
@@ -1273,6 +1278,22 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         }
         return SZ_OK;
     };
+    // plans and histograms to the staging (plain calls): a batch gathers
+    // its histograms next to the plans and reads both in one copy
+    auto read_plans_hists = [&](hipStream_t q) -> sz_status {
+        if (many) {
+            HIP_TRY(c, launch_gather_hist(d_fd, (int)nf, reinterpret_cast<uint32_t*>(d_scr + o_hist),
+                                          (uint32_t)hstride, q));
+            HIP_TRY(c, hipMemcpyAsync(hs + o_plan, d_plan, o_hist + sizeof(uint32_t) * nf * hstride - o_plan,
+                                      hipMemcpyDeviceToHost, q));
+            return SZ_OK;
+        }
+        HIP_TRY(c, hipMemcpyAsync(hs + o_plan, d_plan, sizeof(FieldPlan) * nf, hipMemcpyDeviceToHost, q));
+        for (uint32_t k = 0; k < nf; ++k)
+            HIP_TRY(c, hipMemcpyAsync(hs + o_hist + sizeof(uint32_t) * k * hstride, fds[k].hist,
+                                      sizeof(uint32_t) * 2 * fds[k].R, hipMemcpyDeviceToHost, q));
+        return SZ_OK;
+    };
     // sync 1: plans and histograms to the host
     std::vector<FieldPlan> plans(nf);
     std::vector<std::vector<uint32_t>> hist(nf);
@@ -1312,11 +1333,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         std::memcpy(hs + o_items, items.data(), sizeof(uint64_t) * items.size());
         HIP_TRY(c, hipMemcpyAsync(d_fd, hs + o_fd, end1 - o_fd, hipMemcpyHostToDevice, st));
         if ((s = enqueue1(st))) return s;
-        HIP_TRY(c, hipMemcpyAsync(hs + o_plan, d_plan, sizeof(FieldPlan) * nf, hipMemcpyDeviceToHost,
-                                  st));
-        for (uint32_t k = 0; k < nf; ++k)
-            HIP_TRY(c, hipMemcpyAsync(hs + o_hist + sizeof(uint32_t) * k * hstride, fds[k].hist,
-                                      sizeof(uint32_t) * hist[k].size(), hipMemcpyDeviceToHost, st));
+        if ((s = read_plans_hists(st))) return s;
         HIP_TRY(c, hipStreamSynchronize(st));
         std::memcpy(plans.data(), hs + o_plan, sizeof(FieldPlan) * nf);
         for (uint32_t k = 0; k < nf; ++k)
@@ -1430,10 +1447,16 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         if (graphs)   // the result keeps its own histogram
             HIP_TRY(c, hipMemcpyAsync(res[i].hist, fds[k].hist, sizeof(uint32_t) * nsym,
                                       hipMemcpyDeviceToDevice, st));
-        // lengths, codebook and decode tables in one copy
-        HIP_TRY(c, hipMemcpyAsync(res[i].code_len, h_tabs, tables_bytes(nsym),
-                                  hipMemcpyHostToDevice, st));
+        // lengths, codebook and decode tables in one copy (a batch's in one
+        // copy for all fields and a scatter)
+        fds[k].tab_src = o_cb[k] - o_cb[0];
+        if (!many)
+            HIP_TRY(c, hipMemcpyAsync(res[i].code_len, h_tabs, tables_bytes(nsym),
+                                      hipMemcpyHostToDevice, st));
     }
+    if (many)
+        HIP_TRY(c, hipMemcpyAsync(d_scr + o_cb[0], hs + o_cb[0], o_cb[nf] - o_cb[0],
+                                  hipMemcpyHostToDevice, st));
     std::vector<FieldDesc> hfd(nf);
     {
         uint64_t cb = 0;
@@ -1502,16 +1525,11 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         std::memcpy(hs + o_hfd, hfd.data(), sizeof(FieldDesc) * nf);
         std::memcpy(hs + o_gboff, gboff.data(), sizeof(uint64_t) * gboff.size());
         HIP_TRY(c, hipMemcpyAsync(d_hfd, hs + o_hfd, end2 - o_hfd, hipMemcpyHostToDevice, st));
+        if (many) HIP_TRY(c, launch_scatter_tables(d_hfd, (int)nf, reinterpret_cast<const uint8_t*>(d_scr + o_cb[0]), st));
         cb_mark.reset();
         if ((s = enqueue2(st))) return s;
         HIP_TRY(c, hipMemcpyAsync(hs + o_back, d_bwoff, n_back, hipMemcpyDeviceToHost, st));
-        if (given) {
-            HIP_TRY(c, hipMemcpyAsync(hs + o_plan, d_plan, sizeof(FieldPlan) * nf,
-                                      hipMemcpyDeviceToHost, st));
-            for (uint32_t k = 0; k < nf; ++k)
-                HIP_TRY(c, hipMemcpyAsync(hs + o_hist + sizeof(uint32_t) * k * hstride, fds[k].hist,
-                                          sizeof(uint32_t) * hist[k].size(), hipMemcpyDeviceToHost, st));
-        }
+        if (given && (s = read_plans_hists(st))) return s;
         HIP_TRY(c, hipStreamSynchronize(st));
         std::memcpy(bwoff.data(), hs + o_bwoff, sizeof(uint64_t) * nbw);
         std::memcpy(bnz.data(), hs + o_bnz, sizeof(uint32_t) * total_blocks);

@@ -393,6 +393,26 @@ __global__ void k_zero_hist(const FieldDesc* __restrict__ F) {
         gp(f.hist)[b] = 0u;
 }
 
+// one workgroup per field: its histogram to dst + f * stride
+__global__ void k_gather_hist(const FieldDesc* __restrict__ F, uint32_t* dst, uint32_t stride) {
+    const FieldDesc& f = F[blockIdx.x];
+    for (int b = threadIdx.x; b < 2 * f.R; b += blockDim.x)
+        dst[(uint64_t)blockIdx.x * stride + b] = gp(f.hist)[b];
+}
+
+// one workgroup per field: its code lengths (padded to 16 bytes), codebook
+// and decode tables, staged together at src + tab_src, to the block that
+// holds them (the padded lengths end where cbook starts)
+__global__ void k_scatter_tables(const FieldDesc* __restrict__ F, const uint8_t* __restrict__ src) {
+    const FieldDesc& f = F[blockIdx.x];
+    const int nsym = 2 * f.R;
+    const uint32_t lenw = (uint32_t)((nsym + 15) & ~15) / 4;
+    const uint32_t words = lenw + (uint32_t)nsym + (uint32_t)dtab_words(nsym);
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(src + f.tab_src);
+    uint32_t* d = const_cast<uint32_t*>(f.cbook) - lenw;
+    for (uint32_t k = threadIdx.x; k < words; k += blockDim.x) gp(d)[k] = gp(s)[k];
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
@@ -428,6 +448,20 @@ hipError_t launch_dec_prep(const FieldDesc* d_fields, FieldPlan* d_plans, int nf
     if (nblocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_dec_prep, dim3((unsigned)nblocks), dim3(kDecBlockChunks), 0, st, d_fields,
                        d_plans, nfields, d_dboff, d_bsum);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_hist(const FieldDesc* d_fields, int nfields, uint32_t* dst,
+                              uint32_t stride, hipStream_t st) {
+    if (nfields <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_hist, dim3((unsigned)nfields), dim3(256), 0, st, d_fields, dst, stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_tables(const FieldDesc* d_fields, int nfields, const uint8_t* src,
+                                 hipStream_t st) {
+    if (nfields <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_tables, dim3((unsigned)nfields), dim3(256), 0, st, d_fields, src);
     return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ struct FieldDesc {
     double alpha_req;
     uint64_t npts;
     uint64_t chunk_base;   // first chunk of this field in a batch
+    uint64_t tab_src;      // its code tables' offset in a batch's staged table region
     uint64_t nchunks;
     uint64_t n_outliers;
     uint64_t words_cap;    // capacity of words (encode)
@@ -124,6 +125,13 @@ hipError_t launch_dec_prep(const FieldDesc* d_fields, FieldPlan* d_plans, int nf
                            const uint64_t* d_dboff, uint64_t nblocks, uint32_t* d_bsum,
                            hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
+// batches: every field's histogram into dst + f * stride, and every field's
+// code tables from the staged region src (at tab_src) to its table block
+// (the 16-byte-padded lengths before cbook)
+hipError_t launch_gather_hist(const FieldDesc* d_fields, int nfields, uint32_t* dst,
+                              uint32_t stride, hipStream_t st);
+hipError_t launch_scatter_tables(const FieldDesc* d_fields, int nfields, const uint8_t* src,
+                                 hipStream_t st);
 // Launch shape of a window kernel; every shape gives the same results.
 // variant 0: compiled for three waves per SIMD (168 VGPRs); variant 1: for
 // four (128 VGPRs; 2D only, whose smaller blocks leave LDS for 16 windows
