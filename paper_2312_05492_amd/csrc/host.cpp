@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <cstring>
 #include <array>
+#include <atomic>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -25,6 +27,72 @@
 using namespace szi;
 
 // ------------------------------------------------------------ context
+// Host worker threads that a context keeps for per-field host work of a
+// batch (code books).  run(n, f) calls f(0..n-1) on the workers and the
+// calling thread and returns when all calls have returned.  A worker takes
+// a job's function and count under the lock and is counted busy until it
+// is done with it, so run() never returns while a worker may still call f.
+struct HostPool {
+    std::vector<std::thread> th;
+    std::mutex m;
+    std::condition_variable cv, cv_done;
+    const std::function<void(uint32_t)>* job = nullptr;
+    uint32_t count = 0, busy = 0;
+    uint64_t gen = 0;
+    bool stop = false;
+    std::atomic<uint32_t> next{0};
+
+    explicit HostPool(int workers) {
+        for (int t = 0; t < workers; ++t) {
+            try {
+                th.emplace_back([this] { work(); });
+            } catch (...) {
+                break;   // fewer workers; the caller does the rest
+            }
+        }
+    }
+    ~HostPool() {
+        {
+            std::lock_guard<std::mutex> lk(m);
+            stop = true;
+        }
+        cv.notify_all();
+        for (auto& t : th) t.join();
+    }
+    void work() {
+        uint64_t seen = 0;
+        std::unique_lock<std::mutex> lk(m);
+        for (;;) {
+            cv.wait(lk, [&] { return stop || gen != seen; });
+            if (stop) return;
+            seen = gen;
+            const std::function<void(uint32_t)>* f = job;
+            const uint32_t n = count;
+            ++busy;
+            lk.unlock();
+            if (f)
+                for (uint32_t k; (k = next.fetch_add(1)) < n;) (*f)(k);
+            lk.lock();
+            if (--busy == 0) cv_done.notify_all();
+        }
+    }
+    void run(uint32_t n, const std::function<void(uint32_t)>& f) {
+        {
+            std::lock_guard<std::mutex> lk(m);
+            job = &f;
+            count = n;
+            next = 0;
+            ++gen;
+        }
+        cv.notify_all();
+        for (uint32_t k; (k = next.fetch_add(1)) < n;) f(k);
+        std::unique_lock<std::mutex> lk(m);
+        cv_done.wait(lk, [&] { return busy == 0; });
+        job = nullptr;   // a worker that wakes only now finds nothing to do
+        count = 0;
+    }
+};
+
 struct sz_ctx {
     int device = 0;
     int num_cus = 256;
@@ -66,6 +134,7 @@ struct sz_ctx {
     std::vector<Mark> marks;
     double stage_ms[SZ_STAGE_COUNT] = {0};
     uint64_t stage_n[SZ_STAGE_COUNT] = {0};
+    std::unique_ptr<HostPool> hpool;   // made by the first batch that needs it
 };
 
 namespace {
@@ -1408,24 +1477,12 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
             for (int sy = 0; sy < nsym; ++sy) bits += (uint64_t)hist[k][sy] * R->code_len[sy];
         wbits[k] = bits;
     };
-    {
-        // field k goes to thread k % nt; fields of threads that could not be
-        // started run here
-        const uint32_t nt = std::max<uint32_t>(1, std::min<uint32_t>(nf / 2, 8));
-        std::vector<std::thread> th;
-        uint32_t started = 1;
-        for (uint32_t t = 1; t < nt; ++t, ++started) {
-            try {
-                th.emplace_back([&, t] {
-                    for (uint32_t k = t; k < nf; k += nt) make_codes(k);
-                });
-            } catch (...) {
-                break;
-            }
-        }
-        for (uint32_t k = 0; k < nf; ++k)
-            if (k % nt == 0 || k % nt >= started) make_codes(k);
-        for (auto& x : th) x.join();
+    if (nf >= 4) {   // a batch: the context's host workers join in
+        if (!c->hpool) c->hpool.reset(new HostPool(7));
+        const std::function<void(uint32_t)> f = make_codes;
+        c->hpool->run(nf, f);
+    } else {
+        for (uint32_t k = 0; k < nf; ++k) make_codes(k);
     }
     for (uint32_t k = 0; k < nf; ++k) {
         const uint32_t i = perm[k];

@@ -177,6 +177,37 @@ def test_batch_equals_single_calls(ctx):
         r.free()
 
 
+def test_larger_batch_twice_equals_oracle(ctx):
+    # twelve fields of mixed dimensionality, radius and chunk size (several
+    # encode groups; the context's host workers build the code books), run
+    # twice on one context
+    rng = np.random.default_rng(91)
+    fields, params = [], []
+    for k in range(12):
+        if k % 3 == 2:
+            fields.append(synth.climate_field(920 + k, shape=(int(rng.integers(40, 160)), int(rng.integers(60, 240)))))
+        else:
+            fields.append(synth.spectral_field(tuple(int(v) for v in rng.integers(9, 45, size=3)),
+                                               seed=930 + k, beta=5.0 / 3.0 if k % 2 else 3.0))
+        kw = dict(eb=[1e-2, 1e-3, 1e-4][k % 3])
+        if k % 4 == 1:
+            kw["chunk"] = 512
+        if k % 5 == 3:
+            kw["radius"] = 128
+        params.append(kw)
+    refs = [O.compress(f, _oracle_params(f.shape, kw)) for f, kw in zip(fields, params)]
+    for rep in range(2):
+        print("\n[parity] batch of %d fields, pass %d" % (len(fields), rep), flush=True)
+        outs = ctx.compress_batch([_to_gpu(f) for f in fields], params)
+        for r, ref in zip(outs, refs):
+            assert r.blob() == ref.blob()
+        ys = ctx.decompress_batch(outs)
+        for y, ref in zip(ys, refs):
+            assert np.array_equal(_bits(y.cpu().numpy()), _bits(ref.recon))
+        for r in outs:
+            r.free()
+
+
 def test_launch_shape_is_arithmetic_neutral(ctx):
     x = synth.spectral_field((40, 50, 90), seed=41)
     print("\n[parity] grid sweep", flush=True)
