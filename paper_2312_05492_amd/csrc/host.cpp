@@ -1551,7 +1551,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     // sync 2: block word offsets and non-zero word counts (small) to the host
     std::vector<uint64_t> bwoff(nbw);
     std::vector<uint32_t> bnz(std::max<uint64_t>(total_blocks, 1));
-    if (c->graphs) {
+    if (graphs) {
         char* h = static_cast<char*>(c->parena);
         char* d = static_cast<char*>(c->arena);
         std::memcpy(h + o_hfd, hfd.data(), sizeof(FieldDesc) * nf);

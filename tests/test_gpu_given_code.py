@@ -107,3 +107,25 @@ def test_nonfinite_rejected_with_book(ctx):
     with pytest.raises(szi.SzError) as e:
         ctx.compress_with_code(_gpu(x), np.full(1024, 10, dtype=np.uint8))
     assert e.value.code == -2
+
+
+def test_book_with_graph_mode_on(ctx):
+    # a given code book runs the plain launch path even when the context
+    # replays graphs; the result is the same
+    x = synth.spectral_field((24, 40, 72), seed=45, mean=1.0)
+    first = ctx.compress(_gpu(x))
+    book = szi.code_lengths(first.read(szi.SEC_HIST))
+    first.free()
+    a = ctx.compress_with_code(_gpu(x), book)
+    ctx.set_graphs(True)
+    try:
+        b = ctx.compress_with_code(_gpu(x), book)
+        c = ctx.compress(_gpu(x))   # a graph replay in between
+        d = ctx.compress_with_code(_gpu(x), book)
+        assert a.blob() == b.blob() == d.blob()
+        c.free()
+        b.free()
+        d.free()
+    finally:
+        ctx.set_graphs(False)
+        a.free()
