@@ -196,7 +196,10 @@ sz_status sz_compress(sz_ctx* ctx, const float* d_in, const sz_dims* dims,
 /* Compress nfields fields in one pass of batched launches: one persistent
  * interpolation launch over every window of every field, one batched
  * encode.  d_in[i], dims[i], params[i] describe field i; outs[i] receives
- * its result, byte-identical to what sz_compress returns for it alone. */
+ * its result, byte-identical to what sz_compress returns for it alone.
+ * A batch of four or more fields builds its host code books on worker
+ * threads that the context starts on first use (seven) and keeps until
+ * sz_ctx_destroy. */
 sz_status sz_compress_batch(sz_ctx* ctx, uint32_t nfields, const float* const* d_in,
                             const sz_dims* dims, const sz_params* params, void* stream,
                             sz_result* outs);
