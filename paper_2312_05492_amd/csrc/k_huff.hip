@@ -19,7 +19,7 @@
 
 namespace szi {
 
-constexpr int kEncChunks = 16;
+constexpr int kEncChunks = 32;
 constexpr int kDecChunks = 256;
 static_assert(kEncChunks == kEncBlockChunks && kDecChunks == kDecBlockChunks,
               "the host sizes the Huffman grids with the same chunk counts");

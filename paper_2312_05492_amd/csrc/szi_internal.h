@@ -13,7 +13,7 @@ constexpr int kLutBits = 12;       // decode look-up table width (bits)
 constexpr int kMaxRadius = 1024;   // LDS histogram holds 2R <= 2048 bins
 constexpr int kRangeBlocks = 2048; // partial min/max blocks per field
 constexpr int kThreads = 256;      // threads per interpolation workgroup
-constexpr int kEncBlockChunks = 16;   // Huffman chunks per encode workgroup
+constexpr int kEncBlockChunks = 32;   // Huffman chunks per encode workgroup
 constexpr int kDecBlockChunks = 256;  // Huffman chunks per decode workgroup
 constexpr int kWordPad = 8;        // allocated u32 past the end of every Huffman word array
 
