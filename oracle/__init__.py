@@ -41,16 +41,24 @@ MAGIC = b"SZI1"
 VERSION = 1
 
 
-def build(force: bool = True) -> str:
-    """Compile szo.c into libszo.so with gcc (no contraction, IEEE)."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
-        return _LIB
-    tmp = _LIB + ".tmp%d" % os.getpid()
+def build(force: bool = True, plant: int = 0, out: str = None) -> str:
+    """Compile szo.c into libszo.so with gcc (no contraction, IEEE).
+
+    plant > 0 builds, into `out`, a copy with one deliberate mistake
+    (SZO_PLANT in szo.c) so that tests can show the pins catch it; the
+    library the oracle itself loads is always built with plant = 0."""
+    target = out or _LIB
+    if plant and target == _LIB:
+        raise ValueError("a planted build needs its own output path")
+    if not force and os.path.exists(target) and os.path.getmtime(target) >= os.path.getmtime(_SRC):
+        return target
+    tmp = target + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-           "-shared", "-Wall", "-Wno-unused-function", "-o", tmp, _SRC, "-lm"]
+           "-shared", "-Wall", "-Wno-unused-function", "-DSZO_PLANT=%d" % plant,
+           "-o", tmp, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB)
-    return _LIB
+    os.replace(tmp, target)
+    return target
 
 
 class _Params(C.Structure):
@@ -72,45 +80,50 @@ class _Config(C.Structure):
 _lib = None
 
 
+def load(path: str):
+    """Open an oracle library at `path` and declare its entry points."""
+    L = C.CDLL(path)
+    P = C.POINTER
+    L.szo_alpha.restype = C.c_double
+    L.szo_alpha.argtypes = [C.c_double]
+    L.szo_round_down.restype = C.c_float
+    L.szo_round_down.argtypes = [C.c_double]
+    L.szo_stencil.restype = C.c_float
+    L.szo_stencil.argtypes = [C.c_int, C.c_float, C.c_float, C.c_float, C.c_float]
+    L.szo_plan.restype = C.c_int
+    L.szo_plan.argtypes = [C.c_void_p, P(_Params), P(_Config)]
+    L.szo_num_anchors.restype = C.c_uint64
+    L.szo_num_anchors.argtypes = [P(_Params)]
+    L.szo_compress.restype = C.c_int
+    L.szo_compress.argtypes = [C.c_void_p, P(_Params), P(_Config), C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.c_void_p, P(C.c_uint64), C.c_void_p]
+    L.szo_compress_windowed.restype = C.c_int
+    L.szo_compress_windowed.argtypes = [C.c_void_p, P(_Params), P(_Config), C.c_void_p,
+                                        C.c_void_p]
+    L.szo_decompress.restype = C.c_int
+    L.szo_decompress.argtypes = [P(_Params), P(_Config), C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_uint64, C.c_void_p]
+    L.szo_histogram.restype = None
+    L.szo_histogram.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_void_p]
+    L.szo_huffman_lengths.restype = C.c_int
+    L.szo_huffman_lengths.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p]
+    L.szo_canonical_codes.restype = None
+    L.szo_canonical_codes.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p]
+    L.szo_encode.restype = C.c_uint64
+    L.szo_encode.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_uint32,
+                             C.c_void_p, C.c_void_p]
+    L.szo_decode.restype = C.c_int
+    L.szo_decode.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_uint32,
+                             C.c_void_p, C.c_uint32, C.c_void_p]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
-        L = C.CDLL(_LIB)
-        P = C.POINTER
-        L.szo_alpha.restype = C.c_double
-        L.szo_alpha.argtypes = [C.c_double]
-        L.szo_round_down.restype = C.c_float
-        L.szo_round_down.argtypes = [C.c_double]
-        L.szo_stencil.restype = C.c_float
-        L.szo_stencil.argtypes = [C.c_int, C.c_float, C.c_float, C.c_float, C.c_float]
-        L.szo_plan.restype = C.c_int
-        L.szo_plan.argtypes = [C.c_void_p, P(_Params), P(_Config)]
-        L.szo_num_anchors.restype = C.c_uint64
-        L.szo_num_anchors.argtypes = [P(_Params)]
-        L.szo_compress.restype = C.c_int
-        L.szo_compress.argtypes = [C.c_void_p, P(_Params), P(_Config), C.c_void_p, C.c_void_p,
-                                   C.c_void_p, C.c_void_p, C.c_void_p, P(C.c_uint64), C.c_void_p]
-        L.szo_compress_windowed.restype = C.c_int
-        L.szo_compress_windowed.argtypes = [C.c_void_p, P(_Params), P(_Config), C.c_void_p,
-                                            C.c_void_p]
-        L.szo_decompress.restype = C.c_int
-        L.szo_decompress.argtypes = [P(_Params), P(_Config), C.c_void_p, C.c_void_p, C.c_void_p,
-                                     C.c_void_p, C.c_uint64, C.c_void_p]
-        L.szo_histogram.restype = None
-        L.szo_histogram.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_void_p]
-        L.szo_huffman_lengths.restype = C.c_int
-        L.szo_huffman_lengths.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p]
-        L.szo_canonical_codes.restype = None
-        L.szo_canonical_codes.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p]
-        L.szo_encode.restype = C.c_uint64
-        L.szo_encode.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_uint32,
-                                 C.c_void_p, C.c_void_p]
-        L.szo_decode.restype = C.c_int
-        L.szo_decode.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_uint32,
-                                 C.c_void_p, C.c_uint32, C.c_void_p]
-        _lib = L
+        _lib = load(_LIB)
     return _lib
 
 

@@ -43,6 +43,16 @@
 #include <math.h>
 #include <float.h>
 
+/* SZO_PLANT > 0 compiles one deliberate mistake into a separate test build
+ * (never the oracle's own library), so that tests can show the pins catch it:
+ * 1 NAK outer taps with the wrong sign, 2 natural cubic with its outer term
+ * dropped, 3 left quadratic reading x[n+3] for x[n-3], 4 quantiser truncating
+ * instead of rounding, 5 bound rounded to nearest instead of down, 6 level
+ * bounds shifted by one level, 7 canonical codes counting the wrong length. */
+#ifndef SZO_PLANT
+#define SZO_PLANT 0
+#endif
+
 #define SZO_OK 0
 #define SZO_ERR_ARG (-1)
 #define SZO_ERR_NONFINITE (-2)
@@ -115,7 +125,7 @@ float szo_round_down(double v)
     if (!(v > 0.0)) return 0.0f;
     if (v >= (double)FLT_MAX) return FLT_MAX;
     f = (float)v;
-    if ((double)f > v) f = nextafterf(f, 0.0f);
+    if ((double)f > v && SZO_PLANT != 5) f = nextafterf(f, 0.0f);
     return f;
 }
 
@@ -135,10 +145,14 @@ float szo_stencil(int kind, float a, float b, float c, float d)
     switch (kind) {
     case SZO_ST_ONE:        return b;
     case SZO_ST_LINEAR:     return (b + c) * 0.5f;
-    case SZO_ST_QUAD_LEFT:  return ((6.0f * b + 3.0f * c) - a) * 0.125f;
+    case SZO_ST_QUAD_LEFT:  return ((6.0f * b + 3.0f * c) - (SZO_PLANT == 3 ? d : a)) * 0.125f;
     case SZO_ST_QUAD_RIGHT: return ((3.0f * b + 6.0f * c) - d) * 0.125f;
-    case SZO_ST_NAK:        return (9.0f * (b + c) - (a + d)) * 0.0625f;
-    case SZO_ST_NAT:        return (23.0f * (b + c) - 3.0f * (a + d)) / 40.0f;
+    case SZO_ST_NAK:
+        if (SZO_PLANT == 1) return (9.0f * (b + c) + (a + d)) * 0.0625f;
+        return (9.0f * (b + c) - (a + d)) * 0.0625f;
+    case SZO_ST_NAT:
+        if (SZO_PLANT == 2) return (23.0f * (b + c)) / 40.0f;
+        return (23.0f * (b + c) - 3.0f * (a + d)) / 40.0f;
     }
     return 0.0f;
 }
@@ -231,7 +245,7 @@ int szo_plan(const float *x, const szo_params *p, szo_config *cfg)
     cfg->levels = 0;
     for (k = p->S; k > 1; k >>= 1) cfg->levels++;
     {
-        double apow = 1.0;
+        double apow = SZO_PLANT == 6 ? cfg->alpha : 1.0;
         int l;
         for (l = 1; l <= cfg->levels; ++l) {
             cfg->el[l - 1] = szo_round_down(cfg->e_abs / apow);
@@ -375,7 +389,7 @@ static int quantize(float xv, float p, float el, float ebx2, float inv, int32_t 
     }
     qf = diff * inv;
     if (!(fabsf(qf) < (float)R)) return 1;
-    q = (int32_t)rintf(qf);          /* round half to even */
+    q = SZO_PLANT == 4 ? (int32_t)qf : (int32_t)rintf(qf);   /* round half to even */
     if (q >= R || q <= -R) return 1;
     t = (float)q * ebx2;
     xr = p + t;
@@ -733,7 +747,7 @@ void szo_canonical_codes(const uint8_t *len, uint32_t nsym, uint32_t *code)
     for (s = 0; s < nsym; ++s) bl_count[len[s]]++;
     bl_count[0] = 0;
     for (b = 1; b <= 32; ++b) {
-        c = (c + bl_count[b - 1]) << 1;
+        c = (c + bl_count[SZO_PLANT == 7 ? b : b - 1]) << 1;
         next_code[b] = c;
     }
     for (s = 0; s < nsym; ++s) {

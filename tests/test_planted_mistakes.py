@@ -1,0 +1,44 @@
+"""The oracle's pins catch plausible mistakes.  Each case compiles the oracle
+with one deliberate mistake (a wrong sign, a dropped term, a transposed
+operand, a wrong index, a wrong rounding) into its own library, swaps it in
+for the oracle's own, and checks that the named pins fail on it while they
+pass on the real oracle.  CPU only."""
+import pytest
+
+import oracle as O
+import tests.test_oracle_pins as P
+
+# plant number (SZO_PLANT in the oracle's C source) -> pins that must catch it
+CASES = {
+    1: ("NAK outer taps with the wrong sign (Sec. V-B.1)",
+        [P.test_spline_exactness_on_polynomials, P.test_spline_weights_match_lagrange_and_paper]),
+    2: ("natural cubic with its outer term dropped (Sec. V-B.1)",
+        [P.test_spline_exactness_on_polynomials, P.test_spline_weights_match_lagrange_and_paper]),
+    3: ("left quadratic reading x[n+3] for x[n-3] (Sec. V-B.1)",
+        [P.test_spline_exactness_on_polynomials, P.test_spline_weights_match_lagrange_and_paper]),
+    4: ("quantiser truncating instead of rounding (Sec. III-A)",
+        [lambda: P.test_quantiser_round_half_even_and_radius(1.5, 514),
+         lambda: P.test_quantiser_round_half_even_and_radius(3.5, 516)]),
+    5: ("error bound rounded to nearest instead of down",
+        [P.test_round_down_is_largest_float_below]),
+    6: ("level bounds shifted by one level (Sec. V-B.2)",
+        [P.test_level_bounds_exact_rational]),
+    7: ("canonical codes counting the wrong length (Sec. VI-A)",
+        [P.test_canonical_codes_rfc1951_example]),
+}
+
+
+def setup_module(module):
+    O.build(force=False)
+
+
+@pytest.mark.parametrize("plant", sorted(CASES), ids=[CASES[k][0] for k in sorted(CASES)])
+def test_pins_catch_planted_mistake(plant, tmp_path, monkeypatch):
+    what, pins = CASES[plant]
+    for pin in pins:          # the real oracle passes them
+        pin()
+    path = O.build(plant=plant, out=str(tmp_path / ("libszo_plant%d.so" % plant)))
+    monkeypatch.setattr(O, "_lib", O.load(path))
+    for pin in pins:
+        with pytest.raises(AssertionError):
+            pin()
