@@ -48,7 +48,10 @@
  * 1 NAK outer taps with the wrong sign, 2 natural cubic with its outer term
  * dropped, 3 left quadratic reading x[n+3] for x[n-3], 4 quantiser truncating
  * instead of rounding, 5 bound rounded to nearest instead of down, 6 level
- * bounds shifted by one level, 7 canonical codes counting the wrong length. */
+ * bounds shifted by one level, 7 canonical codes counting the wrong length,
+ * 8 profiling keeping the cubic with the larger error, 9 smoothest dimension
+ * first, 10 x[n+3] unavailable at the window's last point, 11 each code's
+ * bits written least significant first. */
 #ifndef SZO_PLANT
 #define SZO_PLANT 0
 #endif
@@ -301,7 +304,9 @@ int szo_plan(const float *x, const szo_params *p, szo_config *cfg)
         double score[3] = {0, 0, 0};
         for (d = 0; d < p->ndim; ++d) {
             int s = p->interp[d];
-            if (s == SZO_AUTO) s = cfg->prof[d][2] < cfg->prof[d][1] ? SZO_NAT : SZO_NAK;
+            if (s == SZO_AUTO)
+                s = (SZO_PLANT == 8 ? cfg->prof[d][2] > cfg->prof[d][1]
+                                    : cfg->prof[d][2] < cfg->prof[d][1]) ? SZO_NAT : SZO_NAK;
             cfg->spline[d] = s;
             score[d] = cfg->prof[d][s == SZO_LIN ? 0 : (s == SZO_NAK ? 1 : 2)];
         }
@@ -316,7 +321,8 @@ int szo_plan(const float *x, const szo_params *p, szo_config *cfg)
                 int dd;
                 for (dd = (int)p->ndim - 1; dd >= 0; --dd) {
                     if (used[dd]) continue;
-                    if (best < 0 || score[dd] > score[best]) best = dd;
+                    if (best < 0 || (SZO_PLANT == 9 ? score[dd] < score[best]
+                                                    : score[dd] > score[best])) best = dd;
                 }
                 used[best] = 1;
                 cfg->order[k] = best;
@@ -338,7 +344,7 @@ static float predict(const float *r, const uint64_t *n, const uint64_t *c, int d
     uint64_t hi = lo + wd < n[d] - 1 ? lo + wd : n[d] - 1;
     int has_m3 = c[d] >= lo + 3 * s;
     int has_p1 = c[d] + s <= hi;
-    int has_p3 = c[d] + 3 * s <= hi;
+    int has_p3 = SZO_PLANT == 10 ? c[d] + 3 * s < hi : c[d] + 3 * s <= hi;
     uint64_t cc[3];
     uint64_t step;
     float a = 0.0f, b, cp = 0.0f, dp = 0.0f;
@@ -774,7 +780,7 @@ uint64_t szo_encode(const uint16_t *sym, uint64_t n, const uint8_t *len, const u
             int L = len[sym[i]], b;
             if (L == 0) return (uint64_t)-1;
             for (b = L - 1; b >= 0; --b) {
-                uint32_t bit = (code[sym[i]] >> b) & 1u;
+                uint32_t bit = (code[sym[i]] >> (SZO_PLANT == 11 ? L - 1 - b : b)) & 1u;
                 cur |= bit << (31 - filled);
                 ++filled;
                 ++bits;

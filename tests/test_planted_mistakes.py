@@ -25,6 +25,14 @@ CASES = {
         [P.test_level_bounds_exact_rational]),
     7: ("canonical codes counting the wrong length (Sec. VI-A)",
         [P.test_canonical_codes_rfc1951_example]),
+    8: ("profiling keeping the cubic with the larger error (Sec. V-C.1)",
+        [P.test_profile_cubic_along_x_picks_nak, P.test_profile_cosine_picks_natural]),
+    9: ("smoothest dimension first (Sec. V-C.2)",
+        [P.test_profile_order_least_smooth_first]),
+    10: ("x[n+3] unavailable at the window's last point (Sec. V-B.1, V-D)",
+         [P.test_spline_map_matches_paper_figure]),
+    11: ("each code's bits written least significant first (Sec. VI-A)",
+         [P.test_bitstream_hand_example]),
 }
 
 
