@@ -51,7 +51,9 @@
  * bounds shifted by one level, 7 canonical codes counting the wrong length,
  * 8 profiling keeping the cubic with the larger error, 9 smoothest dimension
  * first, 10 x[n+3] unavailable at the window's last point, 11 each code's
- * bits written least significant first. */
+ * bits written least significant first, 12 Eq. 1 falling instead of rising
+ * between 1e-3 and 1e-2, 13 relative bound scaled by the maximum instead of
+ * the range. */
 #ifndef SZO_PLANT
 #define SZO_PLANT 0
 #endif
@@ -115,7 +117,7 @@ double szo_alpha(double eps)
 {
     if (eps >= 1e-1) return 2.0;
     if (eps >= 1e-2) return 1.75 + 0.25 * (eps - 1e-2) / (1e-1 - 1e-2);
-    if (eps >= 1e-3) return 1.5 + 0.25 * (eps - 1e-3) / (1e-2 - 1e-3);
+    if (eps >= 1e-3) return 1.5 + (SZO_PLANT == 12 ? -0.25 : 0.25) * (eps - 1e-3) / (1e-2 - 1e-3);
     if (eps >= 1e-4) return 1.25 + 0.25 * (eps - 1e-4) / (1e-3 - 1e-4);
     if (eps >= 1e-5) return 1.0 + 0.25 * (eps - 1e-5) / (1e-4 - 1e-5);
     return 1.0;
@@ -235,7 +237,7 @@ int szo_plan(const float *x, const szo_params *p, szo_config *cfg)
     /* absolute and relative bound: one divided by the range is the other */
     if (p->eb_mode == 1) {
         cfg->eps = p->eb;
-        cfg->e_abs = p->eb * cfg->range;
+        cfg->e_abs = p->eb * (SZO_PLANT == 13 ? (double)cfg->vmax : cfg->range);
     } else {
         cfg->e_abs = p->eb;
         if (cfg->range > 0.0) cfg->eps = p->eb / cfg->range;

@@ -33,6 +33,10 @@ CASES = {
          [P.test_spline_map_matches_paper_figure]),
     11: ("each code's bits written least significant first (Sec. VI-A)",
          [P.test_bitstream_hand_example]),
+    12: ("Eq. 1 falling instead of rising between 1e-3 and 1e-2",
+         [P.test_alpha_piecewise_linear_and_continuous]),
+    13: ("relative bound scaled by the maximum instead of the range (Sec. V-B.2)",
+         [P.test_level_bounds_exact_rational]),
 }
 
 
