@@ -2,7 +2,9 @@
 with one deliberate mistake (a wrong sign, a dropped term, a transposed
 operand, a wrong index, a wrong rounding) into its own library, swaps it in
 for the oracle's own, and checks that the named pins fail on it while they
-pass on the real oracle.  CPU only."""
+pass on the real oracle.  The blob layout's mistake is planted in Python,
+around the oracle's own elision routine.  CPU only."""
+import numpy as np
 import pytest
 
 import oracle as O
@@ -54,3 +56,28 @@ def test_pins_catch_planted_mistake(plant, tmp_path, monkeypatch):
     for pin in pins:
         with pytest.raises(AssertionError):
             pin()
+
+
+def _bitmap_msb_first(words):
+    """The oracle's elision with the bitmap's bit order reversed (word k
+    marked by bit 31 - k % 32): a planted mistake in the blob layout."""
+    e = _real_elide(words)
+    if e is None:
+        return None
+    nbm = (np.asarray(words).size + 31) // 32
+    bm = e[:nbm].copy()
+    rev = np.zeros_like(bm)
+    for b in range(32):
+        rev |= ((bm >> np.uint32(b)) & np.uint32(1)) << np.uint32(31 - b)
+    e[:nbm] = rev
+    return e
+
+
+_real_elide = O.elide_zero_words
+
+
+def test_pins_catch_planted_bitmap_order(monkeypatch):
+    P.test_zero_word_elision_layout()
+    monkeypatch.setattr(O, "elide_zero_words", _bitmap_msb_first)
+    with pytest.raises(AssertionError):
+        P.test_zero_word_elision_layout()
