@@ -58,6 +58,9 @@ def test_pins_catch_planted_mistake(plant, tmp_path, monkeypatch):
             pin()
 
 
+_real_elide = O.elide_zero_words
+
+
 def _bitmap_msb_first(words):
     """The oracle's elision with the bitmap's bit order reversed (word k
     marked by bit 31 - k % 32): a planted mistake in the blob layout."""
@@ -71,9 +74,6 @@ def _bitmap_msb_first(words):
         rev |= ((bm >> np.uint32(b)) & np.uint32(1)) << np.uint32(31 - b)
     e[:nbm] = rev
     return e
-
-
-_real_elide = O.elide_zero_words
 
 
 def test_pins_catch_planted_bitmap_order(monkeypatch):
