@@ -237,6 +237,20 @@ sz_status sz_decompress(sz_ctx* ctx, const sz_result* res, float* d_out, void* s
 sz_status sz_decompress_batch(sz_ctx* ctx, uint32_t nfields, const sz_result* res,
                               float* const* d_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, serving loops, harnesses that forbid hipMalloc): sz_decompress
+ * of one field without any allocation.  All of its scratch (the decoded
+ * quant-codes, 2 bytes per point, and the launch descriptors) lives in a
+ * static device workspace of the library, one per GPU, of
+ * 2^26 + 2^20 bytes; fields of more than 2^25 points are refused with
+ * UNSUPPORTED.  The call only enqueues work on the stream and returns: the
+ * caller synchronises before reading d_out.  The workspace keeps the last
+ * call's contents; calls on one GPU that overlap in time (other streams,
+ * other host threads, other contexts) race on it and must be serialised by
+ * the caller.  The output equals sz_decompress's bit for bit.
+ * Errors: INVALID_ARG, CORRUPT, UNSUPPORTED, DEVICE. */
+sz_status sz_decompress_noalloc(sz_ctx* ctx, const sz_result* res, float* d_out, void* stream);
+
 /* Write the blob of res to host memory host_dst (capacity cap bytes).
  * *written receives res->compressed_bytes.  CAPACITY if cap is too small. */
 sz_status sz_serialize(sz_ctx* ctx, const sz_result* res, void* host_dst, uint64_t cap,

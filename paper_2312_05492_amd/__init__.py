@@ -131,6 +131,8 @@ def lib():
         L.sz_decompress.argtypes = [vp, P(SzResult), vp, vp]
         L.sz_decompress_batch.restype = C.c_int
         L.sz_decompress_batch.argtypes = [vp, C.c_uint32, P(SzResult), P(vp), vp]
+        L.sz_decompress_noalloc.restype = C.c_int
+        L.sz_decompress_noalloc.argtypes = [vp, P(SzResult), vp, vp]
         L.sz_serialize.restype = C.c_int
         L.sz_serialize.argtypes = [vp, P(SzResult), vp, C.c_uint64, P(C.c_uint64)]
         L.sz_upload.restype = C.c_int
@@ -365,6 +367,14 @@ class Context:
             out = t.empty(res.shape, dtype=t.float32, device="cuda:%d" % self.device)
         self._check(lib().sz_decompress(self.h, C.byref(res.raw), C.c_void_p(out.data_ptr()),
                                         _stream(t, out.device)))
+        return out
+
+    def decompress_noalloc(self, res: Result, out):
+        """sz_decompress_noalloc: the library allocates nothing; the work is
+        only enqueued on the current stream (synchronise before reading)."""
+        self._check(lib().sz_decompress_noalloc(self.h, C.byref(res.raw),
+                                                C.c_void_p(out.data_ptr()),
+                                                _stream(self.torch, out.device)))
         return out
 
     def decompress_batch(self, results, outs=None):

@@ -135,6 +135,7 @@ struct sz_ctx {
     double stage_ms[SZ_STAGE_COUNT] = {0};
     uint64_t stage_n[SZ_STAGE_COUNT] = {0};
     std::unique_ptr<HostPool> hpool;   // made by the first batch that needs it
+    void* noalloc = nullptr;           // this device's static workspace (sz_decompress_noalloc)
 };
 
 namespace {
@@ -999,6 +1000,12 @@ sz_status sz_ctx_create(sz_ctx** out, int device, uint64_t hbm_budget_bytes) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->num_cus = prop.multiProcessorCount;
+    // the device address of the static workspace, once per device
+    if (noalloc_scratch(device, &c->noalloc) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return SZ_ERR_DEVICE;
+    }
     *out = c;
     return SZ_OK;
 }
@@ -1864,6 +1871,82 @@ sz_status sz_decompress(sz_ctx* c, const sz_result* res, float* d_out, void* str
     if (!c) return SZ_ERR_INVALID_ARG;
     float* outs[1] = {d_out};
     return sz_decompress_batch(c, 1, res, outs, stream);
+}
+
+// One field, decompressed with the static workspace only: the same kernels
+// as sz_decompress, launched with their default shapes; nothing is
+// allocated, nothing waits for the stream.
+sz_status sz_decompress_noalloc(sz_ctx* c, const sz_result* res, float* d_out, void* stream) {
+    if (!c) return SZ_ERR_INVALID_ARG;
+    if (!res || !d_out) return fail(c, SZ_ERR_INVALID_ARG, "null result or output");
+    if (!c->noalloc) return fail(c, SZ_ERR_DEVICE, "no workspace on device %d", c->device);
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const ResultInternal* R = ri(res);
+    if (!R || !res->words || !res->chunk_bits || !res->anchors)
+        return fail(c, SZ_ERR_INVALID_ARG, "the result is empty");
+    sz_params p;
+    sz_params_default(&p);
+    p.radius = (uint32_t)R->R;
+    p.huff_chunk = (uint32_t)R->chunk;
+    p.eb_mode = R->eb_mode;
+    p.eb = R->eb >= 0 ? R->eb : 0;
+    Geometry geo;
+    sz_status s = check_field(c, &R->dims, &p, geo);
+    if (s) return s;
+    if (res->n != geo.npts || res->n_chunks != geo.nchunks || res->n_anchors != geo.nanch)
+        return fail(c, SZ_ERR_CORRUPT, "sizes do not match the dimensions");
+    if (geo.npts > kNoAllocMaxPoints)
+        return fail(c, SZ_ERR_UNSUPPORTED,
+                    "%llu points: the workspace of sz_decompress_noalloc holds fields of up to "
+                    "%llu points",
+                    (unsigned long long)geo.npts, (unsigned long long)kNoAllocMaxPoints);
+    // workspace layout: descriptors (staged by one kernel), block word
+    // counts, decoded quant-codes
+    FieldDesc f;
+    fill_desc(geo, &p, f);
+    const uint64_t nblocks = (geo.nchunks + kDecBlockChunks - 1) / kDecBlockChunks;
+    const uint64_t ngroups = (geo.nwin_total + kWinPerGroup - 1) / kWinPerGroup;
+    Layout L;
+    const size_t o_fd = L.take<FieldDesc>(1), o_plan = L.take<FieldPlan>(1);
+    const size_t o_items = L.take<uint64_t>(2), o_dboff = L.take<uint64_t>(2);
+    const size_t staged = L.off;
+    const size_t o_bsum = L.take<uint32_t>(nblocks), o_codes = L.take<uint16_t>(geo.npts);
+    if (L.off > kNoAllocScratchBytes || staged > sizeof(uint32_t) * kStageWordsMax)
+        return fail(c, SZ_ERR_UNSUPPORTED, "workspace of %llu bytes needed",
+                    (unsigned long long)L.off);
+    char* ws = static_cast<char*>(c->noalloc);
+    f.out = d_out;
+    f.anchors = res->anchors;
+    f.words = res->words;
+    f.chunk_bits = res->chunk_bits;
+    f.outlier_idx = res->outlier_idx;
+    f.outlier_val = res->outlier_val;
+    f.n_outliers = res->n_outliers;
+    f.words_cap = res->n_words;
+    f.dtab = R->d_dtab;
+    f.chunk_base = 0;
+    f.codes = reinterpret_cast<uint16_t*>(ws + o_codes);
+    StageWords sw;
+    std::memset(&sw, 0, sizeof sw);
+    sw.n = (uint32_t)((staged + 3) / 4);
+    char* sb = reinterpret_cast<char*>(sw.w);
+    const uint64_t items[2] = {0, ngroups}, dboff[2] = {0, nblocks};
+    std::memcpy(sb + o_fd, &f, sizeof f);
+    std::memcpy(sb + o_plan, &R->plan, sizeof(FieldPlan));
+    std::memcpy(sb + o_items, items, sizeof items);
+    std::memcpy(sb + o_dboff, dboff, sizeof dboff);
+    FieldDesc* d_fd = reinterpret_cast<FieldDesc*>(ws + o_fd);
+    FieldPlan* d_plan = reinterpret_cast<FieldPlan*>(ws + o_plan);
+    const uint64_t* d_items = reinterpret_cast<const uint64_t*>(ws + o_items);
+    const uint64_t* d_dboff = reinterpret_cast<const uint64_t*>(ws + o_dboff);
+    uint32_t* d_bsum = reinterpret_cast<uint32_t*>(ws + o_bsum);
+    HIP_TRY(c, launch_stage_words(reinterpret_cast<uint32_t*>(ws), sw, st));
+    HIP_TRY(c, launch_dec_prep(d_fd, d_plan, 1, d_dboff, nblocks, d_bsum, st));
+    HIP_TRY(c, launch_huff_decode(d_fd, 1, d_dboff, nblocks, d_bsum, 2 * geo.R, st));
+    HIP_TRY(c, launch_decompress(geo.ndim, d_fd, d_plan, d_items, ngroups, c->num_cus,
+                                 shape_for(c, 1, geo.ndim, geo.R), st));
+    return SZ_OK;
 }
 
 sz_status sz_result_free(sz_ctx* c, sz_result* r) {

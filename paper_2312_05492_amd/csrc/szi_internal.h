@@ -163,4 +163,21 @@ hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields, const uint
                               uint64_t nblocks, const uint32_t* d_bsum, int max_nsym,
                               hipStream_t st);
 
+// ---- the entry point that allocates nothing (noalloc.hip) ----
+// Workspace of sz_decompress_noalloc: a static device array of this many
+// bytes per GPU, holding the decoded quant-codes (2 bytes per point) and the
+// call's descriptors; fields of up to kNoAllocMaxPoints points.
+constexpr uint64_t kNoAllocMaxPoints = 1ull << 25;
+constexpr uint64_t kNoAllocScratchBytes = 2 * kNoAllocMaxPoints + (1ull << 20);
+// the device address of this GPU's workspace; called with device current
+hipError_t noalloc_scratch(int device, void** ptr);
+// up to kStageWordsMax u32 written to dst by a kernel that takes them as
+// its argument
+constexpr int kStageWordsMax = 896;
+struct StageWords {
+    uint32_t n;
+    uint32_t w[kStageWordsMax];
+};
+hipError_t launch_stage_words(uint32_t* dst, const StageWords& a, hipStream_t st);
+
 }  // namespace szi
