@@ -85,6 +85,10 @@ __device__ __forceinline__ SZI_G T* at(SZI_G T* base, uint32_t off) {
     return (SZI_G T*)((SZI_G char*)base + (off * (uint32_t)sizeof(T)));
 }
 
+// lane masks straight from a condition (no 0/1 value in a vector register)
+__device__ __forceinline__ bool wave_any(bool c) { return __builtin_amdgcn_ballot_w64(c) != 0; }
+__device__ __forceinline__ uint64_t wave_ballot(bool c) { return __builtin_amdgcn_ballot_w64(c); }
+
 // ------------------------------------------------------------ block staging
 // Slots of the block load, NPRE per lane; slot k of a lane is a (global
 // offset from the window origin, LDS index) pair and whether the lane holds
@@ -329,42 +333,42 @@ __device__ __forceinline__ bool anchor_slot(uint32_t lane, const FieldDesc& f, c
 // "Accelerating correctly rounded floating-point division when the divisor
 // is known in advance", IEEE Trans. Computers 53(8), 2004).  Checked
 // exhaustively over all FP32 inputs: equal to the correctly rounded x / 40
-// for 2^-123 <= |x| < inf.  Other inputs take the division.
+// for 2^-123 <= |x| < inf.  Smaller numerators (zeros included) take the
+// division.  An infinite numerator gives NaN instead of an infinity; both
+// make the point an outlier (the quantiser's range test fails on either),
+// so compression and replay are unchanged.
 __device__ __forceinline__ float div40_fast(float x) {
     const float c = 0.025f;
     const float q0 = x * c;
     const float r = fmaf(-q0, 40.0f, x);
     return fmaf(r, c, q0);
 }
-__device__ __forceinline__ bool div40_fast_ok(float x) {
-    const float ax = fabsf(x);
-    return ax >= 0x1p-123f && ax < INFINITY;
-}
 
 // Sec. V-B.1 splines by neighbour availability (a = x[-3s], b = x[-s],
-// c = x[+s], d = x[+3s]); with one neighbour the value of x[-s].  For the
-// natural cubic, num receives the numerator and cub whether it was used.
+// c = x[+s], d = x[+3s]); with one neighbour the value of x[-s].  num
+// receives the natural cubic's numerator where that cubic gives the
+// prediction, else 1 (a value the fast division handles).  The stencil is
+// picked by selects, not branches: where the flags are compile-time
+// constants only the chosen formula remains, elsewhere the wave computes
+// the candidates and keeps one per lane.
 template <int SPL>
 __device__ __forceinline__ float predict(bool m3, bool p1, bool p3, float a, float b, float c,
-                                         float d, float& num, bool& cub) {
+                                         float d, float& num) {
     const float sbc = b + c;
-    float p = sbc * 0.5f;
-    num = 0.0f;
-    cub = false;
+    float p = sbc * 0.5f;   // linear
+    num = 1.0f;
     if (SPL != SPL_LIN) {
-        if (m3 && p3) {
-            if (SPL == SPL_NAT) {
-                num = 23.0f * sbc - 3.0f * (a + d);           // natural cubic, / 40
-                p = div40_fast(num);
-                cub = p1;
-            } else {
-                p = (9.0f * sbc - (a + d)) * 0.0625f;         // not-a-knot cubic
-            }
-        } else if (m3) {
-            p = ((6.0f * b + 3.0f * c) - a) * 0.125f;         // quadratic on a, b, c
-        } else if (p3) {
-            p = ((3.0f * b + 6.0f * c) - d) * 0.125f;         // quadratic on b, c, d
+        const float ql = ((6.0f * b + 3.0f * c) - a) * 0.125f;   // quadratic on a, b, c
+        const float qr = ((3.0f * b + 6.0f * c) - d) * 0.125f;   // quadratic on b, c, d
+        float cu;
+        if (SPL == SPL_NAT) {
+            const float n = 23.0f * sbc - 3.0f * (a + d);       // natural cubic, / 40
+            cu = div40_fast(n);
+            num = m3 && p3 && p1 ? n : 1.0f;
+        } else {
+            cu = (9.0f * sbc - (a + d)) * 0.0625f;              // not-a-knot cubic
         }
+        p = m3 ? (p3 ? cu : ql) : (p3 ? qr : p);
     }
     return p1 ? p : b;
 }
@@ -423,7 +427,7 @@ __device__ __forceinline__ void pass_lines(float* v, uint32_t lane, const PassDe
     const uint32_t ne = pd.ne, magic = pd.magic;
     const int le = pd.le, lf = pd.lf;
     const float ebx2 = pd.ebx2, inv = pd.inv, Rf = (float)R;
-    const double eld = (double)pd.el;
+    const float el = pd.el;
     const uint32_t ge = pd.ge, gf = pd.gf;
     const uint32_t gsd = D == 0 ? 1u : (D == 1 ? wi.n0 : wi.n01);   // global stride along D
     // owned lines: i0 << she below the owned extent along de, i1 << shg
@@ -466,7 +470,6 @@ __device__ __forceinline__ void pass_lines(float* v, uint32_t lane, const PassDe
     auto compute = [&](const Task<K>& tk) {
         const int p0 = (int)tk.seg * (2 * K * s);   // segment start along D
         float pr[K], nm[K];
-        bool cub[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int pos = (2 * j + 1) * s;   // target position in the segment
@@ -479,56 +482,94 @@ __device__ __forceinline__ void pass_lines(float* v, uint32_t lane, const PassDe
                 p3 = p0 + pos + 3 * s <= ed - 1;
             }
             pr[j] = predict<SPL>(m3, p1, p3, tk.kn[j], tk.kn[j + 1], tk.kn[j + 2], tk.kn[j + 3],
-                                 nm[j], cub[j]);
+                                 nm[j]);
         }
-        if (SPL == SPL_NAT) {   // numerators outside the fast division's range: rare
+        if (SPL == SPL_NAT) {   // numerators below the fast division's range: rare
             bool need = false;
 #pragma unroll
-            for (int j = 0; j < K; ++j) need = need || (cub[j] && !div40_fast_ok(nm[j]));
-            if (__any(need)) {
+            for (int j = 0; j < K; ++j) need = need || !(fabsf(nm[j]) >= 0x1p-123f);
+            if (wave_any(need)) {
 #pragma unroll
                 for (int j = 0; j < K; ++j)
-                    if (cub[j] && !div40_fast_ok(nm[j])) pr[j] = nm[j] / 40.0f;
+                    if (!(fabsf(nm[j]) >= 0x1p-123f)) pr[j] = nm[j] / 40.0f;
             }
         }
+        float* vb = v + tk.base;
+        if (COMP) {
+            float qr[K], xr[K], vv[K];
+            uint32_t cd[K];
+            bool need = false;
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const float p = pr[j];
-            const int pos = (2 * j + 1) * s;
-            const int li = tk.base + pos * SD;
-            const uint32_t gi = tk.gl + (uint32_t)pos * gsd;
-            if (COMP) {
-                // closed-loop quantisation against e_l, with the exact check;
-                // with e_l = 0, inv = 0 gives q = 0 and xr = p + 0 (exact
-                // predictions only: xr == x iff diff == 0)
-                const float xv = tk.xt[j];
-                const float diff = xv - p;
-                const float qr = rintf(diff * inv);   // round half to even
-                const int qi = (int)qr;
-                const float xr = p + (float)qi * ebx2;
-                // |rint(qf)| < R holds iff |qf| < R and |q| < R; NaN fails it
-                const bool ok = fabsf(qr) < Rf && fabs((double)xv - (double)xr) <= eld;
-                v[li] = ok ? xr : xv;
-                // owned targets: the window interval along D ends at ed - 1
-                if (tk.own && (FULL || p0 + pos < ed)) {
-                    const uint32_t code = ok ? (uint32_t)(qi + R) : 0u;
-                    *at(po.cb, gi) = (uint16_t)code;
-                    if (code == (uint32_t)R) ++cntR;
-                    else atomicAdd(&po.hist[code], 1u);
-                }
-            } else {
-                const uint32_t code = tk.ct[j];
-                pr[j] = p + (float)((int)code - R) * ebx2;
+            for (int j = 0; j < K; ++j) {
+                // closed-loop quantisation against e_l (Sec. III-A): with
+                // e_l = 0, inv = 0 gives q = 0 and xr = p + 0, so only exact
+                // predictions pass the bound test below
+                const float p = pr[j], xv = tk.xt[j];
+                qr[j] = rintf((xv - p) * inv);   // round half to even
+                xr[j] = p + qr[j] * ebx2;        // (float)(int)q == q in range
+                // |rint(qf)| < R holds iff |qf| < R and |q| < R; NaN fails it.
+                // The FP64 bound test |x - xr| <= e_l is decided in FP32
+                // where the rounded difference is below e_l (then so is the
+                // exact one), in FP64 otherwise (below).
+                const bool inr = fabsf(qr[j]) < Rf;
+                const bool good = inr && fabsf(xv - xr[j]) < el;
+                vv[j] = good ? xr[j] : xv;
+                cd[j] = good ? (uint32_t)((int)qr[j] + R) : 0u;
+                need = need || (good != inr);
             }
-        }
-        if (!COMP) {
+            if (wave_any(need)) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const float xv = tk.xt[j];
+                    if (fabsf(qr[j]) < Rf && !(fabsf(xv - xr[j]) < el) &&
+                        fabs((double)xv - (double)xr[j]) <= (double)el) {
+                        vv[j] = xr[j];
+                        cd[j] = (uint32_t)((int)qr[j] + R);
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j) vb[(2 * j + 1) * s * SD] = vv[j];
+            // owned targets' quant-codes: the window interval along D ends
+            // at ed - 1
+            if (tk.own) {
+                SZI_G char* cbb = (SZI_G char*)po.cb + (uint64_t)(2u * tk.gl);
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const int pos = (2 * j + 1) * s;
+                    if (FULL || p0 + pos < ed) {
+                        if (D == 0) *(SZI_G uint16_t*)(cbb + 2 * pos) = (uint16_t)cd[j];
+                        else *(SZI_G uint16_t*)(cbb + (uint64_t)(2u * (uint32_t)pos * gsd)) = (uint16_t)cd[j];
+                    }
+                }
+            }
+            // histogram without branches: every target adds one; the centre
+            // code and targets the window does not own go to a bin of the
+            // lane's own past the 2R symbols (no two lanes share an
+            // address), and the count of the latter is taken off the centre
+            // bin when the histogram is flushed
+            const uint32_t rb = (uint32_t)(2 * R) + lane;
+            if (FULL) cntR += (uint32_t)(K * __popcll(wave_ballot(!tk.own)));
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const int pos = (2 * j + 1) * s;
+                const bool ot = tk.own && (FULL || p0 + pos < ed);
+                if (!FULL) cntR += (uint32_t)__popcll(wave_ballot(!ot));
+                const uint32_t bin = ot && cd[j] != (uint32_t)R ? cd[j] : rb;
+                atomicAdd(&po.hist[bin], 1u);
+            }
+        } else {
+            bool out = false;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const uint32_t code = tk.ct[j];
+                pr[j] = pr[j] + (float)((int)code - R) * ebx2;
+                out = out || code == 0u;
+            }
             // code 0: an outlier, whose value the scatter step put in the
             // output array (points outside the field hold a code no point
             // takes, so the load stays inside it); rare, so one uniform test
-            bool out = false;
-#pragma unroll
-            for (int j = 0; j < K; ++j) out = out || tk.ct[j] == 0u;
-            if (__any(out)) {
+            if (wave_any(out)) {
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
                     const int pos = (2 * j + 1) * s;
@@ -536,7 +577,7 @@ __device__ __forceinline__ void pass_lines(float* v, uint32_t lane, const PassDe
                 }
             }
 #pragma unroll
-            for (int j = 0; j < K; ++j) v[tk.base + (2 * j + 1) * s * SD] = pr[j];
+            for (int j = 0; j < K; ++j) vb[(2 * j + 1) * s * SD] = pr[j];
         }
     };
 
@@ -634,7 +675,7 @@ struct OutMap {
 // codes of all other owned points.
 template <int ND>
 __device__ __forceinline__ void write_anchors(const float* v, uint32_t lane, const FieldDesc& f,
-                                              const Win& wi, uint32_t& cntR) {
+                                              const Win& wi, uint32_t* hist) {
     using G = Geo<ND>;
     constexpr int S = 1 << G::SHS;
     if (lane < (uint32_t)(G::W0 / S) && (int)lane * S < wi.o0) {
@@ -643,7 +684,7 @@ __device__ __forceinline__ void write_anchors(const float* v, uint32_t lane, con
                                                  (uint32_t)f.na[1] * (uint32_t)(wi.lo2 >> G::SHS));
         gp(f.anchors)[ai] = v[(int)lane * S];
         *at(gp(f.codes) + wi.gbase, lane * (uint32_t)S) = (uint16_t)f.R;
-        ++cntR;
+        atomicAdd(&hist[2 * f.R + lane], 1u);   // the lane's centre-code bin
     }
 }
 
@@ -710,10 +751,22 @@ __device__ __forceinline__ GroupSeq group_seq(uint64_t ngroups) {
 }
 
 // --------------------------------------------------------------- kernels
-__device__ __forceinline__ void flush_hist(uint32_t* hist, uint32_t& cntR, const FieldDesc& fd) {
-    const uint32_t s = wave_sum(cntR);
-    cntR = 0;
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd(&hist[fd.R], s);
+// LDS histogram of a workgroup: the 2R symbols, then one bin per lane that
+// collects the centre code and the targets a window does not own; nown
+// (wave-uniform) counts the latter.  The flush folds the lane bins into
+// the centre bin (modulo 2^32, so the subtraction may wrap on the way).
+__device__ __forceinline__ void clear_hist(uint32_t* hist, int R) {
+#pragma unroll 1
+    for (int b = threadIdx.x; b < 2 * R + 64; b += kThreads) hist[b] = 0;
+}
+__device__ __forceinline__ void flush_hist(uint32_t* hist, uint32_t& nown, const FieldDesc& fd) {
+    if ((threadIdx.x & 63) == 0 && nown) atomicAdd(&hist[fd.R], 0u - nown);
+    nown = 0;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const uint32_t c = wave_sum(hist[2 * fd.R + threadIdx.x]);
+        if (threadIdx.x == 0) atomicAdd(&hist[fd.R], c);
+    }
     __syncthreads();
 #pragma unroll 1
     for (int b = threadIdx.x; b < 2 * fd.R; b += kThreads)
@@ -741,10 +794,14 @@ SZI_WINDOW_KERNEL void k_compress(const FieldDesc* __restrict__ F, const FieldPl
     uint64_t g = gs.cur;
     if (g >= gs.end) return;
     int f = 0;
-    float pre[G::NPRE];   // block of the next window
+    // block of the next window: 16-byte quads where the window lies in the
+    // field and its rows are aligned, else one value per slot
+    constexpr int NPQ = QuadMap<ND>::N > G::NPRE ? QuadMap<ND>::N : G::NPRE;
+    float pre[NPQ];
     LaneMap<ND> lm;
+    QuadMap<ND> qm;
     Win wn;
-    bool valid;
+    bool valid, quads = false;
     // window of group g for this wave, and the start of its block load
     auto fetch = [&]() {
         while (g >= goff[f + 1]) ++f;
@@ -752,28 +809,34 @@ SZI_WINDOW_KERNEL void k_compress(const FieldDesc* __restrict__ F, const FieldPl
         valid = w < (uint32_t)(F[f].nwin[0] * F[f].nwin[1] * F[f].nwin[2]);
         if (valid) {
             wn = make_win<ND>(F[f], w);
-            lm.init(lane, wn.n0, wn.n01);
             const SZI_G float* wb = gp(F[f].in) + wn.gbase;
-            if (wn.full) load_block<ND, true>(pre, wb, lm, wn, 0.0f);
-            else load_block<ND, false>(pre, wb, lm, wn, 0.0f);
+            quads = wn.full && (wn.n0 & 3u) == 0u && ((uintptr_t)F[f].in & 15u) == 0u;
+            if (quads) {
+                qm.init(lane, wn.n0, wn.n01);
+                load_quads<ND>(pre, wb, qm, lane, wn.n01);
+            } else {
+                lm.init(lane, wn.n0, wn.n01);
+                if (wn.full) load_block<ND, true>(pre, wb, lm, wn, 0.0f);
+                else load_block<ND, false>(pre, wb, lm, wn, 0.0f);
+            }
         }
     };
     fetch();
     int hf = -1;         // field whose histogram the workgroup accumulates
-    uint32_t cntR = 0;   // lane-private count of the centre code (top-1 cache)
+    uint32_t cntR = 0;   // targets counted in the lane bins that the windows do not own
     while (true) {
         const int fc = f;
         const Win wc = wn;
-        const bool vc = valid;
+        const bool vc = valid, qc = quads;
         if (fc != hf) {   // uniform over the workgroup: groups never span fields
             if (hf >= 0) flush_hist(hist, cntR, F[hf]);
-#pragma unroll 1
-            for (int b = threadIdx.x; b < 2 * F[fc].R; b += kThreads) hist[b] = 0;
+            clear_hist(hist, F[fc].R);
             __syncthreads();
             hf = fc;
         }
         if (vc) {
-            if (wc.full) commit_block<ND, true>(v, pre, lm, wc);
+            if (qc) commit_quads<ND>(v, pre, qm, lane, wc.n01);
+            else if (wc.full) commit_block<ND, true>(v, pre, lm, wc);
             else commit_block<ND, false>(v, pre, lm, wc);
         }
         g += gs.step;
@@ -784,7 +847,7 @@ SZI_WINDOW_KERNEL void k_compress(const FieldDesc* __restrict__ F, const FieldPl
             const FieldDesc& fd = F[fc];
             const PassOut po{gp(fd.codes) + wc.gbase, nullptr, hist};
             run_levels<ND, true>(v, lane, P[fc], fd.R, wc, po, cntR);
-            write_anchors<ND>(v, lane, fd, wc, cntR);
+            write_anchors<ND>(v, lane, fd, wc, hist);
             wave_sync();
         }
         if (!more) break;
@@ -899,7 +962,7 @@ hipError_t launch_compress(int ndim, const FieldDesc* d_fields, const FieldPlan*
                            const uint64_t* d_goff, uint64_t ngroups, int num_cus,
                            LaunchShape shape, int max_R, hipStream_t st) {
     if (ngroups == 0) return hipSuccess;
-    const size_t lds = (size_t)2 * max_R * sizeof(uint32_t);
+    const size_t lds = (size_t)(2 * max_R + 64) * sizeof(uint32_t);
     auto go = [&](auto k) {
         const uint64_t grid = resident_grid(k, lds, num_cus, shape.per_cu, ngroups);
         hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kThreads), lds, st, d_fields, d_plans,
