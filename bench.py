@@ -29,15 +29,55 @@ WORKLOADS = {
 
 def algorithmic_bytes(stage, n, n_anchors, n_out, n_words, n_chunks):
     """Bytes each kernel stage must move per launch (no halo re-reads, no
-    scratch): the per-point figures times the points of the launch."""
+    scratch): the per-point figures times the points of the launch.  The
+    pass over the codes that counts each chunk's bits (huff_stats) moves
+    nothing the pipeline needs beyond what the encode reads, so it has none:
+    its time counts, its bytes do not."""
     return {
         "range": 4 * n,
         "interp": 4 * n + 2 * n + 4 * n_anchors,
-        "huff_stats": 2 * n + 2 * n_chunks,
-        "encode": 2 * n + 4 * n_words + 8 * n_out + 4 * n_out,
+        "huff_stats": 0,
+        "encode": 2 * n + 4 * n_words + 2 * n_chunks + 8 * n_out,
         "decode": 4 * n_words + 2 * n_chunks + 2 * n,
-        "replay": 2 * n + 4 * n_anchors + 4 * n + 4 * n_out,
+        "replay": 2 * n + 4 * n_anchors + 4 * n + 8 * n_out,
     }.get(stage)
+
+
+def pipeline_bytes(n, n_anchors, n_out, n_words, n_chunks):
+    """Algorithmic bytes of a whole compression and decompression: read the
+    field twice (range, interpolation), write and read the quant-codes once,
+    the anchors, the outlier lists (index and value) and the bitstream with
+    its chunk sizes; decompression reads the bitstream, writes and reads the
+    codes, reads anchors and outliers and writes the field (about 12 + b/8
+    and 8 + b/8 bytes per point for b bits per symbol)."""
+    meta = 4 * n_anchors + 8 * n_out + 4 * n_words + 2 * n_chunks
+    return {"compress": 4 * n + 4 * n + 2 * n + 2 * n + meta,
+            "decompress": 2 * n + 2 * n + 4 * n + meta}
+
+
+INTERP = {   # per numpy axis, slowest first (0 linear, 1 not-a-knot, 2 natural, 3 profiled)
+    "auto": (3, 3, 3), "linear": (0, 0, 0), "mixed": (0, 3, 3), "nak": (1, 1, 1), "natural": (2, 2, 2),
+}
+INTERP_DESC = {"auto": "cubic per dimension by profiling (Sec. V-C.1)", "linear": "linear in every dimension",
+               "mixed": "linear along z, cubic by profiling along y and x", "nak": "not-a-knot cubic",
+               "natural": "natural cubic"}
+
+
+def host_cpu():
+    """Model name and usable logical CPUs of the host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    return model, ncpu
 
 
 # per-launch HBM traffic from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
@@ -129,6 +169,101 @@ def pmc_summary(fetch_csv, write_csv, n, cmd, out_path):
         o.write("```\n")
 
 
+def short_kernel(k):
+    """A kernel's name without its namespace, return type and arguments
+    (library kernels of torch cut to their first template argument)."""
+    k = k.replace("void ", "").replace("szi::", "")
+    k = k[:k.index("(")] if "(" in k else k
+    if k.startswith("at::native::"):
+        k = "torch: " + k[len("at::native::"):].split(",")[0] + (">" if "<" in k else "")
+    return k
+
+
+def trace_summary(stats_csv, cmd, out_path, title):
+    """rocprofv3 --kernel-trace --stats kernel table as a short markdown file."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    with open(out_path, "w") as o:
+        o.write("# %s\n\nCommand (from the repository root on an MI355X host, $REPO being that "
+                "root):\n\n```\n%s\n```\n\n" % (title, cmd))
+        o.write("| kernel | calls | total us | average us | min us | max us | % |\n"
+                "|---|---|---|---|---|---|---|\n")
+        for r in rows:
+            o.write("| %s | %s | %.1f | %.1f | %.1f | %.1f | %.1f |\n" % (
+                short_kernel(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e3,
+                float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+                float(r["Percentage"])))
+
+
+COUNTER_KERNELS = ("k_range", "k_compress", "k_huff_stats", "k_huff_encode", "k_elide_count",
+                   "k_huff_decode", "k_decompress")
+
+
+def counter_summary(csvs, cmd, out_path, title):
+    """Per-dispatch averages of SQ/GRBM counters over one or more rocprofv3
+    --pmc runs (one pass each), per kernel, with per-wave instruction counts
+    and the derived ratios the kernels are tuned on."""
+    import csv
+    import collections
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    res = {}
+    for path in csvs:
+        for r in csv.DictReader(open(path)):
+            k = short_kernel(r["Kernel_Name"])
+            if not k.startswith(COUNTER_KERNELS):
+                continue
+            acc[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+            res[k] = (r["Workgroup_Size"], r["LDS_Block_Size"], r["VGPR_Count"],
+                      r["Accum_VGPR_Count"], r["SGPR_Count"])
+    avg = {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
+    names = sorted({c for cs in avg.values() for c in cs})
+    with open(out_path, "w") as o:
+        o.write("# %s\n\nOne rocprofv3 counter pass per line (the SQ block collects at most 8 "
+                "counters a pass), from the repository root on an MI355X host, $REPO being that "
+                "root:\n\n```\n%s\n```\n\n" % (title, cmd))
+        o.write("## Resources per kernel\n\n| kernel | workgroup | LDS bytes | VGPR | AGPR | SGPR |\n"
+                "|---|---|---|---|---|---|\n")
+        for k in sorted(res):
+            o.write("| %s | %s | %s | %s | %s | %s |\n" % ((k,) + res[k]))
+        o.write("\n## Counters, average per dispatch\n\n| counter | " + " | ".join(sorted(avg)) +
+                " |\n|---|" + "---|" * len(avg) + "\n")
+        for c in names:
+            o.write("| %s | " % c + " | ".join(
+                "%.0f" % avg[k][c] if c in avg[k] else "" for k in sorted(avg)) + " |\n")
+        o.write("\n## Derived\n\n"
+                "* per wave: instructions of each kind over SQ_WAVES;\n"
+                "* kernel cycles: GRBM_GUI_ACTIVE / 8 (the counter sums the 8 XCDs);\n"
+                "* resident waves per CU: 4 SQ_WAVE_CYCLES / (256 x kernel cycles) (wave "
+                "cycles count in units of 4 cycles);\n"
+                "* VALU busy: 4 SQ_ACTIVE_INST_VALU / (1024 SIMDs x kernel cycles);\n"
+                "* LDS bank conflicts: SQ_LDS_BANK_CONFLICT over SQ_ACTIVE_INST_LDS (cycles);\n"
+                "* issue stall: SQ_WAIT_INST_ANY over SQ_WAVE_CYCLES.\n\n")
+        o.write("| kernel | waves | VALU/wave | SALU/wave | LDS/wave | VMEM rd/wave | VMEM wr/wave | "
+                "kernel cycles | waves/CU | VALU busy | LDS conflict/active | issue stall |\n"
+                "|---|---|---|---|---|---|---|---|---|---|---|---|\n")
+
+        def g(d, c):
+            return d.get(c)
+
+        def ratio(a, b, scale=1.0, fmt="%.0f"):
+            return fmt % (scale * a / b) if a is not None and b else ""
+
+        for k in sorted(avg):
+            d = avg[k]
+            w = g(d, "SQ_WAVES")
+            cyc = g(d, "GRBM_GUI_ACTIVE")
+            cyc = cyc / 8.0 if cyc else None
+            o.write("| %s | %s | %s | %s | %s | %s | %s | %s | %s | %s | %s | %s |\n" % (
+                k, "%.0f" % w if w else "",
+                ratio(g(d, "SQ_INSTS_VALU"), w), ratio(g(d, "SQ_INSTS_SALU"), w),
+                ratio(g(d, "SQ_INSTS_LDS"), w), ratio(g(d, "SQ_INSTS_VMEM_RD"), w),
+                ratio(g(d, "SQ_INSTS_VMEM_WR"), w), "%.0f" % cyc if cyc else "",
+                ratio(g(d, "SQ_WAVE_CYCLES"), (256 * cyc) if cyc else None, 4.0, "%.1f"),
+                ratio(g(d, "SQ_ACTIVE_INST_VALU"), (1024 * cyc) if cyc else None, 4.0, "%.2f"),
+                ratio(g(d, "SQ_LDS_BANK_CONFLICT"), g(d, "SQ_ACTIVE_INST_LDS"), 1.0, "%.2f"),
+                ratio(g(d, "SQ_WAIT_INST_ANY"), g(d, "SQ_WAVE_CYCLES"), 1.0, "%.2f")))
+
+
 def pct(a, q):
     a = sorted(a)
     if not a:
@@ -162,7 +297,7 @@ def run_batch(args):
         params = [dict(eb=e) for e in ebs]
     dev = torch.device("cuda:0")
     xs = [torch.from_numpy(f).to(dev) for f in fields]
-    del fields
+    host_fields = fields
     outs = [torch.empty_like(x) for x in xs]
     in_bytes = sum(4 * x.numel() for x in xs)
     ctx = szi.Context(0)
@@ -200,6 +335,10 @@ def run_batch(args):
     # the candidate shapes and keeps the fastest (results unchanged)
     ctx.set_tuning(True)
     t_batch = timed(batched)
+    # the same batches through the library's captured graphs
+    ctx.set_graphs(True)
+    t_batch_graph = timed(batched)
+    ctx.set_graphs(False)
     nd = xs[0].dim()
     shapes = {k: ctx.shape(i, nd)[:2] for i, k in enumerate(("interp", "replay"))}
     # identity: the batched results equal the per-field ones, bit for bit
@@ -219,11 +358,41 @@ def run_batch(args):
         "speedup": round(t_single / t_batch, 3),
         "ms_batched": round(t_batch * 1e3, 3), "ms_per_field_calls": round(t_single * 1e3, 3),
         "ms_batched_default_shape": round(t_batch_untuned * 1e3, 3),
+        "ms_batched_graphs": round(t_batch_graph * 1e3, 3),
         "tuned_shapes": {k: {"variant": v[0], "workgroups_per_cu": v[1]} for k, v in shapes.items()},
         "steps": args.steps, "fields": len(xs), "input_bytes": in_bytes,
         "ratio": round(in_bytes / comp, 3), "identical": bool(same),
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": BATCHES[args.batch]}}), flush=True)
+        "config": {"workload": BATCHES[args.batch]},
+        "cpu_baseline": None if args.no_cpu_baseline else threaded_oracle(host_fields, params)}),
+        flush=True)
+
+
+def threaded_oracle(fields, params):
+    """The CPU oracle over a batch: every field compressed and decompressed
+    once, one host thread per field (up to the usable logical CPUs; the C
+    oracle runs without the interpreter lock)."""
+    import concurrent.futures as cf
+
+    import oracle
+    oracle.build(force=False)
+    model, ncpu = host_cpu()
+    workers = max(1, min(len(fields), ncpu))
+
+    def one(k):
+        x, kw = fields[k], params[k]
+        p = oracle.Params(shape=x.shape, eb=kw.get("eb", 1e-3))
+        oracle.decompress_blob(oracle.compress(x, p).blob())
+
+    a = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(one, range(len(fields))))
+    t = time.perf_counter() - a
+    nbytes = sum(4 * f.size for f in fields)
+    return {"value": round(nbytes / t / 1e9, 4), "unit": "GB/s", "cores": workers, "kind": "oracle",
+            "sample": "every field of the batch compressed and decompressed once, one thread per "
+                      "field on %d threads, %.1f s" % (workers, t),
+            "cpu_model": model, "host_logical_cpus": ncpu}
 
 
 SERVE_DESC = ("Poisson stream of 2000 requests, half compress, half decompress; sizes log-uniform "
@@ -392,6 +561,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--eb", type=float, default=1e-3)
+    ap.add_argument("--interp", default="auto", choices=sorted(INTERP),
+                    help="spline per dimension: " + "; ".join("%s = %s" % kv for kv in sorted(INTERP_DESC.items())))
     ap.add_argument("--chunk", type=int, default=1024, choices=(256, 512, 1024, 2048),
                     help="Huffman chunk length in symbols")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -401,6 +572,13 @@ def main():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary from two rocprofv3 counter runs and exit")
     ap.add_argument("--pmc-command", default="", help="the profiled command, for the summary")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("STATS_CSV", "OUT_MD"),
+                    help="write a kernel time summary from a rocprofv3 --kernel-trace --stats "
+                         "run and exit")
+    ap.add_argument("--counter-summary", nargs="+", metavar="CSV",
+                    help="OUT_MD then the counter_collection.csv of each rocprofv3 --pmc pass: "
+                         "write a counter summary and exit")
+    ap.add_argument("--title", default="", help="the summary's title")
     ap.add_argument("--serve", action="store_true",
                     help="request server vs sequential plain calls on a Poisson trace (own JSON line)")
     ap.add_argument("--requests", type=int, default=2000)
@@ -413,6 +591,12 @@ def main():
         return
     if args.serve:
         run_serve(args)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary[0], args.pmc_command, args.trace_summary[1], args.title)
+        return
+    if args.counter_summary:
+        counter_summary(args.counter_summary[1:], args.pmc_command, args.counter_summary[0], args.title)
         return
     if args.pmc_summary:
         shape = WORKLOADS[args.workload]["shape"]
@@ -441,7 +625,7 @@ def main():
     d_x = torch.from_numpy(x).to(dev)
     out = torch.empty_like(d_x)
     ctx = szi.Context(0)
-    kw = dict(eb=args.eb, chunk=args.chunk)
+    kw = dict(eb=args.eb, chunk=args.chunk, interp=INTERP[args.interp][-x.ndim:])
 
     if args.calibrate_copy:
         out.copy_(d_x)
@@ -534,12 +718,12 @@ def main():
         rep = {}
         for k, (ms, cnt) in stages.items():
             if k == "codebook":
-                rep[k] = {"avg_ms": ms / cnt}
+                rep[k] = {"avg_ms": round(ms / cnt, 5)}
                 continue
             avg = ms / cnt
             ab = algorithmic_bytes(k, n, n_anch, n_out, n_words, n_chunks)
             rep[k] = {"avg_ms": round(avg, 5)}
-            if ab is not None and avg > 0:
+            if ab and avg > 0:
                 rep[k]["GBps"] = round(ab / (avg * 1e-3) / 1e9, 1)
         return rep
 
@@ -553,6 +737,13 @@ def main():
     dom_ms, dom = max(allk)
     dom_bytes = algorithmic_bytes(dom, n, n_anch, n_out, n_words, n_chunks)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    pb = pipeline_bytes(n, n_anch, n_out, n_words, n_chunks)
+    pipe = {}
+    for k, ms in (("compress", comp_kernel_ms), ("decompress", decomp_kernel_ms)):
+        gbs = pb[k] / (ms * 1e-3) / 1e9
+        pipe[k] = {"kernel_ms": round(ms, 4), "algorithmic_bytes": int(pb[k]),
+                   "bytes_per_point": round(pb[k] / n, 3), "GBps": round(gbs, 1),
+                   "frac": round(gbs / HBM_PEAK_GBS, 4)}
     traffic = read_traffic().get(STAGE_KERNELS.get(dom)) if args.workload == "large" else None
 
     line = {
@@ -569,7 +760,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "shape": list(wl["shape"]), "eb_rel": args.eb,
-                   "interp": "cubic auto (profiled)", "anchor_stride": 8, "radius": 512,
+                   "interp": INTERP_DESC[args.interp], "anchor_stride": 8, "radius": 512,
                    "huffman_chunk": args.chunk},
         "compress_GBps": round(in_bytes / float(np.median(t_c)) / 1e9, 2),
         "decompress_GBps": round(in_bytes / float(np.median(t_d)) / 1e9, 2),
@@ -583,6 +774,7 @@ def main():
                              "decompress_p50": round(pct(g_d, 50) * 1e3, 3)},
         "reused_code_book_compress_p50_ms": round(pct(b_c, 50) * 1e3, 3),
         "kernels": {"compress": comp_rep, "decompress": decomp_rep},
+        "pipeline_roofline": pipe,
         "ratio": round(cr, 3),
         "bitrate": round(32.0 / cr, 4),
         "psnr_db": round(psnr, 2),
@@ -600,7 +792,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
-        p = oracle.Params(shape=x.shape, eb=args.eb)
+        p = oracle.Params(shape=x.shape, eb=args.eb, chunk=args.chunk, interp=INTERP[args.interp][-x.ndim:])
         # whole-field round trips until about 10 s of CPU work
         reps, tc, td = 0, 0.0, 0.0
         while reps < 1 or (tc + td < 10.0 and reps < 8):
@@ -612,11 +804,13 @@ def main():
             c = time.perf_counter()
             tc, td, reps = tc + (b - a), td + (c - b), reps + 1
             del ref, blob
+        model, ncpu = host_cpu()
         line["cpu_baseline"] = {"value": round(reps * in_bytes / (tc + td) / 1e9, 4), "unit": "GB/s",
                                 "cores": 1, "kind": "oracle",
                                 "sample": "%d round trips (compress + decompress) of the full workload "
                                           "field, single-threaded C oracle, %.1f s compress + %.1f s "
-                                          "decompress in total" % (reps, tc, td)}
+                                          "decompress in total" % (reps, tc, td),
+                                "cpu_model": model, "host_logical_cpus": ncpu}
     print(json.dumps(line), flush=True)
 
 

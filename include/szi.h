@@ -174,7 +174,8 @@ typedef enum {
     SZ_STAGE_DECODE = 8,    /* Huffman decode */
     SZ_STAGE_SCATTER = 9,   /* outliers into the output */
     SZ_STAGE_REPLAY = 10,   /* interpolation replay (decompression) */
-    SZ_STAGE_COUNT = 11
+    SZ_STAGE_ELIDE = 11,    /* zero-word elision of the Huffman words (and its restore) */
+    SZ_STAGE_COUNT = 12
 } sz_stage;
 /* enable != 0 turns timing on (and clears the totals). */
 sz_status sz_ctx_set_timing(sz_ctx* ctx, int enable);

@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libszi.so")
 
 STAGES = ["range", "profile", "plan", "interp", "codebook", "huff_stats", "scan", "encode",
-          "decode", "scatter", "replay"]
+          "decode", "scatter", "replay", "elide"]
 SZ_OK = 0
 ERRORS = {-1: "INVALID_ARG", -2: "NONFINITE", -3: "OOM", -4: "DEVICE", -5: "CORRUPT",
           -6: "UNSUPPORTED", -7: "CAPACITY"}

@@ -590,6 +590,7 @@ struct ResultInternal {
     uint32_t* d_cbook = nullptr;
     uint32_t* d_dtab = nullptr;
     uint64_t nzw = UINT64_MAX;     // non-zero Huffman words; UINT64_MAX: unknown
+    uint32_t* d_esec = nullptr;    // the words section with its zero words elided (device)
 };
 
 ResultInternal* ri(const sz_result* r) { return static_cast<ResultInternal*>(r->internal); }
@@ -735,7 +736,7 @@ uint64_t pad8(uint64_t b) { return (b + 7) & ~(uint64_t)7; }
 constexpr uint32_t kFlagWordsElided = 1;
 uint64_t elided_words(uint64_t n_words, uint64_t nzw) { return (n_words + 31) / 32 + nzw; }
 bool words_elided(const sz_result* r, const ResultInternal* R) {
-    return R->nzw != UINT64_MAX && elided_words(r->n_words, R->nzw) < r->n_words;
+    return R->d_esec && R->nzw != UINT64_MAX && elided_words(r->n_words, R->nzw) < r->n_words;
 }
 uint64_t words_section_bytes(const sz_result* r, const ResultInternal* R) {
     return 4 * (words_elided(r, R) ? elided_words(r->n_words, R->nzw) : r->n_words);
@@ -1247,7 +1248,10 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     FieldDesc *d_fd, *d_hfd;
     FieldPlan* d_plan;
     float *d_pmin, *d_pmax;
-    uint32_t *d_pbad, *d_hist = nullptr, *d_bnz;
+    uint32_t *d_pbad, *d_hist = nullptr, *d_bnz, *d_ecnt;
+    unsigned long long* d_fnz;
+    ElideField* d_ef;
+    uint64_t *d_etoff, *d_eoff;
     char* d_scr = nullptr;   // the plain calls' scratch block
     const bool many = !graphs && nf >= 2;   // batch: gathered histograms, scattered tables
     uint64_t *d_items, *d_gboff, *d_bwoff, *d_booff;
@@ -1261,6 +1265,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     const size_t o_pmax = L.take<float>((size_t)nf * kRangeBlocks);
     const size_t o_pbad = L.take<uint32_t>((size_t)nf * kRangeBlocks);
     const size_t o_hfd = L.take<FieldDesc>(nf), o_gboff = L.take<uint64_t>(gboff.size());
+    const size_t o_ef = L.take<ElideField>(nf), o_etoff = L.take<uint64_t>(nf + 1);
     const size_t end2 = L.off;
     const size_t o_cwords = L.take<uint32_t>(std::max<uint64_t>(total_chunks, 1));
     const size_t o_couts = L.take<uint32_t>(std::max<uint64_t>(total_chunks, 1));
@@ -1268,6 +1273,12 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     const size_t o_bo = L.take<uint32_t>(std::max<uint64_t>(total_blocks, 1));
     const size_t o_bwoff = L.take<uint64_t>(nbw), o_booff = L.take<uint64_t>(nbw);
     const size_t o_bnz = L.take<uint32_t>(std::max<uint64_t>(total_blocks, 1));
+    const size_t o_fnz = L.take<unsigned long long>(nf);
+    // zero-word elision: tiles of every field's words at their largest
+    uint64_t etiles_max = 0;
+    for (uint32_t k = 0; k < nf; ++k)
+        etiles_max += (fds[k].npts * kLmax / 32 + fds[k].nchunks + 1) / kElideTileWords + 1;
+    const size_t o_ecnt = L.take<uint32_t>(etiles_max), o_eoff = L.take<uint64_t>(etiles_max + 1);
     // host staging in pinned memory (copies from it are asynchronous): the
     // arena's layout, then each field's code lengths, codebook and decode
     // tables
@@ -1303,6 +1314,11 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         d_bwoff = reinterpret_cast<uint64_t*>(d + o_bwoff);
         d_booff = reinterpret_cast<uint64_t*>(d + o_booff);
         d_bnz = reinterpret_cast<uint32_t*>(d + o_bnz);
+        d_ef = reinterpret_cast<ElideField*>(d + o_ef);
+        d_etoff = reinterpret_cast<uint64_t*>(d + o_etoff);
+        d_ecnt = reinterpret_cast<uint32_t*>(d + o_ecnt);
+        d_eoff = reinterpret_cast<uint64_t*>(d + o_eoff);
+        d_fnz = reinterpret_cast<unsigned long long*>(d + o_fnz);
         for (uint32_t k = 0; k < nf; ++k) fds[k].hist = d_hist + k * hstride;
     } else {
         // one scratch block in the arena's layout, so that the staged
@@ -1327,6 +1343,11 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         d_bwoff = reinterpret_cast<uint64_t*>(d + o_bwoff);
         d_booff = reinterpret_cast<uint64_t*>(d + o_booff);
         d_bnz = reinterpret_cast<uint32_t*>(d + o_bnz);
+        d_ef = reinterpret_cast<ElideField*>(d + o_ef);
+        d_etoff = reinterpret_cast<uint64_t*>(d + o_etoff);
+        d_ecnt = reinterpret_cast<uint32_t*>(d + o_ecnt);
+        d_eoff = reinterpret_cast<uint64_t*>(d + o_eoff);
+        d_fnz = reinterpret_cast<unsigned long long*>(d + o_fnz);
     }
     // the offsets and per-block counts read back at the end, one region
     const size_t o_back = o_bwoff, n_back = o_bnz + sizeof(uint32_t) * total_blocks - o_bwoff;
@@ -1499,6 +1520,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         const uint64_t nout = given ? outlier_guess(geo[i].npts) : hist[k][0];
         const uint64_t wcap = wbits[k] / 32 + geo[i].nchunks + 1;
         if ((s = res_alloc(c, R, wcap + kWordPad, &res[i].words))) return s;
+        if ((s = res_alloc(c, R, (wcap + 31) / 32 + wcap, &R->d_esec))) return s;
         if ((s = res_alloc(c, R, std::max<uint64_t>(nout, 1), &res[i].outlier_idx))) return s;
         if ((s = res_alloc(c, R, std::max<uint64_t>(nout, 1), &res[i].outlier_val))) return s;
         res[i].n_outliers = nout;
@@ -1527,10 +1549,31 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         for (uint32_t j = 0; j < nf; ++j) {
             hfd[j] = fds[hord[j]];
             hfd[j].chunk_base = cb;
+            hfd[j].nzw = d_fnz + j;
             cb += hfd[j].nchunks;
         }
     }
-    // part 2: Huffman stats, block scans, encode with outlier compaction
+    // the elision's fields (encode order): words, section, the device word
+    // offsets that bound them; tiles of each field's word capacity
+    std::vector<ElideField> ef(nf);
+    std::vector<uint64_t> etoff(nf + 1, 0);
+    for (size_t g = 0; g < groups.size(); ++g)
+        for (uint32_t j = groups[g].fs; j < groups[g].fe; ++j) {
+            const uint64_t lo = gboff[gboff_at[g] + (j - groups[g].fs)];
+            const uint64_t hi = gboff[gboff_at[g] + (j - groups[g].fs) + 1];
+            ef[j].words = hfd[j].words;
+            ef[j].sec = ri(&res[perm[hord[j]]])->d_esec;
+            ef[j].wbeg = d_bwoff + goff_at[g] + lo;
+            ef[j].wend = d_bwoff + goff_at[g] + hi;
+            ef[j].nzw = d_fnz + j;
+            ef[j].nw = 0;
+        }
+    for (uint32_t j = 0; j < nf; ++j)
+        etoff[j + 1] = etoff[j] + (hfd[j].words_cap + kElideTileWords - 1) / kElideTileWords;
+    const uint64_t etiles = etoff[nf];
+    if (etiles > etiles_max) return fail(c, SZ_ERR_DEVICE, "elision tiles exceed their bound");
+    // part 2: Huffman stats, block scans, encode with outlier compaction,
+    // zero-word elision
     auto enqueue2 = [&](hipStream_t q) -> sz_status {
         for (size_t g = 0; g < groups.size(); ++g) {
             const uint32_t fs = groups[g].fs, nfg = groups[g].fe - groups[g].fs;
@@ -1553,6 +1596,10 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
                                               d_booff + goff_at[g], d_bnz + b0, 2 * max_R, q));
             }
         }
+        {
+            STAGE(c, SZ_STAGE_ELIDE, q);
+            HIP_TRY(c, launch_elide(d_ef, (int)nf, d_etoff, etiles, d_ecnt, d_eoff, 0, q));
+        }
         return SZ_OK;
     };
     // sync 2: block word offsets and non-zero word counts (small) to the host
@@ -1563,7 +1610,10 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         char* d = static_cast<char*>(c->arena);
         std::memcpy(h + o_hfd, hfd.data(), sizeof(FieldDesc) * nf);
         std::memcpy(h + o_gboff, gboff.data(), sizeof(uint64_t) * gboff.size());
-        std::vector<uint64_t> sig = {nf, groups.size(), total_blocks, total_chunks, (uint64_t)max_R, L.off};
+        std::memcpy(h + o_ef, ef.data(), sizeof(ElideField) * nf);
+        std::memcpy(h + o_etoff, etoff.data(), sizeof(uint64_t) * (nf + 1));
+        std::vector<uint64_t> sig = {nf, groups.size(), total_blocks, total_chunks, (uint64_t)max_R, L.off,
+                                     etiles};
         for (size_t g = 0; g < groups.size(); ++g) {
             sig.push_back(groups[g].fs);
             sig.push_back(groups[g].fe);
@@ -1588,6 +1638,8 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     } else {
         std::memcpy(hs + o_hfd, hfd.data(), sizeof(FieldDesc) * nf);
         std::memcpy(hs + o_gboff, gboff.data(), sizeof(uint64_t) * gboff.size());
+        std::memcpy(hs + o_ef, ef.data(), sizeof(ElideField) * nf);
+        std::memcpy(hs + o_etoff, etoff.data(), sizeof(uint64_t) * (nf + 1));
         HIP_TRY(c, hipMemcpyAsync(d_hfd, hs + o_hfd, end2 - o_hfd, hipMemcpyHostToDevice, st));
         if (many) HIP_TRY(c, launch_scatter_tables(d_hfd, (int)nf, reinterpret_cast<const uint8_t*>(d_scr + o_cb[0]), st));
         cb_mark.reset();
@@ -2002,22 +2054,13 @@ sz_status sz_serialize(sz_ctx* c, const sz_result* r, void* dst, uint64_t cap, u
     uint64_t pos = 256;
     for (int k = 0; k < 6; ++k) {
         if (k == 3 && words_elided(r, R)) {
-            // the words without their zero words: bitmap, then the others
-            std::vector<uint32_t> w(r->n_words);
-            HIP_TRY(c, hipMemcpy(w.data(), r->words, r->n_words * 4, hipMemcpyDeviceToHost));
-            const uint64_t nbm = (r->n_words + 31) / 32;
-            std::vector<uint32_t> sec(elided_words(r->n_words, R->nzw), 0u);
-            uint64_t o = nbm;
-            for (uint64_t j = 0; j < r->n_words; ++j)
-                if (w[j]) {
-                    if (o == sec.size()) return fail(c, SZ_ERR_DEVICE, "non-zero word count changed");
-                    sec[j / 32] |= 1u << (j % 32);
-                    sec[o++] = w[j];
-                }
-            if (o != sec.size()) return fail(c, SZ_ERR_DEVICE, "non-zero word count changed");
-            std::memcpy(out + pos, sec.data(), sec.size() * 4);
-            put32(h, 224 + 4 * k, crc32_update(0, out + pos, sec.size() * 4));
-            pos += pad8(sec.size() * 4);
+            // the words without their zero words, as the compression built
+            // them on the device: bitmap, then the others
+            if (!R->d_esec) return fail(c, SZ_ERR_INVALID_ARG, "no elided words section");
+            const uint64_t nsec = elided_words(r->n_words, R->nzw);
+            HIP_TRY(c, hipMemcpy(out + pos, R->d_esec, nsec * 4, hipMemcpyDeviceToHost));
+            put32(h, 224 + 4 * k, crc32_update(0, out + pos, nsec * 4));
+            pos += pad8(nsec * 4);
             continue;
         }
         if (secs[k].bytes) HIP_TRY(c, hipMemcpy(out + pos, secs[k].src, secs[k].bytes, hipMemcpyDeviceToHost));
@@ -2095,21 +2138,15 @@ sz_status sz_upload(sz_ctx* c, const void* blob, uint64_t bytes, void* stream, s
             if (b[q]) return fail(c, SZ_ERR_CORRUPT, "section %d padding is not zero", k);
         pos += pad8(secb[k]);
     }
-    // the raw words: the words section itself, or its zero words restored
-    std::vector<uint32_t> words_host;
-    const uint8_t* words_src = b + off[3];
+    // an elided section must have no bit past the words and no zero among
+    // the words it keeps (its zero words are restored on the device below)
     if (elided) {
         const uint64_t nbm = (r.n_words + 31) / 32;
-        words_host.assign(r.n_words, 0u);
-        uint64_t o = nbm;
-        for (uint64_t j = 0; j < nbm * 32; ++j) {
-            if (!((get32(b + off[3], 4 * (j / 32)) >> (j % 32)) & 1u)) continue;
-            const uint32_t v = get32(b + off[3], 4 * o++);
-            if (j >= r.n_words || v == 0)
-                return fail(c, SZ_ERR_CORRUPT, "elided words: bit past the end or a zero word");
-            words_host[j] = v;
-        }
-        words_src = reinterpret_cast<const uint8_t*>(words_host.data());
+        if (r.n_words % 32 && (get32(b + off[3], 4 * (nbm - 1)) >> (r.n_words % 32)))
+            return fail(c, SZ_ERR_CORRUPT, "elided words: bit past the end");
+        for (uint64_t j = nbm; j < wsec; ++j)
+            if (get32(b + off[3], 4 * j) == 0u)
+                return fail(c, SZ_ERR_CORRUPT, "elided words: a zero word among the kept ones");
     } else {
         for (uint64_t j = 0; j < r.n_words; ++j) nzw += get32(b + off[3], 4 * j) != 0u;
     }
@@ -2171,23 +2208,57 @@ sz_status sz_upload(sz_ctx* c, const void* blob, uint64_t bytes, void* stream, s
     if ((s = res_alloc(c, R, r.n_anchors, &r.anchors)) || (s = res_alloc(c, R, nsym, &r.code_len)) ||
         (s = res_alloc(c, R, std::max<uint64_t>(r.n_chunks, 1), &r.chunk_bits)) ||
         (s = res_alloc(c, R, r.n_words + kWordPad, &r.words)) ||
+        (elided && (s = res_alloc(c, R, wsec, &R->d_esec))) ||
         (s = res_alloc(c, R, std::max<uint64_t>(r.n_outliers, 1), &r.outlier_idx)) ||
         (s = res_alloc(c, R, std::max<uint64_t>(r.n_outliers, 1), &r.outlier_val)) ||
         (s = res_alloc(c, R, nsym, &R->d_cbook)) || (s = res_alloc(c, R, dtab.size(), &R->d_dtab))) {
         release_result(c, &r);
         return s;
     }
-    void* dsts[6] = {r.anchors, r.code_len, r.chunk_bits, r.words, r.outlier_idx, r.outlier_val};
-    const uint64_t upb[6] = {secb[0], secb[1], secb[2], r.n_words * 4, secb[4], secb[5]};
+    void* dsts[6] = {r.anchors, r.code_len, r.chunk_bits, elided ? (void*)R->d_esec : (void*)r.words,
+                     r.outlier_idx, r.outlier_val};
     for (int k = 0; k < 6; ++k)
-        if (upb[k]) {
-            const uint8_t* src = k == 3 ? words_src : b + off[k];
-            hipError_t e = hipMemcpyAsync(dsts[k], src, upb[k], hipMemcpyHostToDevice, st);
+        if (secb[k]) {
+            hipError_t e = hipMemcpyAsync(dsts[k], b + off[k], secb[k], hipMemcpyHostToDevice, st);
             if (e != hipSuccess) {
                 release_result(c, &r);
                 return fail(c, SZ_ERR_DEVICE, "upload copy: %s", hipGetErrorString(e));
             }
         }
+    Scratch sc(c);
+    if (elided && r.n_words) {
+        // the words from the elided section, on the device
+        ElideField e;
+        e.words = r.words;
+        e.sec = R->d_esec;
+        e.wbeg = e.wend = nullptr;
+        e.nzw = nullptr;
+        e.nw = r.n_words;
+        const uint64_t tiles = (r.n_words + kElideTileWords - 1) / kElideTileWords;
+        const uint64_t toff[2] = {0, tiles};
+        char* d;
+        Layout L;
+        const size_t o_e = L.take<ElideField>(1), o_t = L.take<uint64_t>(2);
+        const size_t o_c = L.take<uint32_t>(tiles), o_o = L.take<uint64_t>(tiles + 1);
+        if ((s = sc.get(L.off, &d))) {
+            release_result(c, &r);
+            return s;
+        }
+        hipError_t e1 = hipMemcpyAsync(d + o_e, &e, sizeof e, hipMemcpyHostToDevice, st);
+        hipError_t e2 = hipMemcpyAsync(d + o_t, toff, sizeof toff, hipMemcpyHostToDevice, st);
+        hipError_t e3 = hipSuccess;
+        if (e1 == hipSuccess && e2 == hipSuccess) {
+            STAGE(c, SZ_STAGE_ELIDE, st);
+            e3 = launch_elide(reinterpret_cast<ElideField*>(d + o_e), 1,
+                              reinterpret_cast<uint64_t*>(d + o_t), tiles,
+                              reinterpret_cast<uint32_t*>(d + o_c), reinterpret_cast<uint64_t*>(d + o_o),
+                              1, st);
+        }
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+            release_result(c, &r);
+            return fail(c, SZ_ERR_DEVICE, "upload: restoring the elided words failed");
+        }
+    }
     hipError_t e1 = hipMemcpyAsync(R->d_cbook, cbook.data(), 4 * nsym, hipMemcpyHostToDevice, st);
     hipError_t e2 = hipMemcpyAsync(R->d_dtab, dtab.data(), 4 * dtab.size(), hipMemcpyHostToDevice, st);
     hipError_t e3 = hipStreamSynchronize(st);

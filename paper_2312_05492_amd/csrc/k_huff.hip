@@ -73,6 +73,8 @@ __global__ __launch_bounds__(256) void k_huff_stats(const FieldDesc* __restrict_
     const int f = block_field(boff, nfields, blockIdx.x);
     const FieldDesc& fd = F[f];
     const int nsym = 2 * fd.R;
+    // the field's non-zero word count, which its encode blocks add to
+    if (threadIdx.x == 0 && blockIdx.x == boff[f] && fd.nzw) *gp(fd.nzw) = 0ull;
     for (int s = threadIdx.x; s < nsym; s += blockDim.x) cb[s] = gp(fd.cbook)[s];
     __syncthreads();
     const uint64_t first = (blockIdx.x - boff[f]) * kEncChunks;
@@ -309,11 +311,15 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
         }
         wave_lds_sync();
     }
-    // one count per block (no atomics on a shared counter)
+    // one count per block, and one atomic per block for the field's total
     nz = wave_sum(nz);
     if (lane == 0) wnz[wave] = nz;
     __syncthreads();
-    if (threadIdx.x == 0) bnz[blockIdx.x] = wnz[0] + wnz[1] + wnz[2] + wnz[3];
+    if (threadIdx.x == 0) {
+        const uint32_t t = wnz[0] + wnz[1] + wnz[2] + wnz[3];
+        bnz[blockIdx.x] = t;
+        if (fd.nzw) atomicAdd(fd.nzw, (unsigned long long)t);
+    }
 }
 
 // One lane decodes one chunk: canonical decode with a 2^kLutBits table of
@@ -504,7 +510,130 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
     }
 }
 
+// ------------------------------------------------------- zero-word elision
+// The de-redundancy step after Huffman coding (taking the place of the
+// closed pass of Sec. VI-B): the words section becomes a bitmap of the
+// non-zero words (bit k % 32 of bitmap word k / 32 for word k) followed by
+// those words in order.  Work is split into tiles of kElideTile words, one
+// wave per tile: a count pass, an exclusive scan of the tile counts over all
+// fields (k_scan_blocks), and a write pass.  The restore (upload of an
+// elided blob) runs the same tiling backwards: counts of set bits, scan,
+// then each tile's words in place.
+constexpr int kElideTile = (int)kElideTileWords;
+static_assert(kElideTile % 64 == 0, "a tile is whole 64-word ballots");
+
+__device__ __forceinline__ uint64_t elide_words(const ElideField& e) {
+    return e.wbeg ? *e.wend - *e.wbeg : e.nw;
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// restore = 0: non-zero words per tile of the words; 1: set bits per tile
+// of the bitmap (the tile's 64 bitmap words)
+template <int RESTORE>
+__global__ __launch_bounds__(256) void k_elide_count(const ElideField* __restrict__ E, int nf,
+                                                     const uint64_t* __restrict__ toff,
+                                                     uint64_t ntiles, uint32_t* cnt) {
+    const uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    if (tile >= ntiles) return;
+    const int f = block_field(toff, nf, tile);
+    const ElideField& e = E[f];
+    const uint64_t nw = elide_words(e);
+    const uint64_t w0 = (tile - toff[f]) * kElideTile;
+    uint32_t n = 0;
+    if (!RESTORE && e.nzw && (nw + 31) / 32 + *gp(e.nzw) >= nw) {
+        // the field keeps its words: nothing to count
+    } else if (RESTORE) {
+        const uint64_t nbm = (nw + 31) / 32, b = w0 / 32 + lane;
+        const uint32_t m = b < nbm ? gp(e.sec)[b] : 0u;
+        n = (uint32_t)__popc(m);
+        for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
+    } else {
+        uint32_t w[kElideTile / 64];
+#pragma unroll
+        for (int it = 0; it < kElideTile / 64; ++it) {
+            const uint64_t i = w0 + (uint64_t)it * 64 + lane;
+            w[it] = i < nw ? gp(e.words)[i] : 0u;
+        }
+#pragma unroll
+        for (int it = 0; it < kElideTile / 64; ++it)
+            n += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(w[it] != 0u));
+    }
+    if (lane == 0) cnt[tile] = n;
+}
+
+// elision: bitmap words and non-zero words of a tile into e.sec, if the
+// field's section is shorter than its words (else nothing is written)
+__global__ __launch_bounds__(256) void k_elide_write(const ElideField* __restrict__ E, int nf,
+                                                     const uint64_t* __restrict__ toff,
+                                                     uint64_t ntiles, const uint64_t* __restrict__ off) {
+    const uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    if (tile >= ntiles) return;
+    const int f = block_field(toff, nf, tile);
+    const ElideField& e = E[f];
+    const uint64_t nw = elide_words(e), nbm = (nw + 31) / 32;
+    const uint64_t first = off[toff[f]];
+    const uint64_t nz = e.nzw ? (uint64_t)*gp(e.nzw) : off[toff[f + 1]] - first;
+    if (nbm + nz >= nw) return;
+    const uint64_t w0 = (tile - toff[f]) * kElideTile;
+    if (w0 >= nw) return;
+    uint64_t at = nbm + (off[tile] - first);
+    SZI_G uint32_t* sec = gp(e.sec);
+#pragma unroll 4
+    for (int it = 0; it < kElideTile / 64; ++it) {
+        const uint64_t i0 = w0 + (uint64_t)it * 64, i = i0 + lane;
+        const uint32_t w = i < nw ? gp(e.words)[i] : 0u;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(w != 0u);
+        if (lane < 2 && i0 + 32 * lane < nw) sec[i0 / 32 + lane] = (uint32_t)(m >> (32 * lane));
+        if (w) sec[at + lanes_below(m)] = w;
+        at += (uint64_t)__popcll(m);
+    }
+}
+
+// restore: the words of a tile from the bitmap and the non-zero words
+__global__ __launch_bounds__(256) void k_restore_write(const ElideField* __restrict__ E, int nf,
+                                                       const uint64_t* __restrict__ toff,
+                                                       uint64_t ntiles, const uint64_t* __restrict__ off) {
+    const uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    if (tile >= ntiles) return;
+    const int f = block_field(toff, nf, tile);
+    const ElideField& e = E[f];
+    const uint64_t nw = elide_words(e), nbm = (nw + 31) / 32;
+    const uint64_t w0 = (tile - toff[f]) * kElideTile;
+    if (w0 >= nw) return;
+    uint64_t at = nbm + (off[tile] - off[toff[f]]);
+    const SZI_G uint32_t* sec = gp(e.sec);
+#pragma unroll 4
+    for (int it = 0; it < kElideTile / 64; ++it) {
+        const uint64_t i0 = w0 + (uint64_t)it * 64, i = i0 + lane;
+        const uint32_t lo = i0 / 32 < nbm ? sec[i0 / 32] : 0u;
+        const uint32_t hi = i0 / 32 + 1 < nbm ? sec[i0 / 32 + 1] : 0u;
+        const uint64_t m = (uint64_t)lo | (uint64_t)hi << 32;
+        const bool set = (m >> lane) & 1u;
+        if (i < nw) gp(e.words)[i] = set ? sec[at + lanes_below(m)] : 0u;
+        at += (uint64_t)__popcll(m);
+    }
+}
+
 // ------------------------------------------------------- launchers
+hipError_t launch_elide(const ElideField* d_e, int nf, const uint64_t* d_toff, uint64_t ntiles,
+                        uint32_t* d_cnt, uint64_t* d_off, int restore, hipStream_t st) {
+    if (ntiles == 0) return hipSuccess;
+    const dim3 g((unsigned)((ntiles + 3) / 4)), b(256);
+    if (restore) hipLaunchKernelGGL(k_elide_count<1>, g, b, 0, st, d_e, nf, d_toff, ntiles, d_cnt);
+    else hipLaunchKernelGGL(k_elide_count<0>, g, b, 0, st, d_e, nf, d_toff, ntiles, d_cnt);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, d_cnt, (const uint32_t*)nullptr,
+                       ntiles, d_off, (uint64_t*)nullptr);
+    if (restore) hipLaunchKernelGGL(k_restore_write, g, b, 0, st, d_e, nf, d_toff, ntiles, d_off);
+    else hipLaunchKernelGGL(k_elide_write, g, b, 0, st, d_e, nf, d_toff, ntiles, d_off);
+    return hipGetLastError();
+}
+
 hipError_t launch_huff_stats(const FieldDesc* d_fields, int nfields, const uint64_t* d_boff,
                              uint64_t nblocks, int chunk, uint32_t* d_cwords, uint32_t* d_couts,
                              uint32_t* d_bw, uint32_t* d_bo, int max_nsym, hipStream_t st) {

@@ -50,6 +50,7 @@ struct FieldDesc {
     uint32_t* outlier_idx;
     float* outlier_val;
     const uint32_t* dtab;  // decode tables (see DecodeTables layout)
+    unsigned long long* nzw;  // compress: the field's non-zero words (stats clears, encode adds)
 };
 
 // One pass of the interpolation (Sec. V-A: levels from stride S/2 to 1, one
@@ -152,12 +153,33 @@ hipError_t launch_huff_stats(const FieldDesc* d_fields, int nfields, const uint6
                              uint32_t* d_bw, uint32_t* d_bo, int max_nsym, hipStream_t st);
 hipError_t launch_scan_blocks(const uint32_t* d_a, const uint32_t* d_b, uint64_t n,
                               uint64_t* d_aoff, uint64_t* d_boff, hipStream_t st);
-// d_bnz: per encode block, the number of non-zero words it wrote
+// d_bnz: per encode block, the number of non-zero words it wrote (each
+// block also adds it to its field's *nzw, where nzw is set)
 hipError_t launch_huff_encode(const FieldDesc* d_fields, int nfields, const uint64_t* d_boff,
                               uint64_t nblocks, int chunk, const uint32_t* d_cwords,
                               const uint32_t* d_couts, const uint64_t* d_bwoff,
                               const uint64_t* d_booff, uint32_t* d_bnz, int max_nsym,
                               hipStream_t st);
+// Zero-word elision of one field's Huffman words: words (the field's word
+// array), sec (the elided section: bitmap words, then the non-zero words;
+// capacity (n_words + 31) / 32 + n_words), and the word count, either n or
+// read on the device as *wend - *wbeg (the field's block word offsets).
+// nzw, when set, is the field's count of non-zero words from the encoder:
+// a field that does not elide is then skipped without reading its words.
+struct ElideField {
+    uint32_t* words;
+    uint32_t* sec;
+    const uint64_t* wbeg;
+    const uint64_t* wend;
+    const unsigned long long* nzw;
+    uint64_t nw;
+};
+constexpr uint64_t kElideTileWords = 2048;
+// restore = 0: elide words into sec where that is shorter; 1: restore words
+// from sec.  Fields own the tiles [toff[f], toff[f + 1]) of kElideTileWords
+// words; cnt and off (u32[ntiles], u64[ntiles + 1]) are scratch.
+hipError_t launch_elide(const ElideField* d_e, int nf, const uint64_t* d_toff, uint64_t ntiles,
+                        uint32_t* d_cnt, uint64_t* d_off, int restore, hipStream_t st);
 // d_bsum: the word count of every decode block (launch_dec_prep)
 hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields, const uint64_t* d_dboff,
                               uint64_t nblocks, const uint32_t* d_bsum, int max_nsym,

@@ -77,3 +77,36 @@ def test_elided_blob_with_a_flipped_bitmap_bit_is_rejected(ctx):
     with pytest.raises(szi.SzError) as e:
         ctx.upload(bytes(blob))
     assert e.value.code == -5
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_batch_elision_mixed_fields(ctx, graphs):
+    """One elision launch covers every field of a batch: fields that elide
+    and fields that keep their words, each spanning several 2048-word
+    tiles, give the oracle's blobs; elided ones restore on upload."""
+    xs = [synth.climate_field(921, shape=(360, 720)),
+          synth.spectral_field((40, 56, 72), seed=922),
+          synth.climate_field(923, shape=(300, 500)),
+          synth.climate_field(924, shape=(7, 9))]
+    kws = [dict(eb=1e-3), dict(eb=1e-3), dict(eb=1e-2), dict(eb=1e-3)]
+    refs = [O.compress(x, O.Params(shape=x.shape, **kw)) for x, kw in zip(xs, kws)]
+    assert [_flags(r.blob()) for r in refs[:3]] == [O.FLAG_WORDS_ELIDED, 0, O.FLAG_WORDS_ELIDED]
+    print("\n[elision batch] graphs=%s shapes=%s" % (graphs, [x.shape for x in xs]), flush=True)
+    ctx.set_graphs(graphs)
+    try:
+        for rep in range(2):
+            res = ctx.compress_batch([_gpu(x) for x in xs], kws)
+            try:
+                for x, ref, r in zip(xs, refs, res):
+                    blob = r.blob()
+                    assert blob == ref.blob(), (rep, x.shape)
+                    up = ctx.upload(blob)
+                    try:
+                        assert np.array_equal(up.read(szi.SEC_WORDS), ref.words)
+                    finally:
+                        up.free()
+            finally:
+                for r in res:
+                    r.free()
+    finally:
+        ctx.set_graphs(False)

@@ -322,6 +322,27 @@ def test_full_size_512_cube(ctx):
     res.free()
 
 
+@pytest.mark.parametrize("case", ["climate_1800x3600", "spectral_100x500x500_e4",
+                                  "front_256x384x384_e2"])
+def test_full_size_batch_shapes(ctx, case):
+    # one field at each full shape of the batched workloads, against the
+    # oracle: a climate field (2D, 5 % fill), a k^-3 field of the uneven
+    # batch at rel 1e-4 and its tanh front at rel 1e-2
+    print("\n[parity] full shape %s" % case, flush=True)
+    if case.startswith("climate"):
+        x, eb = synth.climate_field(300), 1e-3
+    elif case.startswith("spectral"):
+        x, eb = synth.spectral_field((100, 500, 500), beta=3.0, seed=401), 1e-4
+    else:
+        x, eb = synth.front_field((256, 384, 384), 413), 1e-2
+    ref = O.compress(x, O.Params(shape=x.shape, eb=eb))
+    res = ctx.compress(_to_gpu(x), eb=eb)
+    assert res.blob() == ref.blob()
+    y = ctx.decompress(res).cpu().numpy()
+    assert np.array_equal(_bits(y), _bits(ref.recon))
+    res.free()
+
+
 def test_graph_mode_replays_equal_eager(ctx):
     # graph mode against the default mode: several replays of the same
     # signature with eager work and synchronizations between them, a new

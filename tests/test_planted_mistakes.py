@@ -37,7 +37,7 @@ CASES = {
          [P.test_bitstream_hand_example]),
     12: ("Eq. 1 falling instead of rising between 1e-3 and 1e-2",
          [P.test_alpha_piecewise_linear_and_continuous]),
-    13: ("relative bound scaled by the maximum instead of the range (Sec. V-B.2)",
+    13: ("relative bound scaled by the maximum instead of the range (Sec. V-C.1)",
          [P.test_level_bounds_exact_rational]),
 }
 
