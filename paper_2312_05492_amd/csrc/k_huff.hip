@@ -325,24 +325,20 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
 // One lane decodes one chunk: canonical decode with a 2^kLutBits table of
 // u16 entries for short codes; a longer code's length comes from comparing
 // the next bits with the per-length limits, without a loop or a
-// data-dependent branch.  The next bits sit most significant first in a
-// 64-bit buffer, topped up (without a branch) by one word whenever 32 or
-// fewer remain (a lookup needs at most kLmax = 24).  The words come from a
-// 32-word ring per lane in LDS: once per group of 8 symbols every lane
-// requests its next 8 words from global memory (two 16-byte loads, if the
-// ring has room) and commits them to the ring one group later, so global
-// loads sit at fixed points and their latency is covered by a group of
-// decoding.  A group consumes at most 6 words and the ring always holds at
-// least 7 ahead of the buffer.  Every step also reads the ring word the
-// next top-up takes, off the critical path of the table lookups.  Symbols
-// leave 64 at a time per lane in eight back-to-back 16-byte stores.
+// data-dependent branch.  The next bits are a 32-bit window taken with one
+// funnel shift from two words held in registers, w0:w1, at bit o of w0
+// (1 <= o <= 32, so w1 is always whole and the window always has 32 valid
+// bits; a lookup needs at most kLmax = 24).  When o passes 32 the words move
+// up by one, w1 taking the next word, which every step has already read from
+// the lane's ring, off the critical path of the table lookups.  The ring is
+// 32 words per lane in LDS: once per group of 8 symbols every lane requests
+// its next 8 words from global memory (two 16-byte loads, if the ring has
+// room) and commits them to the ring one group later, so global loads sit at
+// fixed points and their latency is covered by a group of decoding.  A group
+// consumes at most 6 words and the ring always holds at least 7 ahead of the
+// window.  Symbols leave 64 at a time per lane in eight back-to-back 16-byte
+// stores.
 constexpr int kRing = 32;   // ring words per lane (power of 2)
-
-__device__ __forceinline__ int ring_slot(uint32_t i, uint32_t sw) {
-    // 16-byte groups of the ring are permuted per lane, so that lanes at the
-    // same ring position hit different LDS banks
-    return (int)((((i >> 2) ^ sw) & (kRing / 4 - 1)) << 2 | (i & 3u));
-}
 
 __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __restrict__ F,
                                                             int nfields,
@@ -356,15 +352,31 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
     uint32_t* scan = smem;                                   // kDecChunks / 64
     uint64_t* pre = reinterpret_cast<uint64_t*>(smem + kDecChunks / 64);   // kDecChunks / 64
     uint32_t* rings = smem + 3 * (kDecChunks / 64);          // kDecChunks x kRing, 16-byte aligned
-    uint32_t* tab = rings + kDecChunks * kRing;
+    uint32_t* tab = rings + kDecChunks * kRing;              // 16-byte aligned
     const uint16_t* lut = reinterpret_cast<const uint16_t*>(tab);
-    for (int k = threadIdx.x; k < ntab; k += blockDim.x) tab[k] = gp(fd.dtab)[k];
+    const int tid = threadIdx.x;
+    {
+        // the decode tables, 16 bytes at a time with four loads in flight
+        // (word by word where they do not start on 16 bytes: odd radius)
+        const SZI_G vu4* src = reinterpret_cast<const SZI_G vu4*>(gp(fd.dtab));
+        vu4* dst = reinterpret_cast<vu4*>(tab);
+        const int n4 = ((uintptr_t)fd.dtab & 15u) == 0u ? ntab / 4 : 0;
+        for (int k0 = tid; k0 < n4; k0 += 4 * kDecChunks) {
+            vu4 v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (k0 + j * kDecChunks < n4) v[j] = src[k0 + j * kDecChunks];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (k0 + j * kDecChunks < n4) dst[k0 + j * kDecChunks] = v[j];
+        }
+        for (int k = 4 * n4 + tid; k < ntab; k += kDecChunks) tab[k] = gp(fd.dtab)[k];
+    }
     // length limits of the codes longer than the LUT, in scalar registers
     uint32_t lim[kLmax - kLutBits - 1];
 #pragma unroll
     for (int l = kLutBits + 1; l < kLmax; ++l)
         lim[l - kLutBits - 1] = __builtin_amdgcn_readfirstlane(gp(fd.dtab)[kDtLimit + l]);
-    const int tid = threadIdx.x;
     const uint64_t first = (blockIdx.x - boff[f]) * kDecChunks;
     const uint64_t ch = first + tid;
     const bool live = ch < fd.nchunks;
@@ -385,68 +397,77 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
     uint64_t before = 0;
     for (int k = 0; k < kDecChunks / 64; ++k) before += pre[k];
     for (int k = 0; k < (tid >> 6); ++k) before += scan[k];
-    const uint64_t w0 = before + wx;
+    const uint64_t w0abs = before + wx;
     const int C = fd.chunk;
     const uint64_t s0 = ch * (uint64_t)C;
     const int cnt = !live ? 0 : (s0 + C <= fd.npts ? C : (int)(fd.npts - s0));
     if (cnt == 0) return;
-    // requests start at the 4-aligned word at or below w0 and stop at the
-    // end of the field's words (the array has kWordPad words of slack, so
-    // the 8-word loads of the last request stay inside it)
-    const uint64_t wcap = fd.words_cap;
-    const SZI_G uint32_t* words = gp(fd.words);
+    // word indices count from the 4-aligned word at or below the chunk's
+    // first; requests stop at the end of the field's words (the array has
+    // kWordPad words of slack, so the 8-word loads of the last request stay
+    // inside it)
+    const uint64_t wbase = w0abs & ~(uint64_t)3;
+    const SZI_G uint32_t* words = gp(fd.words) + wbase;
+    const uint64_t wleft = fd.words_cap > wbase ? fd.words_cap - wbase : 0;
+    const uint32_t wcap = wleft < (1u << 30) ? (uint32_t)wleft : (1u << 30);
+    // the lane's ring: word i at ring[(i ^ sw) % kRing], the 16-byte groups
+    // permuted per lane so that lanes at the same position hit different banks
     uint32_t* ring = rings + tid * kRing;
-    const uint32_t sw = (uint32_t)tid & (kRing / 4 - 1);
-    uint64_t wr = w0 & ~(uint64_t)3;   // next word to request
-    uint64_t rd = w0;                  // next word to move into the buffer
-    auto put = [&](uint64_t at, vu4 a, vu4 b) SZI_INLINE {   // words [at, at + 8) into the ring
-        *reinterpret_cast<vu4*>(ring + ring_slot((uint32_t)at, sw)) = a;
-        *reinterpret_cast<vu4*>(ring + ring_slot((uint32_t)at + 4u, sw)) = b;
+    const uint32_t sw = ((uint32_t)tid & (kRing / 4 - 1)) << 2;
+    auto slot = [&](uint32_t i) SZI_INLINE { return (i ^ sw) & (uint32_t)(kRing - 1); };
+    auto put = [&](uint32_t at, vu4 a, vu4 b) SZI_INLINE {   // words [at, at + 8) into the ring
+        *reinterpret_cast<vu4*>(ring + slot(at)) = a;
+        *reinterpret_cast<vu4*>(ring + slot(at + 4u)) = b;
     };
+    uint32_t wr = 0;                              // next word to request
+    uint32_t rd = (uint32_t)(w0abs - wbase);      // next word to read from the ring
     // prime the ring with 16 words
     {
         vu4 a = {0u, 0u, 0u, 0u}, b = a, c = a, d = a;
-        if (wr < wcap) {
-            a = *reinterpret_cast<const SZI_G vu4*>(words + wr);
-            b = *reinterpret_cast<const SZI_G vu4*>(words + wr + 4);
+        if (wcap > 0) {
+            a = *reinterpret_cast<const SZI_G vu4*>(words);
+            b = *reinterpret_cast<const SZI_G vu4*>(words + 4);
         }
-        if (wr + 8 < wcap) {
-            c = *reinterpret_cast<const SZI_G vu4*>(words + wr + 8);
-            d = *reinterpret_cast<const SZI_G vu4*>(words + wr + 12);
+        if (wcap > 8) {
+            c = *reinterpret_cast<const SZI_G vu4*>(words + 8);
+            d = *reinterpret_cast<const SZI_G vu4*>(words + 12);
         }
-        put(wr, a, b);
-        put(wr + 8, c, d);
-        wr += 16;
+        put(0u, a, b);
+        put(8u, c, d);
+        wr = 16;
     }
-    auto rword = [&](uint64_t i) SZI_INLINE { return ring[ring_slot((uint32_t)i, sw)]; };
-    uint64_t buf = ((uint64_t)rword(rd) << 32) | (uint64_t)rword(rd + 1);
-    rd += 2;
-    int nb = 64;
-    uint32_t nxw = rword(rd);   // the ring word the next top-up takes
+    // the window starts at the top of w1 (o = 32, held as nego = -o)
+    uint32_t w0 = 0u, w1 = ring[slot(rd)];
+    ++rd;
+    uint32_t nxw = ring[slot(rd)];   // the ring word the next move takes
+    int32_t nego = -32;
     auto decode_one = [&]() SZI_INLINE -> uint32_t {
-        const uint32_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
+        // bits [o, o + 32) of w0:w1 (the shift amount is 32 - o, taken mod 32)
+        const uint32_t x = __builtin_amdgcn_alignbit(w0, w1, (uint32_t)nego);
+        const uint32_t e = lut[x >> (32 - kLutBits)];
         uint32_t len = e >> kLutSymBits, sym = e & ((1u << kLutSymBits) - 1u);
-        if (len == 0) {
+        if (wave_any(len == 0)) {
             // longer than the table: the length is one more than the number
             // of length limits at or below the next kLmax bits (canonical
             // codes grow with their length), then one look-up
-            const uint32_t w = (uint32_t)(buf >> (64 - kLmax));
-            len = kLutBits + 1;
+            const uint32_t w = x >> (32 - kLmax);
+            uint32_t ln = kLutBits + 1;
 #pragma unroll
-            for (int l = kLutBits + 1; l < kLmax; ++l) len += w >= lim[l - kLutBits - 1] ? 1u : 0u;
-            const uint32_t i = tab[kDtBase + len] + (w >> (kLmax - len));
-            sym = tab[kDtSorted + (i < (uint32_t)nsym ? i : 0u)];   // a corrupt stream stays inside
+            for (int l = kLutBits + 1; l < kLmax; ++l) ln += w >= lim[l - kLutBits - 1] ? 1u : 0u;
+            const uint32_t i = tab[kDtBase + ln] + (w >> (kLmax - ln));
+            const uint32_t sl = tab[kDtSorted + (i < (uint32_t)nsym ? i : 0u)];   // a corrupt stream stays inside
+            const bool lng = len == 0;
+            sym = lng ? sl : sym;
+            len = lng ? ln : len;
         }
-        buf <<= len;
-        nb -= (int)len;
-        // top-up without a branch: with 32 or fewer bits left (never fewer
-        // than 64 - 2 kLmax) the next word goes in below them; the ring
-        // word at rd is read every time, so the next one is on its way
-        const bool t = nb <= 32;
-        buf |= (uint64_t)(t ? nxw : 0u) << ((32 - nb) & 63);
-        nb += t ? 32 : 0;
+        // o += len; past 32 the words move up by one (len <= kLmax < 32)
+        nego -= (int32_t)len;
+        const bool t = nego < -32;
+        w0 = t ? w1 : w0;
+        w1 = t ? nxw : w1;
+        nego += t ? 32 : 0;
         rd += t ? 1u : 0u;
-        nxw = rword(rd);
+        nxw = ring[slot(rd)];
         return sym;
     };
     SZI_G uint16_t* out = gp(fd.codes) + s0;
@@ -454,13 +475,13 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
     // a group: commit the previous request, maybe request 8 more words,
     // then decode up to 8 symbols
     bool pend = false;
-    uint64_t pat = 0;
+    uint32_t pat = 0;
     vu4 la = {0u, 0u, 0u, 0u}, lb = la;
     auto refill = [&]() SZI_INLINE {
         if (pend) put(pat, la, lb);
         // the ring holds [rd, wr) and a request adds 8; the prefetched word
         // at rd is not overwritten because the ring keeps kRing - 8 >= 7
-        pend = wr < wcap && wr + 8 - rd <= (uint64_t)kRing;
+        pend = wr < wcap && wr + 8 - rd <= (uint32_t)kRing;
         if (pend) {
             pat = wr;
             la = *reinterpret_cast<const SZI_G vu4*>(words + wr);

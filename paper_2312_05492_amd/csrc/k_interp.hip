@@ -85,10 +85,6 @@ __device__ __forceinline__ SZI_G T* at(SZI_G T* base, uint32_t off) {
     return (SZI_G T*)((SZI_G char*)base + (off * (uint32_t)sizeof(T)));
 }
 
-// lane masks straight from a condition (no 0/1 value in a vector register)
-__device__ __forceinline__ bool wave_any(bool c) { return __builtin_amdgcn_ballot_w64(c) != 0; }
-__device__ __forceinline__ uint64_t wave_ballot(bool c) { return __builtin_amdgcn_ballot_w64(c); }
-
 // ------------------------------------------------------------ block staging
 // Slots of the block load, NPRE per lane; slot k of a lane is a (global
 // offset from the window origin, LDS index) pair and whether the lane holds

@@ -119,6 +119,9 @@ CASES = [
     ("denormal_values", lambda: (synth.spectral_field((18, 20, 40), seed=10) * np.float32(1e-40)),
      dict(eb=1e-44, eb_mode=0)),
     ("radius_64", _spec((30, 30, 60), 11, beta=1.0), dict(eb=1e-4, radius=64)),
+    # odd radii: the decode tables start off a 16-byte boundary in the result
+    ("radius_odd_37", _spec((30, 30, 60), 15, beta=1.0), dict(eb=1e-4, radius=37)),
+    ("radius_odd_3", _spec((24, 40, 50), 16, beta=1.0), dict(eb=1e-3, radius=3)),
     ("chunk_256", _spec((30, 30, 60), 12), dict(chunk=256)),
     ("chunk_2048", _spec((30, 30, 60), 12), dict(chunk=2048)),
     ("thin_1x9x100", _spec((1, 9, 100), 13), {}),
