@@ -327,11 +327,16 @@ sz_status sz_result_read(sz_ctx* ctx, const sz_result* res, int32_t section, voi
  * only on the request: the same as a plain call, alone or in any mix.
  *
  * The budget counts, for every running request, an upper bound of the
- * device memory it can take (compression: codes 2 B, words kLmax bits and
- * outliers 8 B per point, plus 1 MiB; decompression: codes 2 B per point
- * plus 1 MiB), and for every compression result not yet freed its actual
- * size.  0 = no limit.  The caller's input and output buffers are not
- * counted.
+ * device memory it can take, and for every compression result not yet freed
+ * its actual size.  Compression: with W = 3 n + 4 (n / 256 + 10) bytes for
+ * the words of n points (kLmax = 24 bits a point, a word a chunk, slack),
+ * 2 n + W + (W + W / 32 + 4) + 8 n + n / 16 + 2 MiB (codes, words, their
+ * elided section while it is built, outliers, scratch, metadata);
+ * decompression: 2 n + 1 MiB (codes).  0 = no limit.  With a budget, the
+ * device memory of all workers together (what they hold and the blocks they
+ * cache for reuse) stays within it: a worker returns cached blocks to the
+ * device, its own first, then every worker's, before an allocation would
+ * pass the budget.  The caller's input and output buffers are not counted.
  *
  * The server may be called from any host thread.  Inputs (the field of a
  * compression, the result and output buffer of a decompression) must stay

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = [os.path.join(HERE, "csrc", f) for f in
-           ("k_plan.hip", "k_interp.hip", "k_huff.hip", "noalloc.hip", "host.cpp")]
+           ("k_plan.hip", "k_interp.hip", "k_huff.hip", "noalloc.hip", "blob.cpp", "host.cpp")]
 LIB = os.path.join(HERE, "libszi.so")
 ARCH = os.environ.get("SZI_OFFLOAD_ARCH", "gfx950")
 

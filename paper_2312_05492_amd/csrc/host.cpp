@@ -21,6 +21,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "blob.h"
 #include "szi.h"
 #include "szi_internal.h"
 
@@ -93,11 +94,20 @@ struct HostPool {
     }
 };
 
+// The device bytes of a server's worker contexts together, against the
+// server's budget: a worker reserves its bytes here before it allocates.
+struct SharedHeld {
+    std::atomic<uint64_t> held{0};
+    uint64_t budget = 0;
+    std::vector<sz_ctx*> ctx;
+};
+
 struct sz_ctx {
     int device = 0;
     int num_cus = 256;
     uint64_t budget = 0;       // 0 = unlimited
     uint64_t held = 0;         // bytes obtained from hipMalloc and not freed
+    SharedHeld* shared = nullptr;   // a server's worker: the server's device bytes
     std::mutex pool_mu;        // pool calls may come from other threads (results freed by a server)
     std::multimap<size_t, void*> free_blocks;
     std::unordered_map<void*, size_t> block_size;
@@ -162,24 +172,62 @@ size_t round_block(size_t b) { return (b + 511) & ~(size_t)511; }
 
 // Caching allocator: freed blocks are kept for reuse (every API call
 // synchronizes its stream before returning, so a freed block is idle).
+// a context's cached free blocks back to the device (its pool_mu held)
+void drop_cache_locked(sz_ctx* c) {
+    for (auto& kv : c->free_blocks) {
+        (void)hipFree(kv.second);
+        const size_t b = c->block_size[kv.second];
+        c->held -= b;
+        if (c->shared) c->shared->held -= b;
+        c->block_size.erase(kv.second);
+    }
+    c->free_blocks.clear();
+}
+
+bool reserve_shared(SharedHeld* sh, uint64_t bytes) {
+    uint64_t cur = sh->held.load();
+    while (cur + bytes <= sh->budget)
+        if (sh->held.compare_exchange_weak(cur, cur + bytes)) return true;
+    return false;
+}
+
 sz_status pool_alloc(sz_ctx* c, size_t bytes, void** out) {
-    std::lock_guard<std::mutex> lock(c->pool_mu);
     if (bytes == 0) bytes = 1;
     bytes = round_block(bytes);
+    std::unique_lock<std::mutex> lock(c->pool_mu);
     auto it = c->free_blocks.lower_bound(bytes);
     if (it != c->free_blocks.end() && it->first <= 2 * bytes + 65536) {
         *out = it->second;
         c->free_blocks.erase(it);
         return SZ_OK;
     }
-    if (c->budget && c->held + bytes > c->budget) {
-        // release cached blocks before giving up
-        for (auto& kv : c->free_blocks) {
-            (void)hipFree(kv.second);
-            c->held -= c->block_size[kv.second];
-            c->block_size.erase(kv.second);
+    if (c->shared) {
+        // a server's worker: the device bytes of all workers stay within the
+        // server's budget; cached blocks go back to the device before an
+        // allocation would pass it, this worker's first, then every worker's
+        // (one pool lock at a time)
+        SharedHeld* sh = c->shared;
+        bool ok = reserve_shared(sh, bytes);
+        if (!ok) {
+            drop_cache_locked(c);
+            ok = reserve_shared(sh, bytes);
         }
-        c->free_blocks.clear();
+        if (!ok) {
+            lock.unlock();
+            for (sz_ctx* o : sh->ctx) {
+                std::lock_guard<std::mutex> g(o->pool_mu);
+                drop_cache_locked(o);
+            }
+            lock.lock();
+            ok = reserve_shared(sh, bytes);
+        }
+        if (!ok)
+            return fail(c, SZ_ERR_OOM, "server budget of %llu bytes exceeded (%llu held, %llu asked)",
+                        (unsigned long long)sh->budget, (unsigned long long)sh->held.load(),
+                        (unsigned long long)bytes);
+    } else if (c->budget && c->held + bytes > c->budget) {
+        // release cached blocks before giving up
+        drop_cache_locked(c);
         if (c->held + bytes > c->budget)
             return fail(c, SZ_ERR_OOM, "device budget of %llu bytes exceeded (%llu held, %llu asked)",
                         (unsigned long long)c->budget, (unsigned long long)c->held,
@@ -189,15 +237,11 @@ sz_status pool_alloc(sz_ctx* c, size_t bytes, void** out) {
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        for (auto& kv : c->free_blocks) {
-            (void)hipFree(kv.second);
-            c->held -= c->block_size[kv.second];
-            c->block_size.erase(kv.second);
-        }
-        c->free_blocks.clear();
+        drop_cache_locked(c);
         e = hipMalloc(&p, bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
+            if (c->shared) c->shared->held -= bytes;
             return fail(c, SZ_ERR_OOM, "hipMalloc(%zu) failed", bytes);
         }
     }
@@ -214,6 +258,7 @@ void pool_free(sz_ctx* c, void* p) {
     if (it == c->block_size.end()) return;
     c->free_blocks.emplace(it->second, p);
 }
+
 
 sz_status pinned_reserve(sz_ctx* c, size_t bytes) {
     if (c->pinned_bytes >= bytes) return SZ_OK;
@@ -401,21 +446,6 @@ sz_status graph_run(sz_ctx* c, int g, std::vector<uint64_t> sig, size_t soff, si
     return SZ_OK;
 }
 
-// ------------------------------------------------------------ CRC-32 (IEEE)
-uint32_t crc32_update(uint32_t crc, const uint8_t* p, size_t n) {
-    static uint32_t table[256];
-    static std::once_flag once;
-    std::call_once(once, [] {
-        for (uint32_t i = 0; i < 256; ++i) {
-            uint32_t c = i;
-            for (int k = 0; k < 8; ++k) c = (c & 1) ? 0xEDB88320u ^ (c >> 1) : c >> 1;
-            table[i] = c;
-        }
-    });
-    crc = ~crc;
-    for (size_t i = 0; i < n; ++i) crc = table[(crc ^ p[i]) & 0xFF] ^ (crc >> 8);
-    return ~crc;
-}
 
 // ------------------------------------------------------------ codebook
 // One package-merge round: merge the sorted leaf weights lw[0, m) (lw[m] a
@@ -565,18 +595,6 @@ void build_tables(const uint8_t* len, int nsym, uint32_t* cbook, uint32_t* dtab)
         if (len[s]) dtab[kDtSorted + off[len[s]]++] = (uint32_t)s;
 }
 
-bool kraft_ok(const uint8_t* len, int nsym) {
-    // sum 2^-len <= 1 with at least one code; all lengths <= kLmax
-    uint64_t sum = 0;
-    int present = 0;
-    for (int s = 0; s < nsym; ++s) {
-        if (!len[s]) continue;
-        if (len[s] > kLmax) return false;
-        sum += (uint64_t)1 << (kLmax - len[s]);
-        ++present;
-    }
-    return present > 0 && sum <= ((uint64_t)1 << kLmax);
-}
 
 // ------------------------------------------------------------ bookkeeping
 struct ResultInternal {
@@ -605,6 +623,16 @@ sz_status res_alloc(sz_ctx* c, ResultInternal* R, size_t count, T** out) {
     return SZ_OK;
 }
 
+// gives one of a result's blocks back to the pool before the result is freed
+void res_release(sz_ctx* c, ResultInternal* R, void* p) {
+    for (size_t k = 0; k < R->blocks.size(); ++k)
+        if (R->blocks[k] == p) {
+            R->blocks.erase(R->blocks.begin() + k);
+            pool_free(c, p);
+            return;
+        }
+}
+
 void release_result(sz_ctx* c, sz_result* r) {
     ResultInternal* R = ri(r);
     if (R) {
@@ -615,83 +643,10 @@ void release_result(sz_ctx* c, sz_result* r) {
     std::memset(r, 0, sizeof(*r));
 }
 
-struct Geometry {
-    int ndim, n[3], S, L, w[3], nwin[3], na[3], R, chunk;
-    uint64_t npts, nanch, nwin_total, nchunks;
-};
-
 sz_status check_field(sz_ctx* c, const sz_dims* d, const sz_params* p, Geometry& g) {
-    if (!d || !p) return fail(c, SZ_ERR_INVALID_ARG, "null dims or params");
-    if (d->ndim != 2 && d->ndim != 3)
-        return fail(c, SZ_ERR_UNSUPPORTED, "ndim %u (2 and 3 are supported)", d->ndim);
-    g.ndim = (int)d->ndim;
-    uint64_t npts = 1;
-    for (int k = 0; k < 3; ++k) {
-        if (k < g.ndim) {
-            if (d->n[k] == 0 || d->n[k] >= (1ull << 31))
-                return fail(c, SZ_ERR_INVALID_ARG, "n[%d] = %llu", k, (unsigned long long)d->n[k]);
-            g.n[k] = (int)d->n[k];
-            npts *= d->n[k];
-        } else {
-            g.n[k] = 1;
-        }
-    }
-    if (npts >= 0xFFFFFFFFull)
-        return fail(c, SZ_ERR_INVALID_ARG, "field of %llu points (limit 2^32 - 1)",
-                    (unsigned long long)npts);
-    g.npts = npts;
-    if (p->eb_mode != SZ_EB_ABS && p->eb_mode != SZ_EB_REL)
-        return fail(c, SZ_ERR_INVALID_ARG, "eb_mode %d", p->eb_mode);
-    if (!(p->eb >= 0.0) || p->eb > 1e300)
-        return fail(c, SZ_ERR_INVALID_ARG, "error bound %g", p->eb);
-    if (!(p->alpha <= 1e300)) return fail(c, SZ_ERR_INVALID_ARG, "alpha %g", p->alpha);
-    if (p->alpha > 0.0 && p->alpha < 1.0)
-        return fail(c, SZ_ERR_INVALID_ARG, "alpha %g < 1", p->alpha);
-    for (int k = 0; k < g.ndim; ++k)
-        if (p->interp[k] < 0 || p->interp[k] > 3)
-            return fail(c, SZ_ERR_INVALID_ARG, "interp[%d] = %d", k, p->interp[k]);
-    if (p->order[0] >= 0) {
-        int seen = 0;
-        for (int k = 0; k < g.ndim; ++k) {
-            if (p->order[k] < 0 || p->order[k] >= g.ndim || (seen >> p->order[k]) & 1)
-                return fail(c, SZ_ERR_INVALID_ARG, "order is not a permutation");
-            seen |= 1 << p->order[k];
-        }
-    }
-    g.R = p->radius ? (int)p->radius : 512;
-    if (g.R < 2 || g.R > kMaxRadius)
-        return fail(c, SZ_ERR_UNSUPPORTED, "radius %d (2..%d supported)", g.R, kMaxRadius);
-    g.chunk = p->huff_chunk ? (int)p->huff_chunk : 1024;
-    if (g.chunk != 256 && g.chunk != 512 && g.chunk != 1024 && g.chunk != 2048)
-        return fail(c, SZ_ERR_UNSUPPORTED, "Huffman chunk %d", g.chunk);
-    const int S = g.ndim == 3 ? 8 : 16;
-    if (p->anchor_stride && (int)p->anchor_stride != S)
-        return fail(c, SZ_ERR_UNSUPPORTED, "anchor stride %u (this build: %d)", p->anchor_stride, S);
-    const int wdef[3] = {g.ndim == 3 ? 32 : 64, g.ndim == 3 ? 8 : 16, g.ndim == 3 ? 8 : 1};
-    for (int k = 0; k < g.ndim; ++k)
-        if (p->window[k] && (int)p->window[k] != wdef[k])
-            return fail(c, SZ_ERR_UNSUPPORTED, "window[%d] = %u (this build: %d)", k,
-                        p->window[k], wdef[k]);
-    g.S = S;
-    g.L = g.ndim == 3 ? 3 : 4;
-    g.nwin_total = 1;
-    g.nanch = 1;
-    for (int k = 0; k < 3; ++k) {
-        g.w[k] = wdef[k];
-        g.nwin[k] = (g.n[k] + g.w[k] - 1) / g.w[k];
-        g.na[k] = k < g.ndim ? (g.n[k] + S - 1) / S : 1;
-        g.nwin_total *= g.nwin[k];
-        g.nanch *= g.na[k];
-    }
-    // the window kernels address a block by 32-bit byte offsets from its
-    // origin and number windows with 32-bit integers
-    const uint64_t span = (uint64_t)g.w[0] + (uint64_t)g.w[1] * (uint64_t)g.n[0] +
-                          (g.ndim == 3 ? (uint64_t)g.w[2] * (uint64_t)g.n[0] * (uint64_t)g.n[1] : 0);
-    if (span * sizeof(float) >= (1ull << 32) || g.nwin_total >= (1ull << 31))
-        return fail(c, SZ_ERR_UNSUPPORTED, "field planes too large (window span %llu points)",
-                    (unsigned long long)span);
-    g.nchunks = (npts + g.chunk - 1) / g.chunk;
-    return SZ_OK;
+    std::string why;
+    const sz_status s = check_geometry(d, p, g, &why);
+    return s ? fail(c, s, "%s", why.c_str()) : SZ_OK;
 }
 
 void fill_desc(const Geometry& g, const sz_params* p, FieldDesc& f) {
@@ -719,22 +674,6 @@ void fill_desc(const Geometry& g, const sz_params* p, FieldDesc& f) {
         if (p->interp[k] == SZ_INTERP_CUBIC_AUTO) f.need_prof = 1;
 }
 
-void put32(uint8_t* h, int off, uint32_t v) { std::memcpy(h + off, &v, 4); }
-void put64(uint8_t* h, int off, uint64_t v) { std::memcpy(h + off, &v, 8); }
-void putf(uint8_t* h, int off, float v) { std::memcpy(h + off, &v, 4); }
-void putd(uint8_t* h, int off, double v) { std::memcpy(h + off, &v, 8); }
-uint32_t get32(const uint8_t* h, int off) { uint32_t v; std::memcpy(&v, h + off, 4); return v; }
-uint64_t get64(const uint8_t* h, int off) { uint64_t v; std::memcpy(&v, h + off, 8); return v; }
-float getf(const uint8_t* h, int off) { float v; std::memcpy(&v, h + off, 4); return v; }
-double getd(const uint8_t* h, int off) { double v; std::memcpy(&v, h + off, 8); return v; }
-
-uint64_t pad8(uint64_t b) { return (b + 7) & ~(uint64_t)7; }
-
-// Zero-word elision of the words section (the blob's de-redundancy step
-// after Huffman coding): a bitmap, bit k % 32 of bitmap word k / 32 set for
-// a non-zero word k, then the non-zero words in order; used when shorter.
-constexpr uint32_t kFlagWordsElided = 1;
-uint64_t elided_words(uint64_t n_words, uint64_t nzw) { return (n_words + 31) / 32 + nzw; }
 bool words_elided(const sz_result* r, const ResultInternal* R) {
     return R->d_esec && R->nzw != UINT64_MAX && elided_words(r->n_words, R->nzw) < r->n_words;
 }
@@ -750,8 +689,7 @@ size_t tables_bytes(int nsym) {
 }
 
 uint64_t blob_bytes(const sz_result* r, int R, uint64_t words_bytes) {
-    return 256 + pad8(r->n_anchors * 4) + pad8((uint64_t)2 * R) + pad8(r->n_chunks * 2) +
-           pad8(words_bytes) + pad8(r->n_outliers * 4) + pad8(r->n_outliers * 4);
+    return szi::blob_bytes(r->n_anchors, R, r->n_chunks, words_bytes, r->n_outliers);
 }
 
 // header without CRCs (they are filled by sz_serialize)
@@ -800,6 +738,7 @@ struct sz_server {
     int device = 0;
     uint64_t budget = 0;     // 0 = unlimited
     uint64_t charged = 0;    // estimates of running requests + bytes of held results
+    std::unique_ptr<SharedHeld> shared;   // the workers' device bytes (with a budget)
     std::vector<sz_ctx*> ctx;
     std::vector<hipStream_t> st;
     std::vector<std::thread> th;
@@ -825,14 +764,18 @@ struct sz_server {
 namespace {
 
 // Device memory a request may take while it runs: compression holds the
-// codes (2 B/point), the words (at most kLmax bits per point) and the
-// outlier lists (at most 8 B per point) plus per-field metadata; the replay
-// holds the codes.
+// codes (2 B/point), the words (at most kLmax bits per point, plus a word per
+// chunk of at least 256 symbols and the slack), the elided section of the
+// words while it is built (a bitmap word per 32 words, then the words), the
+// outlier lists (at most 8 B per point), the call's scratch (per chunk,
+// block and tile: under 1/16 B per point) and 2 MiB for per-field metadata
+// and tables; the replay holds the codes.
 uint64_t request_need(const sz_request& r) {
     if (r.kind == SZ_REQ_COMPRESS) {
         uint64_t n = 1;
         for (uint32_t k = 0; k < r.dims.ndim && k < 3; ++k) n *= r.dims.n[k];
-        return 2 * n + (n * kLmax + 7) / 8 + 8 * n + (1u << 20);
+        const uint64_t words = (n * kLmax + 7) / 8 + 4 * (n / 256 + 2 + kWordPad);
+        return 2 * n + words + (words + words / 32 + 4) + 8 * n + n / 16 + (2u << 20);
     }
     const sz_dims& d = r.src ? ri(r.src)->dims : r.dims;
     uint64_t n = 1;
@@ -968,20 +911,6 @@ sz_status tune_shapes(sz_ctx* c, int ndim, hipStream_t st, LaunchShape* best, La
 
 extern "C" {
 
-void sz_params_default(sz_params* p) {
-    if (!p) return;
-    std::memset(p, 0, sizeof *p);
-    p->eb_mode = SZ_EB_REL;
-    p->eb = 1e-3;
-    for (int k = 0; k < 3; ++k) {
-        p->interp[k] = SZ_INTERP_CUBIC_AUTO;
-        p->order[k] = -1;
-    }
-    p->alpha = 0.0;
-    p->radius = 512;
-    p->huff_chunk = 1024;
-}
-
 sz_status sz_ctx_create(sz_ctx** out, int device, uint64_t hbm_budget_bytes) {
     if (!out) return SZ_ERR_INVALID_ARG;
     *out = nullptr;
@@ -1014,7 +943,10 @@ sz_status sz_ctx_create(sz_ctx** out, int device, uint64_t hbm_budget_bytes) {
 sz_status sz_ctx_destroy(sz_ctx* c) {
     if (!c) return SZ_OK;
     (void)hipSetDevice(c->device);
-    for (auto& kv : c->block_size) (void)hipFree(kv.first);
+    for (auto& kv : c->block_size) {
+        (void)hipFree(kv.first);
+        if (c->shared) c->shared->held -= kv.second;
+    }
     for (auto& m : c->marks) {
         (void)hipEventDestroy(m.a);
         (void)hipEventDestroy(m.b);
@@ -1703,6 +1635,10 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
             uint64_t nz = 0;   // non-zero words of the field's encode blocks
             for (uint64_t b = hboff[j]; b < hboff[j + 1]; ++b) nz += bnz[b];
             ri(&res[i])->nzw = nz;
+            if (!words_elided(&res[i], ri(&res[i]))) {   // the section buffer is not needed
+                res_release(c, ri(&res[i]), ri(&res[i])->d_esec);
+                ri(&res[i])->d_esec = nullptr;
+            }
             res[i].compressed_bytes =
                 blob_bytes(&res[i], fds[k].R, words_section_bytes(&res[i], ri(&res[i])));
             make_header(&res[i], ri(&res[i]), res[i].header);
@@ -2075,133 +2011,53 @@ sz_status sz_upload(sz_ctx* c, const void* blob, uint64_t bytes, void* stream, s
     if (!c) return SZ_ERR_INVALID_ARG;
     if (!blob || !out) return fail(c, SZ_ERR_INVALID_ARG, "null argument");
     const uint8_t* b = static_cast<const uint8_t*>(blob);
-    if (bytes < 256) return fail(c, SZ_ERR_CORRUPT, "blob shorter than its header");
-    if (std::memcmp(b, "SZI1", 4)) return fail(c, SZ_ERR_CORRUPT, "bad magic");
-    if (crc32_update(0, b, 252) != get32(b, 252)) return fail(c, SZ_ERR_CORRUPT, "header CRC mismatch");
-    if (get32(b, 4) != 1) return fail(c, SZ_ERR_UNSUPPORTED, "blob version %u", get32(b, 4));
+    BlobInfo bi;
+    {
+        std::string why;
+        const sz_status s = parse_blob(b, bytes, &bi, &why);
+        if (s) return fail(c, s, "%s", why.c_str());
+    }
     HIP_TRY(c, hipSetDevice(c->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    sz_dims d;
-    std::memset(&d, 0, sizeof d);
-    d.ndim = get32(b, 8);
-    for (int k = 0; k < 3; ++k) d.n[k] = get64(b, 16 + 8 * k);
-    sz_params p;
-    sz_params_default(&p);
-    p.radius = get32(b, 52);
-    p.huff_chunk = get32(b, 60);
-    p.eb_mode = (int32_t)get32(b, 64);
-    p.eb = getd(b, 72);
-    p.anchor_stride = get32(b, 12);
-    for (int k = 0; k < 3 && k < (int)d.ndim; ++k) p.window[k] = get32(b, 40 + 4 * k);
-    Geometry g;
-    sz_status s = check_field(c, &d, &p, g);
-    if (s) return s == SZ_ERR_INVALID_ARG ? fail(c, SZ_ERR_CORRUPT, "header: %s", c->err.c_str()) : s;
-    if (get32(b, 56) != (uint32_t)kLmax || (int)get32(b, 68) != g.L)
-        return fail(c, SZ_ERR_CORRUPT, "header: length limit or level count");
+    const Geometry& g = bi.geo;
+    const bool elided = bi.elided;
+    const uint64_t wsec = bi.wsec;
+    const uint64_t* off = bi.off;
+    const uint64_t* secb = bi.secb;
+    const int nsym = 2 * g.R;
+    sz_status s;
     sz_result r;
     std::memset(&r, 0, sizeof r);
     r.n = g.npts;
-    r.n_anchors = get64(b, 192);
-    r.n_chunks = get64(b, 200);
-    r.n_words = get64(b, 208);
-    r.n_outliers = get64(b, 216);
-    if (r.n_anchors != g.nanch || r.n_chunks != g.nchunks || r.n_outliers > g.npts ||
-        r.n_words > (g.npts * kLmax) / 32 + g.nchunks + 1)
-        return fail(c, SZ_ERR_CORRUPT, "header: section sizes");
-    const int nsym = 2 * g.R;
-    const uint32_t flags = get32(b, 124);
-    if ((flags & ~kFlagWordsElided) || get32(b, 248))
-        return fail(c, SZ_ERR_CORRUPT, "reserved header words are not zero");
-    const bool elided = flags & kFlagWordsElided;
-    // an elided words section: its bitmap tells how many words follow
-    uint64_t wsec = r.n_words, nzw = 0;
-    {
-        const uint64_t at = 256 + pad8(r.n_anchors * 4) + pad8((uint64_t)nsym) + pad8(r.n_chunks * 2);
-        const uint64_t nbm = (r.n_words + 31) / 32;
-        if (elided) {
-            if (at + 4 * nbm > bytes) return fail(c, SZ_ERR_CORRUPT, "blob length %llu", (unsigned long long)bytes);
-            for (uint64_t j = 0; j < nbm; ++j) nzw += (uint64_t)__builtin_popcount(get32(b + at, 4 * j));
-            wsec = nbm + nzw;
-            if (wsec >= r.n_words) return fail(c, SZ_ERR_CORRUPT, "elided words are not shorter");
-        }
-    }
-    if (blob_bytes(&r, g.R, 4 * wsec) != bytes)
-        return fail(c, SZ_ERR_CORRUPT, "blob length %llu", (unsigned long long)bytes);
-    const uint64_t secb[6] = {r.n_anchors * 4, (uint64_t)nsym, r.n_chunks * 2,
-                              wsec * 4, r.n_outliers * 4, r.n_outliers * 4};
-    uint64_t off[6], pos = 256;
-    for (int k = 0; k < 6; ++k) {
-        off[k] = pos;
-        if (crc32_update(0, b + pos, secb[k]) != get32(b, 224 + 4 * k))
-            return fail(c, SZ_ERR_CORRUPT, "section %d CRC mismatch", k);
-        for (uint64_t q = pos + secb[k]; q < pos + pad8(secb[k]); ++q)
-            if (b[q]) return fail(c, SZ_ERR_CORRUPT, "section %d padding is not zero", k);
-        pos += pad8(secb[k]);
-    }
-    // an elided section must have no bit past the words and no zero among
-    // the words it keeps (its zero words are restored on the device below)
-    if (elided) {
-        const uint64_t nbm = (r.n_words + 31) / 32;
-        if (r.n_words % 32 && (get32(b + off[3], 4 * (nbm - 1)) >> (r.n_words % 32)))
-            return fail(c, SZ_ERR_CORRUPT, "elided words: bit past the end");
-        for (uint64_t j = nbm; j < wsec; ++j)
-            if (get32(b + off[3], 4 * j) == 0u)
-                return fail(c, SZ_ERR_CORRUPT, "elided words: a zero word among the kept ones");
-    } else {
-        for (uint64_t j = 0; j < r.n_words; ++j) nzw += get32(b + off[3], 4 * j) != 0u;
-    }
-    {
-        // the chunk bit counts must account for exactly the stored words, and
-        // outlier indices must lie inside the field
-        uint64_t words = 0;
-        for (uint64_t j = 0; j < r.n_chunks; ++j) {
-            uint16_t cbits;
-            std::memcpy(&cbits, b + off[2] + 2 * j, 2);
-            words += (cbits + 31u) / 32u;
-        }
-        if (words != r.n_words) return fail(c, SZ_ERR_CORRUPT, "chunk sizes do not match the words");
-        for (uint64_t j = 0; j < r.n_outliers; ++j)
-            if (get32(b + off[4] + 4 * j, 0) >= g.npts)
-                return fail(c, SZ_ERR_CORRUPT, "outlier index outside the field");
-    }
+    r.n_anchors = bi.n_anchors;
+    r.n_chunks = bi.n_chunks;
+    r.n_words = bi.n_words;
+    r.n_outliers = bi.n_outliers;
     ResultInternal* R = new ResultInternal();
     R->owner = c;
     r.internal = R;
-    R->dims = d;
+    R->dims = bi.dims;
     R->S = g.S;
     for (int k = 0; k < 3; ++k) R->w[k] = g.w[k];
     R->R = g.R;
     R->chunk = g.chunk;
-    R->eb_mode = p.eb_mode;
-    R->eb = p.eb;
-    R->nzw = nzw;
+    R->eb_mode = bi.params.eb_mode;
+    R->eb = bi.params.eb;
+    R->nzw = bi.nzw;
     R->code_len.assign(b + off[1], b + off[1] + nsym);
-    if (!kraft_ok(R->code_len.data(), nsym) && r.n > 0) {
-        release_result(c, &r);
-        return fail(c, SZ_ERR_CORRUPT, "code lengths do not form a prefix code");
-    }
     std::memset(&R->plan, 0, sizeof R->plan);
-    R->plan.alpha = getd(b, 80);
-    R->plan.vmin = getf(b, 88);
-    R->plan.vmax = getf(b, 92);
-    R->plan.e = getf(b, 96);
+    R->plan.alpha = bi.alpha;
+    R->plan.vmin = bi.vmin;
+    R->plan.vmax = bi.vmax;
+    R->plan.e = bi.e;
     R->plan.levels = g.L;
     for (int l = 0; l < g.L; ++l) {
-        R->plan.el[l] = getf(b, 128 + 4 * l);
+        R->plan.el[l] = bi.el[l];
         R->plan.ebx2[l] = 2.0f * R->plan.el[l];
     }
-    int seen = 0;
     for (int k = 0; k < 3; ++k) {
-        R->plan.spline[k] = (int32_t)get32(b, 100 + 4 * k);
-        R->plan.order[k] = (int32_t)get32(b, 112 + 4 * k);
-        if (k < g.ndim) {
-            if (R->plan.spline[k] < 0 || R->plan.spline[k] > 2 || R->plan.order[k] < 0 ||
-                R->plan.order[k] >= g.ndim || ((seen >> R->plan.order[k]) & 1)) {
-                release_result(c, &r);
-                return fail(c, SZ_ERR_CORRUPT, "header: spline or order");
-            }
-            seen |= 1 << R->plan.order[k];
-        }
+        R->plan.spline[k] = bi.spline[k];
+        R->plan.order[k] = bi.order[k];
     }
     std::vector<uint32_t> cbook(nsym), dtab(dtab_words(nsym));
     build_tables(R->code_len.data(), nsym, cbook.data(), dtab.data());
@@ -2298,6 +2154,14 @@ sz_status sz_server_create(sz_server** out, int device, int slots, uint64_t hbm_
         }
         s->ctx.push_back(c);
         s->st.push_back(st);
+    }
+    if (s->budget) {
+        // the workers' caches count against the budget together with what
+        // they hold; a worker returns cached blocks before passing it
+        s->shared.reset(new SharedHeld());
+        s->shared->budget = s->budget;
+        s->shared->ctx = s->ctx;
+        for (sz_ctx* c : s->ctx) c->shared = s->shared.get();
     }
     for (int i = 0; i < slots; ++i) s->th.emplace_back(server_worker, s, i);
     *out = s;

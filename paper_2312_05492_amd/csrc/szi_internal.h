@@ -5,12 +5,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "szi_limits.h"
+
 namespace szi {
 
-constexpr int kMaxLevels = 8;
-constexpr int kLmax = 24;          // Huffman length limit
 constexpr int kLutBits = 13;       // decode look-up table width (bits)
-constexpr int kMaxRadius = 1024;   // LDS histogram holds 2R <= 2048 bins
 constexpr int kRangeBlocks = 2048; // partial min/max blocks per field
 constexpr int kThreads = 256;      // threads per interpolation workgroup
 constexpr int kEncBlockChunks = 32;   // Huffman chunks per encode workgroup

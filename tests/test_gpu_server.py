@@ -94,15 +94,24 @@ def test_server_results_equal_plain_calls():
 
 def test_server_budget_admission():
     _skip_without_gpu()
-    fields = [(synth.spectral_field((40, 50, 60), seed=60 + k), dict(eb=1e-3)) for k in range(6)]
-    n = 40 * 50 * 60
-    need = 2 * n + (n * 24 + 7) // 8 + 8 * n + (1 << 20)   # the documented compression bound
+    import torch
+    fields = [(synth.spectral_field((96, 128, 128), seed=60 + k), dict(eb=1e-3)) for k in range(6)]
+    n = 96 * 128 * 128
+    words = 3 * n + 4 * (n // 256 + 10)                     # the documented compression bound
+    need = 2 * n + words + (words + words // 32 + 4) + 8 * n + n // 16 + (2 << 20)
     budget = need + need // 2                               # one compression at a time
     print("\n[server] budget %d bytes, request bound %d" % (budget, need), flush=True)
     xs = [_gpu(f) for f, _ in fields]
     ctx = szi.Context(0)
     ref = [ctx.compress(x, **kw).blob() for x, (_, kw) in zip(xs, fields)]
+    ctx.close()
+    torch.cuda.synchronize()
     srv = szi.Server(0, slots=4, hbm_budget=budget)
+    # the device memory the server holds (free memory is read around the
+    # requests; the driver hands out memory in pages, hence the slack)
+    free0 = torch.cuda.mem_get_info()[0]
+    slack = 16 << 20
+    peak = 0
     for i, (x, (_, kw)) in enumerate(zip(xs, fields)):
         srv.submit_compress(x, tag=i, **kw)
     done = 0
@@ -110,6 +119,8 @@ def test_server_budget_admission():
         st = srv.stats()
         assert st["charged"] <= budget
         assert st["running"] <= 1
+        peak = max(peak, free0 - torch.cuda.mem_get_info()[0])
+        assert peak <= budget + slack, (peak, budget)
         comp = srv.poll(wait=True)
         assert comp, "server stalled"
         for c in comp:
@@ -117,10 +128,12 @@ def test_server_budget_admission():
             assert c["result"].blob() == ref[c["tag"]]
             c["result"].free()   # returns the bytes, the next request is admitted
             done += 1
+    # what the workers still cache stays within the budget too
+    assert free0 - torch.cuda.mem_get_info()[0] <= budget + slack
+    print("[server] peak device memory %d of budget %d" % (peak, budget), flush=True)
     # a request larger than the whole budget is refused at submission
-    big = _gpu(synth.spectral_field((64, 128, 128), seed=70))
+    big = _gpu(synth.spectral_field((256, 256, 256), seed=70))
     with pytest.raises(szi.SzError) as e:
         srv.submit_compress(big, tag=99)
     assert e.value.code == -3
     srv.close()
-    ctx.close()
