@@ -339,6 +339,26 @@ def run_batch(args):
     ctx.set_graphs(True)
     t_batch_graph = timed(batched)
     ctx.set_graphs(False)
+    # given code books (each field's own histogram, every count plus one,
+    # as a time series would reuse them): no host round trip in the batch
+    rs = batched()
+    books = [szi.code_lengths(r.read(szi.SEC_HIST)) for r in rs]
+    for r in rs:
+        r.free()
+
+    def batched_books():
+        rs = ctx.compress_batch_with_code(xs, books, params)
+        ctx.decompress_batch(rs, outs)
+        return rs
+
+    t_books = timed(batched_books)
+    ctx.set_graphs(True)
+    t_books_graph = timed(batched_books)
+    ctx.set_graphs(False)
+    rs = batched_books()
+    comp_books = sum(r.compressed_bytes for r in rs)
+    for r in rs:
+        r.free()
     nd = xs[0].dim()
     shapes = {k: ctx.shape(i, nd)[:2] for i, k in enumerate(("interp", "replay"))}
     # identity: the batched results equal the per-field ones, bit for bit
@@ -359,6 +379,9 @@ def run_batch(args):
         "ms_batched": round(t_batch * 1e3, 3), "ms_per_field_calls": round(t_single * 1e3, 3),
         "ms_batched_default_shape": round(t_batch_untuned * 1e3, 3),
         "ms_batched_graphs": round(t_batch_graph * 1e3, 3),
+        "ms_batched_given_books": round(t_books * 1e3, 3),
+        "ms_batched_given_books_graphs": round(t_books_graph * 1e3, 3),
+        "ratio_given_books": round(in_bytes / comp_books, 3),
         "tuned_shapes": {k: {"variant": v[0], "workgroups_per_cu": v[1]} for k, v in shapes.items()},
         "steps": args.steps, "fields": len(xs), "input_bytes": in_bytes,
         "ratio": round(in_bytes / comp, 3), "identical": bool(same),
@@ -397,7 +420,8 @@ def threaded_oracle(fields, params):
 
 SERVE_DESC = ("Poisson stream of 2000 requests, half compress, half decompress; sizes log-uniform "
               "64^3..512^3 (3D, k^-5/3 + offset) and 512^2..3600^2 (2D climate-like), drawn from a "
-              "pool of 10 + 8 pre-generated fields; rel eb from {1e-2, 1e-3, 1e-4}; 200 GB budget")
+              "pool of 10 + 8 pre-generated fields; rel eb from {1e-2, 1e-3, 1e-4}; 200 GB budget; "
+              "server_books: compressions name a resident code book per field and bound")
 
 
 def run_serve(args):
@@ -480,13 +504,16 @@ def run_serve(args):
             lat.append(time.perf_counter() - t0 - at[i])
         return time.perf_counter() - t0, lat
 
-    def served(at):
+    def book_of(f, e):   # a resident code book per pool field and bound
+        return 1 + 3 * f + ebs.index(e)
+
+    def served(at, books=False):
         srv = szi.Server(0, slots=slots, hbm_budget=200 * 10 ** 9)
         # warm-up like the plain calls': the slots' pools and caches fill
         for i in range(min(250, nreq)):
             kind, f, e = reqs[i]
             if kind == "c":
-                srv.submit_compress(pool[f], tag=i, eb=e)
+                srv.submit_compress(pool[f], tag=i, eb=e, book=book_of(f, e) if books else 0)
             else:
                 srv.submit_decompress(src[(f, e)], outs[f][i % nout], tag=i)
         left = min(250, nreq)
@@ -507,7 +534,7 @@ def run_serve(args):
                     time.sleep(at[i] - now)
                 kind, f, e = reqs[i]
                 if kind == "c":
-                    srv.submit_compress(pool[f], tag=i, eb=e)
+                    srv.submit_compress(pool[f], tag=i, eb=e, book=book_of(f, e) if books else 0)
                 else:
                     srv.submit_decompress(src[(f, e)], outs[f][i % nout], tag=i)
 
@@ -533,7 +560,8 @@ def run_serve(args):
            "data": "synthetic", "dtype": "f32", "config": {"workload": SERVE_DESC},
            "plain_call_mean_ms": round(svc * 1e3, 3), "offered_rate_per_s": round(rate, 1)}
     for name, at in (("load0.8", arrive), ("saturated", np.zeros(nreq))):
-        for mode, fn in (("server", served), ("sequential", sequential)):
+        for mode, fn in (("server", served), ("server_books", lambda at: served(at, True)),
+                         ("sequential", sequential)):
             # no cyclic garbage collection inside a timed run: its pauses
             # (tens of ms) would hold up the submitting thread
             gc.collect()
@@ -700,6 +728,19 @@ def main():
         b_c.append(time.perf_counter() - a)
         r.free()
     torch.cuda.synchronize()
+    # the same through the captured graphs (both run back to back)
+    ctx.set_graphs(True)
+    for _ in range(2):
+        ctx.compress_with_code(d_x, book, **kw).free()
+    bg_c = []
+    for _ in range(max(3, min(args.steps, 10))):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        r = ctx.compress_with_code(d_x, book, **kw)
+        bg_c.append(time.perf_counter() - a)
+        r.free()
+    ctx.set_graphs(False)
+    torch.cuda.synchronize()
 
     # quality metrics of the last step (untimed)
     cr = 4.0 * n / last.compressed_bytes
@@ -773,6 +814,7 @@ def main():
         "graph_latency_ms": {"compress_p50": round(pct(g_c, 50) * 1e3, 3),
                              "decompress_p50": round(pct(g_d, 50) * 1e3, 3)},
         "reused_code_book_compress_p50_ms": round(pct(b_c, 50) * 1e3, 3),
+        "reused_code_book_graph_compress_p50_ms": round(pct(bg_c, 50) * 1e3, 3),
         "kernels": {"compress": comp_rep, "decompress": decomp_rep},
         "pipeline_roofline": pipe,
         "ratio": round(cr, 3),

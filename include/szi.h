@@ -222,6 +222,17 @@ sz_status sz_compress_with_code(sz_ctx* ctx, const float* d_in, const sz_dims* d
                                 const sz_params* params, const uint8_t* code_len, void* stream,
                                 sz_result* out);
 
+/* sz_compress_batch with a given code book per field (code_len[i]: host
+ * array of 2R_i lengths, as for sz_compress_with_code): the whole batch is
+ * enqueued at once, with no host round trip between the histograms and the
+ * encoding, and in graph mode (sz_ctx_set_graphs) both of its graphs run
+ * back to back.  Each result equals sz_compress_with_code's for its field.
+ * Errors: as sz_compress_batch and sz_compress_with_code. */
+sz_status sz_compress_batch_with_code(sz_ctx* ctx, uint32_t nfields, const float* const* d_in,
+                                      const sz_dims* dims, const sz_params* params,
+                                      const uint8_t* const* code_len, void* stream,
+                                      sz_result* outs);
+
 /* Code lengths for sz_compress_with_code from a histogram of nsym = 2R
  * bins (host memory): the length-limited Huffman lengths of the counts
  * plus one, so that every symbol gets a code.  Host only, no context.
@@ -338,6 +349,16 @@ sz_status sz_result_read(sz_ctx* ctx, const sz_result* res, int32_t section, voi
  * device, its own first, then every worker's, before an allocation would
  * pass the budget.  The caller's input and output buffers are not counted.
  *
+ * Resident code books (Sec. VI-A builds the code book on the host between
+ * the histogram and the encoding; a stream of similar fields, such as the
+ * time steps of a simulation, can keep one).  A compression request with
+ * book = k > 0 uses the server's book k when it holds one for the request's
+ * radius, as sz_compress_with_code does, with no host round trip; otherwise
+ * it builds its own as sz_compress does and leaves sz_code_lengths of its
+ * histogram as book k.  Such a result's blob may then differ from a plain
+ * call's in its code lengths and words, never in its reconstruction.  The
+ * books live until sz_server_destroy.
+ *
  * The server may be called from any host thread.  Inputs (the field of a
  * compression, the result and output buffer of a decompression) must stay
  * valid until the request's completion has been polled; a result must not be
@@ -348,7 +369,7 @@ typedef enum { SZ_REQ_COMPRESS = 0, SZ_REQ_DECOMPRESS = 1 } sz_req_kind;
 
 typedef struct {
     int32_t kind;            /* sz_req_kind */
-    int32_t reserved0;       /* 0 */
+    int32_t book;            /* compression: 0, or a resident code book k > 0 (below) */
     uint64_t tag;            /* the caller's id, echoed in the completion */
     const float* d_in;       /* compression: the field (device) */
     sz_dims dims;            /* compression: its shape */

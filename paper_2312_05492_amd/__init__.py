@@ -60,7 +60,7 @@ class SzResult(C.Structure):
 
 
 class SzRequest(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("reserved0", C.c_int32), ("tag", C.c_uint64),
+    _fields_ = [("kind", C.c_int32), ("book", C.c_int32), ("tag", C.c_uint64),
                 ("d_in", C.c_void_p), ("dims", SzDims), ("params", SzParams),
                 ("src", C.POINTER(SzResult)), ("d_out", C.c_void_p)]
 
@@ -127,6 +127,9 @@ def lib():
         L.sz_compress_batch.restype = C.c_int
         L.sz_compress_batch.argtypes = [vp, C.c_uint32, P(vp), P(SzDims), P(SzParams), vp,
                                         P(SzResult)]
+        L.sz_compress_batch_with_code.restype = C.c_int
+        L.sz_compress_batch_with_code.argtypes = [vp, C.c_uint32, P(vp), P(SzDims), P(SzParams),
+                                                  P(vp), vp, P(SzResult)]
         L.sz_decompress.restype = C.c_int
         L.sz_decompress.argtypes = [vp, P(SzResult), vp, vp]
         L.sz_decompress_batch.restype = C.c_int
@@ -361,6 +364,24 @@ class Context:
                                             _stream(self.torch, xs[0].device), outs))
         return [Result(self, outs[i], xs[i].shape) for i in range(n)]
 
+    def compress_batch_with_code(self, xs, code_lens, params=None) -> list:
+        """A batch with a given code book per field (2R uint8 lengths each)."""
+        xs = [self._field(x) for x in xs]
+        n = len(xs)
+        params = params or [{}] * n
+        ps = (SzParams * n)(*[make_params(x.dim(), **kw) for x, kw in zip(xs, params)])
+        cls = [np.ascontiguousarray(c, dtype=np.uint8) for c in code_lens]
+        for p, cl in zip(ps, cls):
+            if cl.size != 2 * p.radius:
+                raise ValueError("code_len needs %d entries (2R), got %d" % (2 * p.radius, cl.size))
+        ins = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+        dims = (SzDims * n)(*[make_dims(x.shape) for x in xs])
+        books = (C.c_void_p * n)(*[cl.ctypes.data for cl in cls])
+        outs = (SzResult * n)()
+        self._check(lib().sz_compress_batch_with_code(self.h, n, ins, dims, ps, books,
+                                                      _stream(self.torch, xs[0].device), outs))
+        return [Result(self, outs[i], xs[i].shape) for i in range(n)]
+
     def decompress(self, res: Result, out=None):
         t = self.torch
         if out is None:
@@ -443,10 +464,13 @@ class Server:
         if rc != SZ_OK:
             raise SzError(rc, lib().sz_server_last_error(self.h).decode())
 
-    def submit_compress(self, x, tag: int, **kw):
+    def submit_compress(self, x, tag: int, book: int = 0, **kw):
+        """book > 0: use (or, the first time, leave) the server's resident
+        code book of that number."""
         x = self.reader._field(x)
         r = SzRequest()
         r.kind = REQ_COMPRESS
+        r.book = book
         r.tag = tag
         r.d_in = x.data_ptr()
         r.dims = make_dims(x.shape)

@@ -752,6 +752,7 @@ struct sz_server {
     std::deque<Item> q;
     std::deque<sz_completion> done;
     std::unordered_map<void*, uint64_t> held;   // result -> bytes charged
+    std::unordered_map<int32_t, std::vector<uint8_t>> books;   // resident code books
     int running = 0;
     bool stop = false;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -823,11 +824,38 @@ void server_worker(sz_server* s, int slot) {
         cp.t_submit = it.t_submit;
         cp.t_start = s->now();
         sz_status rc;
-        // both calls return after their stream has finished the request
-        if (it.r.kind == SZ_REQ_COMPRESS)
-            rc = sz_compress(c, it.r.d_in, &it.r.dims, &it.r.params, s->st[slot], &cp.result);
-        else
+        // the calls return after their stream has finished the request
+        if (it.r.kind == SZ_REQ_COMPRESS) {
+            const uint32_t nsym = 2 * (it.r.params.radius ? it.r.params.radius : 512u);
+            std::vector<uint8_t> book;
+            if (it.r.book > 0) {
+                std::lock_guard<std::mutex> g(s->m);
+                auto b = s->books.find(it.r.book);
+                if (b != s->books.end() && b->second.size() == nsym) book = b->second;
+            }
+            if (!book.empty()) {
+                rc = sz_compress_with_code(c, it.r.d_in, &it.r.dims, &it.r.params, book.data(),
+                                           s->st[slot], &cp.result);
+            } else {
+                rc = sz_compress(c, it.r.d_in, &it.r.dims, &it.r.params, s->st[slot], &cp.result);
+                if (rc == SZ_OK && it.r.book > 0 && nsym <= 2u * kMaxRadius) {
+                    // this result's histogram becomes book k
+                    std::vector<uint32_t> h(nsym);
+                    std::vector<uint8_t> len(nsym);
+                    if (hipMemcpy(h.data(), cp.result.hist, 4 * (size_t)nsym, hipMemcpyDeviceToHost) ==
+                            hipSuccess &&
+                        sz_code_lengths(h.data(), nsym, len.data()) == SZ_OK) {
+                        std::lock_guard<std::mutex> g(s->m);
+                        auto b = s->books.find(it.r.book);
+                        if (b == s->books.end() || b->second.size() != nsym) s->books[it.r.book] = len;
+                    } else {
+                        (void)hipGetLastError();
+                    }
+                }
+            }
+        } else {
             rc = sz_decompress(c, it.r.src, it.r.d_out, s->st[slot]);
+        }
         cp.t_done = s->now();
         cp.status = rc;
         const uint64_t keep =
@@ -1067,9 +1095,9 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
                             "of 1..%d bits, with Kraft sum <= 1", i, nsym, kLmax);
         }
     }
-    // graphs and launch-shape tuning need the host round trip after the
-    // interpolation, which a given code book does without
-    const bool graphs = c->graphs && !given;
+    // graph mode: the launches replay from captured graphs (with a given
+    // code book both graphs run back to back, without the host round trip)
+    const bool graphs = c->graphs;
     // results (released on any error below)
     std::vector<sz_result> res(nf);
     std::memset(res.data(), 0, sizeof(sz_result) * nf);
@@ -1327,7 +1355,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     std::vector<FieldPlan> plans(nf);
     std::vector<std::vector<uint32_t>> hist(nf);
     for (uint32_t k = 0; k < nf; ++k) hist[k].resize(2 * fds[k].R);
-    if (given) {
+    if (given && !graphs) {
         // no round trip: part 1 now, its plans and histograms read at the end
         std::memcpy(hs + o_fd, fds.data(), sizeof(FieldDesc) * nf);
         std::memcpy(hs + o_items, items.data(), sizeof(uint64_t) * items.size());
@@ -1352,11 +1380,19 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
             return SZ_OK;
         });
         if (s) return s;
-        HIP_TRY(c, hipStreamSynchronize(c->gstream));
-        std::memcpy(plans.data(), h + o_plan, sizeof(FieldPlan) * nf);
-        for (uint32_t k = 0; k < nf; ++k)
-            std::memcpy(hist[k].data(), h + o_hist + sizeof(uint32_t) * k * hstride,
-                        sizeof(uint32_t) * hist[k].size());
+        if (given) {
+            // no round trip: the copies of the histograms into the results
+            // (on the caller's stream) wait for the graph, the plans and
+            // histograms in the pinned mirror are read at the end
+            HIP_TRY(c, hipEventRecord(c->gjoin, c->gstream));
+            HIP_TRY(c, hipStreamWaitEvent(st, c->gjoin, 0));
+        } else {
+            HIP_TRY(c, hipStreamSynchronize(c->gstream));
+            std::memcpy(plans.data(), h + o_plan, sizeof(FieldPlan) * nf);
+            for (uint32_t k = 0; k < nf; ++k)
+                std::memcpy(hist[k].data(), h + o_hist + sizeof(uint32_t) * k * hstride,
+                            sizeof(uint32_t) * hist[k].size());
+        }
     } else {
         std::memcpy(hs + o_fd, fds.data(), sizeof(FieldDesc) * nf);
         std::memcpy(hs + o_items, items.data(), sizeof(uint64_t) * items.size());
@@ -1537,6 +1573,44 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     // sync 2: block word offsets and non-zero word counts (small) to the host
     std::vector<uint64_t> bwoff(nbw);
     std::vector<uint32_t> bnz(std::max<uint64_t>(total_blocks, 1));
+    // with given code books, after the end: the plans and, where a field has
+    // more outliers than its guessed lists hold, exact lists and the encode
+    // again (eagerly, on the caller's stream)
+    auto given_checks = [&](hipStream_t q) -> sz_status {
+        for (uint32_t k = 0; k < nf; ++k) {
+            if (plans[k].status == -2)
+                return fail(c, SZ_ERR_NONFINITE, "field %u holds %u non-finite values", perm[k],
+                            plans[k].nonfinite);
+            ri(&res[perm[k]])->plan = plans[k];
+        }
+        bool again = false;
+        for (uint32_t j = 0; j < nf; ++j) {
+            const uint32_t k = hord[j], i = perm[k];
+            const uint64_t nout = hist[k][0];
+            if (nout > fds[k].n_outliers) {
+                ResultInternal* R = ri(&res[i]);
+                sz_status r;
+                if ((r = res_alloc(c, R, nout, &res[i].outlier_idx))) return r;
+                if ((r = res_alloc(c, R, nout, &res[i].outlier_val))) return r;
+                fds[k].outlier_idx = hfd[j].outlier_idx = res[i].outlier_idx;
+                fds[k].outlier_val = hfd[j].outlier_val = res[i].outlier_val;
+                fds[k].n_outliers = hfd[j].n_outliers = nout;
+                again = true;
+            }
+            res[i].n_outliers = nout;
+        }
+        if (again) {
+            std::memcpy(hs + o_hfd, hfd.data(), sizeof(FieldDesc) * nf);
+            HIP_TRY(c, hipMemcpyAsync(d_hfd, hs + o_hfd, sizeof(FieldDesc) * nf, hipMemcpyHostToDevice, q));
+            sz_status r = enqueue2(q);
+            if (r) return r;
+            HIP_TRY(c, hipMemcpyAsync(hs + o_back, d_bwoff, n_back, hipMemcpyDeviceToHost, q));
+            HIP_TRY(c, hipStreamSynchronize(q));
+            std::memcpy(bwoff.data(), hs + o_bwoff, sizeof(uint64_t) * nbw);
+            std::memcpy(bnz.data(), hs + o_bnz, sizeof(uint32_t) * total_blocks);
+        }
+        return SZ_OK;
+    };
     if (graphs) {
         char* h = static_cast<char*>(c->parena);
         char* d = static_cast<char*>(c->arena);
@@ -1567,6 +1641,13 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         HIP_TRY(c, hipStreamSynchronize(st));
         std::memcpy(bwoff.data(), h + o_bwoff, sizeof(uint64_t) * nbw);
         std::memcpy(bnz.data(), h + o_bnz, sizeof(uint32_t) * total_blocks);
+        if (given) {
+            std::memcpy(plans.data(), h + o_plan, sizeof(FieldPlan) * nf);
+            for (uint32_t k = 0; k < nf; ++k)
+                std::memcpy(hist[k].data(), h + o_hist + sizeof(uint32_t) * k * hstride,
+                            sizeof(uint32_t) * hist[k].size());
+            if ((s = given_checks(st))) return s;
+        }
     } else {
         std::memcpy(hs + o_hfd, hfd.data(), sizeof(FieldDesc) * nf);
         std::memcpy(hs + o_gboff, gboff.data(), sizeof(uint64_t) * gboff.size());
@@ -1586,38 +1667,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
             for (uint32_t k = 0; k < nf; ++k)
                 std::memcpy(hist[k].data(), hs + o_hist + sizeof(uint32_t) * k * hstride,
                             sizeof(uint32_t) * hist[k].size());
-            for (uint32_t k = 0; k < nf; ++k) {
-                if (plans[k].status == -2)
-                    return fail(c, SZ_ERR_NONFINITE, "field %u holds %u non-finite values", perm[k],
-                                plans[k].nonfinite);
-                ri(&res[perm[k]])->plan = plans[k];
-            }
-            // more outliers than the guess: exact lists, and the encode again
-            bool again = false;
-            for (uint32_t j = 0; j < nf; ++j) {
-                const uint32_t k = hord[j], i = perm[k];
-                const uint64_t nout = hist[k][0];
-                if (nout > fds[k].n_outliers) {
-                    ResultInternal* R = ri(&res[i]);
-                    if ((s = res_alloc(c, R, nout, &res[i].outlier_idx))) return s;
-                    if ((s = res_alloc(c, R, nout, &res[i].outlier_val))) return s;
-                    fds[k].outlier_idx = hfd[j].outlier_idx = res[i].outlier_idx;
-                    fds[k].outlier_val = hfd[j].outlier_val = res[i].outlier_val;
-                    fds[k].n_outliers = hfd[j].n_outliers = nout;
-                    again = true;
-                }
-                res[i].n_outliers = nout;
-            }
-            if (again) {
-                std::memcpy(hs + o_hfd, hfd.data(), sizeof(FieldDesc) * nf);
-                HIP_TRY(c, hipMemcpyAsync(d_hfd, hs + o_hfd, sizeof(FieldDesc) * nf,
-                                          hipMemcpyHostToDevice, st));
-                if ((s = enqueue2(st))) return s;
-                HIP_TRY(c, hipMemcpyAsync(hs + o_back, d_bwoff, n_back, hipMemcpyDeviceToHost, st));
-                HIP_TRY(c, hipStreamSynchronize(st));
-                std::memcpy(bwoff.data(), hs + o_bwoff, sizeof(uint64_t) * nbw);
-                std::memcpy(bnz.data(), hs + o_bnz, sizeof(uint32_t) * total_blocks);
-            }
+            if ((s = given_checks(st))) return s;
         }
     }
     resolve_marks(c);
@@ -1656,6 +1706,14 @@ extern "C" {
 sz_status sz_compress_batch(sz_ctx* c, uint32_t nf, const float* const* d_in, const sz_dims* dims,
                             const sz_params* params, void* stream, sz_result* outs) {
     return compress_fields(c, nf, d_in, dims, params, nullptr, stream, outs);
+}
+
+sz_status sz_compress_batch_with_code(sz_ctx* c, uint32_t nf, const float* const* d_in,
+                                      const sz_dims* dims, const sz_params* params,
+                                      const uint8_t* const* code_len, void* stream, sz_result* outs) {
+    if (!c) return SZ_ERR_INVALID_ARG;
+    if (!code_len) return fail(c, SZ_ERR_INVALID_ARG, "null code books");
+    return compress_fields(c, nf, d_in, dims, params, code_len, stream, outs);
 }
 
 sz_status sz_compress(sz_ctx* c, const float* d_in, const sz_dims* dims, const sz_params* params,
@@ -2170,8 +2228,9 @@ sz_status sz_server_create(sz_server** out, int device, int slots, uint64_t hbm_
 
 sz_status sz_server_submit(sz_server* s, const sz_request* req) {
     if (!s || !req) return SZ_ERR_INVALID_ARG;
-    if (req->kind == SZ_REQ_COMPRESS ? !req->d_in : (req->kind != SZ_REQ_DECOMPRESS || !req->src ||
-                                                     !req->src->internal || !req->d_out))
+    if (req->kind == SZ_REQ_COMPRESS ? (!req->d_in || req->book < 0)
+                                     : (req->kind != SZ_REQ_DECOMPRESS || !req->src ||
+                                        !req->src->internal || !req->d_out))
         return SZ_ERR_INVALID_ARG;
     const uint64_t need = request_need(*req);
     std::lock_guard<std::mutex> lk(s->m);

@@ -125,7 +125,10 @@ __global__ __launch_bounds__(256) void k_huff_stats(const FieldDesc* __restrict_
 // Exclusive scan of up to two u32 arrays of length n into u64 offsets; one
 // workgroup of 1024 threads, a contiguous run per thread: run sums, wave
 // scans, the 16 wave totals through LDS (one barrier), then the run's
-// offsets.  off[n] receives the total.
+// offsets.  off[n] receives the total.  LONG = false takes runs of at
+// most kRun (n <= 16384) in registers; LONG = true, longer runs kRun
+// elements a round (the launchers choose by n).
+template <bool LONG>
 __global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t* __restrict__ a,
                                                       const uint32_t* __restrict__ b, uint64_t n,
                                                       uint64_t* aoff, uint64_t* boff) {
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t* __restrict
     const uint64_t end = beg + per < n ? beg + per : n;
     // runs of up to kRun elements sit in registers, all loads issued at once
     constexpr int kRun = 16;
-    const bool regs = per <= (uint64_t)kRun;
+    const bool regs = !LONG && per <= (uint64_t)kRun;   // LONG: runs of more than kRun
     uint32_t va[kRun], vb[kRun];
     uint64_t sa = 0, sb = 0;
     if (regs) {
@@ -150,10 +153,21 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t* __restrict
             sa += va[k];
             sb += vb[k];
         }
-    } else {
-        for (uint64_t i = beg; i < end; ++i) {
-            sa += a[i];
-            if (b) sb += b[i];
+    } else if (LONG) {
+        // longer runs (the LONG instance): kRun elements a round, their
+        // loads issued together
+        for (uint64_t i0 = beg; i0 < end; i0 += kRun) {
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) {
+                const uint64_t i = i0 + k;
+                va[k] = i < end ? a[i] : 0u;
+                vb[k] = (b && i < end) ? b[i] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) {
+                sa += va[k];
+                sb += vb[k];
+            }
         }
     }
     uint64_t xa = sa, xb = sb;   // inclusive scans over the wave's lanes
@@ -186,13 +200,23 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t* __restrict
             ra += va[k];
             rb += vb[k];
         }
-    } else {
-        for (uint64_t i = beg; i < end; ++i) {
-            aoff[i] = ra;
-            ra += a[i];
-            if (b) {
-                boff[i] = rb;
-                rb += b[i];
+    } else if (LONG) {
+        for (uint64_t i0 = beg; i0 < end; i0 += kRun) {
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) {
+                const uint64_t i = i0 + k;
+                va[k] = i < end ? a[i] : 0u;
+                vb[k] = (b && i < end) ? b[i] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) {
+                const uint64_t i = i0 + k;
+                if (i < end) {
+                    aoff[i] = ra;
+                    if (b) boff[i] = rb;
+                }
+                ra += va[k];
+                rb += vb[k];
             }
         }
     }
@@ -541,7 +565,7 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
 // elided blob) runs the same tiling backwards: counts of set bits, scan,
 // then each tile's words in place.
 constexpr int kElideTile = (int)kElideTileWords;
-static_assert(kElideTile % 64 == 0, "a tile is whole 64-word ballots");
+static_assert(kElideTile % 2048 == 0, "a tile is whole rounds of 32 ballots of 64 words");
 
 __device__ __forceinline__ uint64_t elide_words(const ElideField& e) {
     return e.wbeg ? *e.wend - *e.wbeg : e.nw;
@@ -568,20 +592,26 @@ __global__ __launch_bounds__(256) void k_elide_count(const ElideField* __restric
     if (!RESTORE && e.nzw && (nw + 31) / 32 + *gp(e.nzw) >= nw) {
         // the field keeps its words: nothing to count
     } else if (RESTORE) {
-        const uint64_t nbm = (nw + 31) / 32, b = w0 / 32 + lane;
-        const uint32_t m = b < nbm ? gp(e.sec)[b] : 0u;
-        n = (uint32_t)__popc(m);
+        const uint64_t nbm = (nw + 31) / 32;
+#pragma unroll
+        for (int j = 0; j < kElideTile / 2048; ++j) {
+            const uint64_t b = w0 / 32 + (uint64_t)j * 64 + lane;
+            n += (uint32_t)__popc(b < nbm ? gp(e.sec)[b] : 0u);
+        }
         for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
     } else {
-        uint32_t w[kElideTile / 64];
+        // 32 loads in flight a round
+        for (int r = 0; r < kElideTile / 2048; ++r) {
+            uint32_t w[32];
 #pragma unroll
-        for (int it = 0; it < kElideTile / 64; ++it) {
-            const uint64_t i = w0 + (uint64_t)it * 64 + lane;
-            w[it] = i < nw ? gp(e.words)[i] : 0u;
+            for (int it = 0; it < 32; ++it) {
+                const uint64_t i = w0 + (uint64_t)(r * 32 + it) * 64 + lane;
+                w[it] = i < nw ? gp(e.words)[i] : 0u;
+            }
+#pragma unroll
+            for (int it = 0; it < 32; ++it)
+                n += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(w[it] != 0u));
         }
-#pragma unroll
-        for (int it = 0; it < kElideTile / 64; ++it)
-            n += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(w[it] != 0u));
     }
     if (lane == 0) cnt[tile] = n;
 }
@@ -648,8 +678,12 @@ hipError_t launch_elide(const ElideField* d_e, int nf, const uint64_t* d_toff, u
     const dim3 g((unsigned)((ntiles + 3) / 4)), b(256);
     if (restore) hipLaunchKernelGGL(k_elide_count<1>, g, b, 0, st, d_e, nf, d_toff, ntiles, d_cnt);
     else hipLaunchKernelGGL(k_elide_count<0>, g, b, 0, st, d_e, nf, d_toff, ntiles, d_cnt);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, d_cnt, (const uint32_t*)nullptr,
-                       ntiles, d_off, (uint64_t*)nullptr);
+    if (ntiles > 16 * 1024)
+        hipLaunchKernelGGL(k_scan_blocks<true>, dim3(1), dim3(1024), 0, st, d_cnt,
+                           (const uint32_t*)nullptr, ntiles, d_off, (uint64_t*)nullptr);
+    else
+        hipLaunchKernelGGL(k_scan_blocks<false>, dim3(1), dim3(1024), 0, st, d_cnt,
+                           (const uint32_t*)nullptr, ntiles, d_off, (uint64_t*)nullptr);
     if (restore) hipLaunchKernelGGL(k_restore_write, g, b, 0, st, d_e, nf, d_toff, ntiles, d_off);
     else hipLaunchKernelGGL(k_elide_write, g, b, 0, st, d_e, nf, d_toff, ntiles, d_off);
     return hipGetLastError();
@@ -673,7 +707,10 @@ hipError_t launch_huff_stats(const FieldDesc* d_fields, int nfields, const uint6
 
 hipError_t launch_scan_blocks(const uint32_t* d_a, const uint32_t* d_b, uint64_t n,
                               uint64_t* d_aoff, uint64_t* d_boff, hipStream_t st) {
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, d_a, d_b, n, d_aoff, d_boff);
+    if (n > 16 * 1024)
+        hipLaunchKernelGGL(k_scan_blocks<true>, dim3(1), dim3(1024), 0, st, d_a, d_b, n, d_aoff, d_boff);
+    else
+        hipLaunchKernelGGL(k_scan_blocks<false>, dim3(1), dim3(1024), 0, st, d_a, d_b, n, d_aoff, d_boff);
     return hipGetLastError();
 }
 

@@ -173,7 +173,7 @@ struct ElideField {
     const unsigned long long* nzw;
     uint64_t nw;
 };
-constexpr uint64_t kElideTileWords = 2048;
+constexpr uint64_t kElideTileWords = 8192;
 // restore = 0: elide words into sec where that is shorter; 1: restore words
 // from sec.  Fields own the tiles [toff[f], toff[f + 1]) of kElideTileWords
 // words; cnt and off (u32[ntiles], u64[ntiles + 1]) are scratch.

@@ -82,11 +82,11 @@ def test_elided_blob_with_a_flipped_bitmap_bit_is_rejected(ctx):
 @pytest.mark.parametrize("graphs", [False, True])
 def test_batch_elision_mixed_fields(ctx, graphs):
     """One elision launch covers every field of a batch: fields that elide
-    and fields that keep their words, each spanning several 2048-word
+    and fields that keep their words, most spanning several 8192-word
     tiles, give the oracle's blobs; elided ones restore on upload."""
-    xs = [synth.climate_field(921, shape=(360, 720)),
+    xs = [synth.climate_field(921, shape=(900, 1800)),
           synth.spectral_field((40, 56, 72), seed=922),
-          synth.climate_field(923, shape=(300, 500)),
+          synth.climate_field(923, shape=(700, 1200)),
           synth.climate_field(924, shape=(7, 9))]
     kws = [dict(eb=1e-3), dict(eb=1e-3), dict(eb=1e-2), dict(eb=1e-3)]
     refs = [O.compress(x, O.Params(shape=x.shape, **kw)) for x, kw in zip(xs, kws)]

@@ -110,8 +110,8 @@ def test_nonfinite_rejected_with_book(ctx):
 
 
 def test_book_with_graph_mode_on(ctx):
-    # a given code book runs the plain launch path even when the context
-    # replays graphs; the result is the same
+    # a given code book replays both graphs back to back; the result is the
+    # plain path's
     x = synth.spectral_field((24, 40, 72), seed=45, mean=1.0)
     first = ctx.compress(_gpu(x))
     book = szi.code_lengths(first.read(szi.SEC_HIST))
@@ -129,3 +129,94 @@ def test_book_with_graph_mode_on(ctx):
     finally:
         ctx.set_graphs(False)
         a.free()
+
+
+def _batch_case():
+    xs = [synth.spectral_field((40, 56, 72), seed=46, mean=3.0),
+          synth.climate_field(902, shape=(150, 260)),
+          synth.spectral_field((33, 47, 65), seed=47, beta=3.0),
+          synth.spectral_field((30, 40, 50), seed=48)]
+    kws = [{}, {}, dict(eb=1e-4), dict(radius=64, chunk=256)]
+    return xs, kws
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_batch_with_given_books(ctx, graphs):
+    """sz_compress_batch_with_code: every field's blob is the oracle's with
+    the same book, and the single call's; one field takes another field's
+    book, one its own, one has more outliers than the first lists hold."""
+    xs, kws = _batch_case()
+    books = []
+    for x, kw in zip(xs, kws):
+        r = ctx.compress(_gpu(x), **kw)
+        books.append(szi.code_lengths(r.read(szi.SEC_HIST)))
+        r.free()
+    books[0], books[2] = books[2].copy(), books[0].copy()   # both R = 512
+    # radius 2 on a rough field: nearly every point an outlier
+    rng = np.random.default_rng(9)
+    xs.append(rng.standard_normal((24, 32, 48)).astype(np.float32))
+    kws.append(dict(radius=2, eb=1e-4))
+    books.append(np.array([2, 2, 2, 2], dtype=np.uint8))
+    refs = []
+    for x, kw, book in zip(xs, kws, books):
+        m = dict(kw)
+        if "radius" in m:
+            m["R"] = m.pop("radius")
+        refs.append(O.compress(x, O.Params(shape=x.shape, **m), lengths=book).blob())
+    print("\n[given books batch] graphs=%s fields=%d" % (graphs, len(xs)), flush=True)
+    ctx.set_graphs(graphs)
+    try:
+        for rep in range(3):   # graph capture, then replays
+            res = ctx.compress_batch_with_code([_gpu(x) for x in xs], books, kws)
+            try:
+                for k, (r, ref) in enumerate(zip(res, refs)):
+                    assert r.blob() == ref, (rep, k)
+                y = ctx.decompress(res[1]).cpu().numpy()
+                assert np.array_equal(_bits(y), _bits(O.decompress_blob(refs[1])))
+            finally:
+                for r in res:
+                    r.free()
+        one = ctx.compress_with_code(_gpu(xs[3]), books[3], **kws[3])
+        assert one.blob() == refs[3]
+        one.free()
+    finally:
+        ctx.set_graphs(False)
+
+
+def test_server_resident_books(ctx):
+    """Requests naming a resident book: the first ones build it, the later
+    ones use it (every code then has a length, which only a book made by
+    sz_code_lengths gives); each blob is the oracle's with the lengths it
+    holds, and decompresses to the plain reconstruction."""
+    import torch
+    fields = [synth.spectral_field((40, 48, 64), seed=80 + k, mean=5.0) for k in range(4)]
+    xs = [_gpu(f) for f in fields]
+    plain = [O.compress(f, O.Params(shape=f.shape)) for f in fields]
+    srv = szi.Server(0, slots=4)
+    try:
+        for i in range(12):
+            srv.submit_compress(xs[i % 4], tag=i, book=1)
+        got = []
+        while len(got) < 12:
+            comp = srv.poll(wait=True)
+            assert comp, "server stalled"
+            got.extend(comp)
+        used = 0
+        for c in got:
+            assert c["status"] == 0
+            r = c["result"]
+            k = c["tag"] % 4
+            lens = r.read(szi.SEC_CODE_LEN)
+            used += int(np.all(lens > 0))
+            ref = O.compress(fields[k], O.Params(shape=fields[k].shape), lengths=lens)
+            assert r.blob() == ref.blob(), c["tag"]
+            out = torch.empty_like(xs[k])
+            ctx.decompress(r, out)
+            assert np.array_equal(_bits(out.cpu().numpy()), _bits(plain[k].recon))
+            r.free()
+        print("\n[server books] %d of 12 results used the resident book" % used, flush=True)
+        # requests 5..12 wait for a free slot, so a completion (and its book)
+        # came before each of them
+        assert used >= 8
+    finally:
+        srv.close()
