@@ -24,6 +24,8 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "large": dict(shape=(512, 512, 512), desc="512x512x512 FP32 spectral field k^-5/3 + offset 10"),
     "small": dict(shape=(64, 64, 64), desc="64x64x64 FP32 bumps + sinusoids + N(0,1e-4)"),
+    "line": dict(shape=(1 << 27,), desc="2^27-point 1D FP32 spectral field k^-5/3 + offset 10 "
+                                        "(anchors every 512, windows of 2048)"),
 }
 
 
@@ -646,7 +648,7 @@ def main():
     from paper_2312_05492_amd import synth
 
     wl = WORKLOADS[args.workload]
-    x = synth.workload_large(shape=wl["shape"]) if args.workload == "large" else synth.workload_small()
+    x = synth.workload_small() if args.workload == "small" else synth.workload_large(shape=wl["shape"])
     n = x.size
     in_bytes = 4 * n
     dev = torch.device("cuda:0")
@@ -801,7 +803,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "shape": list(wl["shape"]), "eb_rel": args.eb,
-                   "interp": INTERP_DESC[args.interp], "anchor_stride": 8, "radius": 512,
+                   "interp": INTERP_DESC[args.interp], "anchor_stride": {3: 8, 2: 16, 1: 512}[x.ndim], "radius": 512,
                    "huffman_chunk": args.chunk},
         "compress_GBps": round(in_bytes / float(np.median(t_c)) / 1e9, 2),
         "decompress_GBps": round(in_bytes / float(np.median(t_d)) / 1e9, 2),

@@ -157,10 +157,12 @@ class Params:
 
     def c_struct(self) -> _Params:
         D = self.ndim()
-        if D not in (2, 3):
-            raise ValueError("ndim must be 2 or 3")
-        S = self.S or (8 if D == 3 else 16)
-        win = self.window or ((S, S, 4 * S) if D == 3 else (S, 4 * S))
+        if D not in (1, 2, 3):
+            raise ValueError("ndim must be 1, 2 or 3")
+        # Sec. V-A: chunks of 8^3, 16^2 or 512 points; the window spans four
+        # chunks along x and one along the other dimensions
+        S = self.S or {3: 8, 2: 16, 1: 512}[D]
+        win = self.window or {3: (S, S, 4 * S), 2: (S, 4 * S), 1: (4 * S,)}[D]
         interp = self.interp or (AUTO,) * D
         p = _Params()
         p.ndim = D

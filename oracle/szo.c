@@ -80,7 +80,7 @@
 #define SZO_MAX_LEVELS 16
 
 typedef struct {
-    uint32_t ndim;      /* 2 or 3 */
+    uint32_t ndim;      /* 1, 2 or 3 */
     uint32_t S;         /* anchor stride (power of two) */
     uint64_t n[3];      /* n[0] = x (fastest) .. n[ndim-1] slowest */
     uint32_t w[3];      /* window extent per dimension (multiple of S) */
@@ -172,7 +172,7 @@ static int is_pow2(uint32_t v) { return v && !(v & (v - 1)); }
 static int check_params(const szo_params *p)
 {
     uint32_t d;
-    if (p->ndim != 2 && p->ndim != 3) return SZO_ERR_ARG;
+    if (p->ndim < 1 || p->ndim > 3) return SZO_ERR_ARG;
     if (!is_pow2(p->S) || p->S < 2) return SZO_ERR_ARG;
     if (p->R < 2 || p->R > 32768) return SZO_ERR_ARG;
     if (!(p->eb >= 0.0) || !isfinite(p->eb)) return SZO_ERR_ARG;
@@ -195,7 +195,7 @@ static int check_params(const szo_params *p)
 static void dims3(const szo_params *p, uint64_t *n)
 {
     n[0] = p->n[0];
-    n[1] = p->n[1];
+    n[1] = p->ndim >= 2 ? p->n[1] : 1;
     n[2] = p->ndim == 3 ? p->n[2] : 1;
 }
 

@@ -24,8 +24,8 @@ sz_status bad(std::string* err, sz_status s, const char* fmt, ...) {
 
 sz_status check_geometry(const sz_dims* d, const sz_params* p, Geometry& g, std::string* err) {
     if (!d || !p) return bad(err, SZ_ERR_INVALID_ARG, "null dims or params");
-    if (d->ndim != 2 && d->ndim != 3)
-        return bad(err, SZ_ERR_UNSUPPORTED, "ndim %u (2 and 3 are supported)", d->ndim);
+    if (d->ndim < 1 || d->ndim > 3)
+        return bad(err, SZ_ERR_UNSUPPORTED, "ndim %u (1, 2 and 3 are supported)", d->ndim);
     g.ndim = (int)d->ndim;
     uint64_t npts = 1;
     for (int k = 0; k < 3; ++k) {
@@ -65,16 +65,18 @@ sz_status check_geometry(const sz_dims* d, const sz_params* p, Geometry& g, std:
     if (chunk != 256 && chunk != 512 && chunk != 1024 && chunk != 2048)
         return bad(err, SZ_ERR_UNSUPPORTED, "Huffman chunk %u", chunk);
     g.chunk = (int)chunk;
-    const int S = g.ndim == 3 ? 8 : 16;
+    // Sec. V-A: chunks of 8^3, 16^2 or 512 points; a window spans four
+    // chunks along x and one along the other dimensions
+    const int S = g.ndim == 3 ? 8 : (g.ndim == 2 ? 16 : 512);
     if (p->anchor_stride && (int)p->anchor_stride != S)
         return bad(err, SZ_ERR_UNSUPPORTED, "anchor stride %u (this build: %d)", p->anchor_stride, S);
-    const int wdef[3] = {g.ndim == 3 ? 32 : 64, g.ndim == 3 ? 8 : 16, g.ndim == 3 ? 8 : 1};
+    const int wdef[3] = {4 * S, g.ndim >= 2 ? S : 1, g.ndim == 3 ? S : 1};
     for (int k = 0; k < g.ndim; ++k)
         if (p->window[k] && (int)p->window[k] != wdef[k])
             return bad(err, SZ_ERR_UNSUPPORTED, "window[%d] = %u (this build: %d)", k, p->window[k],
                        wdef[k]);
     g.S = S;
-    g.L = g.ndim == 3 ? 3 : 4;
+    g.L = g.ndim == 3 ? 3 : (g.ndim == 2 ? 4 : 9);   // log2 S
     g.nwin_total = 1;
     g.nanch = 1;
     for (int k = 0; k < 3; ++k) {
@@ -86,7 +88,7 @@ sz_status check_geometry(const sz_dims* d, const sz_params* p, Geometry& g, std:
     }
     // the window kernels address a block by 32-bit byte offsets from its
     // origin and number windows with 32-bit integers
-    const uint64_t span = (uint64_t)g.w[0] + (uint64_t)g.w[1] * (uint64_t)g.n[0] +
+    const uint64_t span = (uint64_t)g.w[0] + (g.ndim >= 2 ? (uint64_t)g.w[1] * (uint64_t)g.n[0] : 0) +
                           (g.ndim == 3 ? (uint64_t)g.w[2] * (uint64_t)g.n[0] * (uint64_t)g.n[1] : 0);
     if (span * sizeof(float) >= (1ull << 32) || g.nwin_total >= (1ull << 31))
         return bad(err, SZ_ERR_UNSUPPORTED, "field planes too large (window span %llu points)",

@@ -643,6 +643,11 @@ void release_result(sz_ctx* c, sz_result* r) {
     std::memset(r, 0, sizeof(*r));
 }
 
+// the window kernels run per dimensionality: fields are grouped 3D, 2D, 1D
+constexpr int kGroups = 3;
+inline int group_of(int ndim) { return 3 - ndim; }
+inline int ndim_of(int group) { return 3 - group; }
+
 sz_status check_field(sz_ctx* c, const sz_dims* d, const sz_params* p, Geometry& g) {
     std::string why;
     const sz_status s = check_geometry(d, p, g, &why);
@@ -1151,19 +1156,19 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     Scratch sc(c);
     sz_status s;
     // work lists: one per dimensionality, fields in input order
-    std::vector<uint32_t> grp[2];
-    for (uint32_t i = 0; i < nf; ++i) grp[geo[i].ndim == 3 ? 0 : 1].push_back(i);
-    // stage descriptors grouped: 3D fields first, then 2D, so that each
+    std::vector<uint32_t> grp[kGroups];
+    for (uint32_t i = 0; i < nf; ++i) grp[group_of(geo[i].ndim)].push_back(i);
+    // stage descriptors grouped: 3D fields first, then 2D, then 1D, so that each
     // group's item offsets index a contiguous slice of the descriptor array
     std::vector<uint32_t> perm;
-    for (int gi = 0; gi < 2; ++gi) perm.insert(perm.end(), grp[gi].begin(), grp[gi].end());
+    for (int gi = 0; gi < kGroups; ++gi) perm.insert(perm.end(), grp[gi].begin(), grp[gi].end());
     std::vector<FieldDesc> fds(nf);
     for (uint32_t k = 0; k < nf; ++k) fds[k] = fd[perm[k]];
-    std::vector<uint64_t> items(2 * (nf + 1), 0);
-    uint64_t nitems[2] = {0, 0};
+    std::vector<uint64_t> items(kGroups * (nf + 1), 0);
+    uint64_t nitems[kGroups] = {0, 0, 0};
     {
         uint32_t k = 0;
-        for (int gi = 0; gi < 2; ++gi) {
+        for (int gi = 0; gi < kGroups; ++gi) {
             uint64_t* io = items.data() + gi * (nf + 1);
             io[0] = 0;
             for (size_t j = 0; j < grp[gi].size(); ++j, ++k)
@@ -1324,12 +1329,12 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
             HIP_TRY(c, launch_plan(d_fd, d_plan, (int)nf, d_pmin, d_pmax, d_pbad, q));
         }
         uint32_t base = 0;
-        for (int gi = 0; gi < 2; ++gi) {
+        for (int gi = 0; gi < kGroups; ++gi) {
             if (!grp[gi].empty()) {
                 STAGE(c, SZ_STAGE_INTERP, q);
-                HIP_TRY(c, launch_compress(gi == 0 ? 3 : 2, d_fd + base, d_plan + base,
+                HIP_TRY(c, launch_compress(ndim_of(gi), d_fd + base, d_plan + base,
                                            d_items + gi * (nf + 1), nitems[gi], c->num_cus,
-                                           shape_for(c, 0, gi == 0 ? 3 : 2, max_R), max_R, q));
+                                           shape_for(c, 0, ndim_of(gi), max_R), max_R, q));
             }
             base += (uint32_t)grp[gi].size();
         }
@@ -1366,9 +1371,9 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         std::memcpy(h + o_fd, fds.data(), sizeof(FieldDesc) * nf);
         std::memcpy(h + o_items, items.data(), sizeof(uint64_t) * items.size());
         const LaunchShape s3 = shape_for(c, 0, 3, max_R), s2 = shape_for(c, 0, 2, max_R);
-        const std::vector<uint64_t> sig = {nf, nitems[0], nitems[1], grp[0].size(), (uint64_t)max_R,
-                                           (uint64_t)s3.per_cu, (uint64_t)s2.variant,
-                                           (uint64_t)s2.per_cu, L.off};
+        const std::vector<uint64_t> sig = {nf, nitems[0], nitems[1], nitems[2], grp[0].size(),
+                                           grp[1].size(), (uint64_t)max_R, (uint64_t)s3.per_cu,
+                                           (uint64_t)s2.variant, (uint64_t)s2.per_cu, L.off};
         char* d = static_cast<char*>(c->arena);
         s = graph_run(c, 1, sig, o_fd, end1 - o_fd, st, [&](hipStream_t q) -> sz_status {
             sz_status r = enqueue1(q);
@@ -1409,9 +1414,9 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         // then the histograms rebuilt with the chosen shapes
         bool tuned = false;
         uint32_t base = 0;
-        for (int gi = 0; gi < 2; ++gi) {
-            const int nd = gi == 0 ? 3 : 2;
-            if (!grp[gi].empty() && needs_tuning(c, 0, nd, max_R)) {
+        for (int gi = 0; gi < kGroups; ++gi) {
+            const int nd = ndim_of(gi);
+            if (!grp[gi].empty() && nd >= 2 && needs_tuning(c, 0, nd, max_R)) {
                 LaunchShape best;
                 s = tune_shapes(c, nd, st, &best, [&](LaunchShape sh) -> sz_status {
                     HIP_TRY(c, launch_compress(nd, d_fd + base, d_plan + base, d_items + gi * (nf + 1),
@@ -1427,8 +1432,8 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         if (tuned) {
             HIP_TRY(c, launch_zero_hist(d_fd, (int)nf, st));
             base = 0;
-            for (int gi = 0; gi < 2; ++gi) {
-                const int nd = gi == 0 ? 3 : 2;
+            for (int gi = 0; gi < kGroups; ++gi) {
+                const int nd = ndim_of(gi);
                 if (!grp[gi].empty())
                     HIP_TRY(c, launch_compress(nd, d_fd + base, d_plan + base, d_items + gi * (nf + 1),
                                                nitems[gi], c->num_cus, shape_for(c, 0, nd, max_R),
@@ -1754,7 +1759,7 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
     Scratch sc(c);
     std::vector<FieldDesc> fds(nf);
     std::vector<FieldPlan> plans(nf);
-    std::vector<uint32_t> grp[2];
+    std::vector<uint32_t> grp[kGroups];
     std::vector<Geometry> geo(nf);
     int max_R = 0;
     for (uint32_t i = 0; i < nf; ++i) {
@@ -1772,11 +1777,11 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         if (res[i].n != geo[i].npts || res[i].n_chunks != geo[i].nchunks ||
             res[i].n_anchors != geo[i].nanch)
             return fail(c, SZ_ERR_CORRUPT, "result %u: sizes do not match its dimensions", i);
-        grp[geo[i].ndim == 3 ? 0 : 1].push_back(i);
+        grp[group_of(geo[i].ndim)].push_back(i);
         max_R = std::max(max_R, geo[i].R);
     }
     std::vector<uint32_t> perm;
-    for (int gi = 0; gi < 2; ++gi) perm.insert(perm.end(), grp[gi].begin(), grp[gi].end());
+    for (int gi = 0; gi < kGroups; ++gi) perm.insert(perm.end(), grp[gi].begin(), grp[gi].end());
     uint64_t cb = 0;
     std::vector<uint64_t> dboff(nf + 1, 0);
     for (uint32_t k = 0; k < nf; ++k) {
@@ -1804,9 +1809,9 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         dboff[k + 1] = dboff[k] + (geo[i].nchunks + kDecBlockChunks - 1) / kDecBlockChunks;
         plans[k] = R->plan;
     }
-    std::vector<uint64_t> items(2 * (nf + 1), 0);
-    uint64_t nitems[2] = {0, 0};
-    for (int gi = 0; gi < 2; ++gi) {
+    std::vector<uint64_t> items(kGroups * (nf + 1), 0);
+    uint64_t nitems[kGroups] = {0, 0, 0};
+    for (int gi = 0; gi < kGroups; ++gi) {
         uint64_t* io = items.data() + gi * (nf + 1);
         for (size_t j = 0; j < grp[gi].size(); ++j)
             io[j + 1] = io[j] + (geo[grp[gi][j]].nwin_total + kWinPerGroup - 1) / kWinPerGroup;
@@ -1830,12 +1835,12 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
             HIP_TRY(c, launch_huff_decode(d_fd, (int)nf, d_dboff, nblocks, d_bsum, 2 * max_R, q));
         }
         uint32_t base = 0;
-        for (int gi = 0; gi < 2; ++gi) {
+        for (int gi = 0; gi < kGroups; ++gi) {
             if (!grp[gi].empty()) {
                 STAGE(c, SZ_STAGE_REPLAY, q);
-                HIP_TRY(c, launch_decompress(gi == 0 ? 3 : 2, d_fd + base, d_plan + base,
+                HIP_TRY(c, launch_decompress(ndim_of(gi), d_fd + base, d_plan + base,
                                              d_items + gi * (nf + 1), nitems[gi], c->num_cus,
-                                             shape_for(c, 1, gi == 0 ? 3 : 2, max_R), q));
+                                             shape_for(c, 1, ndim_of(gi), max_R), q));
             }
             base += (uint32_t)grp[gi].size();
         }
@@ -1861,8 +1866,8 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         d_bsum = reinterpret_cast<uint32_t*>(d + o_bsum);
         // everything the launches' arguments depend on
         const LaunchShape s3 = shape_for(c, 1, 3, max_R), s2 = shape_for(c, 1, 2, max_R);
-        const std::vector<uint64_t> sig = {nf, nblocks, nitems[0], nitems[1], grp[0].size(),
-                                           (uint64_t)max_R, (uint64_t)s3.per_cu,
+        const std::vector<uint64_t> sig = {nf, nblocks, nitems[0], nitems[1], nitems[2], grp[0].size(),
+                                           grp[1].size(), (uint64_t)max_R, (uint64_t)s3.per_cu,
                                            (uint64_t)s2.variant, (uint64_t)s2.per_cu, L.off};
         if ((s = graph_run(c, 0, sig, 0, staged, st, enqueue))) return s;
         HIP_TRY(c, hipStreamSynchronize(c->gstream));
@@ -1894,9 +1899,9 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
     if ((s = enqueue(st))) return s;
     // launch-shape tuning: the replay rewrites the same values
     uint32_t base = 0;
-    for (int gi = 0; gi < 2; ++gi) {
-        const int nd = gi == 0 ? 3 : 2;
-        if (!grp[gi].empty() && needs_tuning(c, 1, nd, max_R)) {
+    for (int gi = 0; gi < kGroups; ++gi) {
+        const int nd = ndim_of(gi);
+        if (!grp[gi].empty() && nd >= 2 && needs_tuning(c, 1, nd, max_R)) {
             LaunchShape best;
             s = tune_shapes(c, nd, st, &best, [&](LaunchShape sh) -> sz_status {
                 HIP_TRY(c, launch_decompress(nd, d_fd + base, d_plan + base, d_items + gi * (nf + 1),

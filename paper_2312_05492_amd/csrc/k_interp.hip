@@ -922,6 +922,180 @@ SZI_WINDOW_KERNEL void k_decompress(const FieldDesc* __restrict__ F,
     }
 }
 
+// ------------------------------------------------------------ 1D fields
+// Sec. V-A in one dimension: anchors every kS1 = 512 points, nine levels
+// (strides 256 .. 1), one pass per level.  A window is four chunks, 2048
+// points, plus the far anchor, as the 3D and 2D windows span four chunks
+// along x; one wave per window, its block in LDS, one target per lane at a
+// time.  The stencils, the quantiser and the histogram are those of the
+// window passes above.
+constexpr int kS1 = 512, kL1 = 9, kW1 = 4 * kS1;
+constexpr int kV1 = kW1 + 4;   // LDS floats per wave: the block of kW1 + 1
+
+struct Win1 {
+    uint64_t lo;   // first point
+    int e;         // block extent: owned points, and the far anchor where present
+    int o;         // owned extent
+};
+
+__device__ __forceinline__ Win1 make_win1(const FieldDesc& f, uint32_t w) {
+    Win1 wi;
+    wi.lo = (uint64_t)w * (uint64_t)kW1;
+    const uint64_t left = f.npts - 1 - wi.lo;
+    wi.e = (int)(left < (uint64_t)kW1 ? left : (uint64_t)kW1) + 1;
+    wi.o = wi.e < kW1 ? wi.e : kW1;
+    return wi;
+}
+
+// One level at stride s: the targets at odd multiples of s in the window.
+// Compression stores each owned target's quant-code at cb and counts it;
+// the replay takes an outlier's value from ob.
+template <int SPL, bool COMP>
+__device__ __forceinline__ void level1(float* v, uint32_t lane, int s, const Win1& wi, float el,
+                                       float ebx2, float inv, int R, SZI_G uint16_t* cb,
+                                       const SZI_G float* ob, uint32_t* hist, uint32_t& cntR) {
+    const int nt = kW1 / (2 * s);
+    const float Rf = (float)R;
+    const int last = wi.e - 1;   // the window interval ends here
+#pragma unroll 1
+    for (int t = (int)lane; t < nt; t += 64) {
+        const int p = (2 * t + 1) * s;
+        const bool act = p <= last;
+        const bool m3 = p >= 3 * s;
+        const bool p1 = p + s <= last;
+        const bool p3 = p + 3 * s <= last;
+        const float a = m3 ? v[p - 3 * s] : 0.0f;
+        const float b = v[p - s];
+        const float c = p1 ? v[p + s] : 0.0f;
+        const float d = p3 ? v[p + 3 * s] : 0.0f;
+        float num;
+        float pr = predict<SPL>(m3, p1, p3, a, b, c, d, num);
+        if (SPL == SPL_NAT) {   // numerators below the fast division's range: rare
+            const bool small = !(fabsf(num) >= 0x1p-123f);
+            if (wave_any(small) && small) pr = num / 40.0f;
+        }
+        if (COMP) {
+            const float xv = v[p];
+            const float q = rintf((xv - pr) * inv);
+            const float xr = pr + q * ebx2;
+            const bool inr = fabsf(q) < Rf;
+            const bool good = inr && fabsf(xv - xr) < el;
+            float vv = good ? xr : xv;
+            uint32_t cd = good ? (uint32_t)((int)q + R) : 0u;
+            if (wave_any(act && good != inr)) {   // the FP64 bound test where FP32 cannot decide
+                if (inr && !(fabsf(xv - xr) < el) && fabs((double)xv - (double)xr) <= (double)el) {
+                    vv = xr;
+                    cd = (uint32_t)((int)q + R);
+                }
+            }
+            const bool own = act && p < wi.o;
+            if (act) {
+                v[p] = vv;
+                if (own) cb[p] = (uint16_t)cd;
+                const uint32_t bin = own && cd != (uint32_t)R ? cd : (uint32_t)(2 * R) + lane;
+                atomicAdd(&hist[bin], 1u);
+            }
+            cntR += (uint32_t)__popcll(wave_ballot(act && !own));
+        } else if (act) {
+            const uint32_t code = __float_as_uint(v[p]);
+            // code 0: an outlier, whose value the scatter step put in the output
+            v[p] = code == 0u ? ob[p] : pr + (float)((int)code - R) * ebx2;
+        }
+    }
+}
+
+template <bool COMP>
+__device__ __forceinline__ void levels1(float* v, uint32_t lane, const FieldPlan& pl, const Win1& wi,
+                                        int R, SZI_G uint16_t* cb, const SZI_G float* ob,
+                                        uint32_t* hist, uint32_t& cntR) {
+#pragma unroll 1
+    for (int l = kL1; l >= 1; --l) {
+        const int s = 1 << (l - 1);
+        const float el = pl.el[l - 1], ebx2 = pl.ebx2[l - 1];
+        const float inv = el == 0.0f ? 0.0f : pl.inv[l - 1];
+        if (pl.spline[0] == SPL_LIN) level1<SPL_LIN, COMP>(v, lane, s, wi, el, ebx2, inv, R, cb, ob, hist, cntR);
+        else if (pl.spline[0] == SPL_NAK) level1<SPL_NAK, COMP>(v, lane, s, wi, el, ebx2, inv, R, cb, ob, hist, cntR);
+        else level1<SPL_NAT, COMP>(v, lane, s, wi, el, ebx2, inv, R, cb, ob, hist, cntR);
+        wave_sync();
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_compress1d(const FieldDesc* __restrict__ F,
+                                                         const FieldPlan* __restrict__ P,
+                                                         const uint64_t* __restrict__ goff,
+                                                         uint64_t ngroups) {
+    __shared__ float vbuf[kWaves][kV1];
+    extern __shared__ uint32_t hist[];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t lane = threadIdx.x & 63u;
+    float* v = vbuf[wave];
+    const GroupSeq gs = group_seq(ngroups);
+    int f = 0, hf = -1;
+    uint32_t cntR = 0;
+#pragma unroll 1
+    for (uint64_t g = gs.cur; g < gs.end; g += gs.step) {
+        while (g >= goff[f + 1]) ++f;
+        if (f != hf) {   // uniform over the workgroup: groups never span fields
+            if (hf >= 0) flush_hist(hist, cntR, F[hf]);
+            clear_hist(hist, F[f].R);
+            __syncthreads();
+            hf = f;
+        }
+        const FieldDesc& fd = F[f];
+        const uint32_t w = (uint32_t)(g - goff[f]) * kWaves + (uint32_t)wave;
+        if (w >= (uint32_t)fd.nwin[0]) continue;
+        const Win1 wi = make_win1(fd, w);
+        const SZI_G float* in = gp(fd.in) + wi.lo;
+#pragma unroll 4
+        for (int i = (int)lane; i < wi.e; i += 64) v[i] = in[i];
+        wave_sync();
+        SZI_G uint16_t* cb = gp(fd.codes) + wi.lo;
+        levels1<true>(v, lane, P[f], wi, fd.R, cb, nullptr, hist, cntR);
+        // owned anchors: their values losslessly, quant-code R, counted
+        if (lane < (uint32_t)(kW1 / kS1) && (int)lane * kS1 < wi.o) {
+            gp(fd.anchors)[wi.lo / kS1 + lane] = v[lane * kS1];
+            cb[lane * kS1] = (uint16_t)fd.R;
+            atomicAdd(&hist[2 * fd.R + lane], 1u);
+        }
+        wave_sync();
+    }
+    if (hf >= 0) flush_hist(hist, cntR, F[hf]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_decompress1d(const FieldDesc* __restrict__ F,
+                                                           const FieldPlan* __restrict__ P,
+                                                           const uint64_t* __restrict__ goff,
+                                                           uint64_t ngroups) {
+    __shared__ float vbuf[kWaves][kV1];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t lane = threadIdx.x & 63u;
+    float* v = vbuf[wave];
+    const GroupSeq gs = group_seq(ngroups);
+    int f = 0;
+    uint32_t unused = 0;
+#pragma unroll 1
+    for (uint64_t g = gs.cur; g < gs.end; g += gs.step) {
+        while (g >= goff[f + 1]) ++f;
+        const FieldDesc& fd = F[f];
+        const uint32_t w = (uint32_t)(g - goff[f]) * kWaves + (uint32_t)wave;
+        if (w >= (uint32_t)fd.nwin[0]) continue;
+        const Win1 wi = make_win1(fd, w);
+        // every point takes its code (as float bits), the anchors their values
+        const SZI_G uint16_t* cb = gp(fd.codes) + wi.lo;
+#pragma unroll 4
+        for (int i = (int)lane; i < wi.e; i += 64) v[i] = __uint_as_float((uint32_t)cb[i]);
+        wave_sync();
+        if (lane <= (uint32_t)(kW1 / kS1) && (int)lane * kS1 < wi.e)
+            v[lane * kS1] = gp(fd.anchors)[wi.lo / kS1 + lane];
+        wave_sync();
+        SZI_G float* ob = gp(fd.out) + wi.lo;
+        levels1<false>(v, lane, P[f], wi, fd.R, nullptr, ob, nullptr, unused);
+#pragma unroll 4
+        for (int i = (int)lane; i < wi.o; i += 64) ob[i] = v[i];
+        wave_sync();
+    }
+}
+
 // ------------------------------------------------------- launchers
 // The persistent grid is the number of workgroups resident at once
 // (occupancy from the runtime x compute units) unless per_cu overrides it,
@@ -965,6 +1139,7 @@ hipError_t launch_compress(int ndim, const FieldDesc* d_fields, const FieldPlan*
                            d_goff, ngroups);
     };
     if (ndim == 3) go(k_compress<3, 3>);
+    else if (ndim == 1) go(k_compress1d);
     else if (shape.variant == 1) go(k_compress<2, 4>);
     else go(k_compress<2, 3>);
     return hipGetLastError();
@@ -980,6 +1155,7 @@ hipError_t launch_decompress(int ndim, const FieldDesc* d_fields, const FieldPla
                            d_goff, ngroups);
     };
     if (ndim == 3) go(k_decompress<3, 3>);
+    else if (ndim == 1) go(k_decompress1d);
     else if (shape.variant == 1) go(k_decompress<2, 4>);
     else go(k_decompress<2, 3>);
     return hipGetLastError();

@@ -101,7 +101,7 @@ __device__ void profile_field(const FieldDesc& f, FieldPlan& P) {
     const int t = threadIdx.x;
     if (t >= 64) return;
     const int D = f.ndim;
-    const int ns = D == 3 ? 64 : 16;
+    const int ns = D == 3 ? 64 : (D == 2 ? 16 : 4);   // 4^D samples
     for (int d = 0; d < 3; ++d)
         for (int k = 0; k < 3; ++k) err[t][d][k] = 0.0;
     if (f.need_prof && t < ns) {
@@ -235,7 +235,8 @@ __device__ void make_passes(FieldPlan& p, const PlanIn& in, uint32_t n0, uint32_
 __device__ void make_passes(const FieldDesc& f, FieldPlan& p, const PlanIn& in) {
     const uint32_t n0 = (uint32_t)f.n[0], n01 = n0 * (uint32_t)f.n[1];
     if (f.ndim == 3) make_passes<3>(p, in, n0, n01);
-    else make_passes<2>(p, in, n0, n01);
+    else if (f.ndim == 2) make_passes<2>(p, in, n0, n01);
+    // 1D: the line kernels take the level bounds and the spline directly
 }
 
 // Decompression prologue, one workgroup of kDecBlockChunks threads per

@@ -4,7 +4,7 @@
 
 namespace szi {
 
-constexpr int kMaxLevels = 8;
+constexpr int kMaxLevels = 9;      // 1D: strides 256 .. 1
 constexpr int kLmax = 24;          // Huffman length limit
 constexpr int kMaxRadius = 1024;   // LDS histogram holds 2R <= 2048 bins
 

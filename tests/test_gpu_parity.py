@@ -154,6 +154,18 @@ CASES = [
      dict(interp=(0, 0, 0), eb=0.5, eb_mode=0)),
     ("long_codes_2d", lambda: synth.fib_spikes((700, 700), seed=27),
      dict(interp=(0, 0), eb=0.5, eb_mode=0)),
+    # 1D fields (Sec. V-A: anchors every 512 points, windows of 2048)
+    ("line1d_100003", _spec((100003,), 40, mean=10.0), {}),
+    ("line1d_e4_nat", _spec((65537,), 41, beta=3.0), dict(eb=1e-4, interp=(2,))),
+    ("line1d_linear", _spec((4097,), 42), dict(interp=(0,))),
+    ("line1d_nak_e2", _spec((20000,), 43), dict(eb=1e-2, interp=(1,))),
+    ("line1d_short_700", _spec((700,), 44), {}),
+    ("line1d_exact_window_2048", _spec((2048,), 45), {}),
+    ("line1d_2049", _spec((2049,), 46), {}),
+    ("line1d_single", _const((1,), 2.0), {}),
+    ("line1d_tiny_bound", _spec((5000,), 47), dict(eb=1e-30, eb_mode=0)),
+    ("line1d_zero_bound_signed", _signed_zeros((3000,), 48), dict(eb=0.0, eb_mode=0)),
+    ("line1d_radius_odd", _spec((30000,), 49, beta=1.0), dict(eb=1e-4, radius=37, chunk=256)),
 ]
 
 
@@ -178,6 +190,25 @@ def test_batch_equals_single_calls(ctx):
         assert np.array_equal(_bits(y.cpu().numpy()), _bits(ref.recon))
     for r in outs:
         r.free()
+
+
+def test_batch_of_all_dimensionalities(ctx):
+    # 3D, 2D and 1D fields in one call: three window-kernel groups
+    fields = [synth.spectral_field((300001,), seed=51), synth.spectral_field((20, 30, 70), seed=52),
+              synth.spectral_field((5000,), seed=53, beta=3.0), synth.climate_field(303, shape=(60, 130)),
+              synth.spectral_field((1,), seed=54)]
+    params = [dict(eb=1e-3), dict(eb=1e-4), dict(eb=1e-2, interp=(2,)), {}, {}]
+    refs = [O.compress(f, _oracle_params(f.shape, kw)) for f, kw in zip(fields, params)]
+    print("\n[parity] batch of 3D, 2D and 1D fields", flush=True)
+    for rep in range(2):
+        outs = ctx.compress_batch([_to_gpu(f) for f in fields], params)
+        for r, ref in zip(outs, refs):
+            assert r.blob() == ref.blob()
+        ys = ctx.decompress_batch(outs)
+        for y, ref in zip(ys, refs):
+            assert np.array_equal(_bits(y.cpu().numpy()), _bits(ref.recon))
+        for r in outs:
+            r.free()
 
 
 def test_larger_batch_twice_equals_oracle(ctx):

@@ -247,6 +247,57 @@ def test_anchors_are_the_lattice_points():
     assert np.array_equal(c2.anchors, x2[::16, ::16].ravel())
 
 
+# ------------------------------------------------ 1D (Sec. V-A: chunks of 512)
+@pytest.mark.parametrize("interp", [O.LIN, O.NAK, O.NAT, O.AUTO])
+def test_integer_ramp_1d_all_codes_centre(interp):
+    # n = 4097 = 1 (mod 512): every target has both stride neighbours
+    x = _ramp((4097,), coef=(3,), off=-11)
+    p = O.Params(shape=x.shape, eb=1e-3, interp=(interp,))
+    c = O.compress(x, p)
+    assert c.config.levels == 9                  # strides 256 .. 1
+    assert (c.codes == p.R).all()
+    assert np.array_equal(c.recon.view(np.uint32), x.view(np.uint32))
+
+
+def test_1d_anchors_and_tiny_bound():
+    x = synth.spectral_field((5000,), seed=12)
+    p = O.Params(shape=x.shape, eb=1e-30, eb_mode=O.EB_ABS)
+    c = O.compress(x, p)
+    assert np.array_equal(c.anchors, x[::512])
+    assert c.anchors.size == math.ceil(5000 / 512)
+    is_anchor = np.zeros(x.shape, bool)
+    is_anchor[::512] = True
+    assert (c.codes[is_anchor] == p.R).all() and (c.codes[~is_anchor] == 0).all()
+    assert np.array_equal(c.outlier_idx, np.flatnonzero(~is_anchor))
+
+
+def test_1d_profiling_picks_nak_on_a_cubic():
+    # an integer cubic is reproduced by the not-a-knot stencil, not by the
+    # natural one (whose x^2 and x^3 terms leave an error)
+    i = np.arange(3000, dtype=np.float64)
+    x = (((i / 40.0) - 30.0) ** 3).astype(np.float32)
+    c = O.compress(x, O.Params(shape=x.shape, eb=1e-4))
+    assert c.config.spline[0] == O.NAK
+    assert c.config.prof[0][1] < c.config.prof[0][2]
+
+
+def test_1d_level_strides_and_window():
+    # the first level predicts the chunk midpoints from the anchors (stride
+    # 256); a window of four chunks (2048 points) gives the first and last
+    # chunk of each window one-sided (quadratic) stencils at stride 256
+    x = _ramp((4097,), coef=(1,), off=0)
+    x = (x * x).astype(np.float32) / np.float32(1024.0)    # a quadratic, exact in FP32
+    p = O.Params(shape=x.shape, eb=1e-6, interp=(O.NAK,))
+    c = O.compress(x, p, want_cls=True)
+    cls = np.asarray(c.cls).ravel()
+    mids = np.arange(256, 4097, 512)
+    # at stride 256: midpoints 256 and 1792 of each window lack a side (quadratic),
+    # 768 and 1280 have both (cubic)
+    side = mids % 2048
+    assert set(cls[mids[(side == 256) | (side == 1792)]].tolist()) <= {O.CLS_QUAD}
+    assert set(cls[mids[(side == 768) | (side == 1280)]].tolist()) <= {O.CLS_CUBIC}
+
+
 CASES = [
     ("bumps64", lambda: synth.bumps_field((64, 64, 64), seed=1), dict(eb=1e-3)),
     ("spec3d", lambda: synth.spectral_field((33, 41, 70), seed=2, mean=10), dict(eb=1e-4)),
@@ -263,6 +314,9 @@ CASES = [
      dict(eb=0.0, eb_mode=O.EB_ABS, interp=(O.NAT, O.NAK, O.NAT))),
     ("signed_zeros_abs", lambda: _signed_zeros((12, 20, 36), 8),
      dict(eb=0.25, eb_mode=O.EB_ABS, interp=(O.NAT, O.LIN, O.NAK))),
+    ("line1d", lambda: synth.spectral_field((100003,), seed=13, mean=10.0), dict(eb=1e-3)),
+    ("line1d_short_nat", lambda: synth.spectral_field((700,), seed=14, beta=3.0),
+     dict(eb=1e-4, interp=(O.NAT,))),
 ]
 
 
