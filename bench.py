@@ -595,6 +595,11 @@ def main():
                     help="spline per dimension: " + "; ".join("%s = %s" % kv for kv in sorted(INTERP_DESC.items())))
     ap.add_argument("--chunk", type=int, default=1024, choices=(256, 512, 1024, 2048),
                     help="Huffman chunk length in symbols")
+    ap.add_argument("--stride", type=int, default=0,
+                    help="anchor stride (0: 8 in 3D, 16 in 2D, 512 in 1D)")
+    ap.add_argument("--window", default="",
+                    help="window per numpy axis, e.g. 8,16,16 (default: four chunks along x, one "
+                         "along the others); other strides and windows run the generic window kernels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain device copy of the input (4n bytes read, 4n written) "
@@ -656,6 +661,10 @@ def main():
     out = torch.empty_like(d_x)
     ctx = szi.Context(0)
     kw = dict(eb=args.eb, chunk=args.chunk, interp=INTERP[args.interp][-x.ndim:])
+    if args.stride:
+        kw["S"] = args.stride
+    if args.window:
+        kw["window"] = tuple(int(v) for v in args.window.split(","))
 
     if args.calibrate_copy:
         out.copy_(d_x)
@@ -787,7 +796,8 @@ def main():
         pipe[k] = {"kernel_ms": round(ms, 4), "algorithmic_bytes": int(pb[k]),
                    "bytes_per_point": round(pb[k] / n, 3), "GBps": round(gbs, 1),
                    "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    traffic = read_traffic().get(STAGE_KERNELS.get(dom)) if args.workload == "large" else None
+    default_geometry = not args.stride and not args.window
+    traffic = read_traffic().get(STAGE_KERNELS.get(dom)) if args.workload == "large" and default_geometry else None
 
     line = {
         "metric": METRIC,
@@ -803,7 +813,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "shape": list(wl["shape"]), "eb_rel": args.eb,
-                   "interp": INTERP_DESC[args.interp], "anchor_stride": {3: 8, 2: 16, 1: 512}[x.ndim], "radius": 512,
+                   "interp": INTERP_DESC[args.interp],
+                   "anchor_stride": args.stride or {3: 8, 2: 16, 1: 512}[x.ndim],
+                   "window": list(kw["window"]) if "window" in kw else "default", "radius": 512,
                    "huffman_chunk": args.chunk},
         "compress_GBps": round(in_bytes / float(np.median(t_c)) / 1e9, 2),
         "decompress_GBps": round(in_bytes / float(np.median(t_d)) / 1e9, 2),
@@ -836,7 +848,8 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
-        p = oracle.Params(shape=x.shape, eb=args.eb, chunk=args.chunk, interp=INTERP[args.interp][-x.ndim:])
+        p = oracle.Params(shape=x.shape, eb=args.eb, chunk=args.chunk, interp=INTERP[args.interp][-x.ndim:],
+                          S=args.stride or None, window=kw.get("window"))
         # whole-field round trips until about 10 s of CPU work
         reps, tc, td = 0, 0.0, 0.0
         while reps < 1 or (tc + td < 10.0 and reps < 8):

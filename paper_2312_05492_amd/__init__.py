@@ -172,9 +172,10 @@ def make_dims(shape) -> SzDims:
 
 
 def make_params(ndim, eb=1e-3, eb_mode=EB_REL, interp=None, order=None, alpha=0.0, radius=512,
-                chunk=1024) -> SzParams:
-    """interp and order are given per numpy axis (slowest first), as in the
-    oracle's Params; they are stored per dimension index (0 = fastest)."""
+                chunk=1024, S=0, window=None) -> SzParams:
+    """interp, order and window are given per numpy axis (slowest first), as
+    in the oracle's Params; they are stored per dimension index (0 =
+    fastest).  S: anchor stride (0 = the default of the dimensionality)."""
     p = SzParams()
     lib().sz_params_default(C.byref(p))
     p.eb_mode = eb_mode
@@ -188,6 +189,10 @@ def make_params(ndim, eb=1e-3, eb_mode=EB_REL, interp=None, order=None, alpha=0.
     p.alpha = float(alpha)
     p.radius = int(radius)
     p.huff_chunk = int(chunk)
+    p.anchor_stride = int(S)
+    if window is not None:
+        for ax, w in enumerate(window):
+            p.window[ndim - 1 - ax] = int(w)
     return p
 
 

@@ -65,24 +65,45 @@ sz_status check_geometry(const sz_dims* d, const sz_params* p, Geometry& g, std:
     if (chunk != 256 && chunk != 512 && chunk != 1024 && chunk != 2048)
         return bad(err, SZ_ERR_UNSUPPORTED, "Huffman chunk %u", chunk);
     g.chunk = (int)chunk;
-    // Sec. V-A: chunks of 8^3, 16^2 or 512 points; a window spans four
-    // chunks along x and one along the other dimensions
-    const int S = g.ndim == 3 ? 8 : (g.ndim == 2 ? 16 : 512);
-    if (p->anchor_stride && (int)p->anchor_stride != S)
-        return bad(err, SZ_ERR_UNSUPPORTED, "anchor stride %u (this build: %d)", p->anchor_stride, S);
-    const int wdef[3] = {4 * S, g.ndim >= 2 ? S : 1, g.ndim == 3 ? S : 1};
-    for (int k = 0; k < g.ndim; ++k)
-        if (p->window[k] && (int)p->window[k] != wdef[k])
-            return bad(err, SZ_ERR_UNSUPPORTED, "window[%d] = %u (this build: %d)", k, p->window[k],
-                       wdef[k]);
-    g.S = S;
-    g.L = g.ndim == 3 ? 3 : (g.ndim == 2 ? 4 : 9);   // log2 S
+    // Sec. V-A: chunks of 8^3, 16^2 or 512 points by default; a window spans
+    // four chunks along x and one along the other dimensions.  Other strides
+    // (powers of two, at most kMaxLevels levels) and windows (multiples of
+    // the stride) run the generic window kernels.
+    const int Sdef = g.ndim == 3 ? 8 : (g.ndim == 2 ? 16 : 512);
+    const uint32_t S = p->anchor_stride ? p->anchor_stride : (uint32_t)Sdef;
+    if (S < 2 || (S & (S - 1)) || S > (1u << kMaxLevels))
+        return bad(err, SZ_ERR_UNSUPPORTED, "anchor stride %u (powers of two 2..%d)", S, 1 << kMaxLevels);
+    int L = 0;
+    while ((1u << L) < S) ++L;
+    g.S = (int)S;
+    g.L = L;
+    g.generic = (int)S != Sdef;
+    const int wdef[3] = {4 * (int)S, g.ndim >= 2 ? (int)S : 1, g.ndim == 3 ? (int)S : 1};
+    int wk[3] = {1, 1, 1};
+    uint64_t block = 1;
+    for (int k = 0; k < g.ndim; ++k) {
+        const uint32_t w = p->window[k] ? p->window[k] : (uint32_t)wdef[k];
+        if (w % S || w > (uint32_t)kGenMaxExtent * 4)
+            return bad(err, SZ_ERR_UNSUPPORTED, "window[%d] = %u (a multiple of the stride %u)", k, w, S);
+        wk[k] = (int)w;
+        block *= (uint64_t)w + 1;
+        if ((int)w != (k == 0 ? 4 * Sdef : Sdef)) g.generic = true;
+    }
+    if (g.generic) {
+        for (int k = 0; k < g.ndim; ++k)
+            if (wk[k] > kGenMaxExtent)
+                return bad(err, SZ_ERR_UNSUPPORTED, "window[%d] = %d (other windows: at most %d)", k,
+                           wk[k], kGenMaxExtent);
+        if (block > (uint64_t)kGenMaxBlock)
+            return bad(err, SZ_ERR_UNSUPPORTED, "window block of %llu points (other windows: at most %d)",
+                       (unsigned long long)block, kGenMaxBlock);
+    }
     g.nwin_total = 1;
     g.nanch = 1;
     for (int k = 0; k < 3; ++k) {
-        g.w[k] = wdef[k];
+        g.w[k] = wk[k];
         g.nwin[k] = (g.n[k] + g.w[k] - 1) / g.w[k];
-        g.na[k] = k < g.ndim ? (g.n[k] + S - 1) / S : 1;
+        g.na[k] = k < g.ndim ? (g.n[k] + (int)S - 1) / (int)S : 1;
         g.nwin_total *= (uint64_t)g.nwin[k];
         g.nanch *= (uint64_t)g.na[k];
     }
@@ -90,7 +111,7 @@ sz_status check_geometry(const sz_dims* d, const sz_params* p, Geometry& g, std:
     // origin and number windows with 32-bit integers
     const uint64_t span = (uint64_t)g.w[0] + (g.ndim >= 2 ? (uint64_t)g.w[1] * (uint64_t)g.n[0] : 0) +
                           (g.ndim == 3 ? (uint64_t)g.w[2] * (uint64_t)g.n[0] * (uint64_t)g.n[1] : 0);
-    if (span * sizeof(float) >= (1ull << 32) || g.nwin_total >= (1ull << 31))
+    if ((!g.generic && span * sizeof(float) >= (1ull << 32)) || g.nwin_total >= (1ull << 31))
         return bad(err, SZ_ERR_UNSUPPORTED, "field planes too large (window span %llu points)",
                    (unsigned long long)span);
     g.nchunks = (npts + (uint64_t)g.chunk - 1) / (uint64_t)g.chunk;

@@ -19,6 +19,7 @@ namespace szi {
 struct Geometry {
     int ndim, n[3], S, L, w[3], nwin[3], na[3], R, chunk;
     uint64_t npts, nanch, nwin_total, nchunks;
+    bool generic;   // not the default stride and window: the generic window kernels
 };
 
 // The geometry of a field with these dimensions and parameters, or

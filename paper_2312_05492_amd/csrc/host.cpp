@@ -643,10 +643,28 @@ void release_result(sz_ctx* c, sz_result* r) {
     std::memset(r, 0, sizeof(*r));
 }
 
-// the window kernels run per dimensionality: fields are grouped 3D, 2D, 1D
-constexpr int kGroups = 3;
-inline int group_of(int ndim) { return 3 - ndim; }
-inline int ndim_of(int group) { return 3 - group; }
+// the window kernels run per group of fields: 3D, 2D and 1D with the
+// default stride and window, then every other geometry (the generic kernels)
+constexpr int kGroups = 4, kGenGroup = 3;
+inline int group_of(const Geometry& g) { return g.generic ? kGenGroup : 3 - g.ndim; }
+inline int ndim_of(int group) { return 3 - group; }   // groups 0..2
+
+hipError_t launch_compress_group(sz_ctx* c, int gi, const FieldDesc* d_fd, const FieldPlan* d_plan,
+                                 const uint64_t* d_items, uint64_t nitems, LaunchShape sh, int max_R,
+                                 hipStream_t q) {
+    if (gi == kGenGroup) return launch_compress_gen(d_fd, d_plan, d_items, nitems, c->num_cus, max_R, q);
+    return launch_compress(ndim_of(gi), d_fd, d_plan, d_items, nitems, c->num_cus, sh, max_R, q);
+}
+
+hipError_t launch_decompress_group(sz_ctx* c, int gi, const FieldDesc* d_fd, const FieldPlan* d_plan,
+                                   const uint64_t* d_items, uint64_t nitems, LaunchShape sh,
+                                   hipStream_t q) {
+    if (gi == kGenGroup) return launch_decompress_gen(d_fd, d_plan, d_items, nitems, c->num_cus, q);
+    return launch_decompress(ndim_of(gi), d_fd, d_plan, d_items, nitems, c->num_cus, sh, q);
+}
+
+// the tuner times launch shapes of the 3D and 2D default kernels only
+inline bool tunable(int gi) { return gi == 0 || gi == 1; }
 
 sz_status check_field(sz_ctx* c, const sz_dims* d, const sz_params* p, Geometry& g) {
     std::string why;
@@ -1157,7 +1175,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     sz_status s;
     // work lists: one per dimensionality, fields in input order
     std::vector<uint32_t> grp[kGroups];
-    for (uint32_t i = 0; i < nf; ++i) grp[group_of(geo[i].ndim)].push_back(i);
+    for (uint32_t i = 0; i < nf; ++i) grp[group_of(geo[i])].push_back(i);
     // stage descriptors grouped: 3D fields first, then 2D, then 1D, so that each
     // group's item offsets index a contiguous slice of the descriptor array
     std::vector<uint32_t> perm;
@@ -1165,7 +1183,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     std::vector<FieldDesc> fds(nf);
     for (uint32_t k = 0; k < nf; ++k) fds[k] = fd[perm[k]];
     std::vector<uint64_t> items(kGroups * (nf + 1), 0);
-    uint64_t nitems[kGroups] = {0, 0, 0};
+    uint64_t nitems[kGroups] = {0, 0, 0, 0};
     {
         uint32_t k = 0;
         for (int gi = 0; gi < kGroups; ++gi) {
@@ -1332,9 +1350,9 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         for (int gi = 0; gi < kGroups; ++gi) {
             if (!grp[gi].empty()) {
                 STAGE(c, SZ_STAGE_INTERP, q);
-                HIP_TRY(c, launch_compress(ndim_of(gi), d_fd + base, d_plan + base,
-                                           d_items + gi * (nf + 1), nitems[gi], c->num_cus,
-                                           shape_for(c, 0, ndim_of(gi), max_R), max_R, q));
+                HIP_TRY(c, launch_compress_group(c, gi, d_fd + base, d_plan + base,
+                                                 d_items + gi * (nf + 1), nitems[gi],
+                                                 shape_for(c, 0, ndim_of(gi), max_R), max_R, q));
             }
             base += (uint32_t)grp[gi].size();
         }
@@ -1416,7 +1434,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         uint32_t base = 0;
         for (int gi = 0; gi < kGroups; ++gi) {
             const int nd = ndim_of(gi);
-            if (!grp[gi].empty() && nd >= 2 && needs_tuning(c, 0, nd, max_R)) {
+            if (!grp[gi].empty() && tunable(gi) && needs_tuning(c, 0, nd, max_R)) {
                 LaunchShape best;
                 s = tune_shapes(c, nd, st, &best, [&](LaunchShape sh) -> sz_status {
                     HIP_TRY(c, launch_compress(nd, d_fd + base, d_plan + base, d_items + gi * (nf + 1),
@@ -1435,9 +1453,9 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
             for (int gi = 0; gi < kGroups; ++gi) {
                 const int nd = ndim_of(gi);
                 if (!grp[gi].empty())
-                    HIP_TRY(c, launch_compress(nd, d_fd + base, d_plan + base, d_items + gi * (nf + 1),
-                                               nitems[gi], c->num_cus, shape_for(c, 0, nd, max_R),
-                                               max_R, st));
+                    HIP_TRY(c, launch_compress_group(c, gi, d_fd + base, d_plan + base,
+                                                     d_items + gi * (nf + 1), nitems[gi],
+                                                     shape_for(c, 0, nd, max_R), max_R, st));
                 base += (uint32_t)grp[gi].size();
             }
         }
@@ -1772,12 +1790,14 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         p.huff_chunk = (uint32_t)R->chunk;
         p.eb_mode = R->eb_mode;
         p.eb = R->eb >= 0 ? R->eb : 0;
+        p.anchor_stride = (uint32_t)R->S;
+        for (int k = 0; k < (int)R->dims.ndim && k < 3; ++k) p.window[k] = (uint32_t)R->w[k];
         sz_status s = check_field(c, &R->dims, &p, geo[i]);
         if (s) return s;
         if (res[i].n != geo[i].npts || res[i].n_chunks != geo[i].nchunks ||
             res[i].n_anchors != geo[i].nanch)
             return fail(c, SZ_ERR_CORRUPT, "result %u: sizes do not match its dimensions", i);
-        grp[group_of(geo[i].ndim)].push_back(i);
+        grp[group_of(geo[i])].push_back(i);
         max_R = std::max(max_R, geo[i].R);
     }
     std::vector<uint32_t> perm;
@@ -1810,7 +1830,7 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         plans[k] = R->plan;
     }
     std::vector<uint64_t> items(kGroups * (nf + 1), 0);
-    uint64_t nitems[kGroups] = {0, 0, 0};
+    uint64_t nitems[kGroups] = {0, 0, 0, 0};
     for (int gi = 0; gi < kGroups; ++gi) {
         uint64_t* io = items.data() + gi * (nf + 1);
         for (size_t j = 0; j < grp[gi].size(); ++j)
@@ -1838,9 +1858,9 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         for (int gi = 0; gi < kGroups; ++gi) {
             if (!grp[gi].empty()) {
                 STAGE(c, SZ_STAGE_REPLAY, q);
-                HIP_TRY(c, launch_decompress(ndim_of(gi), d_fd + base, d_plan + base,
-                                             d_items + gi * (nf + 1), nitems[gi], c->num_cus,
-                                             shape_for(c, 1, ndim_of(gi), max_R), q));
+                HIP_TRY(c, launch_decompress_group(c, gi, d_fd + base, d_plan + base,
+                                                   d_items + gi * (nf + 1), nitems[gi],
+                                                   shape_for(c, 1, ndim_of(gi), max_R), q));
             }
             base += (uint32_t)grp[gi].size();
         }
@@ -1901,7 +1921,7 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
     uint32_t base = 0;
     for (int gi = 0; gi < kGroups; ++gi) {
         const int nd = ndim_of(gi);
-        if (!grp[gi].empty() && nd >= 2 && needs_tuning(c, 1, nd, max_R)) {
+        if (!grp[gi].empty() && tunable(gi) && needs_tuning(c, 1, nd, max_R)) {
             LaunchShape best;
             s = tune_shapes(c, nd, st, &best, [&](LaunchShape sh) -> sz_status {
                 HIP_TRY(c, launch_decompress(nd, d_fd + base, d_plan + base, d_items + gi * (nf + 1),
@@ -1942,6 +1962,8 @@ sz_status sz_decompress_noalloc(sz_ctx* c, const sz_result* res, float* d_out, v
     p.huff_chunk = (uint32_t)R->chunk;
     p.eb_mode = R->eb_mode;
     p.eb = R->eb >= 0 ? R->eb : 0;
+    p.anchor_stride = (uint32_t)R->S;
+    for (int k = 0; k < (int)R->dims.ndim && k < 3; ++k) p.window[k] = (uint32_t)R->w[k];
     Geometry geo;
     sz_status s = check_field(c, &R->dims, &p, geo);
     if (s) return s;
@@ -1995,8 +2017,8 @@ sz_status sz_decompress_noalloc(sz_ctx* c, const sz_result* res, float* d_out, v
     HIP_TRY(c, launch_stage_words(reinterpret_cast<uint32_t*>(ws), sw, st));
     HIP_TRY(c, launch_dec_prep(d_fd, d_plan, 1, d_dboff, nblocks, d_bsum, st));
     HIP_TRY(c, launch_huff_decode(d_fd, 1, d_dboff, nblocks, d_bsum, 2 * geo.R, st));
-    HIP_TRY(c, launch_decompress(geo.ndim, d_fd, d_plan, d_items, ngroups, c->num_cus,
-                                 shape_for(c, 1, geo.ndim, geo.R), st));
+    HIP_TRY(c, launch_decompress_group(c, group_of(geo), d_fd, d_plan, d_items, ngroups,
+                                       shape_for(c, 1, geo.ndim, geo.R), st));
     return SZ_OK;
 }
 

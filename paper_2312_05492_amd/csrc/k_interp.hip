@@ -1096,6 +1096,289 @@ __global__ __launch_bounds__(kThreads) void k_decompress1d(const FieldDesc* __re
     }
 }
 
+// ------------------------------------------------------------ any window
+// Fields whose anchor stride or window is not the default one (Sec. V-A and
+// V-D leave both open: the window trades prediction accuracy at its faces
+// against parallelism) run a generic pair of kernels with the geometry read
+// from the field descriptor: one wave per window, its block (window + far
+// faces) in LDS, each pass's targets one per lane at a time.  The passes,
+// stencils, quantiser and histogram are those above.
+struct WinG {
+    uint64_t gbase;
+    uint32_t n0, n01;
+    int lo[3], e[3], o[3];   // origin, block extent, owned extent per dimension
+    int B0, B01;             // LDS strides
+};
+
+__device__ __forceinline__ WinG make_wing(const FieldDesc& f, uint32_t w) {
+    WinG wi;
+    const uint32_t nw0 = (uint32_t)f.nwin[0], nw01 = nw0 * (uint32_t)f.nwin[1];
+    const uint32_t wz = w / nw01, r = w - wz * nw01, wy = r / nw0, wx = r - wy * nw0;
+    const uint32_t wc[3] = {wx, wy, wz};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        wi.lo[k] = (int)wc[k] * f.w[k];
+        const int sk = f.n[k] - 1 - wi.lo[k];
+        wi.e[k] = (sk < f.w[k] ? sk : f.w[k]) + 1;
+        wi.o[k] = wi.e[k] < f.w[k] ? wi.e[k] : f.w[k];
+    }
+    wi.n0 = (uint32_t)f.n[0];
+    wi.n01 = wi.n0 * (uint32_t)f.n[1];
+    wi.B0 = f.ndim >= 1 ? f.w[0] + 1 : 1;
+    wi.B01 = wi.B0 * (f.ndim >= 2 ? f.w[1] + 1 : 1);
+    wi.gbase = (uint64_t)wi.lo[0] + (uint64_t)wi.lo[1] * wi.n0 + (uint64_t)wi.lo[2] * wi.n01;
+    return wi;
+}
+
+// a point's block coordinates from its number among m0 x m1 x m2 grid
+// points with the given spacing and offset per dimension
+struct Grid3 {
+    FastDiv f0, f1;
+    int step[3], off[3];
+    __device__ __forceinline__ void at(uint32_t t, int* c) const {
+        const uint32_t t1 = f0.div(t), i0 = t - t1 * f0.m;
+        const uint32_t i2 = f1.div(t1), i1 = t1 - i2 * f1.m;
+        c[0] = off[0] + (int)i0 * step[0];
+        c[1] = off[1] + (int)i1 * step[1];
+        c[2] = off[2] + (int)i2 * step[2];
+    }
+};
+
+// One pass of the generic kernels: dimension d at stride s; the other
+// dimensions at multiples of s where this level has passed them, of 2 s
+// where not (Sec. V-A).
+template <int SPL, bool COMP>
+__device__ __forceinline__ void pass_gen(float* v, uint32_t lane, const FieldDesc& fd, const WinG& wi,
+                                         int d, int s, const bool* passed, float el, float ebx2,
+                                         float inv, SZI_G uint16_t* cb, const SZI_G float* ob,
+                                         uint32_t* hist, uint32_t& cntR) {
+    const int R = fd.R;
+    Grid3 gr;
+    uint32_t m[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int lim = wi.e[j] - 1;
+        if (j == d) {
+            gr.step[j] = 2 * s;
+            gr.off[j] = s;
+            m[j] = lim >= s ? (uint32_t)((lim - s) / (2 * s) + 1) : 0u;
+        } else {
+            gr.step[j] = passed[j] ? s : 2 * s;
+            gr.off[j] = 0;
+            m[j] = (uint32_t)(lim / gr.step[j] + 1);
+        }
+    }
+    gr.f0.set(m[0]);
+    gr.f1.set(m[1]);
+    const uint32_t nt = m[0] * m[1] * m[2];
+    const int lim = wi.e[d] - 1;
+    const int sd = d == 0 ? 1 : (d == 1 ? wi.B0 : wi.B01);
+    const float Rf = (float)R;
+#pragma unroll 1
+    for (uint32_t t = lane; t < nt; t += 64) {
+        int c[3];
+        gr.at(t, c);
+        const int li = c[0] + c[1] * wi.B0 + c[2] * wi.B01;
+        const int cd = c[d];
+        const bool m3 = cd >= 3 * s;
+        const bool p1 = cd + s <= lim;
+        const bool p3 = cd + 3 * s <= lim;
+        const float a = m3 ? v[li - 3 * s * sd] : 0.0f;
+        const float b = v[li - s * sd];
+        const float cc = p1 ? v[li + s * sd] : 0.0f;
+        const float dd = p3 ? v[li + 3 * s * sd] : 0.0f;
+        float num;
+        float pr = predict<SPL>(m3, p1, p3, a, b, cc, dd, num);
+        if (SPL == SPL_NAT) {
+            const bool small = !(fabsf(num) >= 0x1p-123f);
+            if (wave_any(small) && small) pr = num / 40.0f;
+        }
+        const uint64_t g = (uint64_t)c[0] + (uint64_t)c[1] * wi.n0 + (uint64_t)c[2] * wi.n01;
+        if (COMP) {
+            const float xv = v[li];
+            const float q = rintf((xv - pr) * inv);
+            const float xr = pr + q * ebx2;
+            const bool inr = fabsf(q) < Rf;
+            const bool good = inr && fabsf(xv - xr) < el;
+            float vv = good ? xr : xv;
+            uint32_t code = good ? (uint32_t)((int)q + R) : 0u;
+            if (wave_any(good != inr)) {   // the FP64 bound test where FP32 cannot decide
+                if (inr && !(fabsf(xv - xr) < el) && fabs((double)xv - (double)xr) <= (double)el) {
+                    vv = xr;
+                    code = (uint32_t)((int)q + R);
+                }
+            }
+            v[li] = vv;
+            const bool own = c[0] < wi.o[0] && c[1] < wi.o[1] && c[2] < wi.o[2];
+            if (own) cb[g] = (uint16_t)code;
+            const uint32_t bin = own && code != (uint32_t)R ? code : (uint32_t)(2 * R) + lane;
+            atomicAdd(&hist[bin], 1u);
+            cntR += (uint32_t)__popcll(wave_ballot(!own));
+        } else {
+            const uint32_t code = __float_as_uint(v[li]);
+            // code 0: an outlier, whose value the scatter step put in the output
+            v[li] = code == 0u ? ob[g] : pr + (float)((int)code - R) * ebx2;
+        }
+    }
+}
+
+template <bool COMP>
+__device__ __forceinline__ void levels_gen(float* v, uint32_t lane, const FieldDesc& fd,
+                                           const FieldPlan& pl, const WinG& wi, SZI_G uint16_t* cb,
+                                           const SZI_G float* ob, uint32_t* hist, uint32_t& cntR) {
+#pragma unroll 1
+    for (int l = fd.L; l >= 1; --l) {
+        const int s = 1 << (l - 1);
+        const float el = pl.el[l - 1], ebx2 = pl.ebx2[l - 1];
+        const float inv = el == 0.0f ? 0.0f : pl.inv[l - 1];
+        bool passed[3] = {false, false, false};
+#pragma unroll 1
+        for (int k = 0; k < fd.ndim; ++k) {
+            const int d = pl.order[k];
+            const int spl = pl.spline[d];
+            if (spl == SPL_LIN)
+                pass_gen<SPL_LIN, COMP>(v, lane, fd, wi, d, s, passed, el, ebx2, inv, cb, ob, hist, cntR);
+            else if (spl == SPL_NAK)
+                pass_gen<SPL_NAK, COMP>(v, lane, fd, wi, d, s, passed, el, ebx2, inv, cb, ob, hist, cntR);
+            else
+                pass_gen<SPL_NAT, COMP>(v, lane, fd, wi, d, s, passed, el, ebx2, inv, cb, ob, hist, cntR);
+            passed[d] = true;
+            wave_sync();
+        }
+    }
+}
+
+// the block's points (a grid of step 1), or its anchor points (step S) up
+// to an extent per dimension
+__device__ __forceinline__ Grid3 block_grid(const int* ext, int step, uint32_t& n) {
+    Grid3 gr;
+    uint32_t m[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        gr.step[j] = step;
+        gr.off[j] = 0;
+        m[j] = (uint32_t)((ext[j] - 1) / step + 1);
+    }
+    gr.f0.set(m[0]);
+    gr.f1.set(m[1]);
+    n = m[0] * m[1] * m[2];
+    return gr;
+}
+
+__device__ __forceinline__ uint32_t anchor_index(const FieldDesc& fd, const WinG& wi, const int* c) {
+    return (uint32_t)((wi.lo[0] + c[0]) / fd.S) +
+           (uint32_t)fd.na[0] * ((uint32_t)((wi.lo[1] + c[1]) / fd.S) +
+                                 (uint32_t)fd.na[1] * (uint32_t)((wi.lo[2] + c[2]) / fd.S));
+}
+
+__global__ __launch_bounds__(kThreads) void k_compress_gen(const FieldDesc* __restrict__ F,
+                                                           const FieldPlan* __restrict__ P,
+                                                           const uint64_t* __restrict__ goff,
+                                                           uint64_t ngroups) {
+    __shared__ float vbuf[kWaves][kGenMaxBlock];
+    extern __shared__ uint32_t hist[];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t lane = threadIdx.x & 63u;
+    float* v = vbuf[wave];
+    const GroupSeq gs = group_seq(ngroups);
+    int f = 0, hf = -1;
+    uint32_t cntR = 0;
+#pragma unroll 1
+    for (uint64_t g = gs.cur; g < gs.end; g += gs.step) {
+        while (g >= goff[f + 1]) ++f;
+        if (f != hf) {   // uniform over the workgroup: groups never span fields
+            if (hf >= 0) flush_hist(hist, cntR, F[hf]);
+            clear_hist(hist, F[f].R);
+            __syncthreads();
+            hf = f;
+        }
+        const FieldDesc& fd = F[f];
+        const uint32_t w = (uint32_t)(g - goff[f]) * kWaves + (uint32_t)wave;
+        if (w >= (uint32_t)(fd.nwin[0] * fd.nwin[1] * fd.nwin[2])) continue;
+        const WinG wi = make_wing(fd, w);
+        const SZI_G float* in = gp(fd.in) + wi.gbase;
+        uint32_t nb;
+        const Grid3 bg = block_grid(wi.e, 1, nb);
+#pragma unroll 1
+        for (uint32_t t = lane; t < nb; t += 64) {
+            int c[3];
+            bg.at(t, c);
+            v[c[0] + c[1] * wi.B0 + c[2] * wi.B01] =
+                in[(uint64_t)c[0] + (uint64_t)c[1] * wi.n0 + (uint64_t)c[2] * wi.n01];
+        }
+        wave_sync();
+        SZI_G uint16_t* cb = gp(fd.codes) + wi.gbase;
+        levels_gen<true>(v, lane, fd, P[f], wi, cb, nullptr, hist, cntR);
+        // owned anchors: their values losslessly, quant-code R, counted
+        uint32_t na;
+        const Grid3 ag = block_grid(wi.o, fd.S, na);
+#pragma unroll 1
+        for (uint32_t t = lane; t < na; t += 64) {
+            int c[3];
+            ag.at(t, c);
+            gp(fd.anchors)[anchor_index(fd, wi, c)] = v[c[0] + c[1] * wi.B0 + c[2] * wi.B01];
+            cb[(uint64_t)c[0] + (uint64_t)c[1] * wi.n0 + (uint64_t)c[2] * wi.n01] = (uint16_t)fd.R;
+            atomicAdd(&hist[2 * fd.R + lane], 1u);
+        }
+        wave_sync();
+    }
+    if (hf >= 0) flush_hist(hist, cntR, F[hf]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_decompress_gen(const FieldDesc* __restrict__ F,
+                                                             const FieldPlan* __restrict__ P,
+                                                             const uint64_t* __restrict__ goff,
+                                                             uint64_t ngroups) {
+    __shared__ float vbuf[kWaves][kGenMaxBlock];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t lane = threadIdx.x & 63u;
+    float* v = vbuf[wave];
+    const GroupSeq gs = group_seq(ngroups);
+    int f = 0;
+    uint32_t unused = 0;
+#pragma unroll 1
+    for (uint64_t g = gs.cur; g < gs.end; g += gs.step) {
+        while (g >= goff[f + 1]) ++f;
+        const FieldDesc& fd = F[f];
+        const uint32_t w = (uint32_t)(g - goff[f]) * kWaves + (uint32_t)wave;
+        if (w >= (uint32_t)(fd.nwin[0] * fd.nwin[1] * fd.nwin[2])) continue;
+        const WinG wi = make_wing(fd, w);
+        // every point takes its code (as float bits), the anchors their values
+        const SZI_G uint16_t* cb = gp(fd.codes) + wi.gbase;
+        uint32_t nb;
+        const Grid3 bg = block_grid(wi.e, 1, nb);
+#pragma unroll 1
+        for (uint32_t t = lane; t < nb; t += 64) {
+            int c[3];
+            bg.at(t, c);
+            v[c[0] + c[1] * wi.B0 + c[2] * wi.B01] = __uint_as_float(
+                (uint32_t)cb[(uint64_t)c[0] + (uint64_t)c[1] * wi.n0 + (uint64_t)c[2] * wi.n01]);
+        }
+        wave_sync();
+        uint32_t na;
+        const Grid3 ag = block_grid(wi.e, fd.S, na);
+#pragma unroll 1
+        for (uint32_t t = lane; t < na; t += 64) {
+            int c[3];
+            ag.at(t, c);
+            v[c[0] + c[1] * wi.B0 + c[2] * wi.B01] = gp(fd.anchors)[anchor_index(fd, wi, c)];
+        }
+        wave_sync();
+        SZI_G float* ob = gp(fd.out) + wi.gbase;
+        levels_gen<false>(v, lane, fd, P[f], wi, nullptr, ob, nullptr, unused);
+        uint32_t no;
+        const Grid3 og = block_grid(wi.o, 1, no);
+#pragma unroll 1
+        for (uint32_t t = lane; t < no; t += 64) {
+            int c[3];
+            og.at(t, c);
+            ob[(uint64_t)c[0] + (uint64_t)c[1] * wi.n0 + (uint64_t)c[2] * wi.n01] =
+                v[c[0] + c[1] * wi.B0 + c[2] * wi.B01];
+        }
+        wave_sync();
+    }
+}
+
 // ------------------------------------------------------- launchers
 // The persistent grid is the number of workgroups resident at once
 // (occupancy from the runtime x compute units) unless per_cu overrides it,
@@ -1142,6 +1425,27 @@ hipError_t launch_compress(int ndim, const FieldDesc* d_fields, const FieldPlan*
     else if (ndim == 1) go(k_compress1d);
     else if (shape.variant == 1) go(k_compress<2, 4>);
     else go(k_compress<2, 3>);
+    return hipGetLastError();
+}
+
+hipError_t launch_compress_gen(const FieldDesc* d_fields, const FieldPlan* d_plans,
+                               const uint64_t* d_goff, uint64_t ngroups, int num_cus, int max_R,
+                               hipStream_t st) {
+    if (ngroups == 0) return hipSuccess;
+    const size_t lds = (size_t)(2 * max_R + 64) * sizeof(uint32_t);
+    const uint64_t grid = resident_grid(k_compress_gen, lds, num_cus, 0, ngroups);
+    hipLaunchKernelGGL(k_compress_gen, dim3((unsigned)grid), dim3(kThreads), lds, st, d_fields,
+                       d_plans, d_goff, ngroups);
+    return hipGetLastError();
+}
+
+hipError_t launch_decompress_gen(const FieldDesc* d_fields, const FieldPlan* d_plans,
+                                 const uint64_t* d_goff, uint64_t ngroups, int num_cus,
+                                 hipStream_t st) {
+    if (ngroups == 0) return hipSuccess;
+    const uint64_t grid = resident_grid(k_decompress_gen, 0, num_cus, 0, ngroups);
+    hipLaunchKernelGGL(k_decompress_gen, dim3((unsigned)grid), dim3(kThreads), 0, st, d_fields,
+                       d_plans, d_goff, ngroups);
     return hipGetLastError();
 }
 

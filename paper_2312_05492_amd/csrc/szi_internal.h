@@ -144,6 +144,14 @@ constexpr int kShapeVariants = 2;
 hipError_t launch_compress(int ndim, const FieldDesc* d_fields, const FieldPlan* d_plans,
                            const uint64_t* d_goff, uint64_t ngroups, int num_cus,
                            LaunchShape shape, int max_R, hipStream_t st);
+// Fields of any anchor stride and window (block points <= kGenMaxBlock):
+// the generic window kernels, geometry from the descriptors.
+hipError_t launch_compress_gen(const FieldDesc* d_fields, const FieldPlan* d_plans,
+                               const uint64_t* d_goff, uint64_t ngroups, int num_cus, int max_R,
+                               hipStream_t st);
+hipError_t launch_decompress_gen(const FieldDesc* d_fields, const FieldPlan* d_plans,
+                                 const uint64_t* d_goff, uint64_t ngroups, int num_cus,
+                                 hipStream_t st);
 hipError_t launch_decompress(int ndim, const FieldDesc* d_fields, const FieldPlan* d_plans,
                              const uint64_t* d_goff, uint64_t ngroups, int num_cus,
                              LaunchShape shape, hipStream_t st);

@@ -7,5 +7,9 @@ namespace szi {
 constexpr int kMaxLevels = 9;      // 1D: strides 256 .. 1
 constexpr int kLmax = 24;          // Huffman length limit
 constexpr int kMaxRadius = 1024;   // LDS histogram holds 2R <= 2048 bins
+// other windows than the defaults: at most this many block points (window
+// plus far faces, one wave's LDS), at most kGenMaxExtent along a dimension
+constexpr int kGenMaxBlock = 4096;
+constexpr int kGenMaxExtent = 1024;
 
 }  // namespace szi

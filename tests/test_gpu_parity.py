@@ -166,6 +166,16 @@ CASES = [
     ("line1d_tiny_bound", _spec((5000,), 47), dict(eb=1e-30, eb_mode=0)),
     ("line1d_zero_bound_signed", _signed_zeros((3000,), 48), dict(eb=0.0, eb_mode=0)),
     ("line1d_radius_odd", _spec((30000,), 49, beta=1.0), dict(eb=1e-4, radius=37, chunk=256)),
+    # other windows and strides (Sec. V-D): the generic window kernels
+    ("window3d_16x16x8", _spec((40, 50, 70), 60, mean=3.0), dict(window=(16, 16, 8))),
+    ("window3d_8x8x48_e4", _spec((33, 41, 130), 61), dict(eb=1e-4, window=(8, 8, 48))),
+    ("stride4_3d", _spec((30, 37, 45), 62, beta=3.0), dict(S=4, interp=(2, 1, 0))),
+    ("stride2_3d", _spec((17, 20, 31), 63), dict(S=2, eb=1e-2)),
+    ("window2d_32x32", _spec((100, 130), 64), dict(window=(32, 32))),
+    ("stride8_2d", _spec((90, 77), 65, beta=3.0), dict(S=8, eb=1e-4)),
+    ("window1d_512", _spec((30001,), 66), dict(window=(512,))),
+    ("stride64_1d", _spec((10000,), 67, beta=3.0), dict(S=64, eb=1e-4, interp=(2,))),
+    ("window3d_tiny_bound", _spec((20, 24, 40), 68), dict(window=(16, 8, 16), eb=1e-30, eb_mode=0)),
 ]
 
 
@@ -193,11 +203,13 @@ def test_batch_equals_single_calls(ctx):
 
 
 def test_batch_of_all_dimensionalities(ctx):
-    # 3D, 2D and 1D fields in one call: three window-kernel groups
+    # 3D, 2D and 1D fields and other windows in one call: four window-kernel groups
     fields = [synth.spectral_field((300001,), seed=51), synth.spectral_field((20, 30, 70), seed=52),
               synth.spectral_field((5000,), seed=53, beta=3.0), synth.climate_field(303, shape=(60, 130)),
-              synth.spectral_field((1,), seed=54)]
-    params = [dict(eb=1e-3), dict(eb=1e-4), dict(eb=1e-2, interp=(2,)), {}, {}]
+              synth.spectral_field((1,), seed=54), synth.spectral_field((30, 40, 50), seed=55),
+              synth.spectral_field((70, 90), seed=56)]
+    params = [dict(eb=1e-3), dict(eb=1e-4), dict(eb=1e-2, interp=(2,)), {}, {},
+              dict(window=(8, 16, 16)), dict(S=8, window=(8, 16))]
     refs = [O.compress(f, _oracle_params(f.shape, kw)) for f, kw in zip(fields, params)]
     print("\n[parity] batch of 3D, 2D and 1D fields", flush=True)
     for rep in range(2):
@@ -209,6 +221,21 @@ def test_batch_of_all_dimensionalities(ctx):
             assert np.array_equal(_bits(y.cpu().numpy()), _bits(ref.recon))
         for r in outs:
             r.free()
+
+
+def test_window_limits(ctx):
+    # the generic kernels hold a block of at most 4096 points in LDS; a
+    # window must be a multiple of the stride
+    x = _to_gpu(synth.spectral_field((40, 40, 40), seed=57))
+    with pytest.raises(szi.SzError) as e:
+        ctx.compress(x, window=(16, 16, 16))   # 17^3 block points
+    assert e.value.code == -6
+    with pytest.raises(szi.SzError) as e:
+        ctx.compress(x, window=(8, 8, 36))
+    assert e.value.code == -6
+    with pytest.raises(szi.SzError) as e:
+        ctx.compress(x, S=3)
+    assert e.value.code == -6
 
 
 def test_larger_batch_twice_equals_oracle(ctx):
