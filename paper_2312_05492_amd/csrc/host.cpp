@@ -607,6 +607,7 @@ struct ResultInternal {
     std::vector<uint8_t> code_len; // host copy
     uint32_t* d_cbook = nullptr;
     uint32_t* d_dtab = nullptr;
+    uint16_t* d_sub = nullptr;     // sub-chunk bit offsets from the encoder (null after upload)
     uint64_t nzw = UINT64_MAX;     // non-zero Huffman words; UINT64_MAX: unknown
     uint32_t* d_esec = nullptr;    // the words section with its zero words elided (device)
 };
@@ -1157,6 +1158,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         R->d_cbook = reinterpret_cast<uint32_t*>(tabs + tables_len_bytes(nsym));
         R->d_dtab = R->d_cbook + nsym;
         if ((s = res_alloc(c, R, geo[i].nchunks, &res[i].chunk_bits))) return s;
+        if ((s = res_alloc(c, R, 4 * geo[i].nchunks, &R->d_sub))) return s;
         res[i].n = geo[i].npts;
         res[i].n_anchors = geo[i].nanch;
         res[i].n_chunks = geo[i].nchunks;
@@ -1164,6 +1166,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         fd[i].anchors = res[i].anchors;
         fd[i].hist = res[i].hist;
         fd[i].chunk_bits = res[i].chunk_bits;
+        fd[i].sub = R->d_sub;
         fd[i].cbook = R->d_cbook;
         fd[i].chunk_base = chunk_base;
         chunk_base += geo[i].nchunks;
@@ -1389,9 +1392,10 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         std::memcpy(h + o_fd, fds.data(), sizeof(FieldDesc) * nf);
         std::memcpy(h + o_items, items.data(), sizeof(uint64_t) * items.size());
         const LaunchShape s3 = shape_for(c, 0, 3, max_R), s2 = shape_for(c, 0, 2, max_R);
-        const std::vector<uint64_t> sig = {nf, nitems[0], nitems[1], nitems[2], grp[0].size(),
-                                           grp[1].size(), (uint64_t)max_R, (uint64_t)s3.per_cu,
-                                           (uint64_t)s2.variant, (uint64_t)s2.per_cu, L.off};
+        const std::vector<uint64_t> sig = {nf, nitems[0], nitems[1], nitems[2], nitems[3],
+                                           grp[0].size(), grp[1].size(), grp[2].size(),
+                                           (uint64_t)max_R, (uint64_t)s3.per_cu, (uint64_t)s2.variant,
+                                           (uint64_t)s2.per_cu, L.off};
         char* d = static_cast<char*>(c->arena);
         s = graph_run(c, 1, sig, o_fd, end1 - o_fd, st, [&](hipStream_t q) -> sz_status {
             sz_status r = enqueue1(q);
@@ -1803,6 +1807,7 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
     std::vector<uint32_t> perm;
     for (int gi = 0; gi < kGroups; ++gi) perm.insert(perm.end(), grp[gi].begin(), grp[gi].end());
     uint64_t cb = 0;
+    bool split = true;   // every field has sub-chunk offsets: four decode lanes per chunk
     std::vector<uint64_t> dboff(nf + 1, 0);
     for (uint32_t k = 0; k < nf; ++k) {
         const uint32_t i = perm[k];
@@ -1815,6 +1820,8 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         f.anchors = res[i].anchors;
         f.words = res[i].words;
         f.chunk_bits = res[i].chunk_bits;
+        f.sub = R->d_sub;
+        split = split && R->d_sub != nullptr;
         f.outlier_idx = res[i].outlier_idx;
         f.outlier_val = res[i].outlier_val;
         f.n_outliers = res[i].n_outliers;
@@ -1852,7 +1859,8 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         }
         {
             STAGE(c, SZ_STAGE_DECODE, q);
-            HIP_TRY(c, launch_huff_decode(d_fd, (int)nf, d_dboff, nblocks, d_bsum, 2 * max_R, q));
+            HIP_TRY(c, launch_huff_decode(d_fd, (int)nf, d_dboff, nblocks, d_bsum, 2 * max_R,
+                                          split ? 1 : 0, q));
         }
         uint32_t base = 0;
         for (int gi = 0; gi < kGroups; ++gi) {
@@ -1886,9 +1894,10 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         d_bsum = reinterpret_cast<uint32_t*>(d + o_bsum);
         // everything the launches' arguments depend on
         const LaunchShape s3 = shape_for(c, 1, 3, max_R), s2 = shape_for(c, 1, 2, max_R);
-        const std::vector<uint64_t> sig = {nf, nblocks, nitems[0], nitems[1], nitems[2], grp[0].size(),
-                                           grp[1].size(), (uint64_t)max_R, (uint64_t)s3.per_cu,
-                                           (uint64_t)s2.variant, (uint64_t)s2.per_cu, L.off};
+        const std::vector<uint64_t> sig = {nf, nblocks, nitems[0], nitems[1], nitems[2], nitems[3],
+                                           grp[0].size(), grp[1].size(), grp[2].size(),
+                                           (uint64_t)max_R, (uint64_t)s3.per_cu, (uint64_t)s2.variant,
+                                           (uint64_t)s2.per_cu, L.off, split ? 1u : 0u};
         if ((s = graph_run(c, 0, sig, 0, staged, st, enqueue))) return s;
         HIP_TRY(c, hipStreamSynchronize(c->gstream));
         return SZ_OK;
@@ -1993,6 +2002,7 @@ sz_status sz_decompress_noalloc(sz_ctx* c, const sz_result* res, float* d_out, v
     f.anchors = res->anchors;
     f.words = res->words;
     f.chunk_bits = res->chunk_bits;
+    f.sub = R->d_sub;
     f.outlier_idx = res->outlier_idx;
     f.outlier_val = res->outlier_val;
     f.n_outliers = res->n_outliers;
@@ -2016,7 +2026,8 @@ sz_status sz_decompress_noalloc(sz_ctx* c, const sz_result* res, float* d_out, v
     uint32_t* d_bsum = reinterpret_cast<uint32_t*>(ws + o_bsum);
     HIP_TRY(c, launch_stage_words(reinterpret_cast<uint32_t*>(ws), sw, st));
     HIP_TRY(c, launch_dec_prep(d_fd, d_plan, 1, d_dboff, nblocks, d_bsum, st));
-    HIP_TRY(c, launch_huff_decode(d_fd, 1, d_dboff, nblocks, d_bsum, 2 * geo.R, st));
+    HIP_TRY(c, launch_huff_decode(d_fd, 1, d_dboff, nblocks, d_bsum, 2 * geo.R,
+                                  R->d_sub != nullptr ? 1 : 0, st));
     HIP_TRY(c, launch_decompress_group(c, group_of(geo), d_fd, d_plan, d_items, ngroups,
                                        shape_for(c, 1, geo.ndim, geo.R), st));
     return SZ_OK;

@@ -333,6 +333,16 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
             nz += w != 0u;
             if (ow + k < fd.words_cap) gp(fd.words)[ow + k] = w;
         }
+        if (fd.sub) {
+            // the decoder's starting bits of the chunk's second, third and
+            // last quarters (symbols 16 PER, 32 PER, 48 PER: lanes 16, 32,
+            // 48), as one 8-byte store: 0, b1, b2, b3
+            const uint32_t b1 = (uint32_t)__builtin_amdgcn_readlane((int)pos, 16);
+            const uint32_t b2 = (uint32_t)__builtin_amdgcn_readlane((int)pos, 32);
+            const uint32_t b3 = (uint32_t)__builtin_amdgcn_readlane((int)pos, 48);
+            if (lane == 0)
+                *reinterpret_cast<SZI_G vu2*>(gp(fd.sub) + 4 * ch) = vu2{b1 << 16, b2 | (b3 << 16)};
+        }
         wave_lds_sync();
     }
     // one count per block, and one atomic per block for the field's total
@@ -362,14 +372,27 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
 // consumes at most 6 words and the ring always holds at least 7 ahead of the
 // window.  Symbols leave 64 at a time per lane in eight back-to-back 16-byte
 // stores.
+//
+// With Q = 4 lanes per chunk, each lane decodes a quarter of the chunk's
+// symbols from the bit offset the encoder recorded for it (fd.sub: four
+// per chunk, the first 0, kept with a compressed result): four times the
+// independent chains, each a quarter as long.  A workgroup then covers a
+// quarter of a decode block (kDecChunks chunks, whose word counts the
+// prologue summed).  A field without offsets (an uploaded blob) is decoded
+// by the first lane of each chunk.
 constexpr int kRing = 32;   // ring words per lane (power of 2)
 
+template <int Q>
 __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __restrict__ F,
                                                             int nfields,
                                                             const uint64_t* __restrict__ boff,
                                                             const uint32_t* __restrict__ bsum) {
     extern __shared__ uint32_t smem[];
-    const int f = block_field(boff, nfields, blockIdx.x);
+    static_assert(Q == 1 || Q == 4, "one lane or four per chunk");
+    constexpr int CPW = kDecChunks / Q;   // chunks per workgroup
+    const uint64_t pblk = blockIdx.x / Q;   // the decode block
+    const uint32_t part = blockIdx.x % Q;   // the workgroup's share of it
+    const int f = block_field(boff, nfields, pblk);
     const FieldDesc& fd = F[f];
     const int nsym = 2 * fd.R;
     const int ntab = dtab_words(nsym);
@@ -401,18 +424,24 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
 #pragma unroll
     for (int l = kLutBits + 1; l < kLmax; ++l)
         lim[l - kLutBits - 1] = __builtin_amdgcn_readfirstlane(gp(fd.dtab)[kDtLimit + l]);
-    const uint64_t first = (blockIdx.x - boff[f]) * kDecChunks;
-    const uint64_t ch = first + tid;
+    const uint32_t q = (uint32_t)tid % Q;   // the lane's quarter of its chunk (Q = 4)
+    const uint64_t bfirst = (pblk - boff[f]) * kDecChunks;   // the decode block's first chunk
+    const uint64_t ch = bfirst + part * CPW + (uint64_t)tid / Q;
     const bool live = ch < fd.nchunks;
     const uint32_t cbits = live ? (uint32_t)gp(fd.chunk_bits)[ch] : 0u;
     const uint32_t nw = (cbits + 31) >> 5;
-    // words of the field's earlier blocks (the sum of their word counts)
-    // and the in-block exclusive scan of the chunks' word counts
+    // words of the field's earlier blocks (the sum of their word counts),
+    // of this block's chunks before the workgroup's, and the workgroup's
+    // exclusive scan of its chunks' word counts (each chunk counted once,
+    // by its first lane)
     uint64_t pb = 0;
-    for (uint64_t i = boff[f] + (uint64_t)tid; i < blockIdx.x; i += kDecChunks) pb += bsum[i];
+    for (uint64_t i = boff[f] + (uint64_t)tid; i < pblk; i += kDecChunks) pb += bsum[i];
+    if (Q > 1)
+        for (uint32_t k = (uint32_t)tid; k < part * CPW; k += kDecChunks)
+            if (bfirst + k < fd.nchunks) pb += ((uint32_t)gp(fd.chunk_bits)[bfirst + k] + 31u) >> 5;
     for (int o = 32; o > 0; o >>= 1) pb += __shfl_xor(pb, o);
     uint32_t tot;
-    const uint32_t wx = wave_excl_scan(nw, &tot);
+    const uint32_t wx = wave_excl_scan(q == 0 ? nw : 0u, &tot) - (q == 0 ? 0u : nw);
     if ((tid & 63) == 0) {
         scan[tid >> 6] = tot;
         pre[tid >> 6] = pb;
@@ -421,11 +450,17 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
     uint64_t before = 0;
     for (int k = 0; k < kDecChunks / 64; ++k) before += pre[k];
     for (int k = 0; k < (tid >> 6); ++k) before += scan[k];
-    const uint64_t w0abs = before + wx;
     const int C = fd.chunk;
-    const uint64_t s0 = ch * (uint64_t)C;
-    const int cnt = !live ? 0 : (s0 + C <= fd.npts ? C : (int)(fd.npts - s0));
+    const bool split = Q > 1 && fd.sub != nullptr;   // the field has sub-chunk offsets
+    const int SC = split ? C / Q : C;                // symbols per lane
+    const uint64_t s0 = ch * (uint64_t)C + (uint64_t)(split ? q * (uint32_t)SC : 0u);
+    int cnt = !live || (!split && q != 0) || s0 >= fd.npts ? 0
+              : (s0 + SC <= fd.npts ? SC : (int)(fd.npts - s0));
+    const uint32_t bo = split ? (uint32_t)gp(fd.sub)[4 * ch + q] : 0u;   // entry 0 is 0
+    if (bo > cbits) cnt = 0;   // a corrupt offset: nothing to decode from it
     if (cnt == 0) return;
+    const uint64_t w0abs = before + wx + (bo >> 5);   // the lane's first word
+    const uint32_t b0 = bo & 31u;                     // and bit in it
     // word indices count from the 4-aligned word at or below the chunk's
     // first; requests stop at the end of the field's words (the array has
     // kWordPad words of slack, so the 8-word loads of the last request stay
@@ -460,11 +495,21 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
         put(8u, c, d);
         wr = 16;
     }
-    // the window starts at the top of w1 (o = 32, held as nego = -o)
-    uint32_t w0 = 0u, w1 = ring[slot(rd)];
-    ++rd;
+    // the window starts at bit b0 of the first word: the top of w1 (o = 32,
+    // held as nego = -o) or bit b0 of w0
+    uint32_t w0 = 0u, w1;
+    int32_t nego;
+    if (b0 == 0u) {
+        w1 = ring[slot(rd)];
+        ++rd;
+        nego = -32;
+    } else {
+        w0 = ring[slot(rd)];
+        w1 = ring[slot(rd + 1u)];
+        rd += 2;
+        nego = -(int32_t)b0;
+    }
     uint32_t nxw = ring[slot(rd)];   // the ring word the next move takes
-    int32_t nego = -32;
     auto decode_one = [&]() SZI_INLINE -> uint32_t {
         // bits [o, o + 32) of w0:w1 (the shift amount is 32 - o, taken mod 32)
         const uint32_t x = __builtin_amdgcn_alignbit(w0, w1, (uint32_t)nego);
@@ -494,7 +539,7 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
         nxw = ring[slot(rd)];
         return sym;
     };
-    SZI_G uint16_t* out = gp(fd.codes) + s0;
+    SZI_G uint16_t* out = gp(fd.codes) + s0;   // s0: a multiple of 64 symbols
     const bool vec = ((uintptr_t)fd.codes & 15u) == 0u;   // s0 and k are multiples of 8
     // a group: commit the previous request, maybe request 8 more words,
     // then decode up to 8 symbols
@@ -735,13 +780,17 @@ hipError_t launch_huff_encode(const FieldDesc* d_fields, int nfields, const uint
 
 
 hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields, const uint64_t* d_dboff,
-                              uint64_t nblocks, const uint32_t* d_bsum, int max_nsym,
+                              uint64_t nblocks, const uint32_t* d_bsum, int max_nsym, int split,
                               hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
     const size_t lds = (size_t)(3 * (kDecChunks / 64) + kDecChunks * kRing + dtab_words(max_nsym)) *
                        sizeof(uint32_t);
-    hipLaunchKernelGGL(k_huff_decode, dim3((unsigned)nblocks), dim3(kDecChunks), lds, st,
-                       d_fields, nfields, d_dboff, d_bsum);
+    if (split)
+        hipLaunchKernelGGL(k_huff_decode<4>, dim3((unsigned)(4 * nblocks)), dim3(kDecChunks), lds, st,
+                           d_fields, nfields, d_dboff, d_bsum);
+    else
+        hipLaunchKernelGGL(k_huff_decode<1>, dim3((unsigned)nblocks), dim3(kDecChunks), lds, st,
+                           d_fields, nfields, d_dboff, d_bsum);
     return hipGetLastError();
 }
 

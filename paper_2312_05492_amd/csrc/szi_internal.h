@@ -50,6 +50,7 @@ struct FieldDesc {
     float* outlier_val;
     const uint32_t* dtab;  // decode tables (see DecodeTables layout)
     unsigned long long* nzw;  // compress: the field's non-zero words (stats clears, encode adds)
+    uint16_t* sub;         // per chunk 0 and the bit offsets of its 2nd, 3rd and 4th quarters (or null)
 };
 
 // One pass of the interpolation (Sec. V-A: levels from stride S/2 to 1, one
@@ -188,8 +189,9 @@ constexpr uint64_t kElideTileWords = 8192;
 hipError_t launch_elide(const ElideField* d_e, int nf, const uint64_t* d_toff, uint64_t ntiles,
                         uint32_t* d_cnt, uint64_t* d_off, int restore, hipStream_t st);
 // d_bsum: the word count of every decode block (launch_dec_prep)
+// split: every field has sub-chunk offsets (four lanes per chunk)
 hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields, const uint64_t* d_dboff,
-                              uint64_t nblocks, const uint32_t* d_bsum, int max_nsym,
+                              uint64_t nblocks, const uint32_t* d_bsum, int max_nsym, int split,
                               hipStream_t st);
 
 // ---- the entry point that allocates nothing (noalloc.hip) ----
