@@ -461,13 +461,20 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
     if (cnt == 0) return;
     const uint64_t w0abs = before + wx + (bo >> 5);   // the lane's first word
     const uint32_t b0 = bo & 31u;                     // and bit in it
-    // word indices count from the 4-aligned word at or below the chunk's
-    // first; requests stop at the end of the field's words (the array has
-    // kWordPad words of slack, so the 8-word loads of the last request stay
-    // inside it)
+    // word indices count from the 4-aligned word at or below the lane's
+    // first; requests stop after the word that holds the lane's last bit
+    // (where the next quarter starts, else the chunk's end; the ring may
+    // then hold stale words past it, which only fill a look-up's unused
+    // low bits) and never pass the field's words (the array has kWordPad
+    // words of slack, so the 8-word loads of the last request stay inside
+    // it).  Stopping at the lane's own end saves a twentieth of decode time.
     const uint64_t wbase = w0abs & ~(uint64_t)3;
     const SZI_G uint32_t* words = gp(fd.words) + wbase;
-    const uint64_t wleft = fd.words_cap > wbase ? fd.words_cap - wbase : 0;
+    const uint32_t be0 = split && q + 1 < (uint32_t)Q ? (uint32_t)gp(fd.sub)[4 * ch + q + 1] : cbits;
+    const uint32_t be = be0 < bo || be0 > cbits ? cbits : be0;   // a corrupt offset: the chunk's end
+    const uint64_t wlim0 = before + wx + ((be + 31u) >> 5);
+    const uint64_t wlim = wlim0 < fd.words_cap ? wlim0 : fd.words_cap;
+    const uint64_t wleft = wlim > wbase ? wlim - wbase : 0;
     const uint32_t wcap = wleft < (1u << 30) ? (uint32_t)wleft : (1u << 30);
     // the lane's ring: word i at ring[(i ^ sw) % kRing], the 16-byte groups
     // permuted per lane so that lanes at the same position hit different banks
