@@ -41,8 +41,9 @@ struct Win {
     uint32_t n0, n01;        // field strides
     int lo0, lo1, lo2;       // origin
     int e0, e1, e2;          // block extents (owned points + far face where present)
-    int o0, o1, o2;          // owned extents
+    uint32_t op;             // owned extents o0 | o1 << 8 | o2 << 16 (each at most 64)
     bool full;
+    __device__ int own(int d) const { return (int)((op >> (8 * d)) & 255u); }
 };
 
 template <int ND>
@@ -65,9 +66,11 @@ __device__ __forceinline__ Win make_win(const FieldDesc& f, uint32_t w) {
     wi.e0 = (s0 < G::W0 ? s0 : G::W0) + 1;
     wi.e1 = (s1 < G::W1 ? s1 : G::W1) + 1;
     wi.e2 = ND == 3 ? (s2 < G::W2 ? s2 : G::W2) + 1 : 1;
-    wi.o0 = wi.e0 < G::W0 ? wi.e0 : G::W0;
-    wi.o1 = wi.e1 < G::W1 ? wi.e1 : G::W1;
-    wi.o2 = ND == 3 ? (wi.e2 < G::W2 ? wi.e2 : G::W2) : 1;
+    const int o0 = wi.e0 < G::W0 ? wi.e0 : G::W0;
+    const int o1 = wi.e1 < G::W1 ? wi.e1 : G::W1;
+    const int o2 = ND == 3 ? (wi.e2 < G::W2 ? wi.e2 : G::W2) : 1;
+    static_assert(G::W0 < 256 && G::W1 < 256 && G::W2 < 256, "owned extents fit 8 bits");
+    wi.op = (uint32_t)o0 | ((uint32_t)o1 << 8) | ((uint32_t)o2 << 16);
     wi.full = wi.e0 == G::B0 && wi.e1 == G::B1 && (ND == 2 || wi.e2 == G::B2);
     wi.gbase = (uint64_t)wi.lo0 + (uint64_t)wi.lo1 * wi.n0 + (uint64_t)wi.lo2 * wi.n01;
     return wi;
@@ -427,15 +430,10 @@ __device__ __forceinline__ void pass_lines(float* v, uint32_t lane, const PassDe
     const uint32_t ge = pd.ge, gf = pd.gf;
     const uint32_t gsd = D == 0 ? 1u : (D == 1 ? wi.n0 : wi.n01);   // global stride along D
     // owned lines: i0 << she below the owned extent along de, i1 << shg
-    // below the one along dg
-    // (the extent is picked arithmetically: a select between members would
-    // become an indexed load, which keeps the window record in memory)
-    auto owned_count = [&](int dim, int sh) {
-        const int o = wi.o0 * (dim == 0) + wi.o1 * (dim == 1) + wi.o2 * (dim == 2);
-        return (o + (1 << sh) - 1) >> sh;
-    };
-    const int own0 = owned_count(pd.de, pd.she);
-    const int own1 = ND == 2 ? 1 : owned_count(pd.dg, pd.shg);
+    // below the one along dg (the extents come out of the packed word by
+    // the descriptor's bit offsets: four scalar operations a count)
+    const int own0 = (int)((((wi.op >> pd.obe) & 255u) + (uint32_t)pd.rne) >> pd.she);
+    const int own1 = ND == 2 ? 1 : (int)((((wi.op >> pd.obg) & 255u) + (uint32_t)pd.rng) >> pd.shg);
 
     auto fetch = [&](uint32_t t, Task<K>& tk) {
         tk.seg = NSEG > 1 ? (t & (uint32_t)(NSEG - 1)) : 0u;
@@ -674,7 +672,7 @@ __device__ __forceinline__ void write_anchors(const float* v, uint32_t lane, con
                                               const Win& wi, uint32_t* hist) {
     using G = Geo<ND>;
     constexpr int S = 1 << G::SHS;
-    if (lane < (uint32_t)(G::W0 / S) && (int)lane * S < wi.o0) {
+    if (lane < (uint32_t)(G::W0 / S) && (int)lane * S < wi.own(0)) {
         const uint32_t ai = (uint32_t)(wi.lo0 >> G::SHS) + lane +
                             (uint32_t)f.na[0] * ((uint32_t)(wi.lo1 >> G::SHS) +
                                                  (uint32_t)f.na[1] * (uint32_t)(wi.lo2 >> G::SHS));
@@ -711,12 +709,12 @@ __device__ __forceinline__ void write_values(const float* v, uint32_t lane, cons
 #pragma unroll 1
         for (int k = 0; k < M::NS; ++k) {
             const int y = M::y0(k) + (int)sub, z = M::z0(k);
-            if (y >= wi.o1 || z >= wi.o2) continue;
+            if (y >= wi.own(1) || z >= wi.own(2)) continue;
             const int l = x + y * G::SY + z * G::SZ;
             const uint32_t g = (uint32_t)x + (uint32_t)y * wi.n0 + (uint32_t)z * wi.n01;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                if (x + i < wi.o0) *at(ob, g + (uint32_t)i) = v[l + i];
+                if (x + i < wi.own(0)) *at(ob, g + (uint32_t)i) = v[l + i];
         }
     }
 }

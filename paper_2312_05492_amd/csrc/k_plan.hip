@@ -207,6 +207,8 @@ __device__ void make_passes(FieldPlan& p, const PlanIn& in, uint32_t n0, uint32_
             q.de = e;
             q.she = she;
             q.ge = GS[e] << she;
+            q.obe = 8u * (uint32_t)e;
+            q.rne = (1 << she) - 1;
             if (g >= 0) {
                 const int shg = shift(g);
                 q.nlines = q.ne * (uint32_t)((W[g] >> shg) + 1);
@@ -214,6 +216,8 @@ __device__ void make_passes(FieldPlan& p, const PlanIn& in, uint32_t n0, uint32_
                 q.dg = g;
                 q.shg = shg;
                 q.gf = GS[g] << shg;
+                q.obg = 8u * (uint32_t)g;
+                q.rng = (1 << shg) - 1;
             } else {
                 q.nlines = q.ne;
                 q.lf = 0;

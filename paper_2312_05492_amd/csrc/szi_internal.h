@@ -71,6 +71,9 @@ struct PassDesc {
     int32_t de, dg;            // the other dimensions (dg = de in 2D)
     int32_t she, shg;          // log2 of the line spacing along de and dg
     uint32_t ge, gf;
+    uint32_t obe, obg;         // bit offsets of the owned extents along de and dg in a
+                               // window's packed extents (8 bits a dimension)
+    int32_t rne, rng;          // (1 << she) - 1 and (1 << shg) - 1
 };
 
 // Per-field plan computed on the device from the range and the profile.
