@@ -117,18 +117,21 @@ def read_traffic():
     return out
 
 
-def pmc_summary(fetch_csv, write_csv, n, cmd, out_path):
-    """Per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of every kernel, scaled by
-    what the counters read for the calibration copy of the input (4n bytes
-    read, 4n written), written as a short markdown summary."""
+def pmc_summary(read_csv, write_csv, n, cmd, out_path):
+    """HBM bytes per launch of every stage kernel from two rocprofv3 counter
+    runs: reads from the L2's requests to memory by size (32, 64 and 128
+    bytes: TCC_EA0_RDREQ_32B/64B/128B), writes from WRITE_SIZE (KiB, which
+    counts 32- and 64-byte write requests).  The calibration copy of the
+    input (4n bytes read, 4n written) is reported as a check of both."""
     import csv
     import collections
 
     def load(path):
-        acc = collections.defaultdict(list)
+        acc = collections.defaultdict(lambda: collections.defaultdict(list))
         for r in csv.DictReader(open(path)):
-            acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
-        return acc
+            acc[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        return {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in acc.items()}, \
+            {k: max(len(v) for v in cs.values()) for k, cs in acc.items()}
 
     def short(k):
         k = k.replace("void ", "").replace("szi::", "")
@@ -140,26 +143,39 @@ def pmc_summary(fetch_csv, write_csv, n, cmd, out_path):
             return base + "<" + k.split("<")[1].split(",")[0].split(">")[0].strip() + ">"
         return base
 
-    fe, wr = load(fetch_csv), load(write_csv)
-    copy = max((k for k in fe if "copyBuffer" in k), key=lambda k: max(fe[k]))
-    cal_f = 4.0 * n / (max(fe[copy]) * 1024.0)
-    cal_w = 4.0 * n / (max(wr[copy]) * 1024.0)
+    rd, nrd = load(read_csv)
+    wr, _ = load(write_csv)
+
+    def read_bytes(c):
+        return (32.0 * c.get("TCC_EA0_RDREQ_32B_sum", 0.0) + 64.0 * c.get("TCC_EA0_RDREQ_64B_sum", 0.0)
+                + 128.0 * c.get("TCC_EA0_RDREQ_128B_sum", 0.0))
+
+    def largest_copy(path, value):
+        """The device copy dispatch with the most bytes (the calibration copy)."""
+        per = collections.defaultdict(dict)
+        for r in csv.DictReader(open(path)):
+            if "copyBuffer" in r["Kernel_Name"]:
+                per[r["Dispatch_Id"]][r["Counter_Name"]] = float(r["Counter_Value"])
+        return max((value(c) for c in per.values()), default=float("nan"))
+
+    copy_r = largest_copy(read_csv, read_bytes)
+    copy_w = largest_copy(write_csv, lambda c: c.get("WRITE_SIZE", 0.0) * 1024.0)
     rows = []
-    for k in fe:
+    for k in rd:
         sk = short(k)
         if sk not in STAGE_KERNELS.values() or k not in wr:
             continue
-        f = sum(fe[k]) / len(fe[k]) * 1024.0 * cal_f
-        w = sum(wr[k]) / len(wr[k]) * 1024.0 * cal_w
-        rows.append((sk, len(fe[k]), f, w))
+        rows.append((sk, nrd[k], read_bytes(rd[k]), wr[k]["WRITE_SIZE"] * 1024.0))
     with open(out_path, "w") as o:
         o.write("# HBM traffic per launch, 512^3 FP32 field, rel eb 1e-3\n\n")
-        o.write("From two rocprofv3 counter runs of the same command, one counter each:\n\n")
+        o.write("From two rocprofv3 counter runs of the same command:\n\n")
         o.write("```\n" + cmd + "\n```\n\n")
-        o.write("Counters are in KiB per dispatch. They are scaled by what the same counter reads for the "
-                "calibration copy of the input (`--calibrate-copy`: a device copy of %d bytes, "
-                "read once and written once): FETCH_SIZE x %.3f, WRITE_SIZE x %.3f.\n\n"
-                % (4 * n, cal_f, cal_w))
+        o.write("Reads are 32, 64 and 128 bytes times the L2's read requests to memory of each size "
+                "(TCC_EA0_RDREQ_32B, _64B, _128B, summed over the L2 channels of all XCDs), writes "
+                "WRITE_SIZE (KiB, 32- and 64-byte write requests), each averaged over the kernel's "
+                "dispatches.  Check: the calibration copy of the input (`--calibrate-copy`, %d bytes "
+                "read once and written once) reads %.1f MB and writes %.1f MB by these counters "
+                "(%.1f MB each expected).\n\n" % (4 * n, copy_r / 1e6, copy_w / 1e6, 4 * n / 1e6))
         o.write("| kernel | dispatches | HBM read MB | HBM write MB | total MB |\n|---|---|---|---|---|\n")
         for sk, c, f, w in rows:
             o.write("| %s | %d | %.1f | %.1f | %.1f |\n" % (sk, c, f / 1e6, w / 1e6, (f + w) / 1e6))
@@ -604,7 +620,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain device copy of the input (4n bytes read, 4n written) "
                          "before the steps, to scale HBM byte counters")
-    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("READ_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary from two rocprofv3 counter runs and exit")
     ap.add_argument("--pmc-command", default="", help="the profiled command, for the summary")
     ap.add_argument("--trace-summary", nargs=2, metavar=("STATS_CSV", "OUT_MD"),
