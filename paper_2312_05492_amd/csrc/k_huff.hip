@@ -9,12 +9,14 @@
 //   k_huff_encode  chunk offsets = block offset + in-block prefix; packs the
 //                  codewords MSB-first through LDS and writes the outliers
 //                  (index, original value) in ascending index order
-// Decode: one lane per chunk, kDecChunks chunks per workgroup.
+// Decode: kDecChunks chunks per decode block, four lanes per chunk from the
+// bit offsets of its quarters that the encoder records (one lane per chunk
+// without them).
 //   k_dec_prep     (k_plan.hip) word count of every decode block
 //   k_huff_decode  sum of the field's earlier block sums and an in-block
-//                  scan, then a table-driven canonical decode from a 64-bit
-//                  bit buffer fed by a per-lane LDS word ring; 64 symbols
-//                  per lane stored at once
+//                  scan, then a table-driven canonical decode from a
+//                  two-word register window fed by a per-lane LDS word
+//                  ring; 64 symbols per lane stored at once
 #include "dev_common.h"
 
 namespace szi {
@@ -233,6 +235,12 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// LDS words of one wave's chunk buffer: the longest chunk, one word for the
+// low part of its last code (zero when that code ends in its first word),
+// and one for the symbols past a chunk's end (a zero code at the chunk's
+// last bit, whose two ORs of zeros then land one word further).
+__host__ __device__ constexpr int enc_chunk_words(int chunk) { return (chunk * kLmax + 31) / 32 + 2; }
+
 // One wave per chunk, PER consecutive symbols per lane: the wave scans the
 // lanes' bit counts, ORs every code MSB first into the chunk's words in LDS
 // and copies them out contiguously.  The waves of a workgroup share only
@@ -250,7 +258,7 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
     extern __shared__ uint32_t smem[];
     __shared__ uint32_t wnz[4];
     constexpr int C = PER * 64;
-    constexpr int MCW = (C * kLmax + 31) / 32 + 1;   // words of the longest chunk
+    constexpr int MCW = enc_chunk_words(C);
     const int f = block_field(boff, nfields, blockIdx.x);
     const FieldDesc& fd = F[f];
     const int nsym = 2 * fd.R;
@@ -298,17 +306,19 @@ __global__ __launch_bounds__(256) void k_huff_encode(const FieldDesc* __restrict
         for (uint32_t k = lane; k < nw; k += 64) wbuf[k] = 0;
         wave_lds_sync();
         {
+            // every symbol ORs both words its code may touch, without
+            // branches: the second takes the code's low part, zero when the
+            // code ends in the first; a symbol past the chunk's end has the
+            // zero entry (length 0, no bits) and ORs zeros
             uint32_t p = pos;
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 const uint32_t len = e[k] >> 24;
-                if (len) {
-                    const uint32_t wi = p >> 5, bo = p & 31;
-                    const uint64_t sh = (uint64_t)(e[k] & 0xFFFFFFu) << (64 - len - bo);   // MSB first
-                    atomicOr(&wbuf[wi], (uint32_t)(sh >> 32));
-                    if (bo + len > 32) atomicOr(&wbuf[wi + 1], (uint32_t)sh);
-                    p += len;
-                }
+                const uint32_t wi = p >> 5, bo = p & 31;
+                const uint64_t sh = (uint64_t)(e[k] & 0xFFFFFFu) << ((64u - len - bo) & 63u);   // MSB first
+                atomicOr(&wbuf[wi], (uint32_t)(sh >> 32));
+                atomicOr(&wbuf[wi + 1], (uint32_t)sh);
+                p += len;
             }
         }
         if (tbz >> 16) {   // uniform: outliers in this chunk
@@ -772,7 +782,7 @@ hipError_t launch_huff_encode(const FieldDesc* d_fields, int nfields, const uint
                               const uint64_t* d_booff, uint32_t* d_bnz, int max_nsym,
                               hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
-    const int mcw = (chunk * kLmax + 31) / 32 + 1;
+    const int mcw = enc_chunk_words(chunk);
     const size_t lds = ((size_t)max_nsym + 4 * (size_t)mcw) * sizeof(uint32_t);
     const dim3 g((unsigned)nblocks), b(256);
     switch (chunk) {
