@@ -643,7 +643,9 @@ template <int RESTORE>
 __global__ __launch_bounds__(256) void k_elide_count(const ElideField* __restrict__ E, int nf,
                                                      const uint64_t* __restrict__ toff,
                                                      uint64_t ntiles, uint32_t* cnt) {
-    const uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    // the wave's tile, uniform (so the field record and its pointers sit in
+    // scalar registers, loaded once, not again before every word)
+    const uint64_t tile = (uint64_t)blockIdx.x * 4 + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lane = threadIdx.x & 63u;
     if (tile >= ntiles) return;
     const int f = block_field(toff, nf, tile);
@@ -655,20 +657,30 @@ __global__ __launch_bounds__(256) void k_elide_count(const ElideField* __restric
         // the field keeps its words: nothing to count
     } else if (RESTORE) {
         const uint64_t nbm = (nw + 31) / 32;
+        const SZI_G uint32_t* sec = gp(e.sec);
 #pragma unroll
         for (int j = 0; j < kElideTile / 2048; ++j) {
             const uint64_t b = w0 / 32 + (uint64_t)j * 64 + lane;
-            n += (uint32_t)__popc(b < nbm ? gp(e.sec)[b] : 0u);
+            n += (uint32_t)__popc(b < nbm ? sec[b] : 0u);
         }
         for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
     } else {
-        // 32 loads in flight a round
-        for (int r = 0; r < kElideTile / 2048; ++r) {
+        // 32 loads in flight a round: unconditional loads at indices held
+        // inside the words (a predicated load would be waited for at once),
+        // the words past the end then taken as zero
+        const SZI_G uint32_t* words = gp(e.words);
+        const uint64_t last = nw > 0 ? nw - 1 : 0;
+        for (int r = 0; r < kElideTile / 2048 && nw > 0; ++r) {
             uint32_t w[32];
 #pragma unroll
             for (int it = 0; it < 32; ++it) {
                 const uint64_t i = w0 + (uint64_t)(r * 32 + it) * 64 + lane;
-                w[it] = i < nw ? gp(e.words)[i] : 0u;
+                w[it] = words[i < nw ? i : last];
+            }
+#pragma unroll
+            for (int it = 0; it < 32; ++it) {
+                const uint64_t i = w0 + (uint64_t)(r * 32 + it) * 64 + lane;
+                w[it] = i < nw ? w[it] : 0u;
             }
 #pragma unroll
             for (int it = 0; it < 32; ++it)
@@ -683,7 +695,9 @@ __global__ __launch_bounds__(256) void k_elide_count(const ElideField* __restric
 __global__ __launch_bounds__(256) void k_elide_write(const ElideField* __restrict__ E, int nf,
                                                      const uint64_t* __restrict__ toff,
                                                      uint64_t ntiles, const uint64_t* __restrict__ off) {
-    const uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    // the wave's tile, uniform (so the field record and its pointers sit in
+    // scalar registers, loaded once, not again before every word)
+    const uint64_t tile = (uint64_t)blockIdx.x * 4 + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lane = threadIdx.x & 63u;
     if (tile >= ntiles) return;
     const int f = block_field(toff, nf, tile);
@@ -696,14 +710,24 @@ __global__ __launch_bounds__(256) void k_elide_write(const ElideField* __restric
     if (w0 >= nw) return;
     uint64_t at = nbm + (off[tile] - first);
     SZI_G uint32_t* sec = gp(e.sec);
-#pragma unroll 4
-    for (int it = 0; it < kElideTile / 64; ++it) {
-        const uint64_t i0 = w0 + (uint64_t)it * 64, i = i0 + lane;
-        const uint32_t w = i < nw ? gp(e.words)[i] : 0u;
-        const uint64_t m = __builtin_amdgcn_ballot_w64(w != 0u);
-        if (lane < 2 && i0 + 32 * lane < nw) sec[i0 / 32 + lane] = (uint32_t)(m >> (32 * lane));
-        if (w) sec[at + lanes_below(m)] = w;
-        at += (uint64_t)__popcll(m);
+    const SZI_G uint32_t* words = gp(e.words);
+    // rounds of 32 rows of 64 words, each round's loads in flight together
+    for (int r = 0; r < kElideTile / 2048; ++r) {
+        uint32_t wv[32];
+#pragma unroll
+        for (int it = 0; it < 32; ++it) {
+            const uint64_t i = w0 + (uint64_t)(r * 32 + it) * 64 + lane;
+            wv[it] = i < nw ? words[i] : 0u;
+        }
+#pragma unroll
+        for (int it = 0; it < 32; ++it) {
+            const uint64_t i0 = w0 + (uint64_t)(r * 32 + it) * 64;
+            const uint32_t w = wv[it];
+            const uint64_t m = __builtin_amdgcn_ballot_w64(w != 0u);
+            if (lane < 2 && i0 + 32 * lane < nw) sec[i0 / 32 + lane] = (uint32_t)(m >> (32 * lane));
+            if (w) sec[at + lanes_below(m)] = w;
+            at += (uint64_t)__popcll(m);
+        }
     }
 }
 
@@ -711,7 +735,9 @@ __global__ __launch_bounds__(256) void k_elide_write(const ElideField* __restric
 __global__ __launch_bounds__(256) void k_restore_write(const ElideField* __restrict__ E, int nf,
                                                        const uint64_t* __restrict__ toff,
                                                        uint64_t ntiles, const uint64_t* __restrict__ off) {
-    const uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    // the wave's tile, uniform (so the field record and its pointers sit in
+    // scalar registers, loaded once, not again before every word)
+    const uint64_t tile = (uint64_t)blockIdx.x * 4 + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lane = threadIdx.x & 63u;
     if (tile >= ntiles) return;
     const int f = block_field(toff, nf, tile);

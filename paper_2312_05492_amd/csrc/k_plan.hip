@@ -128,15 +128,16 @@ __device__ void profile_field(const FieldDesc& f, FieldPlan& P) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();   // one wave: threads 0-63
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    if (t == 0) {
-        double s[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        if (f.need_prof)
-            for (int k = 0; k < ns; ++k)
-                for (int d = 0; d < D; ++d)
-                    if (f.n[d] >= 7)
-                        for (int e = 0; e < 3; ++e) s[d][e] = s[d][e] + err[k][d][e];
-        for (int d = 0; d < 3; ++d)
-            for (int e = 0; e < 3; ++e) P.prof[d][e] = s[d][e];
+    // one thread per (dimension, spline) adds that error over the samples in
+    // ascending order (the order a single thread adding them all would take)
+    if (t < 9) {
+        const int d = t / 3, e = t % 3;
+        double s = 0.0;
+        if (f.need_prof && d < D && f.n[d] >= 7) {
+#pragma unroll 8
+            for (int k = 0; k < ns; ++k) s = s + err[k][d][e];
+        }
+        P.prof[d][e] = s;
     }
 }
 
