@@ -397,7 +397,14 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
                                                             int nfields,
                                                             const uint64_t* __restrict__ boff,
                                                             const uint32_t* __restrict__ bsum) {
-    extern __shared__ uint32_t smem[];
+    // the rings and the look-up table at fixed LDS addresses (a look-up's
+    // address is then its index and an offset, with no base to add); the
+    // limits, bases and sorted symbols, sized by the radius, after them
+    __shared__ __align__(16) uint32_t rings[kDecChunks * kRing];
+    __shared__ __align__(16) uint32_t lut32[kDtLimit];   // 2^kLutBits u16 entries
+    __shared__ uint32_t scan[kDecChunks / 64];
+    __shared__ uint64_t pre[kDecChunks / 64];
+    extern __shared__ uint32_t tab_hi[];   // decode-table words kDtLimit .. dtab_words(nsym)
     static_assert(Q == 1 || Q == 4, "one lane or four per chunk");
     constexpr int CPW = kDecChunks / Q;   // chunks per workgroup
     const uint64_t pblk = blockIdx.x / Q;   // the decode block
@@ -406,28 +413,26 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
     const FieldDesc& fd = F[f];
     const int nsym = 2 * fd.R;
     const int ntab = dtab_words(nsym);
-    uint32_t* scan = smem;                                   // kDecChunks / 64
-    uint64_t* pre = reinterpret_cast<uint64_t*>(smem + kDecChunks / 64);   // kDecChunks / 64
-    uint32_t* rings = smem + 3 * (kDecChunks / 64);          // kDecChunks x kRing, 16-byte aligned
-    uint32_t* tab = rings + kDecChunks * kRing;              // 16-byte aligned
-    const uint16_t* lut = reinterpret_cast<const uint16_t*>(tab);
+    const uint16_t* lut = reinterpret_cast<const uint16_t*>(lut32);
     const int tid = threadIdx.x;
     {
-        // the decode tables, 16 bytes at a time with four loads in flight
-        // (word by word where they do not start on 16 bytes: odd radius)
-        const SZI_G vu4* src = reinterpret_cast<const SZI_G vu4*>(gp(fd.dtab));
-        vu4* dst = reinterpret_cast<vu4*>(tab);
-        const int n4 = ((uintptr_t)fd.dtab & 15u) == 0u ? ntab / 4 : 0;
-        for (int k0 = tid; k0 < n4; k0 += 4 * kDecChunks) {
-            vu4 v[4];
+        // the look-up table 16 bytes at a time, its four loads per lane in
+        // flight together (word by word where the tables do not start on 16
+        // bytes: odd radius), then the rest word by word
+        const SZI_G uint32_t* src = gp(fd.dtab);
+        static_assert(kDtLimit % (4 * kDecChunks) == 0, "whole rounds of 16-byte copies");
+        if (((uintptr_t)fd.dtab & 15u) == 0u) {
+            const SZI_G vu4* s4 = reinterpret_cast<const SZI_G vu4*>(src);
+            vu4* d4 = reinterpret_cast<vu4*>(lut32);
+            vu4 v[kDtLimit / (4 * kDecChunks)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (k0 + j * kDecChunks < n4) v[j] = src[k0 + j * kDecChunks];
+            for (int j = 0; j < kDtLimit / (4 * kDecChunks); ++j) v[j] = s4[tid + j * kDecChunks];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (k0 + j * kDecChunks < n4) dst[k0 + j * kDecChunks] = v[j];
+            for (int j = 0; j < kDtLimit / (4 * kDecChunks); ++j) d4[tid + j * kDecChunks] = v[j];
+        } else {
+            for (int k = tid; k < kDtLimit; k += kDecChunks) lut32[k] = src[k];
         }
-        for (int k = 4 * n4 + tid; k < ntab; k += kDecChunks) tab[k] = gp(fd.dtab)[k];
+        for (int k = kDtLimit + tid; k < ntab; k += kDecChunks) tab_hi[k - kDtLimit] = src[k];
     }
     // length limits of the codes longer than the LUT, in scalar registers
     uint32_t lim[kLmax - kLutBits - 1];
@@ -540,8 +545,8 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
             uint32_t ln = kLutBits + 1;
 #pragma unroll
             for (int l = kLutBits + 1; l < kLmax; ++l) ln += w >= lim[l - kLutBits - 1] ? 1u : 0u;
-            const uint32_t i = tab[kDtBase + ln] + (w >> (kLmax - ln));
-            const uint32_t sl = tab[kDtSorted + (i < (uint32_t)nsym ? i : 0u)];   // a corrupt stream stays inside
+            const uint32_t i = tab_hi[kDtBase - kDtLimit + ln] + (w >> (kLmax - ln));
+            const uint32_t sl = tab_hi[kDtSorted - kDtLimit + (i < (uint32_t)nsym ? i : 0u)];   // a corrupt stream stays inside
             const bool lng = len == 0;
             sym = lng ? sl : sym;
             len = lng ? ln : len;
@@ -826,7 +831,7 @@ hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields, const uint
                               uint64_t nblocks, const uint32_t* d_bsum, int max_nsym, int split,
                               hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
-    const size_t lds = (size_t)(3 * (kDecChunks / 64) + kDecChunks * kRing + dtab_words(max_nsym)) *
+    const size_t lds = (size_t)(dtab_words(max_nsym) - kDtLimit) *
                        sizeof(uint32_t);
     if (split)
         hipLaunchKernelGGL(k_huff_decode<4>, dim3((unsigned)(4 * nblocks)), dim3(kDecChunks), lds, st,
