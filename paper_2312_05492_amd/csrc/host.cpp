@@ -1158,7 +1158,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         R->d_cbook = reinterpret_cast<uint32_t*>(tabs + tables_len_bytes(nsym));
         R->d_dtab = R->d_cbook + nsym;
         if ((s = res_alloc(c, R, geo[i].nchunks, &res[i].chunk_bits))) return s;
-        if ((s = res_alloc(c, R, 4 * geo[i].nchunks, &R->d_sub))) return s;
+        if ((s = res_alloc(c, R, (size_t)kSubParts * geo[i].nchunks, &R->d_sub))) return s;
         res[i].n = geo[i].npts;
         res[i].n_anchors = geo[i].nanch;
         res[i].n_chunks = geo[i].nchunks;
@@ -1807,7 +1807,7 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
     std::vector<uint32_t> perm;
     for (int gi = 0; gi < kGroups; ++gi) perm.insert(perm.end(), grp[gi].begin(), grp[gi].end());
     uint64_t cb = 0;
-    bool split = true;   // every field has sub-chunk offsets: four decode lanes per chunk
+    bool split = true;   // every field has sub-chunk offsets: kSubParts decode lanes per chunk
     std::vector<uint64_t> dboff(nf + 1, 0);
     for (uint32_t k = 0; k < nf; ++k) {
         const uint32_t i = perm[k];

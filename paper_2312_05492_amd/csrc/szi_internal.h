@@ -17,6 +17,10 @@ constexpr int kDecBlockChunks = 256;  // Huffman chunks per decode workgroup
 constexpr int kWordPad = 8;        // allocated u32 past the end of every Huffman word array
 
 // Static description of one field, written by the host before launch.
+// Decode lanes per Huffman chunk: the encoder records where each of a
+// chunk's kSubParts equal parts starts, and one lane decodes each part.
+constexpr int kSubParts = 8;
+
 struct FieldDesc {
     int32_t ndim;
     int32_t n[3];          // n[0] fastest; unused dims 1
@@ -50,7 +54,7 @@ struct FieldDesc {
     float* outlier_val;
     const uint32_t* dtab;  // decode tables (see DecodeTables layout)
     unsigned long long* nzw;  // compress: the field's non-zero words (stats clears, encode adds)
-    uint16_t* sub;         // per chunk 0 and the bit offsets of its 2nd, 3rd and 4th quarters (or null)
+    uint16_t* sub;         // per chunk kSubParts bit offsets: 0, then where its 2nd .. last eighth starts (or null)
 };
 
 // One pass of the interpolation (Sec. V-A: levels from stride S/2 to 1, one
@@ -192,7 +196,7 @@ constexpr uint64_t kElideTileWords = 8192;
 hipError_t launch_elide(const ElideField* d_e, int nf, const uint64_t* d_toff, uint64_t ntiles,
                         uint32_t* d_cnt, uint64_t* d_off, int restore, hipStream_t st);
 // d_bsum: the word count of every decode block (launch_dec_prep)
-// split: every field has sub-chunk offsets (four lanes per chunk)
+// split: every field has sub-chunk offsets (kSubParts lanes per chunk)
 hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields, const uint64_t* d_dboff,
                               uint64_t nblocks, const uint32_t* d_bsum, int max_nsym, int split,
                               hipStream_t st);
