@@ -40,7 +40,7 @@ def algorithmic_bytes(stage, n, n_anchors, n_out, n_words, n_chunks):
         "interp": 4 * n + 2 * n + 4 * n_anchors,
         "huff_stats": 0,
         "encode": 2 * n + 4 * n_words + 2 * n_chunks + 8 * n_out,
-        "decode": 4 * n_words + 2 * n_chunks + 8 * n_chunks + 2 * n,   # + the quarter offsets
+        "decode": 4 * n_words + 2 * n_chunks + 16 * n_chunks + 2 * n,   # + the part offsets
         "replay": 2 * n + 4 * n_anchors + 4 * n + 8 * n_out,
     }.get(stage)
 
