@@ -1260,10 +1260,14 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     const size_t o_bwoff = L.take<uint64_t>(nbw), o_booff = L.take<uint64_t>(nbw);
     const size_t o_bnz = L.take<uint32_t>(std::max<uint64_t>(total_blocks, 1));
     const size_t o_fnz = L.take<unsigned long long>(nf);
-    // zero-word elision: tiles of every field's words at their largest
+    // zero-word elision: tiles of every field's words at their largest, of
+    // a size chosen from that bound
+    uint64_t ewords_max = 0;
+    for (uint32_t k = 0; k < nf; ++k) ewords_max += fds[k].npts * kLmax / 32 + fds[k].nchunks + 1;
+    const uint64_t etw = elide_tile_words(ewords_max);
     uint64_t etiles_max = 0;
     for (uint32_t k = 0; k < nf; ++k)
-        etiles_max += (fds[k].npts * kLmax / 32 + fds[k].nchunks + 1) / kElideTileWords + 1;
+        etiles_max += (fds[k].npts * kLmax / 32 + fds[k].nchunks + 1) / etw + 1;
     const size_t o_ecnt = L.take<uint32_t>(etiles_max), o_eoff = L.take<uint64_t>(etiles_max + 1);
     // host staging in pinned memory (copies from it are asynchronous): the
     // arena's layout, then each field's code lengths, codebook and decode
@@ -1564,7 +1568,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
             ef[j].nw = 0;
         }
     for (uint32_t j = 0; j < nf; ++j)
-        etoff[j + 1] = etoff[j] + (hfd[j].words_cap + kElideTileWords - 1) / kElideTileWords;
+        etoff[j + 1] = etoff[j] + (hfd[j].words_cap + etw - 1) / etw;
     const uint64_t etiles = etoff[nf];
     if (etiles > etiles_max) return fail(c, SZ_ERR_DEVICE, "elision tiles exceed their bound");
     // part 2: Huffman stats, block scans, encode with outlier compaction,
@@ -1593,7 +1597,7 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
         }
         {
             STAGE(c, SZ_STAGE_ELIDE, q);
-            HIP_TRY(c, launch_elide(d_ef, (int)nf, d_etoff, etiles, d_ecnt, d_eoff, 0, q));
+            HIP_TRY(c, launch_elide(d_ef, (int)nf, d_etoff, etiles, etw, d_ecnt, d_eoff, 0, q));
         }
         return SZ_OK;
     };
@@ -2186,7 +2190,8 @@ sz_status sz_upload(sz_ctx* c, const void* blob, uint64_t bytes, void* stream, s
         e.wbeg = e.wend = nullptr;
         e.nzw = nullptr;
         e.nw = r.n_words;
-        const uint64_t tiles = (r.n_words + kElideTileWords - 1) / kElideTileWords;
+        const uint64_t tw = elide_tile_words(r.n_words);
+        const uint64_t tiles = (r.n_words + tw - 1) / tw;
         const uint64_t toff[2] = {0, tiles};
         char* d;
         Layout L;
@@ -2202,7 +2207,7 @@ sz_status sz_upload(sz_ctx* c, const void* blob, uint64_t bytes, void* stream, s
         if (e1 == hipSuccess && e2 == hipSuccess) {
             STAGE(c, SZ_STAGE_ELIDE, st);
             e3 = launch_elide(reinterpret_cast<ElideField*>(d + o_e), 1,
-                              reinterpret_cast<uint64_t*>(d + o_t), tiles,
+                              reinterpret_cast<uint64_t*>(d + o_t), tiles, tw,
                               reinterpret_cast<uint32_t*>(d + o_c), reinterpret_cast<uint64_t*>(d + o_o),
                               1, st);
         }

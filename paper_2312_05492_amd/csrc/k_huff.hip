@@ -629,13 +629,13 @@ __global__ __launch_bounds__(kDecChunks) void k_huff_decode(const FieldDesc* __r
 // The de-redundancy step after Huffman coding (taking the place of the
 // closed pass of Sec. VI-B): the words section becomes a bitmap of the
 // non-zero words (bit k % 32 of bitmap word k / 32 for word k) followed by
-// those words in order.  Work is split into tiles of kElideTile words, one
-// wave per tile: a count pass, an exclusive scan of the tile counts over all
-// fields (k_scan_blocks), and a write pass.  The restore (upload of an
+// those words in order.  Work is split into tiles of tw words (8192, or 2048
+// for calls with few words), one wave per tile: a count pass, an exclusive
+// scan of the tile counts over all fields (k_scan_blocks), and a write pass.  The restore (upload of an
 // elided blob) runs the same tiling backwards: counts of set bits, scan,
 // then each tile's words in place.
-constexpr int kElideTile = (int)kElideTileWords;
-static_assert(kElideTile % 2048 == 0, "a tile is whole rounds of 32 ballots of 64 words");
+static_assert(kElideTileWords % 2048 == 0 && kElideTileSmall % 2048 == 0,
+              "a tile is whole rounds of 32 ballots of 64 words");
 
 __device__ __forceinline__ uint64_t elide_words(const ElideField& e) {
     return e.wbeg ? *e.wend - *e.wbeg : e.nw;
@@ -650,7 +650,7 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 template <int RESTORE>
 __global__ __launch_bounds__(256) void k_elide_count(const ElideField* __restrict__ E, int nf,
                                                      const uint64_t* __restrict__ toff,
-                                                     uint64_t ntiles, uint32_t* cnt) {
+                                                     uint64_t ntiles, uint64_t tw, uint32_t* cnt) {
     // the wave's tile, uniform (so the field record and its pointers sit in
     // scalar registers, loaded once, not again before every word)
     const uint64_t tile = (uint64_t)blockIdx.x * 4 + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -659,15 +659,15 @@ __global__ __launch_bounds__(256) void k_elide_count(const ElideField* __restric
     const int f = block_field(toff, nf, tile);
     const ElideField& e = E[f];
     const uint64_t nw = elide_words(e);
-    const uint64_t w0 = (tile - toff[f]) * kElideTile;
+    const uint64_t w0 = (tile - toff[f]) * tw;
+    const int rounds = (int)(tw / 2048);
     uint32_t n = 0;
     if (!RESTORE && e.nzw && (nw + 31) / 32 + *gp(e.nzw) >= nw) {
         // the field keeps its words: nothing to count
     } else if (RESTORE) {
         const uint64_t nbm = (nw + 31) / 32;
         const SZI_G uint32_t* sec = gp(e.sec);
-#pragma unroll
-        for (int j = 0; j < kElideTile / 2048; ++j) {
+        for (int j = 0; j < rounds; ++j) {
             const uint64_t b = w0 / 32 + (uint64_t)j * 64 + lane;
             n += (uint32_t)__popc(b < nbm ? sec[b] : 0u);
         }
@@ -678,7 +678,7 @@ __global__ __launch_bounds__(256) void k_elide_count(const ElideField* __restric
         // the words past the end then taken as zero
         const SZI_G uint32_t* words = gp(e.words);
         const uint64_t last = nw > 0 ? nw - 1 : 0;
-        for (int r = 0; r < kElideTile / 2048 && nw > 0; ++r) {
+        for (int r = 0; r < rounds && nw > 0; ++r) {
             uint32_t w[32];
 #pragma unroll
             for (int it = 0; it < 32; ++it) {
@@ -702,7 +702,8 @@ __global__ __launch_bounds__(256) void k_elide_count(const ElideField* __restric
 // field's section is shorter than its words (else nothing is written)
 __global__ __launch_bounds__(256) void k_elide_write(const ElideField* __restrict__ E, int nf,
                                                      const uint64_t* __restrict__ toff,
-                                                     uint64_t ntiles, const uint64_t* __restrict__ off) {
+                                                     uint64_t ntiles, uint64_t tw,
+                                                     const uint64_t* __restrict__ off) {
     // the wave's tile, uniform (so the field record and its pointers sit in
     // scalar registers, loaded once, not again before every word)
     const uint64_t tile = (uint64_t)blockIdx.x * 4 + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -714,13 +715,13 @@ __global__ __launch_bounds__(256) void k_elide_write(const ElideField* __restric
     const uint64_t first = off[toff[f]];
     const uint64_t nz = e.nzw ? (uint64_t)*gp(e.nzw) : off[toff[f + 1]] - first;
     if (nbm + nz >= nw) return;
-    const uint64_t w0 = (tile - toff[f]) * kElideTile;
+    const uint64_t w0 = (tile - toff[f]) * tw;
     if (w0 >= nw) return;
     uint64_t at = nbm + (off[tile] - first);
     SZI_G uint32_t* sec = gp(e.sec);
     const SZI_G uint32_t* words = gp(e.words);
     // rounds of 32 rows of 64 words, each round's loads in flight together
-    for (int r = 0; r < kElideTile / 2048; ++r) {
+    for (int r = 0; r < (int)(tw / 2048); ++r) {
         uint32_t wv[32];
 #pragma unroll
         for (int it = 0; it < 32; ++it) {
@@ -742,7 +743,8 @@ __global__ __launch_bounds__(256) void k_elide_write(const ElideField* __restric
 // restore: the words of a tile from the bitmap and the non-zero words
 __global__ __launch_bounds__(256) void k_restore_write(const ElideField* __restrict__ E, int nf,
                                                        const uint64_t* __restrict__ toff,
-                                                       uint64_t ntiles, const uint64_t* __restrict__ off) {
+                                                       uint64_t ntiles, uint64_t tw,
+                                                       const uint64_t* __restrict__ off) {
     // the wave's tile, uniform (so the field record and its pointers sit in
     // scalar registers, loaded once, not again before every word)
     const uint64_t tile = (uint64_t)blockIdx.x * 4 + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -751,12 +753,12 @@ __global__ __launch_bounds__(256) void k_restore_write(const ElideField* __restr
     const int f = block_field(toff, nf, tile);
     const ElideField& e = E[f];
     const uint64_t nw = elide_words(e), nbm = (nw + 31) / 32;
-    const uint64_t w0 = (tile - toff[f]) * kElideTile;
+    const uint64_t w0 = (tile - toff[f]) * tw;
     if (w0 >= nw) return;
     uint64_t at = nbm + (off[tile] - off[toff[f]]);
     const SZI_G uint32_t* sec = gp(e.sec);
 #pragma unroll 4
-    for (int it = 0; it < kElideTile / 64; ++it) {
+    for (int it = 0; it < (int)(tw / 64); ++it) {
         const uint64_t i0 = w0 + (uint64_t)it * 64, i = i0 + lane;
         const uint32_t lo = i0 / 32 < nbm ? sec[i0 / 32] : 0u;
         const uint32_t hi = i0 / 32 + 1 < nbm ? sec[i0 / 32 + 1] : 0u;
@@ -769,19 +771,20 @@ __global__ __launch_bounds__(256) void k_restore_write(const ElideField* __restr
 
 // ------------------------------------------------------- launchers
 hipError_t launch_elide(const ElideField* d_e, int nf, const uint64_t* d_toff, uint64_t ntiles,
-                        uint32_t* d_cnt, uint64_t* d_off, int restore, hipStream_t st) {
+                        uint64_t tw, uint32_t* d_cnt, uint64_t* d_off, int restore, hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
+    if (tw == 0 || tw % 2048 != 0) return hipErrorInvalidValue;
     const dim3 g((unsigned)((ntiles + 3) / 4)), b(256);
-    if (restore) hipLaunchKernelGGL(k_elide_count<1>, g, b, 0, st, d_e, nf, d_toff, ntiles, d_cnt);
-    else hipLaunchKernelGGL(k_elide_count<0>, g, b, 0, st, d_e, nf, d_toff, ntiles, d_cnt);
+    if (restore) hipLaunchKernelGGL(k_elide_count<1>, g, b, 0, st, d_e, nf, d_toff, ntiles, tw, d_cnt);
+    else hipLaunchKernelGGL(k_elide_count<0>, g, b, 0, st, d_e, nf, d_toff, ntiles, tw, d_cnt);
     if (ntiles > 16 * 1024)
         hipLaunchKernelGGL(k_scan_blocks<true>, dim3(1), dim3(1024), 0, st, d_cnt,
                            (const uint32_t*)nullptr, ntiles, d_off, (uint64_t*)nullptr);
     else
         hipLaunchKernelGGL(k_scan_blocks<false>, dim3(1), dim3(1024), 0, st, d_cnt,
                            (const uint32_t*)nullptr, ntiles, d_off, (uint64_t*)nullptr);
-    if (restore) hipLaunchKernelGGL(k_restore_write, g, b, 0, st, d_e, nf, d_toff, ntiles, d_off);
-    else hipLaunchKernelGGL(k_elide_write, g, b, 0, st, d_e, nf, d_toff, ntiles, d_off);
+    if (restore) hipLaunchKernelGGL(k_restore_write, g, b, 0, st, d_e, nf, d_toff, ntiles, tw, d_off);
+    else hipLaunchKernelGGL(k_elide_write, g, b, 0, st, d_e, nf, d_toff, ntiles, tw, d_off);
     return hipGetLastError();
 }
 

@@ -189,12 +189,19 @@ struct ElideField {
     const unsigned long long* nzw;
     uint64_t nw;
 };
+// Elision tiles: 8192 words, or 2048 where the call has few words (then
+// four times the waves share them, each with one round of loads instead of
+// four); the tile size only splits the work, the section is the same.
 constexpr uint64_t kElideTileWords = 8192;
+constexpr uint64_t kElideTileSmall = 2048;
+inline uint64_t elide_tile_words(uint64_t words) {
+    return words < (uint64_t)1024 * kElideTileSmall ? kElideTileSmall : kElideTileWords;
+}
 // restore = 0: elide words into sec where that is shorter; 1: restore words
-// from sec.  Fields own the tiles [toff[f], toff[f + 1]) of kElideTileWords
-// words; cnt and off (u32[ntiles], u64[ntiles + 1]) are scratch.
+// from sec.  Fields own the tiles [toff[f], toff[f + 1]) of tw words (a
+// multiple of 2048); cnt and off (u32[ntiles], u64[ntiles + 1]) are scratch.
 hipError_t launch_elide(const ElideField* d_e, int nf, const uint64_t* d_toff, uint64_t ntiles,
-                        uint32_t* d_cnt, uint64_t* d_off, int restore, hipStream_t st);
+                        uint64_t tw, uint32_t* d_cnt, uint64_t* d_off, int restore, hipStream_t st);
 // d_bsum: the word count of every decode block (launch_dec_prep)
 // split: every field has sub-chunk offsets (kSubParts lanes per chunk)
 hipError_t launch_huff_decode(const FieldDesc* d_fields, int nfields, const uint64_t* d_dboff,
