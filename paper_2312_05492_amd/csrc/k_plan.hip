@@ -293,7 +293,9 @@ __global__ __launch_bounds__(kDecBlockChunks) void k_dec_prep(const FieldDesc* _
 __global__ __launch_bounds__(256) void k_plan(const FieldDesc* __restrict__ F, FieldPlan* P,
                                               const float* pmin, const float* pmax,
                                               const uint32_t* pbad) {
-    const FieldDesc& f = F[blockIdx.x];
+    // a copy of the field record: the plan's stores below then cannot make
+    // the compiler load its members again (one wait each)
+    const FieldDesc f = F[blockIdx.x];
     FieldPlan& p = P[blockIdx.x];
     float mn = INFINITY, mx = -INFINITY;
     uint32_t bad = 0;
@@ -317,6 +319,12 @@ __global__ __launch_bounds__(256) void k_plan(const FieldDesc* __restrict__ F, F
     for (int b = threadIdx.x; b < 2 * f.R; b += blockDim.x) gp(f.hist)[b] = 0u;
     __syncthreads();
     if (threadIdx.x != 0) return;
+    // the profiling's errors (k_range), read before the plan is written
+    double prof[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) prof[d][e] = p.prof[d][e];
     for (int k = 1; k < 4; ++k) {
         mn = fminf(mn, smn[k]);
         mx = fmaxf(mx, smx[k]);
@@ -360,10 +368,10 @@ __global__ __launch_bounds__(256) void k_plan(const FieldDesc* __restrict__ F, F
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         int s = d < D ? f.interp[d] : SPL_LIN;
-        if (s == SPL_AUTO) s = p.prof[d][2] < p.prof[d][1] ? SPL_NAT : SPL_NAK;
+        if (s == SPL_AUTO) s = prof[d][2] < prof[d][1] ? SPL_NAT : SPL_NAK;
         in.spline[d] = s;
         p.spline[d] = s;
-        score[d] = p.prof[d][s];
+        score[d] = prof[d][s];
     }
     if (f.order_req[0] >= 0) {
 #pragma unroll
