@@ -65,6 +65,31 @@ def test_elision_matches_oracle(ctx, name, gen, kw, elided):
         res.free()
 
 
+def test_large_elided_blob_in_large_tiles(ctx):
+    """A smooth 8000 x 9600 field whose words (about 2.4 M) exceed the bound
+    below which the elision and the upload's restore use 2048-word tiles: the
+    blob, the restored words and the reconstruction equal the oracle's with
+    8192-word tiles on both sides."""
+    x = synth.climate_field(931, shape=(8000, 9600))
+    print("\n[elision large] shape=%s" % (x.shape,), flush=True)
+    ref = O.compress(x, O.Params(shape=x.shape, eb=1e-3))
+    assert ref.words.size >= 1024 * 2048   # the large tiles
+    res = ctx.compress(_gpu(x), eb=1e-3)
+    try:
+        blob = res.blob()
+        assert _flags(blob) == O.FLAG_WORDS_ELIDED
+        assert blob == ref.blob()
+        up = ctx.upload(blob)
+        try:
+            assert np.array_equal(up.read(szi.SEC_WORDS), ref.words)
+            y = ctx.decompress(up).cpu().numpy()
+            assert np.array_equal(y.view(np.uint32), ref.recon.view(np.uint32))
+        finally:
+            up.free()
+    finally:
+        res.free()
+
+
 def test_elided_blob_with_a_flipped_bitmap_bit_is_rejected(ctx):
     x = synth.climate_field(914, shape=(120, 240))
     res = ctx.compress(_gpu(x))
