@@ -82,7 +82,7 @@ def host_cpu():
     return model, ncpu
 
 
-# per-launch HBM traffic from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# per-launch HBM traffic from rocprofv3 read-request and WRITE_SIZE runs
 # (python bench.py --pmc-summary), kept with a hash of the kernel sources
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_512cube_rel1e-3.md")
 STAGE_KERNELS = {"range": "k_range", "interp": "k_compress<3>", "huff_stats": "k_huff_stats",

@@ -107,8 +107,9 @@ def test_elided_blob_with_a_flipped_bitmap_bit_is_rejected(ctx):
 @pytest.mark.parametrize("graphs", [False, True])
 def test_batch_elision_mixed_fields(ctx, graphs):
     """One elision launch covers every field of a batch: fields that elide
-    and fields that keep their words, most spanning several 8192-word
-    tiles, give the oracle's blobs; elided ones restore on upload."""
+    and fields that keep their words, most spanning several tiles (of 2048
+    words at these sizes), give the oracle's blobs; elided ones restore on
+    upload."""
     xs = [synth.climate_field(921, shape=(900, 1800)),
           synth.spectral_field((40, 56, 72), seed=922),
           synth.climate_field(923, shape=(700, 1200)),
