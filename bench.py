@@ -91,12 +91,14 @@ STAGE_KERNELS = {"range": "k_range", "interp": "k_compress<3>", "huff_stats": "k
 
 
 def kernel_source_hash():
+    """A hash of the device sources (the kernels and the headers they
+    include): host-only code does not change what the counters measured."""
     import hashlib
     h = hashlib.sha256()
     for sub in ("paper_2312_05492_amd/csrc", "include"):
         d = os.path.join(ROOT, sub)
         for f in sorted(os.listdir(d)):
-            if f.endswith((".hip", ".h", ".cpp")):
+            if f.endswith((".hip", ".h")):
                 h.update(f.encode())
                 h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()
@@ -145,6 +147,11 @@ def pmc_summary(read_csv, write_csv, n, cmd, out_path):
 
     rd, nrd = load(read_csv)
     wr, _ = load(write_csv)
+    need = ("TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum")
+    if not any(all(c in cs for c in need) for cs in rd.values()):
+        raise SystemExit("%s holds no %s counters" % (read_csv, ", ".join(need)))
+    if not any("WRITE_SIZE" in cs for cs in wr.values()):
+        raise SystemExit("%s holds no WRITE_SIZE counter" % write_csv)
 
     def read_bytes(c):
         return (32.0 * c.get("TCC_EA0_RDREQ_32B_sum", 0.0) + 64.0 * c.get("TCC_EA0_RDREQ_64B_sum", 0.0)
