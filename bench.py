@@ -158,15 +158,18 @@ def pmc_summary(read_csv, write_csv, n, cmd, out_path):
                 + 128.0 * c.get("TCC_EA0_RDREQ_128B_sum", 0.0))
 
     def largest_copy(path, value):
-        """The device copy dispatch with the most bytes (the calibration copy)."""
+        """(bytes, microseconds) of the device copy dispatch with the most
+        bytes (the calibration copy), its duration from the dispatch's
+        timestamps."""
         per = collections.defaultdict(dict)
         for r in csv.DictReader(open(path)):
             if "copyBuffer" in r["Kernel_Name"]:
                 per[r["Dispatch_Id"]][r["Counter_Name"]] = float(r["Counter_Value"])
-        return max((value(c) for c in per.values()), default=float("nan"))
+                per[r["Dispatch_Id"]]["_us"] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        return max(((value(c), c["_us"]) for c in per.values()), default=(float("nan"), float("nan")))
 
-    copy_r = largest_copy(read_csv, read_bytes)
-    copy_w = largest_copy(write_csv, lambda c: c.get("WRITE_SIZE", 0.0) * 1024.0)
+    copy_r, copy_us = largest_copy(read_csv, read_bytes)
+    copy_w, _ = largest_copy(write_csv, lambda c: c.get("WRITE_SIZE", 0.0) * 1024.0)
     rows = []
     for k in rd:
         sk = short(k)
@@ -182,7 +185,9 @@ def pmc_summary(read_csv, write_csv, n, cmd, out_path):
                 "WRITE_SIZE (KiB, 32- and 64-byte write requests), each averaged over the kernel's "
                 "dispatches.  Check: the calibration copy of the input (`--calibrate-copy`, %d bytes "
                 "read once and written once) reads %.1f MB and writes %.1f MB by these counters "
-                "(%.1f MB each expected).\n\n" % (4 * n, copy_r / 1e6, copy_w / 1e6, 4 * n / 1e6))
+                "(%.1f MB each expected), in %.1f us: %.2f TB/s read and written together (the "
+                "streaming rate the chip reaches).\n\n" % (4 * n, copy_r / 1e6, copy_w / 1e6, 4 * n / 1e6,
+                                                          copy_us, (copy_r + copy_w) / (copy_us * 1e-6) / 1e12))
         o.write("| kernel | dispatches | HBM read MB | HBM write MB | total MB |\n|---|---|---|---|---|\n")
         for sk, c, f, w in rows:
             o.write("| %s | %d | %.1f | %.1f | %.1f |\n" % (sk, c, f / 1e6, w / 1e6, (f + w) / 1e6))
