@@ -33,12 +33,16 @@ __global__ __launch_bounds__(256) void k_range(const FieldDesc* __restrict__ F, 
     if ((reinterpret_cast<uintptr_t>(in) & 15) == 0) {
         const SZI_G vf4* in4 = reinterpret_cast<const SZI_G vf4*>(in);
         const uint64_t n4 = n / 4;
-        uint64_t i = tid;
-        // eight 16-byte loads in flight per lane
-        for (; i + 7 * stride < n4; i += 8 * stride) {
+        // a contiguous slice of quads per block, eight rows of 256 quads in
+        // flight (each round reads 32 KB in a row; a grid-stride pattern, the
+        // eight loads of a lane 8 MB apart, ran at 5.0 TB/s against 6.4)
+        const uint64_t per = ((n4 + kRangeBlocks - 1) / kRangeBlocks + 255) / 256 * 256;
+        const uint64_t beg = (uint64_t)blk * per, end = beg + per < n4 ? beg + per : n4;
+        uint64_t i = beg + threadIdx.x;
+        for (; i + 7 * 256 < end; i += 8 * 256) {
             vf4 a[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) a[k] = __builtin_nontemporal_load(in4 + i + k * stride);
+            for (int k = 0; k < 8; ++k) a[k] = __builtin_nontemporal_load(in4 + i + k * 256);
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 take(a[k].x);
@@ -47,7 +51,7 @@ __global__ __launch_bounds__(256) void k_range(const FieldDesc* __restrict__ F, 
                 take(a[k].w);
             }
         }
-        for (; i < n4; i += stride) {
+        for (; i < end; i += 256) {
             const vf4 a = in4[i];
             take(a.x);
             take(a.y);
