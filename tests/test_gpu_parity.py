@@ -223,6 +223,34 @@ def test_batch_of_all_dimensionalities(ctx):
             r.free()
 
 
+@pytest.mark.parametrize("shape,seed", [((24, 40, 64), 61), ((96, 200), 62), ((9001,), 63)])
+def test_field_and_output_off_16_byte_alignment(ctx, shape, seed):
+    """A field and an output buffer one float past a 16-byte boundary: the
+    range kernel's scalar loop, the window kernels' per-slot block loads
+    (not the 16-byte ones) and the replay's per-value writes; the blob and
+    the reconstruction are the oracle's."""
+    import torch
+    x = synth.spectral_field(shape, seed=seed)
+    print("\n[parity] unaligned shape=%s" % (shape,), flush=True)
+    ref = O.compress(x, _oracle_params(x.shape, {}))
+    n = x.size
+    buf = torch.empty(n + 4, dtype=torch.float32, device="cuda")
+    xin = buf[1:1 + n].view(shape)
+    xin.copy_(torch.from_numpy(x))
+    assert xin.data_ptr() % 16 == 4
+    res = ctx.compress(xin)
+    try:
+        assert res.blob() == ref.blob()
+        obuf = torch.zeros(n + 4, dtype=torch.float32, device="cuda")
+        out = obuf[1:1 + n].view(shape)
+        ctx.decompress(res, out)
+        y = obuf.cpu().numpy()
+        assert np.array_equal(_bits(y[1:1 + n]), _bits(ref.recon.ravel()))
+        assert y[0] == 0.0 and not np.any(y[1 + n:])   # nothing written outside
+    finally:
+        res.free()
+
+
 def test_window_limits(ctx):
     # the generic kernels hold a block of at most 4096 points in LDS; a
     # window must be a multiple of the stride
