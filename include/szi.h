@@ -184,7 +184,9 @@ sz_status sz_ctx_set_timing(sz_ctx* ctx, int enable);
  * clears the totals afterwards. */
 sz_status sz_ctx_read_timing(sz_ctx* ctx, double* ms, uint64_t* launches, int reset);
 
-/* Compress the device field d_in (n[0]*n[1]*n[2] floats).  Runs the whole
+/* Compress the device field d_in (n[0]*n[1]*n[2] floats, 4-byte aligned as
+ * any float array is; INVALID_ARG otherwise, no 16-byte alignment needed:
+ * the kernels take a faster path where rows start on 16 bytes).  Runs the whole
  * pipeline on `stream`: range and profiling (Sec. V-C.1), auto-tuning
  * (Sec. V-C.2, Eq. 1), level bounds (Sec. V-B.2), the interpolation
  * predictor-quantiser with a fused histogram (Sec. V-A/B/D, VI-A), the host
@@ -239,8 +241,9 @@ sz_status sz_compress_batch_with_code(sz_ctx* ctx, uint32_t nfields, const float
  * Errors: INVALID_ARG (null pointer, nsym outside 2..2048). */
 sz_status sz_code_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* code_len);
 
-/* Decompress a device-resident result into d_out (n floats), replaying the
- * predictions (Sec. V-B.1).  Returns after the stream has completed.
+/* Decompress a device-resident result into d_out (n floats, 4-byte aligned;
+ * INVALID_ARG otherwise), replaying the predictions (Sec. V-B.1).  Returns
+ * after the stream has completed.
  * Errors: INVALID_ARG, OOM, DEVICE, CORRUPT. */
 sz_status sz_decompress(sz_ctx* ctx, const sz_result* res, float* d_out, void* stream);
 

@@ -1117,6 +1117,8 @@ sz_status compress_fields(sz_ctx* c, uint32_t nf, const float* const* d_in, cons
     std::vector<FieldDesc> fd(nf);
     for (uint32_t i = 0; i < nf; ++i) {
         if (!d_in[i]) return fail(c, SZ_ERR_INVALID_ARG, "field %u: null input", i);
+        if (reinterpret_cast<uintptr_t>(d_in[i]) & 3u)
+            return fail(c, SZ_ERR_INVALID_ARG, "field %u: input not 4-byte aligned", i);
         sz_status s = check_field(c, &dims[i], &params[i], geo[i]);
         if (s) return s;
         fill_desc(geo[i], &params[i], fd[i]);
@@ -1805,6 +1807,8 @@ sz_status sz_decompress_batch(sz_ctx* c, uint32_t nf, const sz_result* res, floa
         const ResultInternal* R = ri(&res[i]);
         if (!R || !d_out[i] || !res[i].words || !res[i].chunk_bits || !res[i].anchors)
             return fail(c, SZ_ERR_INVALID_ARG, "result %u is empty or output is null", i);
+        if (reinterpret_cast<uintptr_t>(d_out[i]) & 3u)
+            return fail(c, SZ_ERR_INVALID_ARG, "output %u not 4-byte aligned", i);
         sz_params p;
         sz_params_default(&p);
         p.radius = (uint32_t)R->R;
@@ -1976,6 +1980,8 @@ sz_status sz_decompress(sz_ctx* c, const sz_result* res, float* d_out, void* str
 sz_status sz_decompress_noalloc(sz_ctx* c, const sz_result* res, float* d_out, void* stream) {
     if (!c) return SZ_ERR_INVALID_ARG;
     if (!res || !d_out) return fail(c, SZ_ERR_INVALID_ARG, "null result or output");
+    if (reinterpret_cast<uintptr_t>(d_out) & 3u)
+        return fail(c, SZ_ERR_INVALID_ARG, "output not 4-byte aligned");
     if (!c->noalloc) return fail(c, SZ_ERR_DEVICE, "no workspace on device %d", c->device);
     HIP_TRY(c, hipSetDevice(c->device));
     hipStream_t st = static_cast<hipStream_t>(stream);

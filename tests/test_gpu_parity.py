@@ -251,6 +251,29 @@ def test_field_and_output_off_16_byte_alignment(ctx, shape, seed):
         res.free()
 
 
+def test_pointers_off_4_byte_alignment_are_rejected(ctx):
+    """A field or output pointer that is not 4-byte aligned (no float array
+    is) is an argument error, found before any work is queued."""
+    import ctypes as C
+    import torch
+    x = synth.spectral_field((16, 16, 16), seed=64)
+    buf = torch.zeros(x.size + 4, dtype=torch.float32, device="cuda")
+    buf[:x.size].copy_(torch.from_numpy(x.ravel()))
+    d = szi.make_dims(x.shape)
+    p = szi.make_params(3)
+    r = szi.SzResult()
+    rc = szi.lib().sz_compress(ctx.h, C.c_void_p(buf.data_ptr() + 2), C.byref(d), C.byref(p),
+                               C.c_void_p(0), C.byref(r))
+    assert rc == -1
+    res = ctx.compress(buf[:x.size].view(x.shape))
+    try:
+        rc = szi.lib().sz_decompress(ctx.h, C.byref(res.raw), C.c_void_p(buf.data_ptr() + 2),
+                                     C.c_void_p(0))
+        assert rc == -1
+    finally:
+        res.free()
+
+
 def test_window_limits(ctx):
     # the generic kernels hold a block of at most 4096 points in LDS; a
     # window must be a multiple of the stride
