@@ -183,10 +183,17 @@ struct PlanIn {
     float el[kMaxLevels], ebx2[kMaxLevels], inv[kMaxLevels];
 };
 
+// Pass np of the execution order (level L - np / ND, its np % ND-th pass);
+// the descriptors past the last pass are cleared.  Passes are independent:
+// one thread each, or a loop.
 template <int ND>
-__device__ void make_passes(FieldPlan& p, const PlanIn& in, uint32_t n0, uint32_t n01) {
+__device__ void make_pass(FieldPlan& p, const PlanIn& in, uint32_t n0, uint32_t n01, int np) {
     using G = Geo<ND>;
     constexpr int L = G::SHS;
+    if (np >= L * ND) {
+        if (np < kMaxPasses) p.pass[np] = PassDesc{};
+        return;
+    }
     const int W[3] = {G::W0, G::W1, G::W2};
     const int ST[3] = {1, G::SY, G::SZ};
     const uint32_t GS[3] = {1u, n0, n01};
@@ -196,11 +203,9 @@ __device__ void make_passes(FieldPlan& p, const PlanIn& in, uint32_t n0, uint32_
 #pragma unroll
         for (int j = 0; j < ND; ++j)
             if (in.order[k] == j) pos[j] = k;
-    int np = 0;
-#pragma unroll
-    for (int lvl = L; lvl >= 1; --lvl) {
-#pragma unroll
-        for (int k = 0; k < ND; ++k, ++np) {
+    {
+        const int lvl = L - np / ND, k = np % ND;
+        {
             PassDesc q{};
             const int d = in.order[k];
             // the other dimensions, ascending
@@ -243,15 +248,17 @@ __device__ void make_passes(FieldPlan& p, const PlanIn& in, uint32_t n0, uint32_
             p.pass[np] = q;
         }
     }
-#pragma unroll
-    for (int k = L * ND; k < kMaxPasses; ++k) p.pass[k] = PassDesc{};
+}
+
+__device__ void make_pass(const FieldDesc& f, FieldPlan& p, const PlanIn& in, int np) {
+    const uint32_t n0 = (uint32_t)f.n[0], n01 = n0 * (uint32_t)f.n[1];
+    if (f.ndim == 3) make_pass<3>(p, in, n0, n01, np);
+    else if (f.ndim == 2) make_pass<2>(p, in, n0, n01, np);
+    // 1D: the line kernels take the level bounds and the spline directly
 }
 
 __device__ void make_passes(const FieldDesc& f, FieldPlan& p, const PlanIn& in) {
-    const uint32_t n0 = (uint32_t)f.n[0], n01 = n0 * (uint32_t)f.n[1];
-    if (f.ndim == 3) make_passes<3>(p, in, n0, n01);
-    else if (f.ndim == 2) make_passes<2>(p, in, n0, n01);
-    // 1D: the line kernels take the level bounds and the spline directly
+    for (int np = 0; np < kMaxPasses; ++np) make_pass(f, p, in, np);
 }
 
 // Decompression prologue, one workgroup of kDecBlockChunks threads per
@@ -328,86 +335,98 @@ __global__ __launch_bounds__(256) void k_plan(const FieldDesc* __restrict__ F, F
     // the histogram the interpolation accumulates starts at zero
     for (int b = threadIdx.x; b < 2 * f.R; b += blockDim.x) gp(f.hist)[b] = 0u;
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    // the profiling's errors (k_range), read before the plan is written
-    double prof[3][3];
+    // thread 0: the range, the bound, alpha, the splines and the order; then
+    // one thread per level for the level bounds and one per pass for the
+    // pass descriptors (the same arithmetic, each value computed once)
+    __shared__ PlanIn s_in;
+    __shared__ double s_eabs, s_alpha;
+    if (threadIdx.x == 0) {
+        // the profiling's errors (k_range), read before the plan is written
+        double prof[3][3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+        for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int e = 0; e < 3; ++e) prof[d][e] = p.prof[d][e];
-    for (int k = 1; k < 4; ++k) {
-        mn = fminf(mn, smn[k]);
-        mx = fmaxf(mx, smx[k]);
-        bad += sbad[k];
-    }
-    p.vmin = mn + 0.0f;
-    p.vmax = mx + 0.0f;
-    p.nonfinite = bad;
-    p.status = bad ? -2 : 0;
-    p.range = (double)p.vmax - (double)p.vmin;
-    if (f.eb_mode == 1) {
-        p.eps = f.eb;
-        p.e_abs = f.eb * p.range;
-    } else {
-        p.e_abs = f.eb;
-        p.eps = p.range > 0.0 ? f.eb / p.range : (f.eb > 0.0 ? INFINITY : 0.0);
-    }
-    p.e = floor_to_f32(p.e_abs);
-    p.alpha = f.alpha_req > 0.0 ? f.alpha_req : eq1_alpha(p.eps);
-    p.levels = f.L;
-    PlanIn in;
-    double apow = 1.0;
-#pragma unroll
-    for (int l = 0; l < kMaxLevels; ++l) {
-        if (l < f.L) {
-            in.el[l] = floor_to_f32(p.e_abs / apow);
-            in.ebx2[l] = 2.0f * in.el[l];
-            in.inv[l] = 1.0f / in.ebx2[l];
-            apow = apow * p.alpha;
+            for (int e = 0; e < 3; ++e) prof[d][e] = p.prof[d][e];
+        for (int k = 1; k < 4; ++k) {
+            mn = fminf(mn, smn[k]);
+            mx = fmaxf(mx, smx[k]);
+            bad += sbad[k];
+        }
+        p.vmin = mn + 0.0f;
+        p.vmax = mx + 0.0f;
+        p.nonfinite = bad;
+        p.status = bad ? -2 : 0;
+        p.range = (double)p.vmax - (double)p.vmin;
+        if (f.eb_mode == 1) {
+            p.eps = f.eb;
+            p.e_abs = f.eb * p.range;
         } else {
-            in.el[l] = 0.0f;
-            in.ebx2[l] = 0.0f;
-            in.inv[l] = 0.0f;
+            p.e_abs = f.eb;
+            p.eps = p.range > 0.0 ? f.eb / p.range : (f.eb > 0.0 ? INFINITY : 0.0);
         }
-        p.el[l] = in.el[l];
-        p.ebx2[l] = in.ebx2[l];
-        p.inv[l] = in.inv[l];
-    }
-    const int D = f.ndim;
-    double score[3] = {0.0, 0.0, 0.0};
+        p.e = floor_to_f32(p.e_abs);
+        p.alpha = f.alpha_req > 0.0 ? f.alpha_req : eq1_alpha(p.eps);
+        p.levels = f.L;
+        s_eabs = p.e_abs;
+        s_alpha = p.alpha;
+        PlanIn& in = s_in;
+        const int D = f.ndim;
+        double score[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        int s = d < D ? f.interp[d] : SPL_LIN;
-        if (s == SPL_AUTO) s = prof[d][2] < prof[d][1] ? SPL_NAT : SPL_NAK;
-        in.spline[d] = s;
-        p.spline[d] = s;
-        score[d] = prof[d][s];
-    }
-    if (f.order_req[0] >= 0) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) in.order[k] = k < D ? f.order_req[k] : -1;
-    } else {
-        // least smooth first; a strictly larger error wins, else the slower
-        bool used[3] = {false, false, false};
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            if (k >= D) {
-                in.order[k] = -1;
-                continue;
-            }
-            int best = -1;
-#pragma unroll
-            for (int d = 2; d >= 0; --d) {
-                if (d >= D || used[d]) continue;
-                if (best < 0 || score[d] > score[best]) best = d;
-            }
-            used[best] = true;
-            in.order[k] = best;
+        for (int d = 0; d < 3; ++d) {
+            int s = d < D ? f.interp[d] : SPL_LIN;
+            if (s == SPL_AUTO) s = prof[d][2] < prof[d][1] ? SPL_NAT : SPL_NAK;
+            in.spline[d] = s;
+            p.spline[d] = s;
+            score[d] = prof[d][s];
         }
-    }
+        if (f.order_req[0] >= 0) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) p.order[k] = in.order[k];
-    make_passes(f, p, in);
+            for (int k = 0; k < 3; ++k) in.order[k] = k < D ? f.order_req[k] : -1;
+        } else {
+            // least smooth first; a strictly larger error wins, else the slower
+            bool used[3] = {false, false, false};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (k >= D) {
+                    in.order[k] = -1;
+                    continue;
+                }
+                int best = -1;
+#pragma unroll
+                for (int d = 2; d >= 0; --d) {
+                    if (d >= D || used[d]) continue;
+                    if (best < 0 || score[d] > score[best]) best = d;
+                }
+                used[best] = true;
+                in.order[k] = best;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) p.order[k] = in.order[k];
+    }
+    __syncthreads();
+    // level l: e_l = e / alpha^l rounded down to FP32, alpha^l as l products
+    // in order from 1 (as one loop over the levels forms it)
+    if (threadIdx.x < kMaxLevels) {
+        const int l = (int)threadIdx.x;
+        float el = 0.0f, ebx2 = 0.0f, inv = 0.0f;
+        if (l < f.L) {
+            double apow = 1.0;
+            for (int i = 0; i < l; ++i) apow = apow * s_alpha;
+            el = floor_to_f32(s_eabs / apow);
+            ebx2 = 2.0f * el;
+            inv = 1.0f / ebx2;
+        }
+        s_in.el[l] = el;
+        s_in.ebx2[l] = ebx2;
+        s_in.inv[l] = inv;
+        p.el[l] = el;
+        p.ebx2[l] = ebx2;
+        p.inv[l] = inv;
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxPasses) make_pass(f, p, s_in, (int)threadIdx.x);
 }
 
 // zero the histogram of every field (one y-row of workgroups per field)
