@@ -257,9 +257,6 @@ __device__ void make_pass(const FieldDesc& f, FieldPlan& p, const PlanIn& in, in
     // 1D: the line kernels take the level bounds and the spline directly
 }
 
-__device__ void make_passes(const FieldDesc& f, FieldPlan& p, const PlanIn& in) {
-    for (int np = 0; np < kMaxPasses; ++np) make_pass(f, p, in, np);
-}
 
 // Decompression prologue, one workgroup of kDecBlockChunks threads per
 // Huffman decode block: the block's word count (the decoder's offsets come
@@ -283,7 +280,7 @@ __global__ __launch_bounds__(kDecBlockChunks) void k_dec_prep(const FieldDesc* _
         const uint32_t idx = gp(fd.outlier_idx)[k];
         if (idx < fd.npts) gp(fd.out)[idx] = gp(fd.outlier_val)[k];
     }
-    if (b == 0 && threadIdx.x == 0) {
+    if (b == 0 && threadIdx.x < kMaxPasses) {   // one pass descriptor per thread
         const FieldPlan& p = P[f];
         PlanIn in;
 #pragma unroll
@@ -297,7 +294,7 @@ __global__ __launch_bounds__(kDecBlockChunks) void k_dec_prep(const FieldDesc* _
             in.ebx2[l] = p.ebx2[l];
             in.inv[l] = p.inv[l];
         }
-        make_passes(fd, P[f], in);
+        make_pass(fd, P[f], in, (int)threadIdx.x);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
