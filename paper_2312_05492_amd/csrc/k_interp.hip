@@ -723,24 +723,46 @@ __device__ __forceinline__ void write_values(const float* v, uint32_t lane, cons
 // Work is handed out in groups of kWaves windows of one field (the host
 // pads each field to whole groups).  Workgroups on one L2 domain take one
 // contiguous eighth of the groups, so that windows sharing faces are
-// processed close in time on the same L2.
+// processed close in time on the same L2: in round k its S workgroups take
+// the k-th run of S groups, workgroup j the group (j + k) mod S of the run.
+// The rotation, and that of the wave slots within a group every kWaves
+// rounds, spread windows of one kind (the field's far boundary along x
+// always falls in the same slot of every fourth group) over all waves.  A
+// fixed group and slot per workgroup and wave sent all of them to a
+// quarter of the workgroups, one wave each, which finished a fifth later
+// than the rest.
 struct GroupSeq {
-    uint64_t cur, end, step;
+    uint64_t lo, end;   // the L2 domain's groups
+    uint32_t S, j, k;   // workgroups in the domain, this one's index, round
+    uint64_t g;         // the round's group (increasing; past end: done)
+    __device__ __forceinline__ void set() { g = lo + (uint64_t)k * S + (j + k) % S; }
+    __device__ __forceinline__ bool ok() const { return g < end; }
+    __device__ __forceinline__ void next() {
+        ++k;
+        set();
+    }
+    // the window slot of a wave in the round's group
+    __device__ __forceinline__ uint32_t slot(int wave) const {
+        return ((uint32_t)wave + k / (uint32_t)kWaves) % (uint32_t)kWaves;
+    }
 };
 __device__ __forceinline__ GroupSeq group_seq(uint64_t ngroups) {
     const uint32_t G = gridDim.x, b = blockIdx.x;
     GroupSeq s;
     if (G >= (uint32_t)kXcds && G % (uint32_t)kXcds == 0u) {
         const uint64_t chunk = (ngroups + kXcds - 1) / kXcds;
-        const uint64_t lo = (uint64_t)(b % (uint32_t)kXcds) * chunk;
-        s.cur = lo + b / (uint32_t)kXcds;
-        s.end = lo + chunk < ngroups ? lo + chunk : ngroups;
-        s.step = G / (uint32_t)kXcds;
+        s.lo = (uint64_t)(b % (uint32_t)kXcds) * chunk;
+        s.end = s.lo + chunk < ngroups ? s.lo + chunk : ngroups;
+        s.S = G / (uint32_t)kXcds;
+        s.j = b / (uint32_t)kXcds;
     } else {
-        s.cur = b;
+        s.lo = 0;
         s.end = ngroups;
-        s.step = G;
+        s.S = G;
+        s.j = b;
     }
+    s.k = 0;
+    s.set();
     return s;
 }
 
@@ -784,9 +806,8 @@ SZI_WINDOW_KERNEL void k_compress(const FieldDesc* __restrict__ F, const FieldPl
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lane = threadIdx.x & 63u;
     float* v = vbuf[wave] + kPad;
-    const GroupSeq gs = group_seq(ngroups);
-    uint64_t g = gs.cur;
-    if (g >= gs.end) return;
+    GroupSeq gs = group_seq(ngroups);
+    if (!gs.ok()) return;
     int f = 0;
     // block of the next window: 16-byte quads where the window lies in the
     // field and its rows are aligned, else one value per slot
@@ -798,8 +819,8 @@ SZI_WINDOW_KERNEL void k_compress(const FieldDesc* __restrict__ F, const FieldPl
     bool valid, quads = false;
     // window of group g for this wave, and the start of its block load
     auto fetch = [&]() {
-        while (g >= goff[f + 1]) ++f;
-        const uint32_t w = (uint32_t)(g - goff[f]) * kWaves + (uint32_t)wave;
+        while (gs.g >= goff[f + 1]) ++f;
+        const uint32_t w = (uint32_t)(gs.g - goff[f]) * kWaves + gs.slot(wave);
         valid = w < (uint32_t)(F[f].nwin[0] * F[f].nwin[1] * F[f].nwin[2]);
         if (valid) {
             wn = make_win<ND>(F[f], w);
@@ -833,8 +854,8 @@ SZI_WINDOW_KERNEL void k_compress(const FieldDesc* __restrict__ F, const FieldPl
             else if (wc.full) commit_block<ND, true>(v, pre, lm, wc);
             else commit_block<ND, false>(v, pre, lm, wc);
         }
-        g += gs.step;
-        const bool more = g < gs.end;
+        gs.next();
+        const bool more = gs.ok();
         if (more) fetch();   // in flight during the passes below
         if (vc) {
             wave_sync();
@@ -858,9 +879,8 @@ SZI_WINDOW_KERNEL void k_decompress(const FieldDesc* __restrict__ F,
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lane = threadIdx.x & 63u;
     float* v = vbuf[wave] + kPad;
-    const GroupSeq gs = group_seq(ngroups);
-    uint64_t g = gs.cur;
-    if (g >= gs.end) return;
+    GroupSeq gs = group_seq(ngroups);
+    if (!gs.ok()) return;
     int f = 0;
     // codes of the next window's block; block points outside the field
     // hold a value no code takes
@@ -871,8 +891,8 @@ SZI_WINDOW_KERNEL void k_decompress(const FieldDesc* __restrict__ F,
     Win wn;
     bool valid;
     auto fetch = [&]() {
-        while (g >= goff[f + 1]) ++f;
-        const uint32_t w = (uint32_t)(g - goff[f]) * kWaves + (uint32_t)wave;
+        while (gs.g >= goff[f + 1]) ++f;
+        const uint32_t w = (uint32_t)(gs.g - goff[f]) * kWaves + gs.slot(wave);
         valid = w < (uint32_t)(F[f].nwin[0] * F[f].nwin[1] * F[f].nwin[2]);
         if (valid) {
             wn = make_win<ND>(F[f], w);
@@ -904,8 +924,8 @@ SZI_WINDOW_KERNEL void k_decompress(const FieldDesc* __restrict__ F,
             int la;
             if (anchor_slot<ND>(lane, F[fc], wc, ga, la)) v[la] = apre;
         }
-        g += gs.step;
-        const bool more = g < gs.end;
+        gs.next();
+        const bool more = gs.ok();
         if (more) fetch();   // in flight during the passes below
         if (vc) {
             wave_sync();
@@ -1027,12 +1047,11 @@ __global__ __launch_bounds__(kThreads) void k_compress1d(const FieldDesc* __rest
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lane = threadIdx.x & 63u;
     float* v = vbuf[wave];
-    const GroupSeq gs = group_seq(ngroups);
     int f = 0, hf = -1;
     uint32_t cntR = 0;
 #pragma unroll 1
-    for (uint64_t g = gs.cur; g < gs.end; g += gs.step) {
-        while (g >= goff[f + 1]) ++f;
+    for (GroupSeq gs = group_seq(ngroups); gs.ok(); gs.next()) {
+        while (gs.g >= goff[f + 1]) ++f;
         if (f != hf) {   // uniform over the workgroup: groups never span fields
             if (hf >= 0) flush_hist(hist, cntR, F[hf]);
             clear_hist(hist, F[f].R);
@@ -1040,7 +1059,7 @@ __global__ __launch_bounds__(kThreads) void k_compress1d(const FieldDesc* __rest
             hf = f;
         }
         const FieldDesc& fd = F[f];
-        const uint32_t w = (uint32_t)(g - goff[f]) * kWaves + (uint32_t)wave;
+        const uint32_t w = (uint32_t)(gs.g - goff[f]) * kWaves + gs.slot(wave);
         if (w >= (uint32_t)fd.nwin[0]) continue;
         const Win1 wi = make_win1(fd, w);
         const SZI_G float* in = gp(fd.in) + wi.lo;
@@ -1068,14 +1087,13 @@ __global__ __launch_bounds__(kThreads) void k_decompress1d(const FieldDesc* __re
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lane = threadIdx.x & 63u;
     float* v = vbuf[wave];
-    const GroupSeq gs = group_seq(ngroups);
     int f = 0;
     uint32_t unused = 0;
 #pragma unroll 1
-    for (uint64_t g = gs.cur; g < gs.end; g += gs.step) {
-        while (g >= goff[f + 1]) ++f;
+    for (GroupSeq gs = group_seq(ngroups); gs.ok(); gs.next()) {
+        while (gs.g >= goff[f + 1]) ++f;
         const FieldDesc& fd = F[f];
-        const uint32_t w = (uint32_t)(g - goff[f]) * kWaves + (uint32_t)wave;
+        const uint32_t w = (uint32_t)(gs.g - goff[f]) * kWaves + gs.slot(wave);
         if (w >= (uint32_t)fd.nwin[0]) continue;
         const Win1 wi = make_win1(fd, w);
         // every point takes its code (as float bits), the anchors their values
@@ -1278,12 +1296,11 @@ __global__ __launch_bounds__(kThreads) void k_compress_gen(const FieldDesc* __re
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lane = threadIdx.x & 63u;
     float* v = vbuf[wave];
-    const GroupSeq gs = group_seq(ngroups);
     int f = 0, hf = -1;
     uint32_t cntR = 0;
 #pragma unroll 1
-    for (uint64_t g = gs.cur; g < gs.end; g += gs.step) {
-        while (g >= goff[f + 1]) ++f;
+    for (GroupSeq gs = group_seq(ngroups); gs.ok(); gs.next()) {
+        while (gs.g >= goff[f + 1]) ++f;
         if (f != hf) {   // uniform over the workgroup: groups never span fields
             if (hf >= 0) flush_hist(hist, cntR, F[hf]);
             clear_hist(hist, F[f].R);
@@ -1291,7 +1308,7 @@ __global__ __launch_bounds__(kThreads) void k_compress_gen(const FieldDesc* __re
             hf = f;
         }
         const FieldDesc& fd = F[f];
-        const uint32_t w = (uint32_t)(g - goff[f]) * kWaves + (uint32_t)wave;
+        const uint32_t w = (uint32_t)(gs.g - goff[f]) * kWaves + gs.slot(wave);
         if (w >= (uint32_t)(fd.nwin[0] * fd.nwin[1] * fd.nwin[2])) continue;
         const WinG wi = make_wing(fd, w);
         const SZI_G float* in = gp(fd.in) + wi.gbase;
@@ -1331,14 +1348,13 @@ __global__ __launch_bounds__(kThreads) void k_decompress_gen(const FieldDesc* __
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lane = threadIdx.x & 63u;
     float* v = vbuf[wave];
-    const GroupSeq gs = group_seq(ngroups);
     int f = 0;
     uint32_t unused = 0;
 #pragma unroll 1
-    for (uint64_t g = gs.cur; g < gs.end; g += gs.step) {
-        while (g >= goff[f + 1]) ++f;
+    for (GroupSeq gs = group_seq(ngroups); gs.ok(); gs.next()) {
+        while (gs.g >= goff[f + 1]) ++f;
         const FieldDesc& fd = F[f];
-        const uint32_t w = (uint32_t)(g - goff[f]) * kWaves + (uint32_t)wave;
+        const uint32_t w = (uint32_t)(gs.g - goff[f]) * kWaves + gs.slot(wave);
         if (w >= (uint32_t)(fd.nwin[0] * fd.nwin[1] * fd.nwin[2])) continue;
         const WinG wi = make_wing(fd, w);
         // every point takes its code (as float bits), the anchors their values
