@@ -745,6 +745,22 @@ struct GroupSeq {
     __device__ __forceinline__ uint32_t slot(int wave) const {
         return ((uint32_t)wave + k / (uint32_t)kWaves) % (uint32_t)kWaves;
     }
+    // Issue priority of the round.  A SIMD issues from its oldest wave
+    // first, so with equal work the workgroups dispatched first on a CU
+    // finish first and the last ones run on alone.  The T workgroups that
+    // share a CU (j / kCusPerDomain apart in dispatch order, with T = S /
+    // kCusPerDomain of them) take the highest priority in turn, one round
+    // each.
+    __device__ __forceinline__ void set_priority() const {
+        constexpr uint32_t kCusPerDomain = 32;
+        uint32_t T = S / kCusPerDomain;
+        T = T < 1u ? 1u : (T > 4u ? 4u : T);
+        const uint32_t p = (k + j / kCusPerDomain) % T;
+        if (p == 0u) __builtin_amdgcn_s_setprio(0);
+        else if (p == 1u) __builtin_amdgcn_s_setprio(1);
+        else if (p == 2u) __builtin_amdgcn_s_setprio(2);
+        else __builtin_amdgcn_s_setprio(3);
+    }
 };
 __device__ __forceinline__ GroupSeq group_seq(uint64_t ngroups) {
     const uint32_t G = gridDim.x, b = blockIdx.x;
@@ -855,6 +871,7 @@ SZI_WINDOW_KERNEL void k_compress(const FieldDesc* __restrict__ F, const FieldPl
             else commit_block<ND, false>(v, pre, lm, wc);
         }
         gs.next();
+        gs.set_priority();
         const bool more = gs.ok();
         if (more) fetch();   // in flight during the passes below
         if (vc) {
@@ -925,6 +942,7 @@ SZI_WINDOW_KERNEL void k_decompress(const FieldDesc* __restrict__ F,
             if (anchor_slot<ND>(lane, F[fc], wc, ga, la)) v[la] = apre;
         }
         gs.next();
+        gs.set_priority();
         const bool more = gs.ok();
         if (more) fetch();   // in flight during the passes below
         if (vc) {
