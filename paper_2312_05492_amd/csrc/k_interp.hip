@@ -747,12 +747,13 @@ struct GroupSeq {
     }
     // Issue priority of the round.  A SIMD issues from its oldest wave
     // first, so with equal work the workgroups dispatched first on a CU
-    // finish first and the last ones run on alone.  The T workgroups that
-    // share a CU (j / kCusPerDomain apart in dispatch order, with T = S /
-    // kCusPerDomain of them) take the highest priority in turn, one round
-    // each.
+    // finish first and the last ones run on alone.  Dispatch fills the
+    // domain's 32 CUs one workgroup each before it places second ones, so
+    // the T = S / 32 workgroups that share a CU are j, j + 32, .. of the
+    // domain; with priority (k + j / 32) mod T they hold the highest
+    // priority in turn, one round each.
     __device__ __forceinline__ void set_priority() const {
-        constexpr uint32_t kCusPerDomain = 32;
+        constexpr uint32_t kCusPerDomain = 32;   // 256 CUs in 8 L2 domains
         uint32_t T = S / kCusPerDomain;
         T = T < 1u ? 1u : (T > 4u ? 4u : T);
         const uint32_t p = (k + j / kCusPerDomain) % T;
