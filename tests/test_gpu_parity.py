@@ -329,8 +329,36 @@ def test_launch_shape_is_arithmetic_neutral(ctx):
         r = ctx.compress(_to_gpu(x))
         blobs.append(r.blob())
         r.free()
-    ctx.set_grid(8)
+    ctx.set_grid(0)
     assert all(b == blobs[0] for b in blobs)
+
+
+def test_window_order_over_grids_equals_oracle(ctx):
+    # The order in which workgroups take groups of windows, the wave slots
+    # within a group and the issue-priority tiers all follow from the grid.
+    # A ragged field of 1920 groups (240 per L2 domain, partial windows on
+    # three faces) with grids of 1, 2, 3 and 5 workgroups per CU (5 is more
+    # than fit at once) gives 7.5, 3.75, 2.5 and 1.5 rounds per workgroup
+    # and one to four priority tiers; each must give the oracle's blob and
+    # reconstruction.
+    x = synth.spectral_field((120, 250, 500), seed=43)
+    ref = O.compress(x, _oracle_params(x.shape, {}))
+    want = ref.blob()
+    d = _to_gpu(x)
+    try:
+        for per_cu in (1, 2, 3, 5):
+            print("\n[parity] window order, %d workgroups per CU" % per_cu, flush=True)
+            ctx.set_grid(per_cu)
+            r = ctx.compress(d)
+            try:
+                assert r.blob() == want, "blob, %d workgroups per CU" % per_cu
+                y = ctx.decompress(r).cpu().numpy()
+                assert np.array_equal(_bits(y), _bits(ref.recon)), \
+                    "reconstruction, %d workgroups per CU" % per_cu
+            finally:
+                r.free()
+    finally:
+        ctx.set_grid(0)
 
 
 def test_tuned_shapes_are_arithmetic_neutral():
